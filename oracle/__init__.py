@@ -1,0 +1,246 @@
+"""FP64 CPU oracle of the coupled viscoelastic lattice Boltzmann step -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (``paper_2508_16997_amd``)
+never imports, links or calls anything here, and the oracle shares no code with it.
+
+The arithmetic lives in ``vlb_oracle.cpp`` (plain C++17, double precision, no
+fast-math, FMA contraction off); this module only builds it with g++ and marshals
+arguments through ctypes.  Functions whose result is pinned only by other oracle code
+are listed in the design notes as "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vlb_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MODES = {"periodic": 0, "wall": 1, "open": 2}
+FLAG_NO_SOURCE = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` (g++, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-shared", "-fPIC", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = C.CDLL(_LIB)
+    P = C.c_void_p
+    D = C.c_double
+    DP = C.POINTER(C.c_double)
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, DP, C.c_int, C.c_int]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_max_threads.restype = C.c_int
+    lib.orc_set_params.argtypes = [P, D, D, D, D, D, D, C.c_int]
+    lib.orc_set_force.argtypes = [P, D, D, DP, DP]
+    lib.orc_set_tangent.argtypes = [P, D, D, DP, DP]
+    lib.orc_set_inlet.argtypes = [P, DP, DP, DP, DP]
+    lib.orc_init.argtypes = [P, DP, DP, DP, DP, DP, DP]
+    lib.orc_step.argtypes = [P, C.c_longlong]
+    lib.orc_get_step.restype = C.c_longlong
+    lib.orc_get_step.argtypes = [P]
+    lib.orc_read.argtypes = [P, DP, DP, DP, DP, DP, DP]
+    lib.orc_read_tangent.argtypes = [P, DP, DP, DP, DP, DP, DP]
+    lib.orc_read_history.argtypes = [P, DP, DP, DP, DP, DP]
+    lib.orc_read_populations.argtypes = [P, DP, DP]
+    lib.orc_geometry.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p, DP, C.c_int]
+    lib.orc_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, DP]
+    lib.orc_node_feq.argtypes = [D, D, D, DP]
+    lib.orc_node_geq.argtypes = [D, D, D, DP]
+    lib.orc_node_hydro.argtypes = [DP, D, D, D, D, D, D, D, D, D, DP]
+    lib.orc_node_cde.argtypes = [DP, D, D, D, D, D, D, D, D, D, D, D, DP]
+    lib.orc_node_source.argtypes = [DP, DP, D, DP]
+    lib.orc_node_fd.restype = D
+    lib.orc_node_fd.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
+    _lib = lib
+    return lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+class OracleSim:
+    """One oracle simulation built from a :class:`synth.Problem`."""
+
+    def __init__(self, prob, dual: bool = False, flags: int = 0):
+        lib = _load()
+        self.prob = prob
+        self.nx, self.ny = prob.nx, prob.ny
+        self.dual = dual
+        mask = None
+        if prob.solid is not None:
+            mask = np.ascontiguousarray(prob.solid, dtype=np.uint8)
+        circ = np.ascontiguousarray(np.array(prob.circles, dtype=np.float64).reshape(-1))
+        self._keep = [mask, circ]
+        self.h = lib.orc_create(prob.nx, prob.ny, MODES[prob.xmode], MODES[prob.ymode],
+                                None if mask is None else mask.ctypes.data,
+                                _dp(circ) if circ.size else None, len(prob.circles),
+                                1 if dual else 0)
+        if not self.h:
+            raise ValueError("oracle: invalid grid")
+        rc = lib.orc_set_params(self.h, prob.nu_s, prob.eta_p, prob.lam, prob.kappa,
+                                prob.Lambda_s, prob.Lambda_p, flags)
+        if rc != 0:
+            raise ValueError("oracle: invalid parameters")
+        self.set_force(prob.Fx, prob.Fy)
+        if prob.inlet is not None:
+            i = prob.inlet
+            arrs = [_c64(i[k]) for k in ("ux", "axx", "axy", "ayy")]
+            lib.orc_set_inlet(self.h, *[_dp(a) for a in arrs])
+        self.init()
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _load().orc_destroy(self.h)
+            self.h = None
+
+    def set_force(self, Fx, Fy):
+        lib = _load()
+        if np.ndim(Fx) == 0 and np.ndim(Fy) == 0:
+            lib.orc_set_force(self.h, float(Fx), float(Fy), None, None)
+        else:
+            fx = _c64(np.broadcast_to(np.asarray(Fx, np.float64), (self.ny, self.nx)))
+            fy = _c64(np.broadcast_to(np.asarray(Fy, np.float64), (self.ny, self.nx)))
+            lib.orc_set_force(self.h, 0.0, 0.0, _dp(fx), _dp(fy))
+
+    def set_tangent(self, dlam=0.0, deta=0.0, dFx=None, dFy=None):
+        fx = None if dFx is None else _c64(np.broadcast_to(dFx, (self.ny, self.nx)))
+        fy = None if dFy is None else _c64(np.broadcast_to(dFy, (self.ny, self.nx)))
+        rc = _load().orc_set_tangent(self.h, float(dlam), float(deta), _dp(fx), _dp(fy))
+        if rc != 0:
+            raise ValueError("oracle: tangent needs a dual-number simulation")
+
+    def init(self, fields: Optional[dict] = None):
+        f = self.prob.init_arrays() if fields is None else fields
+        arrs = [_c64(f[k]) for k in ("rho", "ux", "uy", "axx", "axy", "ayy")]
+        _load().orc_init(self.h, *[_dp(a) for a in arrs])
+
+    def step(self, n: int = 1):
+        _load().orc_step(self.h, int(n))
+
+    @property
+    def time(self) -> int:
+        return int(_load().orc_get_step(self.h))
+
+    def read(self) -> dict:
+        out = {k: np.zeros((self.ny, self.nx)) for k in ("rho", "ux", "uy", "axx", "axy", "ayy")}
+        _load().orc_read(self.h, *[_dp(out[k]) for k in ("rho", "ux", "uy", "axx", "axy", "ayy")])
+        return out
+
+    def read_tangent(self) -> dict:
+        out = {k: np.zeros((self.ny, self.nx)) for k in ("rho", "ux", "uy", "axx", "axy", "ayy")}
+        rc = _load().orc_read_tangent(self.h, *[_dp(out[k]) for k in
+                                                ("rho", "ux", "uy", "axx", "axy", "ayy")])
+        if rc != 0:
+            raise ValueError("oracle: tangents need a dual-number simulation")
+        return out
+
+    def history(self):
+        out = {k: np.zeros((self.ny, self.nx)) for k in ("sxx", "sxy", "syy", "uxp", "uyp")}
+        first = _load().orc_read_history(self.h, *[_dp(out[k]) for k in
+                                                   ("sxx", "sxy", "syy", "uxp", "uyp")])
+        return out, bool(first)
+
+    def populations(self):
+        n = self.nx * self.ny
+        f = np.zeros((9, n))
+        g = np.zeros((3, 9, n))
+        _load().orc_read_populations(self.h, _dp(f), _dp(g))
+        return f.reshape(9, self.ny, self.nx), g.reshape(3, 9, self.ny, self.nx)
+
+    def geometry(self):
+        """(node_class (ny, nx) uint8, links structured array of (node, dir, q))."""
+        lib = _load()
+        cls = np.zeros((self.ny, self.nx), dtype=np.uint8)
+        cnt = lib.orc_geometry(self.h, cls.ctypes.data, None, None, None, 0)
+        node = np.zeros(cnt, dtype=np.int32)
+        d = np.zeros(cnt, dtype=np.int8)
+        q = np.zeros(cnt, dtype=np.float64)
+        lib.orc_geometry(self.h, cls.ctypes.data, node.ctypes.data, d.ctypes.data, _dp(q), cnt)
+        return cls, node, d, q
+
+
+def lattice():
+    lib = _load()
+    ex = np.zeros(9, np.int32)
+    ey = np.zeros(9, np.int32)
+    opp = np.zeros(9, np.int32)
+    w = np.zeros(9)
+    lib.orc_lattice(ex.ctypes.data, ey.ctypes.data, opp.ctypes.data, _dp(w))
+    return ex, ey, opp, w
+
+
+def node_feq(rho, ux, uy):
+    out = np.zeros(9)
+    _load().orc_node_feq(rho, ux, uy, _dp(out))
+    return out
+
+
+def node_geq(phi, ux, uy):
+    out = np.zeros(9)
+    _load().orc_node_geq(phi, ux, uy, _dp(out))
+    return out
+
+
+def node_hydro(f9, Fx, Fy, tau_s1, tau_s2, tau_ab=(0.0, 0.0, 0.0), D=(0.0, 0.0)):
+    f9 = _c64(f9)
+    out = np.zeros(9)
+    _load().orc_node_hydro(_dp(f9), Fx, Fy, tau_s1, tau_s2, tau_ab[0], tau_ab[1], tau_ab[2],
+                           D[0], D[1], _dp(out))
+    return out
+
+
+def node_cde(g9, rho, ux, uy, Fx, Fy, S, Sp, uxp, uyp, tau_p1, tau_p2):
+    g9 = _c64(g9)
+    out = np.zeros(9)
+    _load().orc_node_cde(_dp(g9), rho, ux, uy, Fx, Fy, S, Sp, uxp, uyp, tau_p1, tau_p2, _dp(out))
+    return out
+
+
+def node_source(A3, L4, lam):
+    A3 = _c64(A3)
+    L4 = _c64(L4)
+    out = np.zeros(3)
+    _load().orc_node_source(_dp(A3), _dp(L4), lam, _dp(out))
+    return out
+
+
+def node_fd(lo_solid, qlo, plo, p0, hi_solid, qhi, phi):
+    return float(_load().orc_node_fd(int(lo_solid), qlo, plo, p0, int(hi_solid), qhi, phi))

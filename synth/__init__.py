@@ -1,0 +1,20 @@
+"""Seeded synthetic workloads shared by the HIP path, the oracle and the benchmark.
+
+This package holds problem set-ups only (grid sizes, boundary kinds, dimensionless
+groups converted to lattice units, initial and forcing fields, inlet profiles and the
+seeded draws of the batched and adjoint workloads).  It contains none of the lattice
+Boltzmann arithmetic: relaxation times, equilibria, collisions and boundary schemes are
+implemented separately by the library and by the oracle.
+"""
+from .workloads import (  # noqa: F401
+    Problem,
+    lattice_units,
+    poiseuille,
+    four_roll_mill,
+    cylinder,
+    batch_c4,
+    adjoint_c5,
+    rest_state,
+    random_periodic,
+    waves,
+)
