@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled viscoelastic LB step on one MI355X.
+
+Workload (default): simplified four-roll mill, 512 x 512 periodic, FP32, Wi = 5,
+beta = 0.5, Stokes-Oldroyd-B set-up of the paper's Sec. 4.1 with synthetic (analytic)
+fields.  One "step" is one coupled update: 1 hydrodynamic + 3 conformation D2Q9
+lattices, every step of the hot path on the GPU.
+
+Prints one JSON line with the metric (coupled MLUPS), the roofline of the step kernel
+(algorithmic bytes per launch / average launch time from HIP events on the launch
+stream, against the 8 TB/s HBM peak) and the FP64 oracle timed on the host's cores on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "coupled MLUPS (FP32) & % HBM roofline; batched vs single; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    import synth
+
+    if name == "four_roll_512":
+        pr = synth.four_roll_mill(N=512, steps=20000)
+        desc = "four-roll mill 512x512 periodic, FP32, Wi=5, beta=0.5, Re=1, Sc=1e5"
+    elif name == "cylinder_4096x1024":
+        pr = synth.cylinder(Wi=1.0)
+        desc = "channel flow past cylinder 4096x1024, R=128, FP32, Wi=1, beta=0.59, Sc=1e6"
+    elif name == "poiseuille_64x32_fp64":
+        pr = synth.poiseuille()
+        desc = "Oldroyd-B Poiseuille 64x32, FP64, Wi=1, beta=0.5"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return pr, desc
+
+
+def bytes_per_node(pr, esz):
+    """Algorithmic HBM bytes of one coupled node update (one read + one write each)."""
+    b = 2 * 36 * esz + 2 * 5 * esz  # populations and S/u history
+    if not pr.uniform_force():
+        b += 2 * esz  # per-node body force (read only)
+    if pr.ymode == "wall" or pr.xmode == "wall" or pr.circles or pr.solid is not None:
+        b += 2  # geometry word (read only)
+    return b
+
+
+def cpu_baseline(pr, seconds):
+    import oracle
+
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    oracle.set_threads(cores)
+    o = oracle.OracleSim(pr)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(seconds / max(t1, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    nodes = int(pr.fluid_mask().sum())
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{n} coupled FP64 steps of the same {pr.nx}x{pr.ny} workload "
+                      f"(after 1 untimed step), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="four_roll_512",
+                    choices=["four_roll_512", "cylinder_4096x1024", "poiseuille_64x32_fp64"])
+    ap.add_argument("--tile", type=int, default=4)
+    ap.add_argument("--graph-chunk", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); the "
+              "coupled step is a single-GPU kernel and multi-GPU runs are not part of this "
+              "build", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2508_16997_amd import Simulation
+
+    pr, desc = workload(args.workload)
+    prec = pr.precision
+    esz = 4 if prec == "fp32" else 8
+    stream = torch.cuda.Stream()
+    sim = Simulation.from_problem(pr, stream=stream, tile=args.tile, graph_chunk=args.graph_chunk)
+    nodes = int(pr.fluid_mask().sum())
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    mon = sim.monitors()
+    if mon["nonfinite"]:
+        print("non-finite fields after the timed steps", file=sys.stderr)
+        return 3
+
+    mlups = nodes * args.steps / wall / 1e6
+    bpn = bytes_per_node(pr, esz)
+    launch_s = gpu_ms / 1e3 / args.steps
+    bytes_launch = bpn * nodes
+    achieved = bytes_launch / launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "nx": pr.nx, "ny": pr.ny, "fluid_nodes": nodes,
+                   "bytes_per_node": bpn, "tile": f"64x{args.tile}",
+                   "graph_chunk_steps": 2 * args.graph_chunk},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_step",
+                     "avg_launch_us": round(launch_s * 1e6, 3),
+                     "bytes_per_launch": bytes_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

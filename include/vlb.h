@@ -1,0 +1,191 @@
+/*
+ * vlb.h -- C ABI of the MI355X coupled viscoelastic lattice Boltzmann library.
+ *
+ * One time step couples (Yu, Chen, Wang, Yuan, Shu, arXiv:2508.16997):
+ *   - a D2Q9 two-relaxation-time regularized hydrodynamic lattice with a third-order
+ *     Hermite equilibrium, the Galilean correction G_i, the first-order Hermite body
+ *     force F_i and the local viscoelastic source T_i (Sec. 3.1);
+ *   - three D2Q9 two-relaxation-time regularized convection-diffusion lattices for the
+ *     conformation components A_xx, A_xy, A_yy with the Oldroyd-B constitutive source,
+ *     the auxiliary term G~_i (incompressible form), the source term F~_i and its
+ *     backward time difference (Sec. 2.2-2.3, 3.2);
+ *   - conservative non-equilibrium bounce-back (CNEBB) for every conformation lattice
+ *     at solid walls (Sec. 3.3), half-way or linearly interpolated bounce-back for the
+ *     hydrodynamic lattice, equilibrium inlet and zero-gradient outlet columns.
+ *
+ * Conventions
+ *   - Every call returns an int status: VLB_OK (0) or a negative VLB_E_* code; a
+ *     thread-local detail string is available from vlb_last_error_detail().  No C++
+ *     exception crosses this interface.  Invalid arguments are rejected before any
+ *     device work is enqueued.
+ *   - Memory: the library never allocates or frees device memory.  The caller owns
+ *     the workspace (size from vlb_workspace_bytes) and every array it passes.  Host
+ *     arrays given to the library are copied before the call returns.
+ *   - Device arrays of fields are row-major [ny][nx] (x fastest), in the simulation's
+ *     precision (float for VLB_FP32, double for VLB_FP64), unless stated otherwise.
+ *   - Streams: all device work is enqueued on the HIP stream given to vlb_bind
+ *     (hipStream_t passed as void*; 0 is the null stream).  Calls that return data
+ *     to the host (vlb_monitors, vlb_load_state) synchronize that stream.
+ *   - Threads: a vlb_sim must not be used from two host threads at once.
+ */
+#ifndef VLB_H
+#define VLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VLB_OK = 0,
+    VLB_E_INVALID_ARG = -1, /* bad size, mode, parameter (tau <= 1/2, lambda <= 0) */
+    VLB_E_WORKSPACE = -2,   /* workspace missing, too small or misaligned            */
+    VLB_E_HIP = -3,         /* a HIP runtime call failed (detail string has it)      */
+    VLB_E_NONFINITE = -4,   /* NaN/Inf detected by the monitors: numerical breakdown */
+    VLB_E_STATE = -5,       /* call out of order (e.g. step before bind/init)        */
+    VLB_E_UNSUPPORTED = -6  /* feature not available for this configuration          */
+};
+
+enum { VLB_FP32 = 0, VLB_FP64 = 1 };
+/* Boundary kind of an axis.  VLB_OPEN (x only): inlet ghost column at x = -1 carrying
+ * the prescribed profile (vlb_set_inlet) at equilibrium, zero-gradient outlet ghost at
+ * x = nx.  VLB_WALL: no-slip wall half a spacing outside the first and last rows
+ * (columns). */
+enum { VLB_PERIODIC = 0, VLB_WALL = 1, VLB_OPEN = 2 };
+/* Node classes returned by vlb_geometry. */
+enum { VLB_NODE_FLUID = 0, VLB_NODE_SOLID = 1, VLB_NODE_BOUNDARY = 2 };
+/* Parameter flags. */
+enum { VLB_FLAG_NO_SOURCE = 1 /* constitutive source S forced to 0 (conservation checks) */ };
+
+typedef struct vlb_sim vlb_sim;
+
+/* Grid description.  A node is solid if solid_mask[y*nx + x] != 0 or if
+ * (x - xc)^2 + (y - yc)^2 <= R^2 for one of the circles (evaluated in double without
+ * fused multiply-add; exact for half-integer centres and radii).  Links that end in a
+ * circle carry the wall fraction q of the exact circle; every other wall link has
+ * q = 1/2. */
+typedef struct {
+    int nx, ny;               /* 1 <= nx, ny; nx * ny < 2^31                           */
+    int xmode, ymode;         /* VLB_PERIODIC / VLB_WALL / VLB_OPEN (xmode only)       */
+    int precision;            /* VLB_FP32 or VLB_FP64                                  */
+    const uint8_t* solid_mask;/* host, ny*nx, nullable                                 */
+    const double* circles;    /* host, 3 per circle (xc, yc, R), nullable              */
+    int ncircles;
+} vlb_grid;
+
+/* Lattice-unit parameters (rho0 = 1).  The library derives the relaxation times of
+ * Sec. 3.1-3.2: tau_s1 = nu_s / c_s^2 + 1/2, tau_s2 = Lambda_s / (tau_s1 - 1/2) + 1/2,
+ * tau_p1 = kappa / c_s^2 + 1/2, tau_p2 = Lambda_p / (tau_p1 - 1/2) + 1/2, and uses the
+ * Oldroyd-B closure tau_ab = (eta_p / lambda)(A_ab - delta_ab). */
+typedef struct {
+    double nu_s;      /* solvent kinematic viscosity, > 0                  */
+    double eta_p;     /* polymer viscosity, >= 0                           */
+    double lambda;    /* polymer relaxation time, > 0                      */
+    double kappa;     /* centre-of-mass diffusion coefficient, > 0         */
+    double Lambda_s;  /* hydrodynamic magic parameter, > 0                 */
+    double Lambda_p;  /* conformation magic parameter, > 0                 */
+    double Fx, Fy;    /* uniform body force (used until a force field is set) */
+    int flags;        /* VLB_FLAG_*                                        */
+} vlb_params;
+
+typedef struct {
+    double mass[4];     /* sum over fluid nodes of rho, A_xx, A_xy, A_yy (FP64 accumulation) */
+    double residual;    /* max |u(now) - u(previous monitor call)| over fluid nodes           */
+    double umax;        /* max |u| over fluid nodes                                          */
+    int64_t step;       /* time step of the state                                            */
+    int64_t nonfinite;  /* fluid nodes with a non-finite rho, u or A                         */
+    int64_t spd_violations; /* fluid nodes with det(A) <= 0 or tr(A) <= 0                    */
+} vlb_monitor;
+
+/* ---- creation (host only, no device work) -------------------------------------- */
+
+/* Builds the node classes and the boundary-link list on the host. */
+int vlb_create(const vlb_grid* grid, vlb_sim** out);
+void vlb_destroy(vlb_sim* sim);
+
+/* Bytes of device workspace this simulation needs (populations, history, force,
+ * geometry tables, monitors). */
+int vlb_workspace_bytes(const vlb_sim* sim, size_t* bytes);
+
+/* Node classes (host array of ny*nx, VLB_NODE_*) and the boundary-link list: one entry
+ * per fluid node and direction d (1..8, D2Q9 order of the paper) whose neighbour
+ * x + e_d is solid, as (node = y*nx + x, d, q), sorted by (node, d).  *nlinks receives
+ * the total count; at most cap entries are written (cap = 0 and null arrays to query).
+ * Host-only: usable without a device. */
+int vlb_geometry(const vlb_sim* sim, uint8_t* node_class, int32_t* link_node,
+                 int8_t* link_dir, double* link_q, int cap, int* nlinks);
+
+/* ---- binding and set-up ------------------------------------------------------- */
+
+/* Attaches a caller-owned device workspace (>= vlb_workspace_bytes, 256-byte aligned)
+ * and the stream for all later work; uploads the geometry tables (async). */
+int vlb_bind(vlb_sim* sim, void* workspace_dev, size_t bytes, void* hip_stream);
+
+/* Validates and stores the parameters (tau_s1, tau_p1 > 1/2 follow from nu_s, kappa > 0). */
+int vlb_set_params(vlb_sim* sim, const vlb_params* p);
+
+/* Per-node body force: device arrays [ny][nx] in the simulation precision, copied into
+ * the workspace on the stream.  Both null: back to the uniform force of vlb_params. */
+int vlb_set_force_field(vlb_sim* sim, const void* fx_dev, const void* fy_dev);
+
+/* Inlet profile for VLB_OPEN x: host arrays of ny doubles (u_x, A_xx, A_xy, A_yy);
+ * u_y = 0 and rho = 1 at the inlet ghost column. */
+int vlb_set_inlet(vlb_sim* sim, const double* ux, const double* axx, const double* axy,
+                  const double* ayy);
+
+/* Equilibrium initial state (Sec. 4.2: populations at equilibrium, zero
+ * non-equilibrium part): f = f^eq(rho, u), g = g^eq(A, u).  Device arrays [ny][nx] in
+ * the simulation precision; a null array takes rho = 1, u = 0, A = I.  Resets the
+ * step counter; the first step uses F~(t-1) = F~(t). */
+int vlb_init_equilibrium(vlb_sim* sim, const void* rho, const void* ux, const void* uy,
+                         const void* axx, const void* axy, const void* ayy);
+
+/* ---- time stepping and read-out ----------------------------------------------- */
+
+/* Advances nsteps coupled time steps (async on the stream). */
+int vlb_step(vlb_sim* sim, int64_t nsteps);
+
+/* Current step count (host-side, no synchronization). */
+int vlb_get_step(const vlb_sim* sim, int64_t* step);
+
+/* Macroscopic fields at the current time: rho, u (with the half-force shift), A.
+ * Device arrays [ny][nx] in the simulation precision; any may be null; solid nodes
+ * read 0. */
+int vlb_read_fields(vlb_sim* sim, void* rho, void* ux, void* uy, void* axx, void* axy,
+                    void* ayy);
+
+/* History the next step will use: S(t-1) for the three components and u(t-1).
+ * Device arrays as for vlb_read_fields. */
+int vlb_read_history(vlb_sim* sim, void* sxx, void* sxy, void* syy, void* uxp, void* uyp);
+
+/* Wavefront-reduced monitors (mass per lattice, residual since the previous call,
+ * non-finite and SPD counts).  Synchronizes the stream.  Returns VLB_E_NONFINITE when
+ * any fluid node is non-finite (the paper's numerical breakdown), with *out filled. */
+int vlb_monitors(vlb_sim* sim, vlb_monitor* out);
+
+/* ---- checkpoint ------------------------------------------------------------------ */
+
+/* Bytes of a saved state (populations, history, step counter). */
+int vlb_state_bytes(const vlb_sim* sim, size_t* bytes);
+/* Copies the state into / from a caller-owned device buffer (async / synchronizing). */
+int vlb_save_state(vlb_sim* sim, void* dev, size_t bytes);
+int vlb_load_state(vlb_sim* sim, const void* dev, size_t bytes);
+
+/* ---- tuning ------------------------------------------------------------------------ */
+
+/* Tile height of the step kernel (64 x ty nodes per workgroup, ty in {1, 2, 4, 8});
+ * results are bit-identical for every choice. */
+int vlb_set_tile(vlb_sim* sim, int ty);
+/* Use hipGraph replay for runs of nsteps >= 2 * chunk (chunk 0 disables graphs). */
+int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
+
+/* ---- errors ------------------------------------------------------------------------ */
+const char* vlb_error_string(int status);
+const char* vlb_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLB_H */

@@ -1,0 +1,738 @@
+// vlb_api.cpp -- host side of the C ABI declared in include/vlb.h.
+//
+// Geometry (node classes, wall links, wall fractions) is built here on the host; the
+// rules must match any other implementation bit for bit, so the wall fraction uses the
+// fixed expression order below and this file is compiled without FP contraction.
+// All device memory comes from the caller's workspace; the library only carves it.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vlb.h"
+#include "vlb_internal.h"
+
+namespace {
+
+thread_local std::string g_detail;
+
+int fail(int code, const std::string& msg) {
+    g_detail = msg;
+    return code;
+}
+
+#define VLB_HIP(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(VLB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// D2Q9 in the paper's order (Sec. 3.1).
+const int EXH[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int EYH[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const int OPPH[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Link {
+    int32_t node;
+    int8_t dir;
+    double q;
+};
+
+template <class T>
+using Run = vlb::RunDev<T>;
+
+}  // namespace
+
+struct vlb_sim {
+    int nx = 0, ny = 0, xmode = 0, ymode = 0, prec = 0, pitch = 0;
+    long long plane = 0;
+    size_t esz = 4;
+    std::vector<uint8_t> solid;     // [ny][nx]
+    std::vector<int> circle_of;     // [ny][nx]
+    std::vector<double> circles;    // xc, yc, R
+    std::vector<uint16_t> bits;     // [ny][pitch]
+    std::vector<Link> links;
+    std::vector<int> bidx;          // [ny][pitch], curved only
+    std::vector<double> bq;         // 8 per boundary node
+    int nbq = 0;
+    bool has_bits = false, has_curved = false;
+
+    // binding
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    size_t off_pop[2] = {0, 0}, off_hist = 0, off_force = 0, off_usnap = 0, off_inlet = 0,
+           off_bq = 0, off_bits = 0, off_bidx = 0, off_run = 0, off_items = 0, off_mon = 0,
+           total = 0;
+
+    std::vector<vlb::Item> items;
+    int nitems = 0;
+    int ty = 4;
+    int items_cap = 0;
+
+    vlb_params params{};
+    bool params_set = false, force_field = false, inited = false;
+    std::vector<double> inlet;  // 4 * ny
+    int parity = 0, first = 1;
+    int64_t step = 0;
+
+    int graph_chunk = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+    template <class T>
+    T* dptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+// Wall fraction of the link from fluid node (x, y) in direction d toward the circle c:
+// smallest root of |x + t e_d - c|^2 = R^2.
+double circle_q(const vlb_sim* s, int x, int y, int d, int c) {
+    const double dx = (double)EXH[d], dy = (double)EYH[d];
+    const double px = (double)x - s->circles[3 * c], py = (double)y - s->circles[3 * c + 1];
+    const double r = s->circles[3 * c + 2];
+    const double a = dx * dx + dy * dy;
+    const double b = 2.0 * (px * dx + py * dy);
+    const double cc = px * px + py * py - r * r;
+    const double disc = b * b - 4.0 * a * cc;
+    return (-b - std::sqrt(disc)) / (2.0 * a);
+}
+
+// Node classes, geometry bits, links, and the curved-link table.
+void build_geometry(vlb_sim* s, const uint8_t* mask) {
+    const int nx = s->nx, ny = s->ny;
+    const int nc = (int)s->circles.size() / 3;
+    s->solid.assign((size_t)nx * ny, 0);
+    s->circle_of.assign((size_t)nx * ny, -1);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t n = (size_t)y * nx + x;
+            if (mask && mask[n]) s->solid[n] = 1;
+            for (int c = 0; c < nc; ++c) {
+                const double dx = (double)x - s->circles[3 * c];
+                const double dy = (double)y - s->circles[3 * c + 1];
+                const double r = s->circles[3 * c + 2];
+                if (dx * dx + dy * dy <= r * r) {
+                    s->solid[n] = 1;
+                    if (s->circle_of[n] < 0) s->circle_of[n] = c;
+                }
+            }
+        }
+    s->bits.assign((size_t)ny * s->pitch, 0);
+    s->links.clear();
+    bool any_bits = false, curved = false;
+    std::vector<double> qnode(9);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t n = (size_t)y * nx + x;
+            const size_t pp = (size_t)y * s->pitch + x;
+            if (s->solid[n]) {
+                s->bits[pp] = vlb::BIT_SELF_SOLID;
+                any_bits = true;
+                continue;
+            }
+            uint16_t b = 0;
+            for (int d = 1; d < 9; ++d) {
+                // neighbour x + e_d (the source of direction opp(d))
+                int xn = x + EXH[d], yn = y + EYH[d];
+                const bool xout = xn < 0 || xn >= nx, yout = yn < 0 || yn >= ny;
+                bool is_solid = false;
+                double q = 0.5;
+                if ((yout && s->ymode == VLB_WALL) || (xout && s->xmode == VLB_WALL)) {
+                    is_solid = true;
+                } else {
+                    if (yout) yn = wrap(yn, ny);
+                    bool ghost = false;
+                    if (xout) {
+                        if (s->xmode == VLB_PERIODIC) xn = wrap(xn, nx);
+                        else ghost = true;  // inlet / outlet ghost column
+                    }
+                    if (!ghost) {
+                        const size_t m = (size_t)yn * nx + xn;
+                        if (s->solid[m]) {
+                            is_solid = true;
+                            if (s->circle_of[m] >= 0) {
+                                q = circle_q(s, x, y, d, s->circle_of[m]);
+                                curved = true;
+                            }
+                        }
+                    }
+                }
+                if (is_solid) {
+                    b |= (uint16_t)(1u << OPPH[d]);
+                    s->links.push_back(Link{(int32_t)n, (int8_t)d, q});
+                }
+            }
+            s->bits[pp] = b;
+            if (b) any_bits = true;
+        }
+    s->has_bits = any_bits;
+    s->has_curved = curved;
+    s->bidx.clear();
+    s->bq.clear();
+    s->nbq = 0;
+    if (curved) {
+        s->bidx.assign((size_t)ny * s->pitch, -1);
+        // links are in (node, dir) order; group them per node
+        size_t i = 0;
+        while (i < s->links.size()) {
+            const int32_t n = s->links[i].node;
+            const int x = n % nx, y = n / nx;
+            std::fill(qnode.begin(), qnode.end(), 0.5);
+            for (; i < s->links.size() && s->links[i].node == n; ++i)
+                qnode[OPPH[s->links[i].dir]] = s->links[i].q;  // indexed by unknown direction
+            s->bidx[(size_t)y * s->pitch + x] = s->nbq++;
+            for (int k = 1; k < 9; ++k) s->bq.push_back(qnode[k]);
+        }
+    }
+}
+
+// Work items in an XCD-aware order: consecutive workgroups go round-robin to the 8
+// XCDs, so block b is given tile (start of XCD b % 8) + b / 8 and every XCD sweeps a
+// contiguous band of tiles (shared halo rows stay in one L2).
+void build_items(vlb_sim* s) {
+    const int ntx = (s->nx + 63) / 64, nty = (s->ny + s->ty - 1) / s->ty;
+    const int n = ntx * nty;
+    s->items.assign(n, vlb::Item{0, 0, 0, 0});
+    const int nxcd = 8;
+    std::vector<int> start(nxcd + 1, 0);
+    for (int k = 0; k < nxcd; ++k) start[k + 1] = start[k] + n / nxcd + (k < n % nxcd ? 1 : 0);
+    for (int b = 0; b < n; ++b) {
+        const int t = start[b % nxcd] + b / nxcd;
+        s->items[b] = vlb::Item{0, t % ntx, t / ntx, 0};
+    }
+    s->nitems = n;
+}
+
+void layout(vlb_sim* s) {
+    const size_t e = s->esz;
+    const size_t plane_b = (size_t)s->plane * e;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + bytes); return r; };
+    s->off_pop[0] = take(36 * plane_b);
+    s->off_pop[1] = take(36 * plane_b);
+    s->off_hist = take(5 * plane_b);
+    s->off_force = take(2 * plane_b);
+    s->off_usnap = take(2 * (size_t)s->nx * s->ny * e);
+    s->off_inlet = take(4 * (size_t)s->ny * e);
+    s->off_bq = take(std::max<size_t>(1, (size_t)s->nbq * 8) * e);
+    s->off_bits = take((size_t)s->plane * sizeof(uint16_t));
+    s->off_bidx = take(s->has_curved ? (size_t)s->plane * sizeof(int) : 256);
+    s->off_run = take(sizeof(Run<double>));
+    s->items_cap = ((s->nx + 63) / 64) * s->ny;  // enough for any tile height >= 1
+    s->off_items = take((size_t)s->items_cap * sizeof(vlb::Item));
+    s->off_mon = take(sizeof(vlb::MonitorAcc));
+    s->total = o;
+}
+
+template <class T>
+Run<T> make_run(const vlb_sim* s) {
+    Run<T> r{};
+    r.nx = s->nx; r.ny = s->ny; r.pitch = s->pitch; r.xmode = s->xmode; r.ymode = s->ymode;
+    r.has_bits = s->has_bits ? 1 : 0;
+    r.has_curved = s->has_curved ? 1 : 0;
+    r.uniform_force = s->force_field ? 0 : 1;
+    r.no_source = (s->params.flags & VLB_FLAG_NO_SOURCE) ? 1 : 0;
+    r.plane = s->plane;
+    r.pop[0] = s->dptr<T>(s->off_pop[0]);
+    r.pop[1] = s->dptr<T>(s->off_pop[1]);
+    r.hist = s->dptr<T>(s->off_hist);
+    r.force = s->dptr<T>(s->off_force);
+    r.bits = s->dptr<uint16_t>(s->off_bits);
+    r.bidx = s->has_curved ? s->dptr<int>(s->off_bidx) : nullptr;
+    r.bq = s->dptr<T>(s->off_bq);
+    r.inlet = s->dptr<T>(s->off_inlet);
+    const vlb_params& p = s->params;
+    // relaxation times from the transport relations (Sec. 3.1-3.2), c_s^2 = 1/3
+    const double ts1 = 3.0 * p.nu_s + 0.5;
+    const double ts2 = p.Lambda_s / (3.0 * p.nu_s) + 0.5;
+    const double tp1 = 3.0 * p.kappa + 0.5;
+    const double tp2 = p.Lambda_p / (3.0 * p.kappa) + 0.5;
+    r.c1 = (T)((ts1 - 1.0) / ts1);
+    r.c2 = (T)((ts2 - 1.0) / ts2);
+    r.h1 = (T)((3.0 * p.nu_s) / ts1);  // 1 - 1/(2 tau_s1) without cancellation
+    r.inv_ts1 = (T)(1.0 / ts1);
+    r.p1 = (T)((tp1 - 1.0) / tp1);
+    r.p2 = (T)((tp2 - 1.0) / tp2);
+    r.h2 = (T)((3.0 * p.kappa) / tp1);
+    r.inv_lam = (T)(1.0 / p.lambda);
+    r.eta_over_lam = (T)(p.eta_p / p.lambda);
+    r.Fx = (T)p.Fx;
+    r.Fy = (T)p.Fy;
+    return r;
+}
+
+template <class T>
+__global__ void k_store_run(Run<T> v, Run<T>* dst) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+int upload_run(vlb_sim* s) {
+    if (s->prec == VLB_FP32) {
+        hipLaunchKernelGGL((k_store_run<float>), dim3(1), dim3(64), 0, s->stream, make_run<float>(s),
+                           s->dptr<Run<float>>(s->off_run));
+    } else {
+        hipLaunchKernelGGL((k_store_run<double>), dim3(1), dim3(64), 0, s->stream,
+                           make_run<double>(s), s->dptr<Run<double>>(s->off_run));
+    }
+    VLB_HIP(hipGetLastError());
+    return VLB_OK;
+}
+
+int upload_items(vlb_sim* s) {
+    build_items(s);
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_items, s->items.data(),
+                           s->items.size() * sizeof(vlb::Item), hipMemcpyHostToDevice, s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    return VLB_OK;
+}
+
+void drop_graphs(vlb_sim* s) {
+    for (auto& g : s->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+int check_bound(const vlb_sim* s) {
+    if (!s) return fail(VLB_E_INVALID_ARG, "null simulation");
+    if (!s->bound) return fail(VLB_E_STATE, "workspace not bound (vlb_bind)");
+    return VLB_OK;
+}
+
+int check_ready(const vlb_sim* s) {
+    int rc = check_bound(s);
+    if (rc) return rc;
+    if (!s->params_set) return fail(VLB_E_STATE, "parameters not set (vlb_set_params)");
+    if (!s->inited) return fail(VLB_E_STATE, "state not initialised (vlb_init_equilibrium)");
+    return VLB_OK;
+}
+
+template <class T>
+int launch_steps(vlb_sim* s, int64_t n) {
+    const Run<T>* rd = s->dptr<Run<T>>(s->off_run);
+    const vlb::Item* it = s->dptr<vlb::Item>(s->off_items);
+    for (int64_t k = 0; k < n; ++k) {
+        VLB_HIP(vlb::launch_step<T>(rd, it, s->nitems, s->ty, s->parity, s->first, s->stream));
+        s->parity ^= 1;
+        s->first = 0;
+        ++s->step;
+    }
+    return VLB_OK;
+}
+
+// hipGraph of 2*chunk steps starting from buffer `par` (parity returns to par).
+template <class T>
+int graph_for(vlb_sim* s, int par, hipGraphExec_t* out) {
+    if (s->graph[par]) { *out = s->graph[par]; return VLB_OK; }
+    hipGraph_t g = nullptr;
+    VLB_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    const Run<T>* rd = s->dptr<Run<T>>(s->off_run);
+    const vlb::Item* it = s->dptr<vlb::Item>(s->off_items);
+    hipError_t err = hipSuccess;
+    int p = par;
+    for (int k = 0; k < 2 * s->graph_chunk && err == hipSuccess; ++k) {
+        err = vlb::launch_step<T>(rd, it, s->nitems, s->ty, p, 0, s->stream);
+        p ^= 1;
+    }
+    hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(VLB_E_HIP, std::string("graph capture: ") +
+                                   hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return fail(VLB_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+    s->graph[par] = ex;
+    *out = ex;
+    return VLB_OK;
+}
+
+template <class T>
+int do_step(vlb_sim* s, int64_t n) {
+    if (s->first && n > 0) {
+        int rc = launch_steps<T>(s, 1);
+        if (rc) return rc;
+        --n;
+    }
+    if (s->graph_chunk > 0 && s->stream != nullptr) {
+        const int64_t per = 2 * (int64_t)s->graph_chunk;
+        while (n >= per) {
+            hipGraphExec_t ex = nullptr;
+            int rc = graph_for<T>(s, s->parity, &ex);
+            if (rc) return rc;
+            VLB_HIP(hipGraphLaunch(ex, s->stream));
+            s->step += per;
+            n -= per;
+        }
+    }
+    return launch_steps<T>(s, n);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vlb_error_string(int status) {
+    switch (status) {
+        case VLB_OK: return "ok";
+        case VLB_E_INVALID_ARG: return "invalid argument";
+        case VLB_E_WORKSPACE: return "workspace missing or too small";
+        case VLB_E_HIP: return "HIP runtime error";
+        case VLB_E_NONFINITE: return "non-finite value (numerical breakdown)";
+        case VLB_E_STATE: return "call out of order";
+        case VLB_E_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* vlb_last_error_detail(void) { return g_detail.c_str(); }
+
+int vlb_create(const vlb_grid* g, vlb_sim** out) {
+    if (!g || !out) return fail(VLB_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (g->nx < 1 || g->ny < 1 || (long long)g->nx * g->ny >= (1LL << 31) / 64)
+        return fail(VLB_E_INVALID_ARG, "grid size out of range");
+    if (g->xmode < VLB_PERIODIC || g->xmode > VLB_OPEN || g->ymode < VLB_PERIODIC ||
+        g->ymode > VLB_WALL)
+        return fail(VLB_E_INVALID_ARG, "boundary mode out of range (ymode cannot be open)");
+    if (g->precision != VLB_FP32 && g->precision != VLB_FP64)
+        return fail(VLB_E_INVALID_ARG, "precision must be VLB_FP32 or VLB_FP64");
+    if (g->ncircles < 0 || (g->ncircles > 0 && !g->circles))
+        return fail(VLB_E_INVALID_ARG, "circles");
+    for (int c = 0; c < g->ncircles; ++c)
+        if (!(g->circles[3 * c + 2] > 0) || !std::isfinite(g->circles[3 * c]) ||
+            !std::isfinite(g->circles[3 * c + 1]))
+            return fail(VLB_E_INVALID_ARG, "circle radius must be > 0 and centre finite");
+    vlb_sim* s = new (std::nothrow) vlb_sim();
+    if (!s) return fail(VLB_E_INVALID_ARG, "out of host memory");
+    s->nx = g->nx;
+    s->ny = g->ny;
+    s->xmode = g->xmode;
+    s->ymode = g->ymode;
+    s->prec = g->precision;
+    s->esz = g->precision == VLB_FP32 ? 4 : 8;
+    s->pitch = ((g->nx + 63) / 64) * 64;
+    s->plane = (long long)s->pitch * g->ny;
+    if (g->ncircles) s->circles.assign(g->circles, g->circles + 3 * g->ncircles);
+    build_geometry(s, g->solid_mask);
+    s->inlet.assign(4 * (size_t)g->ny, 0.0);
+    for (int y = 0; y < g->ny; ++y) { s->inlet[g->ny + y] = 1.0; s->inlet[3 * g->ny + y] = 1.0; }
+    layout(s);
+    *out = s;
+    return VLB_OK;
+}
+
+void vlb_destroy(vlb_sim* s) {
+    if (!s) return;
+    drop_graphs(s);
+    delete s;
+}
+
+int vlb_workspace_bytes(const vlb_sim* s, size_t* bytes) {
+    if (!s || !bytes) return fail(VLB_E_INVALID_ARG, "null argument");
+    *bytes = s->total;
+    return VLB_OK;
+}
+
+int vlb_geometry(const vlb_sim* s, uint8_t* cls, int32_t* lnode, int8_t* ldir, double* lq,
+                 int cap, int* nlinks) {
+    if (!s) return fail(VLB_E_INVALID_ARG, "null simulation");
+    if (cap < 0 || (cap > 0 && (!lnode || !ldir || !lq)))
+        return fail(VLB_E_INVALID_ARG, "link arrays");
+    if (cls) {
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                const size_t n = (size_t)y * s->nx + x;
+                const uint16_t b = s->bits[(size_t)y * s->pitch + x];
+                cls[n] = s->solid[n] ? VLB_NODE_SOLID
+                                     : ((b & 0x1FE) ? VLB_NODE_BOUNDARY : VLB_NODE_FLUID);
+            }
+    }
+    const int cnt = (int)s->links.size();
+    for (int i = 0; i < cnt && i < cap; ++i) {
+        lnode[i] = s->links[i].node;
+        ldir[i] = s->links[i].dir;
+        lq[i] = s->links[i].q;
+    }
+    if (nlinks) *nlinks = cnt;
+    return VLB_OK;
+}
+
+int vlb_bind(vlb_sim* s, void* ws, size_t bytes, void* stream) {
+    if (!s) return fail(VLB_E_INVALID_ARG, "null simulation");
+    if (!ws) return fail(VLB_E_WORKSPACE, "null workspace");
+    if (((uintptr_t)ws & 255u) != 0) return fail(VLB_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (bytes < s->total)
+        return fail(VLB_E_WORKSPACE, "workspace too small: need " + std::to_string(s->total) +
+                                         " bytes, got " + std::to_string(bytes));
+    drop_graphs(s);
+    s->ws = static_cast<char*>(ws);
+    s->ws_bytes = bytes;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->bound = true;
+    s->inited = false;
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_bits, s->bits.data(), s->bits.size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, s->stream));
+    if (s->has_curved) {
+        VLB_HIP(hipMemcpyAsync(s->ws + s->off_bidx, s->bidx.data(), s->bidx.size() * sizeof(int),
+                               hipMemcpyHostToDevice, s->stream));
+    }
+    // wall fractions and inlet rows in the simulation precision
+    std::vector<char> tmp(std::max<size_t>(s->bq.size(), s->inlet.size()) * s->esz + 8);
+    auto put = [&](const std::vector<double>& v, size_t off) -> int {
+        if (v.empty()) return VLB_OK;
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (s->esz == 4) { const float f = (float)v[i]; std::memcpy(&tmp[i * 4], &f, 4); }
+            else std::memcpy(&tmp[i * 8], &v[i], 8);
+        }
+        VLB_HIP(hipMemcpyAsync(s->ws + off, tmp.data(), v.size() * s->esz, hipMemcpyHostToDevice,
+                               s->stream));
+        VLB_HIP(hipStreamSynchronize(s->stream));
+        return VLB_OK;
+    };
+    int rc = put(s->bq, s->off_bq);
+    if (rc) return rc;
+    rc = put(s->inlet, s->off_inlet);
+    if (rc) return rc;
+    rc = upload_items(s);
+    if (rc) return rc;
+    if (s->params_set) return upload_run(s);
+    return VLB_OK;
+}
+
+int vlb_set_params(vlb_sim* s, const vlb_params* p) {
+    if (!s || !p) return fail(VLB_E_INVALID_ARG, "null argument");
+    const double v[8] = {p->nu_s, p->eta_p, p->lambda, p->kappa, p->Lambda_s, p->Lambda_p, p->Fx, p->Fy};
+    for (double d : v)
+        if (!std::isfinite(d)) return fail(VLB_E_INVALID_ARG, "non-finite parameter");
+    if (!(p->nu_s > 0)) return fail(VLB_E_INVALID_ARG, "nu_s must be > 0 (tau_s1 > 1/2)");
+    if (!(p->kappa > 0)) return fail(VLB_E_INVALID_ARG, "kappa must be > 0 (tau_p1 > 1/2)");
+    if (!(p->lambda > 0)) return fail(VLB_E_INVALID_ARG, "lambda must be > 0");
+    if (!(p->eta_p >= 0)) return fail(VLB_E_INVALID_ARG, "eta_p must be >= 0");
+    if (!(p->Lambda_s > 0) || !(p->Lambda_p > 0))
+        return fail(VLB_E_INVALID_ARG, "magic parameters must be > 0");
+    if (p->flags & ~VLB_FLAG_NO_SOURCE) return fail(VLB_E_INVALID_ARG, "unknown flag");
+    s->params = *p;
+    s->params_set = true;
+    if (s->bound) return upload_run(s);
+    return VLB_OK;
+}
+
+int vlb_set_force_field(vlb_sim* s, const void* fx, const void* fy) {
+    int rc = check_bound(s);
+    if (rc) return rc;
+    if ((fx == nullptr) != (fy == nullptr))
+        return fail(VLB_E_INVALID_ARG, "force field needs both components or neither");
+    if (!fx) {
+        s->force_field = false;
+    } else {
+        const size_t row = (size_t)s->nx * s->esz, dp = (size_t)s->pitch * s->esz;
+        VLB_HIP(hipMemcpy2DAsync(s->ws + s->off_force, dp, fx, row, row, s->ny,
+                                 hipMemcpyDeviceToDevice, s->stream));
+        VLB_HIP(hipMemcpy2DAsync(s->ws + s->off_force + (size_t)s->plane * s->esz, dp, fy, row,
+                                 row, s->ny, hipMemcpyDeviceToDevice, s->stream));
+        s->force_field = true;
+    }
+    if (s->params_set) return upload_run(s);
+    return VLB_OK;
+}
+
+int vlb_set_inlet(vlb_sim* s, const double* ux, const double* axx, const double* axy,
+                  const double* ayy) {
+    if (!s || !ux || !axx || !axy || !ayy) return fail(VLB_E_INVALID_ARG, "null argument");
+    if (s->xmode != VLB_OPEN) return fail(VLB_E_UNSUPPORTED, "inlet needs xmode = VLB_OPEN");
+    const double* src[4] = {ux, axx, axy, ayy};
+    for (int c = 0; c < 4; ++c)
+        for (int y = 0; y < s->ny; ++y) {
+            if (!std::isfinite(src[c][y])) return fail(VLB_E_INVALID_ARG, "non-finite inlet value");
+            s->inlet[(size_t)c * s->ny + y] = src[c][y];
+        }
+    if (!s->bound) return VLB_OK;
+    std::vector<char> tmp(s->inlet.size() * s->esz);
+    for (size_t i = 0; i < s->inlet.size(); ++i) {
+        if (s->esz == 4) { const float f = (float)s->inlet[i]; std::memcpy(&tmp[i * 4], &f, 4); }
+        else std::memcpy(&tmp[i * 8], &s->inlet[i], 8);
+    }
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_inlet, tmp.data(), tmp.size(), hipMemcpyHostToDevice,
+                           s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    return VLB_OK;
+}
+
+int vlb_init_equilibrium(vlb_sim* s, const void* rho, const void* ux, const void* uy,
+                         const void* axx, const void* axy, const void* ayy) {
+    int rc = check_bound(s);
+    if (rc) return rc;
+    if (!s->params_set) return fail(VLB_E_STATE, "parameters not set (vlb_set_params)");
+    if (s->prec == VLB_FP32) {
+        VLB_HIP(vlb::launch_init<float>(make_run<float>(s), s->dptr<Run<float>>(s->off_run),
+                                        (const float*)rho, (const float*)ux, (const float*)uy,
+                                        (const float*)axx, (const float*)axy, (const float*)ayy,
+                                        s->stream));
+    } else {
+        VLB_HIP(vlb::launch_init<double>(make_run<double>(s), s->dptr<Run<double>>(s->off_run),
+                                         (const double*)rho, (const double*)ux, (const double*)uy,
+                                         (const double*)axx, (const double*)axy,
+                                         (const double*)ayy, s->stream));
+    }
+    VLB_HIP(vlb::launch_fill_bytes(s->ws + s->off_usnap, 2 * (size_t)s->nx * s->ny * s->esz, 0,
+                                   s->stream));
+    s->parity = 0;
+    s->first = 1;
+    s->step = 0;
+    s->inited = true;
+    return VLB_OK;
+}
+
+int vlb_step(vlb_sim* s, int64_t n) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (n < 0) return fail(VLB_E_INVALID_ARG, "negative step count");
+    return s->prec == VLB_FP32 ? do_step<float>(s, n) : do_step<double>(s, n);
+}
+
+int vlb_get_step(const vlb_sim* s, int64_t* step) {
+    if (!s || !step) return fail(VLB_E_INVALID_ARG, "null argument");
+    *step = s->step;
+    return VLB_OK;
+}
+
+int vlb_read_fields(vlb_sim* s, void* rho, void* ux, void* uy, void* axx, void* axy, void* ayy) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (s->prec == VLB_FP32) {
+        VLB_HIP(vlb::launch_read<float>(make_run<float>(s), s->dptr<Run<float>>(s->off_run),
+                                        s->parity, s->first, (float*)rho, (float*)ux, (float*)uy,
+                                        (float*)axx, (float*)axy, (float*)ayy, s->stream));
+    } else {
+        VLB_HIP(vlb::launch_read<double>(make_run<double>(s), s->dptr<Run<double>>(s->off_run),
+                                         s->parity, s->first, (double*)rho, (double*)ux,
+                                         (double*)uy, (double*)axx, (double*)axy, (double*)ayy,
+                                         s->stream));
+    }
+    return VLB_OK;
+}
+
+int vlb_read_history(vlb_sim* s, void* sxx, void* sxy, void* syy, void* uxp, void* uyp) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    void* out[5] = {sxx, sxy, syy, uxp, uyp};
+    const size_t row = (size_t)s->nx * s->esz, dp = (size_t)s->pitch * s->esz;
+    for (int c = 0; c < 5; ++c) {
+        if (!out[c]) continue;
+        VLB_HIP(hipMemcpy2DAsync(out[c], row, s->ws + s->off_hist + (size_t)c * s->plane * s->esz,
+                                 dp, row, s->ny, hipMemcpyDeviceToDevice, s->stream));
+    }
+    return VLB_OK;
+}
+
+int vlb_monitors(vlb_sim* s, vlb_monitor* out) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!out) return fail(VLB_E_INVALID_ARG, "null output");
+    vlb::MonitorAcc* acc = s->dptr<vlb::MonitorAcc>(s->off_mon);
+    VLB_HIP(vlb::launch_fill_bytes(acc, sizeof(vlb::MonitorAcc), 0, s->stream));
+    if (s->prec == VLB_FP32) {
+        VLB_HIP(vlb::launch_monitor<float>(make_run<float>(s), s->dptr<Run<float>>(s->off_run),
+                                           s->parity, s->first, s->dptr<float>(s->off_usnap), acc,
+                                           s->stream));
+    } else {
+        VLB_HIP(vlb::launch_monitor<double>(make_run<double>(s), s->dptr<Run<double>>(s->off_run),
+                                            s->parity, s->first, s->dptr<double>(s->off_usnap),
+                                            acc, s->stream));
+    }
+    vlb::MonitorAcc h{};
+    VLB_HIP(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    for (int c = 0; c < 4; ++c) out->mass[c] = h.mass[c];
+    out->residual = h.residual;
+    out->umax = h.umax;
+    out->step = s->step;
+    out->nonfinite = (int64_t)h.nonfinite;
+    out->spd_violations = (int64_t)h.spd;
+    if (h.nonfinite) return fail(VLB_E_NONFINITE, "non-finite fields at step " + std::to_string(s->step));
+    return VLB_OK;
+}
+
+int vlb_state_bytes(const vlb_sim* s, size_t* bytes) {
+    if (!s || !bytes) return fail(VLB_E_INVALID_ARG, "null argument");
+    *bytes = 256 + 41 * (size_t)s->plane * s->esz;
+    return VLB_OK;
+}
+
+static const unsigned long long kStateMagic = 0x564C425354415445ULL;  // "VLBSTATE"
+
+int vlb_save_state(vlb_sim* s, void* dev, size_t bytes) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    size_t need = 0;
+    vlb_state_bytes(s, &need);
+    if (!dev || bytes < need) return fail(VLB_E_WORKSPACE, "state buffer too small");
+    char* d = static_cast<char*>(dev);
+    const unsigned long long shape = ((unsigned long long)(unsigned)s->nx << 32) | (unsigned)s->ny;
+    VLB_HIP(vlb::launch_write_words(reinterpret_cast<unsigned long long*>(d), kStateMagic,
+                                    (unsigned long long)s->step, (unsigned long long)s->first,
+                                    shape, s->stream));
+    const size_t pb = (size_t)s->plane * s->esz;
+    VLB_HIP(hipMemcpyAsync(d + 256, s->ws + s->off_pop[s->parity], 36 * pb,
+                           hipMemcpyDeviceToDevice, s->stream));
+    VLB_HIP(hipMemcpyAsync(d + 256 + 36 * pb, s->ws + s->off_hist, 5 * pb,
+                           hipMemcpyDeviceToDevice, s->stream));
+    return VLB_OK;
+}
+
+int vlb_load_state(vlb_sim* s, const void* dev, size_t bytes) {
+    int rc = check_bound(s);
+    if (rc) return rc;
+    if (!s->params_set) return fail(VLB_E_STATE, "parameters not set (vlb_set_params)");
+    size_t need = 0;
+    vlb_state_bytes(s, &need);
+    if (!dev || bytes < need) return fail(VLB_E_WORKSPACE, "state buffer too small");
+    unsigned long long hdr[4] = {0, 0, 0, 0};
+    VLB_HIP(hipMemcpyAsync(hdr, dev, sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    const unsigned long long shape = ((unsigned long long)(unsigned)s->nx << 32) | (unsigned)s->ny;
+    if (hdr[0] != kStateMagic || hdr[3] != shape)
+        return fail(VLB_E_INVALID_ARG, "state buffer does not hold a state of this grid");
+    const char* d = static_cast<const char*>(dev);
+    const size_t pb = (size_t)s->plane * s->esz;
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_pop[0], d + 256, 36 * pb, hipMemcpyDeviceToDevice,
+                           s->stream));
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_hist, d + 256 + 36 * pb, 5 * pb,
+                           hipMemcpyDeviceToDevice, s->stream));
+    s->parity = 0;
+    s->first = hdr[2] ? 1 : 0;
+    s->step = (int64_t)hdr[1];
+    s->inited = true;
+    return VLB_OK;
+}
+
+int vlb_set_tile(vlb_sim* s, int ty) {
+    if (!s) return fail(VLB_E_INVALID_ARG, "null simulation");
+    if (ty != 1 && ty != 2 && ty != 4 && ty != 8) return fail(VLB_E_INVALID_ARG, "ty must be 1, 2, 4 or 8");
+    s->ty = ty;
+    drop_graphs(s);
+    if (s->bound) return upload_items(s);
+    return VLB_OK;
+}
+
+int vlb_set_graph_chunk(vlb_sim* s, int chunk) {
+    if (!s || chunk < 0 || chunk > 4096) return fail(VLB_E_INVALID_ARG, "chunk out of range");
+    drop_graphs(s);
+    s->graph_chunk = chunk;
+    return VLB_OK;
+}
+
+}  // extern "C"

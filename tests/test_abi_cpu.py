@@ -1,0 +1,137 @@
+"""Host-side checks of the HIP library: loads, exports, geometry, argument validation.
+
+No device work is done here: vlb_create / vlb_geometry / vlb_set_params are host-only.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def vlb():
+    import paper_2508_16997_amd as pkg
+
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_2508_16997_amd import build
+
+        build.build()
+    return pkg
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "vlb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vlb_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(vlb):
+    lib = vlb.load()
+    declared = _header_symbols()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(vlb.EXPORTS) == declared
+
+
+def _geom_cases():
+    mask = np.zeros((23, 41), np.uint8)
+    mask[5:9, 10:13] = 1
+    mask[15, 30] = 1
+    return [
+        dict(nx=64, ny=32, xmode="periodic", ymode="wall"),
+        dict(nx=41, ny=23, xmode="periodic", ymode="periodic", solid=mask),
+        dict(nx=41, ny=23, xmode="wall", ymode="periodic", circles=[(20.5, 11.0, 6.5)]),
+        dict(nx=80, ny=40, xmode="open", ymode="wall", circles=[(40.0, 20.0, 10.0)]),
+        dict(nx=60, ny=60, xmode="periodic", ymode="periodic",
+             circles=[(15.0, 15.0, 7.3), (40.5, 38.0, 9.9)], solid=None),
+    ]
+
+
+@pytest.mark.parametrize("case", _geom_cases())
+def test_geometry_bit_exact_vs_oracle(vlb, oracle_lib, case):
+    """Node classes and boundary-link lists are identical, q bit for bit (pin: a11)."""
+    from paper_2508_16997_amd.sim import host_geometry
+
+    cls, node, d, q = host_geometry(**case)
+    pr = synth.rest_state(nx=case["nx"], ny=case["ny"], xmode=case["xmode"],
+                          ymode=case["ymode"], circles=case.get("circles", ()),
+                          solid=case.get("solid"))
+    o = oracle_lib.OracleSim(pr)
+    ocls, onode, od, oq = o.geometry()
+    assert np.array_equal(cls, ocls)
+    assert np.array_equal(node, onode)
+    assert np.array_equal(d, od)
+    assert np.array_equal(q.view(np.uint64), oq.view(np.uint64))
+
+
+def test_cylinder_geometry_full_size(vlb):
+    """4096 x 1024 channel with R = 128 cylinder: counts and invariants."""
+    from paper_2508_16997_amd.sim import host_geometry
+
+    pr = synth.cylinder(steps=0)
+    cls, node, d, q = host_geometry(pr.nx, pr.ny, "open", "wall", circles=pr.circles)
+    fluid = pr.fluid_mask()
+    assert np.array_equal(cls == 1, ~fluid)
+    assert (cls == 1).sum() == (~fluid).sum() > 50000
+    assert np.all((q > 0) & (q <= 1))
+    wall_links = (q == 0.5).sum()
+    assert wall_links >= 2 * 3 * 4096 - 4
+
+
+def _lib_and_sim(vlb, **kw):
+    from paper_2508_16997_amd import _lib as L
+
+    lib = L.load()
+    grid = L.VlbGrid(kw.get("nx", 16), kw.get("ny", 8), kw.get("xmode", 0), kw.get("ymode", 0),
+                     kw.get("prec", 0), None, None, 0)
+    h = C.c_void_p()
+    st = lib.vlb_create(C.byref(grid), C.byref(h))
+    return lib, L, st, h
+
+
+def test_invalid_grid_rejected(vlb):
+    lib, L, st, h = _lib_and_sim(vlb, nx=0)
+    assert st == L.VLB_E_INVALID_ARG
+    lib, L, st, h = _lib_and_sim(vlb, ymode=2)
+    assert st == L.VLB_E_INVALID_ARG
+    lib, L, st, h = _lib_and_sim(vlb, prec=7)
+    assert st == L.VLB_E_INVALID_ARG
+
+
+def test_invalid_params_rejected_before_launch(vlb):
+    lib, L, st, h = _lib_and_sim(vlb)
+    assert st == L.VLB_OK
+    try:
+        bad = [dict(nu_s=0.0), dict(kappa=-1.0), dict(lambda_=0.0), dict(eta_p=-0.1),
+               dict(Lambda_p=0.0), dict(nu_s=float("nan"))]
+        for b in bad:
+            p = dict(nu_s=0.1, eta_p=0.1, lambda_=10.0, kappa=0.01, Lambda_s=0.25, Lambda_p=1e-6,
+                     Fx=0.0, Fy=0.0, flags=0)
+            p.update(b)
+            assert lib.vlb_set_params(h, C.byref(L.VlbParams(**p))) == L.VLB_E_INVALID_ARG
+        # stepping an unbound simulation is a state error, not a crash
+        assert lib.vlb_step(h, 1) == L.VLB_E_STATE
+        assert b"bind" in lib.vlb_last_error_detail()
+        # a too-small or misaligned workspace is refused before any device call
+        assert lib.vlb_bind(h, C.c_void_p(256), 16, None) == L.VLB_E_WORKSPACE
+        assert lib.vlb_bind(h, C.c_void_p(257), 1 << 40, None) == L.VLB_E_WORKSPACE
+    finally:
+        lib.vlb_destroy(h)
+
+
+def test_workspace_size_accounts_for_layout(vlb):
+    lib, L, st, h = _lib_and_sim(vlb, nx=100, ny=50, prec=0)
+    try:
+        n = C.c_size_t()
+        assert lib.vlb_workspace_bytes(h, C.byref(n)) == 0
+        pitch = 128
+        assert n.value >= (2 * 36 + 5 + 2) * pitch * 50 * 4
+    finally:
+        lib.vlb_destroy(h)
