@@ -178,6 +178,9 @@ int vlb_load_state(vlb_sim* sim, const void* dev, size_t bytes);
 /* Tile height of the step kernel (64 x ty nodes per workgroup, ty in {1, 2, 4, 8});
  * results are bit-identical for every choice. */
 int vlb_set_tile(vlb_sim* sim, int ty);
+/* Stores of the post-collision state: 0 = automatic (non-temporal once the two
+ * population buffers exceed the last-level cache), 1 = cached, 2 = non-temporal. */
+int vlb_set_store_mode(vlb_sim* sim, int mode);
 /* Use hipGraph replay for runs of nsteps >= 2 * chunk (chunk 0 disables graphs). */
 int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
 

@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libvlb.so")
+# VLB_LIBRARY selects another in-tree build of the same library (tuning variants).
+LIB_PATH = os.environ.get("VLB_LIBRARY") or os.path.join(PKG, "libvlb.so")
 
 VLB_OK = 0
 VLB_E_INVALID_ARG = -1
@@ -29,7 +30,7 @@ EXPORTS = [
     "vlb_set_params", "vlb_set_force_field", "vlb_set_inlet", "vlb_init_equilibrium",
     "vlb_step", "vlb_get_step", "vlb_read_fields", "vlb_read_history", "vlb_monitors",
     "vlb_state_bytes", "vlb_save_state", "vlb_load_state", "vlb_set_tile",
-    "vlb_set_graph_chunk", "vlb_error_string", "vlb_last_error_detail",
+    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_error_string", "vlb_last_error_detail",
 ]
 
 
@@ -90,6 +91,7 @@ def load():
     lib.vlb_load_state.argtypes = [P, P, C.c_size_t]
     lib.vlb_set_tile.argtypes = [P, I]
     lib.vlb_set_graph_chunk.argtypes = [P, I]
+    lib.vlb_set_store_mode.argtypes = [P, I]
     lib.vlb_error_string.argtypes = [I]
     lib.vlb_error_string.restype = C.c_char_p
     lib.vlb_last_error_detail.argtypes = []

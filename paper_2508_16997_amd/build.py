@@ -28,32 +28,38 @@ COMMON = [
 PER_FILE = {
     # host geometry must be bit-reproducible: no fused multiply-add contraction
     "vlb_api.cpp": ["-x", "hip", "-ffp-contract=off"],
-    "vlb_kernels.hip": ["-ffp-contract=fast"],
+    # contraction decided per source expression, so every inlined copy of a device
+    # function rounds identically (results independent of the tiling)
+    "vlb_kernels.hip": ["-ffp-contract=on"],
 }
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link ``libvlb.so``; returns its path."""
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source and link ``libvlb.so`` (or ``out``); returns its path.
+
+    ``defines`` are extra -D tuning knobs of the kernels (e.g. VLB_WAVES_PER_EU=4).
+    """
     if not os.path.exists(HIPCC) and shutil.which("hipcc") is None:
         raise RuntimeError("hipcc not found; the HIP library cannot be built")
     hipcc = HIPCC if os.path.exists(HIPCC) else shutil.which("hipcc")
-    objdir = os.path.join(PKG, "_build")
+    objdir = os.path.join(PKG, "_build", os.path.basename(out).replace(".so", ""))
     os.makedirs(objdir, exist_ok=True)
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
-        cmd = [hipcc, *COMMON, *PER_FILE.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *COMMON, *[f"-D{d}" for d in defines], *PER_FILE.get(src, []), "-c",
+               os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

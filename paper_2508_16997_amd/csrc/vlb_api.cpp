@@ -50,15 +50,17 @@ using Run = vlb::RunDev<T>;
 }  // namespace
 
 struct vlb_sim {
-    int nx = 0, ny = 0, xmode = 0, ymode = 0, prec = 0, pitch = 0;
+    int nx = 0, ny = 0, xmode = 0, ymode = 0, prec = 0, pitch = 0, off0 = 0;
     long long plane = 0;
     size_t esz = 4;
     std::vector<uint8_t> solid;     // [ny][nx]
     std::vector<int> circle_of;     // [ny][nx]
     std::vector<double> circles;    // xc, yc, R
-    std::vector<uint16_t> bits;     // [ny][pitch]
+    std::vector<uint16_t> bits;     // padded plane
     std::vector<Link> links;
-    std::vector<int> bidx;          // [ny][pitch], curved only
+    std::vector<int> bidx;          // padded plane, curved only
+    std::vector<vlb::FillOp> fill;  // boundary links served by the fill kernel
+    std::vector<vlb::FillItem> fill_items;
     std::vector<double> bq;         // 8 per boundary node
     int nbq = 0;
     bool has_bits = false, has_curved = false;
@@ -70,7 +72,7 @@ struct vlb_sim {
     bool bound = false;
     size_t off_pop[2] = {0, 0}, off_hist = 0, off_force = 0, off_usnap = 0, off_inlet = 0,
            off_bq = 0, off_bits = 0, off_bidx = 0, off_run = 0, off_items = 0, off_mon = 0,
-           total = 0;
+           off_fill = 0, off_fill_items = 0, total = 0;
 
     std::vector<vlb::Item> items;
     int nitems = 0;
@@ -84,6 +86,7 @@ struct vlb_sim {
     int64_t step = 0;
 
     int graph_chunk = 0;
+    int store_mode = 0;  // 0 auto (by working-set size), 1 cached stores, 2 streaming stores
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 
     template <class T>
@@ -127,14 +130,14 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
                 }
             }
         }
-    s->bits.assign((size_t)ny * s->pitch, 0);
+    s->bits.assign((size_t)s->plane, 0);
     s->links.clear();
     bool any_bits = false, curved = false;
     std::vector<double> qnode(9);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             const size_t n = (size_t)y * nx + x;
-            const size_t pp = (size_t)y * s->pitch + x;
+            const size_t pp = (size_t)s->off0 + (size_t)y * s->pitch + x;
             if (s->solid[n]) {
                 s->bits[pp] = vlb::BIT_SELF_SOLID;
                 any_bits = true;
@@ -181,7 +184,7 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
     s->bq.clear();
     s->nbq = 0;
     if (curved) {
-        s->bidx.assign((size_t)ny * s->pitch, -1);
+        s->bidx.assign((size_t)s->plane, -1);
         // links are in (node, dir) order; group them per node
         size_t i = 0;
         while (i < s->links.size()) {
@@ -190,10 +193,80 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
             std::fill(qnode.begin(), qnode.end(), 0.5);
             for (; i < s->links.size() && s->links[i].node == n; ++i)
                 qnode[OPPH[s->links[i].dir]] = s->links[i].q;  // indexed by unknown direction
-            s->bidx[(size_t)y * s->pitch + x] = s->nbq++;
+            s->bidx[(size_t)s->off0 + (size_t)y * s->pitch + x] = s->nbq++;
             for (int k = 1; k < 9; ++k) s->bq.push_back(qnode[k]);
         }
     }
+}
+
+// One fill op per fluid node and direction whose source x - e_i is not a fluid node
+// of the domain: the op writes into the slot of x - e_i (ghost or solid node) the value
+// the boundary rule gives for that link.
+void build_fill(vlb_sim* s) {
+    const int nx = s->nx, ny = s->ny;
+    s->fill.clear();
+    auto slot = [&](int xx, int yy) { return s->off0 + yy * s->pitch + xx; };
+    auto fluid_at = [&](int xx, int yy, int* idx) -> bool {
+        // in-domain fluid node after periodic wrap
+        if (yy < 0 || yy >= ny) {
+            if (s->ymode != VLB_PERIODIC) return false;
+            yy = wrap(yy, ny);
+        }
+        if (xx < 0 || xx >= nx) {
+            if (s->xmode != VLB_PERIODIC) return false;
+            xx = wrap(xx, nx);
+        }
+        if (s->solid[(size_t)yy * nx + xx]) return false;
+        *idx = slot(xx, yy);
+        return true;
+    };
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (s->solid[(size_t)y * nx + x]) continue;
+            const int p = slot(x, y);
+            const uint16_t b = s->bits[(size_t)p];
+            int bi = -1;
+            if (s->has_curved) bi = s->bidx[(size_t)p];
+            for (int i = 1; i < 9; ++i) {
+                const int xs = x - EXH[i], ys = y - EYH[i];
+                vlb::FillOp op{slot(xs, ys), p, -1, i, 0.5};
+                if (b & (1u << i)) {
+                    const double q = bi >= 0 ? s->bq[(size_t)bi * 8 + (i - 1)] : 0.5;
+                    int far = -1;
+                    if (q == 0.5) {
+                        op.dir_kind = i | (vlb::FILL_WALL << 8);
+                    } else if (q < 0.5 && !fluid_at(x + EXH[i], y + EYH[i], &far)) {
+                        op.dir_kind = i | (vlb::FILL_WALL << 8);
+                    } else {
+                        op.dir_kind = i | (vlb::FILL_CURVED << 8);
+                        op.q = q;
+                        op.far = q < 0.5 ? far : -1;
+                    }
+                    s->fill.push_back(op);
+                    continue;
+                }
+                const bool xout = xs < 0 || xs >= nx, yout = ys < 0 || ys >= ny;
+                if (!xout && !yout) continue;  // ordinary pull from a fluid node
+                const int yw = yout ? wrap(ys, ny) : ys;
+                if (xout && s->xmode == VLB_OPEN) {
+                    if (xs < 0) {
+                        op.dir_kind = i | (vlb::FILL_INLET << 8);
+                        op.far = yw;
+                        op.src = p;
+                    } else {
+                        op.dir_kind = i | (vlb::FILL_COPY << 8);
+                        op.src = slot(nx - 1, yw);  // zero-gradient outlet
+                    }
+                } else {
+                    // periodic image: written by the step kernel's edge stores
+                    continue;
+                }
+                s->fill.push_back(op);
+            }
+        }
+    s->fill_items.clear();
+    for (int f = 0; f < (int)s->fill.size(); f += 256)
+        s->fill_items.push_back(vlb::FillItem{0, f, std::min(256, (int)s->fill.size() - f), 0});
 }
 
 // Work items in an XCD-aware order: consecutive workgroups go round-robin to the 8
@@ -223,21 +296,24 @@ void layout(vlb_sim* s) {
     s->off_hist = take(5 * plane_b);
     s->off_force = take(2 * plane_b);
     s->off_usnap = take(2 * (size_t)s->nx * s->ny * e);
-    s->off_inlet = take(4 * (size_t)s->ny * e);
-    s->off_bq = take(std::max<size_t>(1, (size_t)s->nbq * 8) * e);
+    s->off_inlet = take(4 * (size_t)s->ny * sizeof(double));
+    s->off_bq = take(std::max<size_t>(1, (size_t)s->nbq * 8) * sizeof(double));
     s->off_bits = take((size_t)s->plane * sizeof(uint16_t));
     s->off_bidx = take(s->has_curved ? (size_t)s->plane * sizeof(int) : 256);
     s->off_run = take(sizeof(Run<double>));
     s->items_cap = ((s->nx + 63) / 64) * s->ny;  // enough for any tile height >= 1
     s->off_items = take((size_t)s->items_cap * sizeof(vlb::Item));
     s->off_mon = take(sizeof(vlb::MonitorAcc));
+    s->off_fill = take(std::max<size_t>(1, s->fill.size()) * sizeof(vlb::FillOp));
+    s->off_fill_items = take(std::max<size_t>(1, s->fill_items.size()) * sizeof(vlb::FillItem));
     s->total = o;
 }
 
 template <class T>
 Run<T> make_run(const vlb_sim* s) {
     Run<T> r{};
-    r.nx = s->nx; r.ny = s->ny; r.pitch = s->pitch; r.xmode = s->xmode; r.ymode = s->ymode;
+    r.nx = s->nx; r.ny = s->ny; r.pitch = s->pitch; r.off0 = s->off0;
+    r.xmode = s->xmode; r.ymode = s->ymode;
     r.has_bits = s->has_bits ? 1 : 0;
     r.has_curved = s->has_curved ? 1 : 0;
     r.uniform_force = s->force_field ? 0 : 1;
@@ -249,25 +325,27 @@ Run<T> make_run(const vlb_sim* s) {
     r.force = s->dptr<T>(s->off_force);
     r.bits = s->dptr<uint16_t>(s->off_bits);
     r.bidx = s->has_curved ? s->dptr<int>(s->off_bidx) : nullptr;
-    r.bq = s->dptr<T>(s->off_bq);
-    r.inlet = s->dptr<T>(s->off_inlet);
+    r.bq = s->dptr<double>(s->off_bq);
+    r.inlet = s->dptr<double>(s->off_inlet);
+    r.fill = s->dptr<vlb::FillOp>(s->off_fill);
+    r.nfill = (int)s->fill.size();
     const vlb_params& p = s->params;
     // relaxation times from the transport relations (Sec. 3.1-3.2), c_s^2 = 1/3
     const double ts1 = 3.0 * p.nu_s + 0.5;
     const double ts2 = p.Lambda_s / (3.0 * p.nu_s) + 0.5;
     const double tp1 = 3.0 * p.kappa + 0.5;
     const double tp2 = p.Lambda_p / (3.0 * p.kappa) + 0.5;
-    r.c1 = (T)((ts1 - 1.0) / ts1);
-    r.c2 = (T)((ts2 - 1.0) / ts2);
-    r.h1 = (T)((3.0 * p.nu_s) / ts1);  // 1 - 1/(2 tau_s1) without cancellation
-    r.inv_ts1 = (T)(1.0 / ts1);
-    r.p1 = (T)((tp1 - 1.0) / tp1);
-    r.p2 = (T)((tp2 - 1.0) / tp2);
-    r.h2 = (T)((3.0 * p.kappa) / tp1);
-    r.inv_lam = (T)(1.0 / p.lambda);
-    r.eta_over_lam = (T)(p.eta_p / p.lambda);
-    r.Fx = (T)p.Fx;
-    r.Fy = (T)p.Fy;
+    r.c1 = (ts1 - 1.0) / ts1;
+    r.c2 = (ts2 - 1.0) / ts2;
+    r.h1 = (3.0 * p.nu_s) / ts1;  // 1 - 1/(2 tau_s1) without cancellation
+    r.inv_ts1 = 1.0 / ts1;
+    r.p1 = (tp1 - 1.0) / tp1;
+    r.p2 = (tp2 - 1.0) / tp2;
+    r.h2 = (3.0 * p.kappa) / tp1;
+    r.inv_lam = 1.0 / p.lambda;
+    r.eta_over_lam = p.eta_p / p.lambda;
+    r.Fx = p.Fx;
+    r.Fy = p.Fy;
     return r;
 }
 
@@ -317,15 +395,27 @@ int check_ready(const vlb_sim* s) {
     return VLB_OK;
 }
 
+// Non-temporal stores pay off once both population buffers exceed the last-level
+// cache (256 MB Infinity Cache); below that the state stays cache resident.
+int streaming(const vlb_sim* s) {
+    if (s->store_mode == 1) return 0;
+    if (s->store_mode == 2) return 1;
+    const double bytes = 2.0 * 36.0 * (double)s->nx * (double)s->ny * (double)s->esz;
+    return bytes > 192.0 * 1024 * 1024 ? 1 : 0;
+}
+
 template <class T>
 int launch_steps(vlb_sim* s, int64_t n) {
     const Run<T>* rd = s->dptr<Run<T>>(s->off_run);
     const vlb::Item* it = s->dptr<vlb::Item>(s->off_items);
+    const vlb::FillItem* fi = s->dptr<vlb::FillItem>(s->off_fill_items);
     for (int64_t k = 0; k < n; ++k) {
-        VLB_HIP(vlb::launch_step<T>(rd, it, s->nitems, s->ty, s->parity, s->first, s->stream));
+        VLB_HIP(vlb::launch_step<T>(rd, it, s->nitems, s->ty, s->parity, s->first, streaming(s),
+                                    s->stream));
         s->parity ^= 1;
         s->first = 0;
         ++s->step;
+        VLB_HIP(vlb::launch_fill<T>(rd, fi, (int)s->fill_items.size(), s->parity, s->stream));
     }
     return VLB_OK;
 }
@@ -339,10 +429,12 @@ int graph_for(vlb_sim* s, int par, hipGraphExec_t* out) {
     const Run<T>* rd = s->dptr<Run<T>>(s->off_run);
     const vlb::Item* it = s->dptr<vlb::Item>(s->off_items);
     hipError_t err = hipSuccess;
+    const vlb::FillItem* fi = s->dptr<vlb::FillItem>(s->off_fill_items);
     int p = par;
     for (int k = 0; k < 2 * s->graph_chunk && err == hipSuccess; ++k) {
-        err = vlb::launch_step<T>(rd, it, s->nitems, s->ty, p, 0, s->stream);
+        err = vlb::launch_step<T>(rd, it, s->nitems, s->ty, p, 0, streaming(s), s->stream);
         p ^= 1;
+        if (err == hipSuccess) err = vlb::launch_fill<T>(rd, fi, (int)s->fill_items.size(), p, s->stream);
     }
     hipError_t e2 = hipStreamEndCapture(s->stream, &g);
     if (err != hipSuccess || e2 != hipSuccess) {
@@ -402,7 +494,7 @@ const char* vlb_last_error_detail(void) { return g_detail.c_str(); }
 int vlb_create(const vlb_grid* g, vlb_sim** out) {
     if (!g || !out) return fail(VLB_E_INVALID_ARG, "null argument");
     *out = nullptr;
-    if (g->nx < 1 || g->ny < 1 || (long long)g->nx * g->ny >= (1LL << 31) / 64)
+    if (g->nx < 1 || g->ny < 1 || ((long long)g->nx + 129) * (g->ny + 2) >= (1LL << 31) / 64)
         return fail(VLB_E_INVALID_ARG, "grid size out of range");
     if (g->xmode < VLB_PERIODIC || g->xmode > VLB_OPEN || g->ymode < VLB_PERIODIC ||
         g->ymode > VLB_WALL)
@@ -423,10 +515,12 @@ int vlb_create(const vlb_grid* g, vlb_sim** out) {
     s->ymode = g->ymode;
     s->prec = g->precision;
     s->esz = g->precision == VLB_FP32 ? 4 : 8;
-    s->pitch = ((g->nx + 63) / 64) * 64;
-    s->plane = (long long)s->pitch * g->ny;
+    s->pitch = ((g->nx + vlb::XOFF + 1 + 63) / 64) * 64;
+    s->off0 = s->pitch + vlb::XOFF;
+    s->plane = (long long)s->pitch * (g->ny + 2);
     if (g->ncircles) s->circles.assign(g->circles, g->circles + 3 * g->ncircles);
     build_geometry(s, g->solid_mask);
+    build_fill(s);
     s->inlet.assign(4 * (size_t)g->ny, 0.0);
     for (int y = 0; y < g->ny; ++y) { s->inlet[g->ny + y] = 1.0; s->inlet[3 * g->ny + y] = 1.0; }
     layout(s);
@@ -455,7 +549,7 @@ int vlb_geometry(const vlb_sim* s, uint8_t* cls, int32_t* lnode, int8_t* ldir, d
         for (int y = 0; y < s->ny; ++y)
             for (int x = 0; x < s->nx; ++x) {
                 const size_t n = (size_t)y * s->nx + x;
-                const uint16_t b = s->bits[(size_t)y * s->pitch + x];
+                const uint16_t b = s->bits[(size_t)s->off0 + (size_t)y * s->pitch + x];
                 cls[n] = s->solid[n] ? VLB_NODE_SOLID
                                      : ((b & 0x1FE) ? VLB_NODE_BOUNDARY : VLB_NODE_FLUID);
             }
@@ -483,29 +577,28 @@ int vlb_bind(vlb_sim* s, void* ws, size_t bytes, void* stream) {
     s->stream = static_cast<hipStream_t>(stream);
     s->bound = true;
     s->inited = false;
+    VLB_HIP(vlb::launch_fill_bytes(s->ws, s->total, 0, s->stream));
+    if (!s->fill.empty()) {
+        VLB_HIP(hipMemcpyAsync(s->ws + s->off_fill, s->fill.data(), s->fill.size() * sizeof(vlb::FillOp),
+                               hipMemcpyHostToDevice, s->stream));
+        VLB_HIP(hipMemcpyAsync(s->ws + s->off_fill_items, s->fill_items.data(),
+                               s->fill_items.size() * sizeof(vlb::FillItem), hipMemcpyHostToDevice,
+                               s->stream));
+    }
     VLB_HIP(hipMemcpyAsync(s->ws + s->off_bits, s->bits.data(), s->bits.size() * sizeof(uint16_t),
                            hipMemcpyHostToDevice, s->stream));
     if (s->has_curved) {
         VLB_HIP(hipMemcpyAsync(s->ws + s->off_bidx, s->bidx.data(), s->bidx.size() * sizeof(int),
                                hipMemcpyHostToDevice, s->stream));
     }
-    // wall fractions and inlet rows in the simulation precision
-    std::vector<char> tmp(std::max<size_t>(s->bq.size(), s->inlet.size()) * s->esz + 8);
-    auto put = [&](const std::vector<double>& v, size_t off) -> int {
-        if (v.empty()) return VLB_OK;
-        for (size_t i = 0; i < v.size(); ++i) {
-            if (s->esz == 4) { const float f = (float)v[i]; std::memcpy(&tmp[i * 4], &f, 4); }
-            else std::memcpy(&tmp[i * 8], &v[i], 8);
-        }
-        VLB_HIP(hipMemcpyAsync(s->ws + off, tmp.data(), v.size() * s->esz, hipMemcpyHostToDevice,
-                               s->stream));
-        VLB_HIP(hipStreamSynchronize(s->stream));
-        return VLB_OK;
-    };
-    int rc = put(s->bq, s->off_bq);
-    if (rc) return rc;
-    rc = put(s->inlet, s->off_inlet);
-    if (rc) return rc;
+    // wall fractions and inlet rows (double)
+    if (!s->bq.empty())
+        VLB_HIP(hipMemcpyAsync(s->ws + s->off_bq, s->bq.data(), s->bq.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s->stream));
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_inlet, s->inlet.data(), s->inlet.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    int rc = VLB_OK;
     rc = upload_items(s);
     if (rc) return rc;
     if (s->params_set) return upload_run(s);
@@ -539,10 +632,10 @@ int vlb_set_force_field(vlb_sim* s, const void* fx, const void* fy) {
         s->force_field = false;
     } else {
         const size_t row = (size_t)s->nx * s->esz, dp = (size_t)s->pitch * s->esz;
-        VLB_HIP(hipMemcpy2DAsync(s->ws + s->off_force, dp, fx, row, row, s->ny,
+        char* f0 = s->ws + s->off_force + (size_t)s->off0 * s->esz;
+        VLB_HIP(hipMemcpy2DAsync(f0, dp, fx, row, row, s->ny, hipMemcpyDeviceToDevice, s->stream));
+        VLB_HIP(hipMemcpy2DAsync(f0 + (size_t)s->plane * s->esz, dp, fy, row, row, s->ny,
                                  hipMemcpyDeviceToDevice, s->stream));
-        VLB_HIP(hipMemcpy2DAsync(s->ws + s->off_force + (size_t)s->plane * s->esz, dp, fy, row,
-                                 row, s->ny, hipMemcpyDeviceToDevice, s->stream));
         s->force_field = true;
     }
     if (s->params_set) return upload_run(s);
@@ -560,13 +653,8 @@ int vlb_set_inlet(vlb_sim* s, const double* ux, const double* axx, const double*
             s->inlet[(size_t)c * s->ny + y] = src[c][y];
         }
     if (!s->bound) return VLB_OK;
-    std::vector<char> tmp(s->inlet.size() * s->esz);
-    for (size_t i = 0; i < s->inlet.size(); ++i) {
-        if (s->esz == 4) { const float f = (float)s->inlet[i]; std::memcpy(&tmp[i * 4], &f, 4); }
-        else std::memcpy(&tmp[i * 8], &s->inlet[i], 8);
-    }
-    VLB_HIP(hipMemcpyAsync(s->ws + s->off_inlet, tmp.data(), tmp.size(), hipMemcpyHostToDevice,
-                           s->stream));
+    VLB_HIP(hipMemcpyAsync(s->ws + s->off_inlet, s->inlet.data(), s->inlet.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
     VLB_HIP(hipStreamSynchronize(s->stream));
     return VLB_OK;
 }
@@ -632,7 +720,8 @@ int vlb_read_history(vlb_sim* s, void* sxx, void* sxy, void* syy, void* uxp, voi
     const size_t row = (size_t)s->nx * s->esz, dp = (size_t)s->pitch * s->esz;
     for (int c = 0; c < 5; ++c) {
         if (!out[c]) continue;
-        VLB_HIP(hipMemcpy2DAsync(out[c], row, s->ws + s->off_hist + (size_t)c * s->plane * s->esz,
+        VLB_HIP(hipMemcpy2DAsync(out[c], row,
+                                 s->ws + s->off_hist + ((size_t)c * s->plane + s->off0) * s->esz,
                                  dp, row, s->ny, hipMemcpyDeviceToDevice, s->stream));
     }
     return VLB_OK;
@@ -725,6 +814,13 @@ int vlb_set_tile(vlb_sim* s, int ty) {
     s->ty = ty;
     drop_graphs(s);
     if (s->bound) return upload_items(s);
+    return VLB_OK;
+}
+
+int vlb_set_store_mode(vlb_sim* s, int mode) {
+    if (!s || mode < 0 || mode > 2) return fail(VLB_E_INVALID_ARG, "store mode must be 0, 1 or 2");
+    s->store_mode = mode;
+    drop_graphs(s);
     return VLB_OK;
 }
 

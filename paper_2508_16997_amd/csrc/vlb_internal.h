@@ -10,38 +10,69 @@ namespace vlb {
 
 enum { XM_PERIODIC = 0, XM_WALL = 1, XM_OPEN = 2 };
 
-// Per-node geometry byte: bit 0 = the node itself is solid; bit i (1..8) = the source
+// Per-node geometry word: bit 0 = the node itself is solid; bit i (1..8) = the source
 // x - e_i of direction i is solid (domain wall or solid node).
 enum { BIT_SELF_SOLID = 1u };
 
-// Device descriptor of one simulation ("run").  The step kernel reads it through
-// uniform (scalar) loads; a batch is an array of these.
-template <class T>
+// Storage layout: every plane holds (ny + 2) rows of `pitch` elements.  Node (x, y) is
+// element off0 + y * pitch + x with off0 = pitch + XOFF; row -1, row ny, column -1 and
+// column nx around the domain are ghost slots.  XOFF = 64 keeps the rows of a 64-wide
+// tile aligned to 256 bytes.
+enum { XOFF = 64 };
+
+// Kinds of fill operations (run after each step on the post-collision buffer, before
+// the next step pulls from it).  One op serves direction `dir` of one fluid node.
+enum {
+    FILL_COPY = 0,     // all four lattices: slot dst <- node src (periodic image, outlet)
+    FILL_WALL = 1,     // half-way bounce-back: f_dir(dst) <- f_opp(src); g likewise
+    FILL_CURVED = 2,   // interpolated bounce-back for f (q, far node); g as FILL_WALL
+    FILL_INLET = 3     // equilibrium of the inlet profile at row `far`
+};
+
+struct FillOp {
+    int dst;       // slot that the fluid node pulls direction dir from
+    int src;       // fluid node x (or copy source)
+    int far;       // x + e_dir for FILL_CURVED (or -1), inlet row for FILL_INLET
+    int dir_kind;  // dir | kind << 8
+    double q;      // wall fraction for FILL_CURVED
+};
+
+// Device descriptor of one simulation ("run").  The kernels read it through uniform
+// (scalar) loads; a batch is an array of these.  S is the storage type of the
+// populations and fields (float or double); all arithmetic is done in double.
+template <class S>
 struct RunDev {
-    int nx, ny, pitch, xmode, ymode;
+    int nx, ny, pitch, off0, xmode, ymode;
     int has_bits;       // bits plane present (walls or solid nodes)
     int has_curved;     // curved links present (bidx / bq valid)
     int uniform_force;  // 1: use Fx, Fy below; 0: force planes
     int no_source;      // constitutive source forced to zero
-    int pad0;
-    long long plane;    // elements per plane (ny * pitch)
-    T* pop[2];          // two population buffers of 36 planes: f (9), g_xx, g_xy, g_yy (9 each)
-    T* hist;            // 5 planes: S_xx, S_xy, S_yy, u_x, u_y of the previous step
-    const T* force;     // 2 planes (F_x, F_y) when !uniform_force
+    long long plane;    // elements per plane ((ny + 2) * pitch)
+    S* pop[2];          // two population buffers of 36 planes: f (9), g_xx, g_xy, g_yy (9 each)
+    S* hist;            // 5 planes: S_xx, S_xy, S_yy, u_x, u_y of the previous step
+    const S* force;     // 2 planes (F_x, F_y) when !uniform_force
     const uint16_t* bits;  // per node, see BIT_SELF_SOLID
     const int* bidx;    // per node: row of bq for nodes with curved links, else -1
-    const T* bq;        // 8 wall fractions per boundary node (directions 1..8)
-    const T* inlet;     // 4 rows of ny: u_x, A_xx, A_xy, A_yy
+    const double* bq;   // 8 wall fractions per boundary node (directions 1..8)
+    const double* inlet;  // 4 rows of ny: u_x, A_xx, A_xy, A_yy
+    const FillOp* fill;   // fill operations of this run
+    int nfill;
+    int pad1;
     // coefficients, computed in double on the host
-    T c1, c2, h1, inv_ts1;  // 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
-    T p1, p2, h2;           // 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)
-    T inv_lam, eta_over_lam;
-    T Fx, Fy;
+    double c1, c2, h1, inv_ts1;  // 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
+    double p1, p2, h2;           // 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)
+    double inv_lam, eta_over_lam;
+    double Fx, Fy;
 };
 
 // Work item of the step kernel: run index, tile column, tile row.
 struct Item {
     int run, tx, ty, pad;
+};
+
+// Work item of the fill kernel: run index and a chunk of that run's ops.
+struct FillItem {
+    int run, first, count, pad;
 };
 
 struct MonitorAcc {
@@ -53,19 +84,23 @@ struct MonitorAcc {
 };
 
 // Kernel launchers (vlb_kernels.hip).  Return hipSuccess or the launch error.
-template <class T>
-hipError_t launch_step(const RunDev<T>* runs_dev, const Item* items_dev, int nitems, int ty,
-                       int parity, int first, hipStream_t s);
-template <class T>
-hipError_t launch_init(const RunDev<T>& run_host, const RunDev<T>* run_dev, const T* rho,
-                       const T* ux, const T* uy, const T* axx, const T* axy, const T* ayy,
+// streaming != 0 selects non-temporal stores of the post-collision state.
+template <class S>
+hipError_t launch_step(const RunDev<S>* runs_dev, const Item* items_dev, int nitems, int ty,
+                       int parity, int first, int streaming, hipStream_t s);
+template <class S>
+hipError_t launch_fill(const RunDev<S>* runs_dev, const FillItem* items_dev, int nitems,
+                       int parity, hipStream_t s);
+template <class S>
+hipError_t launch_init(const RunDev<S>& run_host, const RunDev<S>* run_dev, const S* rho,
+                       const S* ux, const S* uy, const S* axx, const S* axy, const S* ayy,
                        hipStream_t s);
-template <class T>
-hipError_t launch_read(const RunDev<T>& run_host, const RunDev<T>* run_dev, int parity,
-                       int first, T* rho, T* ux, T* uy, T* axx, T* axy, T* ayy, hipStream_t s);
-template <class T>
-hipError_t launch_monitor(const RunDev<T>& run_host, const RunDev<T>* run_dev, int parity,
-                          int first, T* usnap, MonitorAcc* acc, hipStream_t s);
+template <class S>
+hipError_t launch_read(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,
+                       int first, S* rho, S* ux, S* uy, S* axx, S* axy, S* ayy, hipStream_t s);
+template <class S>
+hipError_t launch_monitor(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,
+                          int first, S* usnap, MonitorAcc* acc, hipStream_t s);
 hipError_t launch_fill_bytes(void* dst, size_t bytes, unsigned char v, hipStream_t s);
 hipError_t launch_write_words(unsigned long long* dst, unsigned long long w0,
                               unsigned long long w1, unsigned long long w2,

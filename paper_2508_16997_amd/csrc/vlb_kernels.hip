@@ -1,25 +1,62 @@
 // vlb_kernels.hip -- gfx950 kernels of the coupled viscoelastic lattice Boltzmann step.
 //
-// One fused kernel per time step (pull scheme, two population buffers):
-//   phase 1  every lane pulls its node's 36 post-collision populations from the
-//            neighbours (one load each, structure-of-arrays planes, x fastest, so a
-//            wavefront of 64 lanes reads contiguous rows), fills wall links
-//            (half-way or linear interpolated bounce-back for f, the wall-bound
-//            post-collision populations for g), and computes rho and u; a one-node
-//            ring around the 64 x TY tile recomputes rho and u of its nodes from
-//            their hydrodynamic populations only.  rho, u of tile and ring go to LDS.
-//   phase 2  velocity gradient and d(rho u^3) by finite differences from LDS,
-//            CNEBB at boundary nodes, constitutive source, the hydrodynamic and three
-//            convection-diffusion collisions in moment form, and 36 + 5 coalesced
-//            stores to the other buffer.
-// Populations are stored as deviations from the rest state (f_i - w_i,
-// g_i - w_i phi0 with phi0 = 1, 0, 1) so that single precision keeps the small
-// velocity and stress signals; the collision is the paper's regularized TRT
-// operator rewritten in Hermite-moment space (algebraically identical).
+// Per time step two launches (pull scheme, two population buffers):
+//   k_step  every lane pulls its node's 36 post-collision populations from the
+//           neighbours' slots with one branch-free global load each (structure-of-
+//           arrays planes, x fastest, 64 lanes read contiguous rows).  Slots that do
+//           not hold a fluid node -- ghost rows/columns around the domain and solid
+//           nodes -- were written by k_fill with exactly the value the boundary rule
+//           gives for that link.  rho and u of the 64 x TY tile and of a one-node ring
+//           around it go to LDS; then the velocity gradient and d(rho u^3) by finite
+//           differences, CNEBB at wall-adjacent nodes, the constitutive source, the
+//           hydrodynamic and three convection-diffusion collisions in moment form,
+//           and 36 + 5 coalesced stores.
+//   k_fill  walks the run's list of boundary links (one op per fluid node and
+//           direction whose source is not a fluid node) and writes the periodic image,
+//           the bounced or interpolated population, or the inlet equilibrium into the
+//           slot that the next k_step pulls.  Every (slot, direction) pair belongs to
+//           one fluid node, so the ops never conflict.
+// Storage is float or double (template S); populations are kept as deviations from
+// the rest state (f_i - w_i, g_i - w_i phi0 with phi0 = 1, 0, 1).  All arithmetic is
+// double precision: on CDNA the vector FP64 rate equals the unpacked FP32 rate, and
+// single-precision arithmetic lets rounding drift accumulate over many steps.
+// The collision is the paper's regularized TRT operator rewritten in Hermite-moment
+// space (algebraically identical to the per-direction form).
 #include "vlb_internal.h"
+
+#define VLB_GLOBAL __attribute__((address_space(1)))
+
+// Register budget of the step kernel: single-precision storage fits four waves per
+// SIMD (a few spilled registers cost less than the lost latency hiding); double
+// precision keeps its natural allocation.
+template <class S, int TY>
+struct StepBounds {
+    static constexpr int threads = 64 * TY;
+    static constexpr int min_waves_per_eu = sizeof(S) == 4 ? 4 : 1;
+};
 
 namespace vlb {
 namespace {
+
+using T = double;  // arithmetic type
+
+// load/store with a uniform base pointer and a non-negative 32-bit element offset
+template <class S>
+__device__ __forceinline__ T ldu(const S* base, unsigned off) {
+    return (T)((const VLB_GLOBAL S*)base)[off];
+}
+template <class S>
+__device__ __forceinline__ void stu(S* base, unsigned off, T v) {
+    ((VLB_GLOBAL S*)base)[off] = (S)v;
+}
+// store of a streamed value, read by other workgroups in the next step only: a
+// non-temporal store when the working set exceeds the last-level cache, a plain one
+// when the whole state stays cache resident
+template <bool NT, class S>
+__device__ __forceinline__ void st_stream(S* base, unsigned off, T v) {
+    if (NT) __builtin_nontemporal_store((S)v, (VLB_GLOBAL S*)base + off);
+    else ((VLB_GLOBAL S*)base)[off] = (S)v;
+}
 
 // D2Q9 velocities in the paper's order (Sec. 3.1), their opposites and weights.
 __host__ __device__ constexpr int ex(int i) {
@@ -31,178 +68,87 @@ __host__ __device__ constexpr int ey(int i) {
 __host__ __device__ constexpr int opp(int i) {
     return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
 }
-template <class T>
 __device__ __forceinline__ constexpr T wgt(int i) {
-    return i == 0 ? T(4.0 / 9.0) : (i <= 4 ? T(1.0 / 9.0) : T(1.0 / 36.0));
+    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
 }
-template <class T>
-__device__ __forceinline__ constexpr T third() { return T(1.0 / 3.0); }
+constexpr T R3 = 1.0 / 3.0;
 
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
 
-// Per-node pull sources: element index of x - e_i (or the node itself for wall links),
-// the inlet row for inlet links.
-struct Srcs {
-    int idx[9];
-    unsigned solid;  // bit i: wall link (source solid)
-    unsigned inl;    // bit i: source is the inlet ghost column
-};
-
-template <class T>
-__device__ __forceinline__ void node_srcs(const RunDev<T>& R, int px, int py, unsigned b,
-                                          bool pull, Srcs& s) {
-    const int p = py * R.pitch + px;
-    s.solid = pull ? (b & 0x1FEu) : 0u;
-    s.inl = 0u;
-    s.idx[0] = p;
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        if (!pull || ((s.solid >> i) & 1u)) {
-            s.idx[i] = p;
-            continue;
-        }
-        int xs = px - ex(i), ys = py - ey(i);
-        // Domain walls are flagged in the geometry bits, so only periodic wraps remain.
-        if (ys < 0) ys += R.ny;
-        else if (ys >= R.ny) ys -= R.ny;
-        if (xs < 0) {
-            if (R.xmode == XM_OPEN) {
-                s.inl |= 1u << i;
-                s.idx[i] = ys;
-                continue;
-            }
-            xs += R.nx;
-        } else if (xs >= R.nx) {
-            xs = (R.xmode == XM_OPEN) ? R.nx - 1 : xs - R.nx;  // outlet: zero gradient
-        }
-        s.idx[i] = ys * R.pitch + xs;
-    }
+template <class S>
+__device__ __forceinline__ int node_index(const RunDev<S>& R, int x, int y) {
+    return R.off0 + y * R.pitch + x;
 }
 
 // Deviation of the third-order Hermite hydrodynamic equilibrium (Sec. 3.1):
 // f_i^eq - w_i = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u + 13.5 h3_i(u))].
-template <class T>
 __device__ __forceinline__ T dfeq(int i, T drho, T rho, T ux, T uy) {
     const T eu = T(ex(i)) * ux + T(ey(i)) * uy;
-    const T hxxy = (T(ex(i) * ex(i)) - third<T>()) * T(ey(i));
-    const T hxyy = (T(ey(i) * ey(i)) - third<T>()) * T(ex(i));
+    const T hxxy = (T(ex(i) * ex(i)) - R3) * T(ey(i));
+    const T hxyy = (T(ey(i) * ey(i)) - R3) * T(ex(i));
     const T h3 = hxxy * ux * ux * uy + hxyy * ux * uy * uy;
-    return wgt<T>(i) * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * (ux * ux + uy * uy) +
-                                      T(13.5) * h3));
+    return wgt(i) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy) + 13.5 * h3));
 }
 
 // Deviation of the second-order convection-diffusion equilibrium (Sec. 3.2).
-template <class T>
 __device__ __forceinline__ T dgeq(int i, T dphi, T phi, T ux, T uy) {
     const T eu = T(ex(i)) * ux + T(ey(i)) * uy;
-    return wgt<T>(i) * (dphi + phi * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * (ux * ux + uy * uy)));
+    return wgt(i) * (dphi + phi * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy)));
 }
 
-template <class T>
-__device__ __forceinline__ T phi0(int k) { return k == 1 ? T(0) : T(1); }
+__device__ __forceinline__ constexpr T phi0(int k) { return k == 1 ? 0.0 : 1.0; }
 
-// Wall fill of the hydrodynamic population moving in direction i into node p whose
-// source is solid: half-way bounce-back for q = 1/2, linear interpolated bounce-back
-// otherwise (q is the wall fraction of the link from p toward the solid).
-template <class T>
-__device__ __noinline__ T wall_fill_curved(const RunDev<T>& R, const T* __restrict__ src, int px,
-                                           int py, int p, int i, T q) {
-    const long long plane = R.plane;
-    const int o = opp(i);
-    const T fo = src[o * plane + p];
-    if (q < T(0.5)) {
-        int xf = px + ex(i), yf = py + ey(i);
-        bool ok = true;
-        if (yf < 0 || yf >= R.ny) {
-            if (R.ymode == XM_PERIODIC) yf = yf < 0 ? yf + R.ny : yf - R.ny;
-            else ok = false;
-        }
-        if (xf < 0 || xf >= R.nx) {
-            if (R.xmode == XM_PERIODIC) xf = xf < 0 ? xf + R.nx : xf - R.nx;
-            else ok = false;
-        }
-        if (ok && R.has_bits) ok = (R.bits[yf * R.pitch + xf] & BIT_SELF_SOLID) == 0;
-        if (!ok) return fo;
-        return T(2) * q * fo + (T(1) - T(2) * q) * src[o * plane + yf * R.pitch + xf];
-    }
-    return fo / (T(2) * q) + (T(2) * q - T(1)) / (T(2) * q) * src[i * plane + p];
+template <class S>
+__device__ __forceinline__ T link_q(const RunDev<S>& R, int bi, int i) {
+    return bi >= 0 ? R.bq[bi * 8 + (i - 1)] : 0.5;
 }
 
-template <class T>
-__device__ __forceinline__ T link_q(const RunDev<T>& R, int bi, int i) {
-    return bi >= 0 ? R.bq[bi * 8 + (i - 1)] : T(0.5);
+template <class S>
+__device__ __forceinline__ unsigned node_bits(const RunDev<S>& R, int p) {
+    return R.has_bits ? (unsigned)((const VLB_GLOBAL uint16_t*)R.bits)[p] : 0u;
 }
 
-// Pulled (and wall-filled) hydrodynamic populations of node (px, py).
-template <class T>
-__device__ __forceinline__ void load_hydro(const RunDev<T>& R, const T* __restrict__ src, int px,
-                                           int py, const Srcs& s, int bi, T f[9]) {
-    const long long plane = R.plane;
-    const int p = py * R.pitch + px;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        if ((s.solid >> i) & 1u) {
-            const T q = link_q(R, bi, i);
-            if (q == T(0.5)) f[i] = src[opp(i) * plane + p];
-            else f[i] = wall_fill_curved(R, src, px, py, p, i, q);
-        } else if ((s.inl >> i) & 1u) {
-            const T uin = R.inlet[s.idx[i]];
-            f[i] = dfeq<T>(i, T(0), T(1), uin, T(0));
-        } else {
-            f[i] = src[i * plane + s.idx[i]];
-        }
-    }
-}
-
-// Pulled conformation populations of lattice k; wall links take the post-collision
-// population that left toward the wall (input of the CNEBB phi_b).
-template <class T>
-__device__ __forceinline__ void load_cde(const RunDev<T>& R, const T* __restrict__ src, int k,
-                                         int p, const Srcs& s, T g[9]) {
-    const long long plane = R.plane;
-    const T* __restrict__ base = src + (long long)(9 + 9 * k) * plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        if ((s.solid >> i) & 1u) {
-            g[i] = base[opp(i) * plane + p];
-        } else if ((s.inl >> i) & 1u) {
-            const int row = s.idx[i];
-            const T uin = R.inlet[row];
-            const T a = R.inlet[(1 + k) * R.ny + row];
-            g[i] = dgeq<T>(i, a - phi0<T>(k), a, uin, T(0));
-        } else {
-            g[i] = base[i * plane + s.idx[i]];
-        }
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void node_force(const RunDev<T>& R, int p, T& Fx, T& Fy) {
+template <class S>
+__device__ __forceinline__ void node_force(const RunDev<S>& R, int p, T& Fx, T& Fy) {
     if (R.uniform_force) {
         Fx = R.Fx;
         Fy = R.Fy;
     } else {
-        Fx = R.force[p];
-        Fy = R.force[R.plane + p];
+        Fx = ldu(R.force, (unsigned)p);
+        Fy = ldu(R.force + R.plane, (unsigned)p);
+    }
+}
+
+// The nine populations of lattice L (0 hydro, 1..3 conformation) that arrive at slot
+// p: pulled from p - e_i, or the node's own values on the first step.  Kept in storage
+// precision until their moments are taken.
+template <class S>
+__device__ __forceinline__ void pull9(const RunDev<S>& R, const S* src, int L, int p, bool pull,
+                                      S v[9]) {
+    const long long plane = R.plane;
+    const S* base = src + (long long)(9 * L) * plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int off = pull ? p - ex(i) - ey(i) * R.pitch : p;
+        v[i] = ((const VLB_GLOBAL S*)(base + i * plane))[(unsigned)off];
     }
 }
 
 // rho, u with the half-force shift (Sec. 3.1).
-template <class T>
-__device__ __forceinline__ void hydro_macros(const T f[9], T Fx, T Fy, T& drho, T& rho, T& ux,
+template <class V>
+__device__ __forceinline__ void hydro_macros(const V f[9], T Fx, T Fy, T& drho, T& rho, T& ux,
                                              T& uy) {
-    T s = T(0), jx = T(0), jy = T(0);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        s += f[i];
-        if (ex(i) != 0) jx += T(ex(i)) * f[i];
-        if (ey(i) != 0) jy += T(ey(i)) * f[i];
-    }
-    drho = s;
-    rho = T(1) + s;
-    ux = (jx + T(0.5) * Fx) / rho;
-    uy = (jy + T(0.5) * Fy) / rho;
+    const T s13 = T(f[1]) + T(f[3]), s24 = T(f[2]) + T(f[4]);
+    const T s57 = T(f[5]) + T(f[7]), s68 = T(f[6]) + T(f[8]);
+    const T d13 = T(f[1]) - T(f[3]), d24 = T(f[2]) - T(f[4]);
+    const T d57 = T(f[5]) - T(f[7]), d68 = T(f[6]) - T(f[8]);
+    drho = T(f[0]) + (s13 + s24) + (s57 + s68);
+    const T jx = d13 + (d57 - d68), jy = d24 + (d57 + d68);
+    rho = 1.0 + drho;
+    const T inv = 1.0 / rho;
+    ux = (jx + 0.5 * Fx) * inv;
+    uy = (jy + 0.5 * Fy) * inv;
 }
 
 // Conservative non-equilibrium bounce-back for one lattice at a boundary node
@@ -211,22 +157,19 @@ __device__ __forceinline__ void hydro_macros(const T f[9], T Fx, T Fy, T& drho, 
 // sum.  Unknowns are rebuilt from the equilibrium at (phi_b, u_b) plus the
 // non-equilibrium part of the known opposite population (the equilibrium alone when
 // the opposite is unknown too); g_0 restores phi_b exactly.
-template <class T>
-__device__ __forceinline__ void cnebb(unsigned solid, int k, T ux, T uy, T g[9], T& dphi) {
-    T sum = T(0);
+// An unknown is never read as the known opposite of another unknown, so the update is
+// done in place.
+__device__ __forceinline__ void cnebb(unsigned solid, int k, T ux, T uy, T g[9]) {
+    T sum = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) sum += g[i];
-    dphi = sum;
-    const T phi = phi0<T>(k) + sum;
-    T known[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) known[i] = g[i];
+    const T phi = phi0(k) + sum;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         if (!((solid >> i) & 1u)) continue;
         const int o = opp(i);
-        T v = dgeq<T>(i, sum, phi, ux, uy);
-        if (!((solid >> o) & 1u)) v += known[o] - dgeq<T>(o, sum, phi, ux, uy);
+        T v = dgeq(i, sum, phi, ux, uy);
+        if (!((solid >> o) & 1u)) v += g[o] - dgeq(o, sum, phi, ux, uy);
         g[i] = v;
     }
     T rest = sum;
@@ -237,12 +180,56 @@ __device__ __forceinline__ void cnebb(unsigned solid, int k, T ux, T uy, T g[9],
 
 // Finite-difference derivative along one axis: central difference, or the quadratic
 // through the no-slip wall value 0 at fraction q when a neighbour is a wall.
-template <class T>
 __device__ __forceinline__ T dgrad(bool lo_wall, T qlo, T vlo, T v0, bool hi_wall, T qhi, T vhi) {
-    if (!lo_wall && !hi_wall) return T(0.5) * (vhi - vlo);
-    if (lo_wall && !hi_wall) return qlo / (T(1) + qlo) * vhi + (T(1) - qlo) / qlo * v0;
-    if (!lo_wall) return -(qhi / (T(1) + qhi) * vlo + (T(1) - qhi) / qhi * v0);
+    if (!lo_wall && !hi_wall) return 0.5 * (vhi - vlo);
+    if (lo_wall && !hi_wall) return qlo / (1.0 + qlo) * vhi + (1.0 - qlo) / qlo * v0;
+    if (!lo_wall) return -(qhi / (1.0 + qhi) * vlo + (1.0 - qhi) / qhi * v0);
     return v0 * (qhi - qlo) / (qlo * qhi);
+}
+
+// Moments of one D2Q9 population set via opposite-pair sums and differences:
+// zeroth, first (x, y), second (xx, yy, xy) and the two third-order ones (xxy, xyy).
+struct Mom {
+    T m0, mx, my, pxx, pyy, pxy, qxxy, qxyy;
+};
+template <class V>
+__device__ __forceinline__ Mom moments(const V v[9]) {
+    const T s13 = T(v[1]) + T(v[3]), d13 = T(v[1]) - T(v[3]);
+    const T s24 = T(v[2]) + T(v[4]), d24 = T(v[2]) - T(v[4]);
+    const T s57 = T(v[5]) + T(v[7]), d57 = T(v[5]) - T(v[7]);
+    const T s68 = T(v[6]) + T(v[8]), d68 = T(v[6]) - T(v[8]);
+    Mom m;
+    m.m0 = T(v[0]) + (s13 + s24) + (s57 + s68);
+    m.mx = d13 + (d57 - d68);
+    m.my = d24 + (d57 + d68);
+    m.pxx = s13 + (s57 + s68);
+    m.pyy = s24 + (s57 + s68);
+    m.pxy = s57 - s68;
+    m.qxxy = d57 + d68;
+    m.qxyy = d57 - d68;
+    return m;
+}
+
+// Populations w_i [e0 + 3 e.M1 + 4.5 H2:M2 + 13.5 H3:M3] rebuilt pairwise: for the
+// opposite directions i and i' the even part is shared and the odd part changes sign.
+__device__ __forceinline__ void rebuild(T e0, T m1x, T m1y, T m2xx, T m2yy, T m2xy, T m3xxy,
+                                        T m3xyy, T out[9]) {
+    constexpr T w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
+    const T tr = m2xx + m2yy;
+    out[0] = w0 * (e0 - 1.5 * tr);
+    const T e13 = e0 + 3.0 * m2xx - 1.5 * m2yy, o13 = 3.0 * m1x - 4.5 * m3xyy;
+    out[1] = w1 * (e13 + o13);
+    out[3] = w1 * (e13 - o13);
+    const T e24 = e0 + 3.0 * m2yy - 1.5 * m2xx, o24 = 3.0 * m1y - 4.5 * m3xxy;
+    out[2] = w1 * (e24 + o24);
+    out[4] = w1 * (e24 - o24);
+    const T ed = e0 + 3.0 * tr;
+    const T e57 = ed + 9.0 * m2xy, o57 = 3.0 * (m1x + m1y) + 9.0 * (m3xxy + m3xyy);
+    out[5] = w5 * (e57 + o57);
+    out[7] = w5 * (e57 - o57);
+    const T e68 = ed - 9.0 * m2xy, o68 = 3.0 * (m1y - m1x) + 9.0 * (m3xxy - m3xyy);
+    out[6] = w5 * (e68 + o68);
+    out[8] = w5 * (e68 - o68);
 }
 
 // Hydrodynamic TRT regularized collision in Hermite-moment form (Sec. 3.1): the
@@ -252,30 +239,18 @@ __device__ __forceinline__ T dgrad(bool lo_wall, T qlo, T vlo, T v0, bool hi_wal
 //        (G_i and T_i)
 //   M3 = rho uuu + (1 - 1/tau_s2) a_3   (xxy and xyy; H_xxx = H_yyy = 0 on D2Q9)
 // where a_n are the off-equilibrium Hermite moments of f (a_0 = 0 identically).
-template <class T>
-__device__ __forceinline__ void collide_hydro(const RunDev<T>& R, const T f[9], T drho, T rho,
-                                              T ux, T uy, T Fx, T Fy, T txx, T txy, T tyy,
-                                              T Dx, T Dy, T out[9]) {
-    T jx = T(0), jy = T(0), pxx = T(0), pyy = T(0), pxy = T(0), qxxy = T(0), qxyy = T(0);
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const int cx = ex(i), cy = ey(i);
-        if (cx != 0) { jx += T(cx) * f[i]; pxx += f[i]; }
-        if (cy != 0) { jy += T(cy) * f[i]; pyy += f[i]; }
-        if (cx != 0 && cy != 0) {
-            pxy += T(cx * cy) * f[i];
-            qxxy += T(cy) * f[i];
-            qxyy += T(cx) * f[i];
-        }
-    }
-    const T r3 = third<T>();
+template <class S>
+__device__ __forceinline__ void collide_hydro(const RunDev<S>& R, const Mom& m, T rho, T ux, T uy,
+                                              T Fx, T Fy, T txx, T txy, T tyy, T Dx, T Dy,
+                                              T out[9]) {
+    const T drho = m.m0;
     const T ruxx = rho * ux * ux, ruyy = rho * uy * uy, ruxy = rho * ux * uy;
-    const T ax = jx - rho * ux, ay = jy - rho * uy;
-    const T axx = pxx - r3 * drho - ruxx;
-    const T ayy = pyy - r3 * drho - ruyy;
-    const T axy = pxy - ruxy;
-    const T axxy = qxxy - r3 * jy - ruxx * uy;
-    const T axyy = qxyy - r3 * jx - ruyy * ux;
+    const T ax = m.mx - rho * ux, ay = m.my - rho * uy;
+    const T axx = m.pxx - R3 * drho - ruxx;
+    const T ayy = m.pyy - R3 * drho - ruyy;
+    const T axy = m.pxy - ruxy;
+    const T axxy = m.qxxy - R3 * m.my - ruxx * uy;
+    const T axyy = m.qxyy - R3 * m.mx - ruyy * ux;
     const T m1x = rho * ux + R.c1 * ax + R.h1 * Fx;
     const T m1y = rho * uy + R.c1 * ay + R.h1 * Fy;
     const T m2xx = ruxx + R.c1 * axx - R.h1 * Dx - R.inv_ts1 * txx;
@@ -283,15 +258,7 @@ __device__ __forceinline__ void collide_hydro(const RunDev<T>& R, const T f[9], 
     const T m2xy = ruxy + R.c1 * axy - R.inv_ts1 * txy;
     const T m3xxy = ruxx * uy + R.c2 * axxy;
     const T m3xyy = ruyy * ux + R.c2 * axyy;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int cx = ex(i), cy = ey(i);
-        const T hxx = T(cx * cx) - r3, hyy = T(cy * cy) - r3;
-        T v = drho + T(3) * (T(cx) * m1x + T(cy) * m1y) +
-              T(4.5) * (hxx * m2xx + hyy * m2yy + T(2 * cx * cy) * m2xy);
-        if (cx != 0 || cy != 0) v += T(13.5) * (hxx * T(cy) * m3xxy + hyy * T(cx) * m3xyy);
-        out[i] = wgt<T>(i) * v;
-    }
+    rebuild(drho, m1x, m1y, m2xx, m2yy, m2xy, m3xxy, m3xyy, out);
 }
 
 // Convection-diffusion TRT regularized collision in moment form (Sec. 3.2):
@@ -300,41 +267,28 @@ __device__ __forceinline__ void collide_hydro(const RunDev<T>& R, const T f[9], 
 //   N2 = phi uu + (1 - 1/tau_p2) b_2,
 // i.e. the equilibrium, the regularized non-equilibrium part, G~_i, F~_i and half the
 // backward time difference of F~_i.
-template <class T>
-__device__ __forceinline__ void collide_cde(const RunDev<T>& R, const T g[9], T dphi, T phi, T ux,
-                                            T uy, T fr, T Fx, T Fy, T S, T Sp, T uxp, T uyp,
+template <class S>
+__device__ __forceinline__ void collide_cde(const RunDev<S>& R, const Mom& m, T phi, T ux, T uy,
+                                            T fr, T Fx, T Fy, T Sk, T Sp, T uxp, T uyp,
                                             T out[9]) {
-    T mx = T(0), my = T(0), pxx = T(0), pyy = T(0), pxy = T(0);
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const int cx = ex(i), cy = ey(i);
-        if (cx != 0) { mx += T(cx) * g[i]; pxx += g[i]; }
-        if (cy != 0) { my += T(cy) * g[i]; pyy += g[i]; }
-        if (cx != 0 && cy != 0) pxy += T(cx * cy) * g[i];
-    }
-    const T r3 = third<T>();
-    const T bx = mx - phi * ux, by = my - phi * uy;
-    const T bxx = pxx - r3 * dphi - phi * ux * ux;
-    const T byy = pyy - r3 * dphi - phi * uy * uy;
-    const T bxy = pxy - phi * ux * uy;
-    const T s0 = dphi + T(1.5) * S - T(0.5) * Sp;
-    const T n1x = phi * ux + R.p1 * bx + R.h2 * (Fx * fr + T(1.5) * S * ux - T(0.5) * Sp * uxp);
-    const T n1y = phi * uy + R.p1 * by + R.h2 * (Fy * fr + T(1.5) * S * uy - T(0.5) * Sp * uyp);
-    const T n2xx = phi * ux * ux + R.p2 * bxx;
-    const T n2yy = phi * uy * uy + R.p2 * byy;
-    const T n2xy = phi * ux * uy + R.p2 * bxy;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int cx = ex(i), cy = ey(i);
-        const T hxx = T(cx * cx) - r3, hyy = T(cy * cy) - r3;
-        const T v = s0 + T(3) * (T(cx) * n1x + T(cy) * n1y) +
-                    T(4.5) * (hxx * n2xx + hyy * n2yy + T(2 * cx * cy) * n2xy);
-        out[i] = wgt<T>(i) * v;
-    }
+    const T dphi = m.m0;
+    const T pux = phi * ux, puy = phi * uy;
+    const T bx = m.mx - pux, by = m.my - puy;
+    const T bxx = m.pxx - R3 * dphi - pux * ux;
+    const T byy = m.pyy - R3 * dphi - puy * uy;
+    const T bxy = m.pxy - pux * uy;
+    const T s0 = dphi + 1.5 * Sk - 0.5 * Sp;
+    const T n1x = pux + R.p1 * bx + R.h2 * (Fx * fr + 1.5 * Sk * ux - 0.5 * Sp * uxp);
+    const T n1y = puy + R.p1 * by + R.h2 * (Fy * fr + 1.5 * Sk * uy - 0.5 * Sp * uyp);
+    const T n2xx = pux * ux + R.p2 * bxx;
+    const T n2yy = puy * uy + R.p2 * byy;
+    const T n2xy = pux * uy + R.p2 * bxy;
+    rebuild(s0, n1x, n1y, n2xx, n2yy, n2xy, 0.0, 0.0, out);
 }
 
-template <class T>
-__device__ __forceinline__ bool wrap_cell(const RunDev<T>& R, int& xx, int& yy) {
+// Periodic image of a tile/ring cell; false when it lies beyond a wall or open end.
+template <class S>
+__device__ __forceinline__ bool wrap_cell(const RunDev<S>& R, int& xx, int& yy) {
     if (yy < 0 || yy >= R.ny) {
         if (R.ymode != XM_PERIODIC) return false;
         yy = ((yy % R.ny) + R.ny) % R.ny;
@@ -346,41 +300,31 @@ __device__ __forceinline__ bool wrap_cell(const RunDev<T>& R, int& xx, int& yy) 
     return true;
 }
 
-template <class T>
-__device__ __forceinline__ unsigned node_bits(const RunDev<T>& R, int p) {
-    return R.has_bits ? (unsigned)R.bits[p] : 0u;
-}
-
-// rho and u of one tile/ring cell (pull + hydrodynamic wall fill + moments).
-template <class T>
-__device__ __forceinline__ bool cell_macros(const RunDev<T>& R, const T* __restrict__ src, int cx,
-                                            int cy, bool pull, T& rho, T& ux, T& uy) {
+// rho and u of one tile/ring cell (hydrodynamic pull + moments); false if not fluid.
+template <class S>
+__device__ __forceinline__ bool cell_macros(const RunDev<S>& R, const S* src, int cx, int cy,
+                                            bool pull, T& rho, T& ux, T& uy) {
     if (!wrap_cell(R, cx, cy)) return false;
-    const int p = cy * R.pitch + cx;
-    const unsigned b = node_bits(R, p);
-    if (b & BIT_SELF_SOLID) return false;
-    Srcs s;
-    node_srcs(R, cx, cy, b, pull, s);
-    const int bi = (R.has_curved && (s.solid != 0u)) ? R.bidx[p] : -1;
-    T f[9];
-    load_hydro(R, src, cx, cy, s, bi, f);
+    const int p = node_index(R, cx, cy);
+    if (node_bits(R, p) & BIT_SELF_SOLID) return false;
+    S f[9];
+    pull9(R, src, 0, p, pull, f);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
     return true;
 }
 
-template <class T, int TY>
-__global__ __launch_bounds__(64 * TY) void k_step(const RunDev<T>* __restrict__ runs,
-                                                  const Item* __restrict__ items, int parity,
-                                                  int first) {
+template <class S, int TY, bool NT>
+__global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::min_waves_per_eu)) void k_step(
+    const RunDev<S>* __restrict__ runs, const Item* __restrict__ items, int parity, int first) {
     __shared__ T s_rho[TY + 2][66];
     __shared__ T s_ux[TY + 2][66];
     __shared__ T s_uy[TY + 2][66];
     const Item it = items[blockIdx.x];
-    const RunDev<T>& R = runs[it.run];
-    const T* __restrict__ src = R.pop[parity];
-    T* __restrict__ dst = R.pop[parity ^ 1];
+    const RunDev<S>& R = runs[it.run];
+    const S* src = R.pop[parity];
+    S* dst = R.pop[parity ^ 1];
     const long long plane = R.plane;
     const bool pull = first == 0;
     const int lx = threadIdx.x, ly = threadIdx.y;
@@ -388,28 +332,24 @@ __global__ __launch_bounds__(64 * TY) void k_step(const RunDev<T>* __restrict__ 
     const int x0 = it.tx * 64, y0 = it.ty * TY;
     const int x = x0 + lx, y = y0 + ly;
 
-    // ---- phase 1: own node (all 36 pulls, history, force) ----
+    // ---- phase 1: own node (36 pulls, history, force) ----
     const bool in_dom = x < R.nx && y < R.ny;
-    const int p = y * R.pitch + x;
+    const int p = node_index(R, x, y);
     unsigned b = 0u;
     if (in_dom) b = node_bits(R, p);
     const bool active = in_dom && !(b & BIT_SELF_SOLID);
-    Srcs s;
-    T f[9], g[3][9];
-    T Fx = T(0), Fy = T(0), hS[3] = {T(0), T(0), T(0)}, hux = T(0), huy = T(0);
-    int bi = -1;
+    S f[9], g[3][9];
+    T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
     if (active) {
-        node_srcs(R, x, y, b, pull, s);
-        if (R.has_curved && (b & 0x1FEu)) bi = R.bidx[p];
-        load_hydro(R, src, x, y, s, bi, f);
+        pull9(R, src, 0, p, pull, f);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) load_cde(R, src, k, p, s, g[k]);
+        for (int k = 0; k < 3; ++k) pull9(R, src, 1 + k, p, pull, g[k]);
         node_force(R, p, Fx, Fy);
-        if (!first) {
+        if (pull) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) hS[k] = R.hist[k * plane + p];
-            hux = R.hist[3 * plane + p];
-            huy = R.hist[4 * plane + p];
+            for (int k = 0; k < 3; ++k) hS[k] = ldu(R.hist + k * plane, (unsigned)p);
+            hux = ldu(R.hist + 3 * plane, (unsigned)p);
+            huy = ldu(R.hist + 4 * plane, (unsigned)p);
         }
     }
     // ring cells: rows above/below the tile, columns left/right of it
@@ -426,17 +366,17 @@ __global__ __launch_bounds__(64 * TY) void k_step(const RunDev<T>* __restrict__ 
             s_uy[lcy][lcx] = vy;
         }
     }
-    T drho = T(0), rho = T(1), ux = T(0), uy = T(0);
+    T drho = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
     if (active) {
         hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
         s_rho[ly + 1][lx + 1] = rho;
         s_ux[ly + 1][lx + 1] = ux;
         s_uy[ly + 1][lx + 1] = uy;
-    } else {
+    } else if (!in_dom) {
         // out-of-domain tile cell: periodic image for the neighbours' differences
-        T r, vx, vy;
-        if (!in_dom && cell_macros(R, src, x, y, pull, r, vx, vy)) {
-            s_rho[ly + 1][lx + 1] = r;
+        T rr, vx, vy;
+        if (cell_macros(R, src, x, y, pull, rr, vx, vy)) {
+            s_rho[ly + 1][lx + 1] = rr;
             s_ux[ly + 1][lx + 1] = vx;
             s_uy[ly + 1][lx + 1] = vy;
         }
@@ -445,22 +385,23 @@ __global__ __launch_bounds__(64 * TY) void k_step(const RunDev<T>* __restrict__ 
     if (!active) return;
 
     // ---- phase 2 ----
-    // neighbour values for the differences (reading of the paper's silent gradient):
-    // LDS for fluid neighbours, wall formula at walls, inlet/outlet ghosts at open ends.
+    // neighbour values for the differences: LDS for fluid neighbours, the wall formula
+    // at walls, inlet/outlet ghost values at open ends.
     const bool wxl = (b >> 1) & 1u, wxh = (b >> 3) & 1u, wyl = (b >> 2) & 1u, wyh = (b >> 4) & 1u;
-    const int bq_row = bi;
-    const T qxl = link_q(R, bq_row, 1), qxh = link_q(R, bq_row, 3);
-    const T qyl = link_q(R, bq_row, 2), qyh = link_q(R, bq_row, 4);
+    T qxl = 0.5, qxh = 0.5, qyl = 0.5, qyh = 0.5;
+    if (R.has_curved && (b & 0x1Eu)) {
+        const int bi = R.bidx[p];
+        qxl = link_q(R, bi, 1); qxh = link_q(R, bi, 3);
+        qyl = link_q(R, bi, 2); qyh = link_q(R, bi, 4);
+    }
     const bool open_l = R.xmode == XM_OPEN && x == 0;
     const bool open_h = R.xmode == XM_OPEN && x == R.nx - 1;
-    T rl, uxl, uyl, rh, uxh, uyh;
-    if (open_l) { rl = T(1); uxl = R.inlet[y]; uyl = T(0); }
+    T rl = 0.0, uxl = 0.0, uyl = 0.0, rh = 0.0, uxh = 0.0, uyh = 0.0;
+    if (open_l) { rl = 1.0; uxl = R.inlet[y]; }
     else if (!wxl) { rl = s_rho[ly + 1][lx]; uxl = s_ux[ly + 1][lx]; uyl = s_uy[ly + 1][lx]; }
-    else { rl = T(0); uxl = T(0); uyl = T(0); }
     if (open_h) { rh = rho; uxh = ux; uyh = uy; }
     else if (!wxh) { rh = s_rho[ly + 1][lx + 2]; uxh = s_ux[ly + 1][lx + 2]; uyh = s_uy[ly + 1][lx + 2]; }
-    else { rh = T(0); uxh = T(0); uyh = T(0); }
-    T rd = T(0), uxd = T(0), uyd = T(0), ru = T(0), uxu = T(0), uyu = T(0);
+    T rd = 0.0, uxd = 0.0, uyd = 0.0, ru = 0.0, uxu = 0.0, uyu = 0.0;
     if (!wyl) { rd = s_rho[ly][lx + 1]; uxd = s_ux[ly][lx + 1]; uyd = s_uy[ly][lx + 1]; }
     if (!wyh) { ru = s_rho[ly + 2][lx + 1]; uxu = s_ux[ly + 2][lx + 1]; uyu = s_uy[ly + 2][lx + 1]; }
     const T Lxx = dgrad(wxl, qxl, uxl, ux, wxh, qxh, uxh);
@@ -472,128 +413,204 @@ __global__ __launch_bounds__(64 * TY) void k_step(const RunDev<T>* __restrict__ 
     const T Dy = dgrad(wyl, qyl, rd * uyd * uyd * uyd, rho * uy * uy * uy, wyh, qyh,
                        ru * uyu * uyu * uyu);
 
-    // conformation: phi_k (CNEBB at boundary nodes), Oldroyd-B stress and source
-    T dphi[3];
-    if (s.solid) {
+    // conformation: CNEBB at wall-adjacent nodes, then the moments of each lattice
+    const unsigned solid = pull ? (b & 0x1FEu) : 0u;
+    Mom gm[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) cnebb(s.solid, k, ux, uy, g[k], dphi[k]);
-    } else {
+    for (int k = 0; k < 3; ++k) {
+        if (solid) {
+            T gg[9];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            T acc = T(0);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) acc += g[k][i];
-            dphi[k] = acc;
+            for (int i = 0; i < 9; ++i) gg[i] = T(g[k][i]);
+            cnebb(solid, k, ux, uy, gg);
+            gm[k] = moments(gg);
+        } else {
+            gm[k] = moments(g[k]);
         }
     }
-    const T axx = T(1) + dphi[0], axy = dphi[1], ayy = T(1) + dphi[2];
-    const T txx = R.eta_over_lam * dphi[0], txy = R.eta_over_lam * dphi[1],
-            tyy = R.eta_over_lam * dphi[2];
-    T S[3];
+    const T d0 = gm[0].m0, d1 = gm[1].m0, d2 = gm[2].m0;
+    const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
+    const T txx = R.eta_over_lam * d0, txy = R.eta_over_lam * d1, tyy = R.eta_over_lam * d2;
+    T Sc[3];
     if (R.no_source) {
-        S[0] = S[1] = S[2] = T(0);
+        Sc[0] = Sc[1] = Sc[2] = 0.0;
     } else {
         const T d = Lxx + Lyy;
-        S[0] = -R.inv_lam * dphi[0] + T(2) * (axx * Lxx + axy * Lyx) + axx * d;
-        S[1] = -R.inv_lam * dphi[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
-        S[2] = -R.inv_lam * dphi[2] + T(2) * (axy * Lxy + ayy * Lyy) + ayy * d;
+        Sc[0] = -R.inv_lam * d0 + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
+        Sc[1] = -R.inv_lam * d1 + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
+        Sc[2] = -R.inv_lam * d2 + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
     }
-    if (first) {
-        hS[0] = S[0]; hS[1] = S[1]; hS[2] = S[2];
+    if (!pull) {  // first step: F~(t - 1) := F~(t)
+        hS[0] = Sc[0]; hS[1] = Sc[1]; hS[2] = Sc[2];
         hux = ux; huy = uy;
     }
 
+    // Periodic images: an edge node also writes the populations that leave the domain
+    // into the ghost slots its periodic neighbours pull from (no fill op needed).
+    const bool px_per = R.xmode == XM_PERIODIC, py_per = R.ymode == XM_PERIODIC;
+    const int gxo = (px_per && x == R.nx - 1) ? -R.nx : ((px_per && x == 0) ? R.nx : 0);
+    const int gyo = (py_per && y == R.ny - 1) ? -R.ny : ((py_per && y == 0) ? R.ny : 0);
+    const bool edge = (gxo | gyo) != 0;
+    // ghost slot of direction i for this node, or -1: a population moving in direction
+    // i leaves through the edge it points at
+    auto ghost = [&](int i) -> int {
+        const int sx = (gxo != 0 && ex(i) == (gxo < 0 ? 1 : -1)) ? gxo : 0;
+        const int sy = (gyo != 0 && ey(i) == (gyo < 0 ? 1 : -1)) ? gyo : 0;
+        if (sx == 0 && sy == 0) return -1;
+        return p + sx + sy * R.pitch;
+    };
+
     T out[9];
-    collide_hydro(R, f, drho, rho, ux, uy, Fx, Fy, txx, txy, tyy, Dx, Dy, out);
+    collide_hydro(R, moments(f), rho, ux, uy, Fx, Fy, txx, txy, tyy, Dx, Dy, out);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dst[i * plane + p] = out[i];
+    for (int i = 0; i < 9; ++i) st_stream<NT>(dst + i * plane, (unsigned)p, out[i]);
+    if (edge) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int gs = ghost(i);
+            if (gs >= 0) stu(dst + i * plane, (unsigned)gs, out[i]);
+        }
+    }
+    const T inv_rho = 1.0 / rho;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const T phi = phi0<T>(k) + dphi[k];
-        collide_cde(R, g[k], dphi[k], phi, ux, uy, phi / rho, Fx, Fy, S[k], hS[k], hux, huy, out);
+        const T phi = phi0(k) + gm[k].m0;
+        collide_cde(R, gm[k], phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], hS[k], hux, huy, out);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) dst[(9 + 9 * k + i) * plane + p] = out[i];
+        for (int i = 0; i < 9; ++i) st_stream<NT>(dst + (9 + 9 * k + i) * plane, (unsigned)p, out[i]);
+        if (edge) {
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int gs = ghost(i);
+                if (gs >= 0) stu(dst + (9 + 9 * k + i) * plane, (unsigned)gs, out[i]);
+            }
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) R.hist[k * plane + p] = S[k];
-    R.hist[3 * plane + p] = ux;
-    R.hist[4 * plane + p] = uy;
+    for (int k = 0; k < 3; ++k) st_stream<NT>(R.hist + k * plane, (unsigned)p, Sc[k]);
+    st_stream<NT>(R.hist + 3 * plane, (unsigned)p, ux);
+    st_stream<NT>(R.hist + 4 * plane, (unsigned)p, uy);
+}
+
+// Boundary links of the buffer just written: write into each ghost or solid slot the
+// value its fluid neighbour pulls in the next step.
+template <class S>
+__global__ __launch_bounds__(256) void k_fill(const RunDev<S>* __restrict__ runs,
+                                              const FillItem* __restrict__ items, int parity) {
+    const FillItem it = items[blockIdx.x];
+    if ((int)threadIdx.x >= it.count) return;
+    const RunDev<S>& R = runs[it.run];
+    const FillOp op = R.fill[it.first + threadIdx.x];
+    S* buf = R.pop[parity];
+    const long long plane = R.plane;
+    const int dir = op.dir_kind & 0xff, kind = op.dir_kind >> 8;
+    const int o = opp(dir);
+    if (kind == FILL_COPY) {
+#pragma unroll
+        for (int L = 0; L < 4; ++L) {
+            S* pl = buf + (9 * L + dir) * plane;
+            stu(pl, (unsigned)op.dst, ldu(pl, (unsigned)op.src));
+        }
+    } else if (kind == FILL_INLET) {
+        const int row = op.far;
+        const T uin = R.inlet[row];
+        stu(buf + dir * plane, (unsigned)op.dst, dfeq(dir, 0.0, 1.0, uin, 0.0));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T a = R.inlet[(1 + k) * R.ny + row];
+            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst, dgeq(dir, a - phi0(k), a, uin, 0.0));
+        }
+    } else {
+        // conformation lattices: the population that left toward the wall (CNEBB input)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
+                ldu(buf + (9 + 9 * k + o) * plane, (unsigned)op.src));
+        // hydrodynamic lattice: half-way or linear interpolated bounce-back
+        const T fo = ldu(buf + o * plane, (unsigned)op.src);
+        T v = fo;
+        if (kind == FILL_CURVED) {
+            const T q = op.q;
+            if (q < 0.5) {
+                if (op.far >= 0) v = 2.0 * q * fo + (1.0 - 2.0 * q) * ldu(buf + o * plane, (unsigned)op.far);
+            } else {
+                v = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * ldu(buf + dir * plane, (unsigned)op.src);
+            }
+        }
+        stu(buf + dir * plane, (unsigned)op.dst, v);
+    }
 }
 
 // Equilibrium initial state into buffer 0; history cleared.
-template <class T>
-__global__ void k_init(const RunDev<T>* __restrict__ run, const T* rho0, const T* ux0,
-                       const T* uy0, const T* a0, const T* a1, const T* a2) {
-    const RunDev<T>& R = *run;
+template <class S>
+__global__ void k_init(const RunDev<S>* __restrict__ run, const S* rho0, const S* ux0,
+                       const S* uy0, const S* a0, const S* a1, const S* a2) {
+    const RunDev<S>& R = *run;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= R.nx || y >= R.ny) return;
-    const int p = y * R.pitch + x;
+    const int p = node_index(R, x, y);
     const int q = y * R.nx + x;
     const long long plane = R.plane;
-    T* __restrict__ dst = R.pop[0];
-    const bool solid = R.has_bits && (R.bits[p] & BIT_SELF_SOLID);
-    const T r = rho0 ? rho0[q] : T(1);
-    const T vx = ux0 ? ux0[q] : T(0), vy = uy0 ? uy0[q] : T(0);
-    const T* a[3] = {a0, a1, a2};
+    S* dst = R.pop[0];
+    const bool solid = node_bits(R, p) & BIT_SELF_SOLID;
+    const T r = rho0 ? (T)rho0[q] : 1.0;
+    const T vx = ux0 ? (T)ux0[q] : 0.0, vy = uy0 ? (T)uy0[q] : 0.0;
+    const S* a[3] = {a0, a1, a2};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dst[i * plane + p] = solid ? T(0) : dfeq<T>(i, r - T(1), r, vx, vy);
+    for (int i = 0; i < 9; ++i) stu(dst + i * plane, (unsigned)p, solid ? 0.0 : dfeq(i, r - 1.0, r, vx, vy));
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const T phi = a[k] ? a[k][q] : phi0<T>(k);
+        const T phi = a[k] ? (T)a[k][q] : phi0(k);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            dst[(9 + 9 * k + i) * plane + p] = solid ? T(0) : dgeq<T>(i, phi - phi0<T>(k), phi, vx, vy);
+            stu(dst + (9 + 9 * k + i) * plane, (unsigned)p,
+                solid ? 0.0 : dgeq(i, phi - phi0(k), phi, vx, vy));
     }
 #pragma unroll
-    for (int c = 0; c < 5; ++c) R.hist[c * plane + p] = T(0);
+    for (int c = 0; c < 5; ++c) stu(R.hist + c * plane, (unsigned)p, 0.0);
 }
 
-// Macroscopic fields of node (x, y) at the current time; false for solid nodes.
-template <class T>
-__device__ __forceinline__ bool node_fields(const RunDev<T>& R, const T* __restrict__ src, int x,
-                                            int y, bool pull, T& rho, T& ux, T& uy, T a[3]) {
-    const int p = y * R.pitch + x;
-    const unsigned b = node_bits(R, p);
-    if (b & BIT_SELF_SOLID) return false;
-    Srcs s;
-    node_srcs(R, x, y, b, pull, s);
-    const int bi = (R.has_curved && s.solid) ? R.bidx[p] : -1;
-    T f[9];
-    load_hydro(R, src, x, y, s, bi, f);
+// Macroscopic fields of node (x, y) at the current time; false for solid nodes.  At a
+// wall-adjacent node phi is phi_b, which CNEBB keeps.
+template <class S>
+__device__ __forceinline__ bool node_fields(const RunDev<S>& R, const S* src, int x, int y,
+                                            bool pull, T& rho, T& ux, T& uy, T a[3]) {
+    const int p = node_index(R, x, y);
+    if (node_bits(R, p) & BIT_SELF_SOLID) return false;
+    S f[9];
+    pull9(R, src, 0, p, pull, f);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        T g[9];
-        load_cde(R, src, k, p, s, g);
-        T acc = T(0);
+        S g[9];
+        pull9(R, src, 1 + k, p, pull, g);
+        T acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) acc += g[i];
-        a[k] = phi0<T>(k) + acc;  // phi_b at boundary nodes (CNEBB keeps it)
+        for (int i = 0; i < 9; ++i) acc += T(g[i]);
+        a[k] = phi0(k) + acc;
     }
     return true;
 }
 
-template <class T>
-__global__ void k_read(const RunDev<T>* __restrict__ run, int parity, int first, T* rho_o,
-                       T* ux_o, T* uy_o, T* axx_o, T* axy_o, T* ayy_o) {
-    const RunDev<T>& R = *run;
+template <class S>
+__global__ void k_read(const RunDev<S>* __restrict__ run, int parity, int first, S* rho_o, S* ux_o,
+                       S* uy_o, S* axx_o, S* axy_o, S* ayy_o) {
+    const RunDev<S>& R = *run;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= R.nx || y >= R.ny) return;
     const int q = y * R.nx + x;
-    T r = T(0), vx = T(0), vy = T(0), a[3] = {T(0), T(0), T(0)};
-    if (!node_fields(R, R.pop[parity], x, y, first == 0, r, vx, vy, a)) {
-        r = T(0);
-    }
-    if (rho_o) rho_o[q] = r;
-    if (ux_o) ux_o[q] = vx;
-    if (uy_o) uy_o[q] = vy;
-    if (axx_o) axx_o[q] = a[0];
-    if (axy_o) axy_o[q] = a[1];
-    if (ayy_o) ayy_o[q] = a[2];
+    T r = 0.0, vx = 0.0, vy = 0.0, a[3] = {0.0, 0.0, 0.0};
+    if (!node_fields(R, R.pop[parity], x, y, first == 0, r, vx, vy, a)) r = 0.0;
+    if (rho_o) rho_o[q] = (S)r;
+    if (ux_o) ux_o[q] = (S)vx;
+    if (uy_o) uy_o[q] = (S)vy;
+    if (axx_o) axx_o[q] = (S)a[0];
+    if (axy_o) axy_o[q] = (S)a[1];
+    if (ayy_o) ayy_o[q] = (S)a[2];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -614,10 +631,10 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
 
 // Monitors: mass of each lattice (FP64), residual since the last snapshot, max |u|,
 // non-finite and non-SPD counts; wavefront shuffles then one atomic per wavefront.
-template <class T>
-__global__ __launch_bounds__(256) void k_monitor(const RunDev<T>* __restrict__ run, int parity,
-                                                 int first, T* usnap, MonitorAcc* acc) {
-    const RunDev<T>& R = *run;
+template <class S>
+__global__ __launch_bounds__(256) void k_monitor(const RunDev<S>* __restrict__ run, int parity,
+                                                 int first, S* usnap, MonitorAcc* acc) {
+    const RunDev<S>& R = *run;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     double m[4] = {0, 0, 0, 0}, res = 0, umax = 0, nf = 0, spd = 0;
@@ -625,22 +642,20 @@ __global__ __launch_bounds__(256) void k_monitor(const RunDev<T>* __restrict__ r
         T r, vx, vy, a[3];
         if (node_fields(R, R.pop[parity], x, y, first == 0, r, vx, vy, a)) {
             const int q = y * R.nx + x;
-            const double dr = (double)r, dx = (double)vx, dy = (double)vy;
-            const double ok = (isfinite(dr) && isfinite(dx) && isfinite(dy) &&
-                               isfinite((double)a[0]) && isfinite((double)a[1]) &&
-                               isfinite((double)a[2])) ? 1.0 : 0.0;
-            if (ok != 0.0) {
-                m[0] = dr; m[1] = (double)a[0]; m[2] = (double)a[1]; m[3] = (double)a[2];
-                const double ex_ = dx - (double)usnap[q], ey_ = dy - (double)usnap[R.nx * R.ny + q];
-                res = sqrt(ex_ * ex_ + ey_ * ey_);
-                umax = sqrt(dx * dx + dy * dy);
-                const double det = (double)a[0] * (double)a[2] - (double)a[1] * (double)a[1];
-                spd = (det <= 0.0 || (double)a[0] + (double)a[2] <= 0.0) ? 1.0 : 0.0;
+            const bool ok = isfinite(r) && isfinite(vx) && isfinite(vy) && isfinite(a[0]) &&
+                            isfinite(a[1]) && isfinite(a[2]);
+            if (ok) {
+                m[0] = r; m[1] = a[0]; m[2] = a[1]; m[3] = a[2];
+                const double dx = vx - (double)usnap[q], dy = vy - (double)usnap[R.nx * R.ny + q];
+                res = sqrt(dx * dx + dy * dy);
+                umax = sqrt(vx * vx + vy * vy);
+                const double det = a[0] * a[2] - a[1] * a[1];
+                spd = (det <= 0.0 || a[0] + a[2] <= 0.0) ? 1.0 : 0.0;
             } else {
                 nf = 1.0;
             }
-            usnap[q] = vx;
-            usnap[R.nx * R.ny + q] = vy;
+            usnap[q] = (S)vx;
+            usnap[R.nx * R.ny + q] = (S)vy;
         }
     }
     for (int c = 0; c < 4; ++c) m[c] = wave_sum(m[c]);
@@ -675,41 +690,56 @@ __global__ void k_write_words(unsigned long long* dst, unsigned long long w0,
 
 }  // namespace
 
-template <class T>
-hipError_t launch_step(const RunDev<T>* runs_dev, const Item* items_dev, int nitems, int ty,
-                       int parity, int first, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
+template <class S, bool NT>
+hipError_t launch_step_nt(const RunDev<S>* runs_dev, const Item* items_dev, int nitems, int ty,
+                          int parity, int first, hipStream_t s) {
     switch (ty) {
-        case 1: hipLaunchKernelGGL((k_step<T, 1>), dim3(nitems), dim3(64, 1), 0, s, runs_dev, items_dev, parity, first); break;
-        case 2: hipLaunchKernelGGL((k_step<T, 2>), dim3(nitems), dim3(64, 2), 0, s, runs_dev, items_dev, parity, first); break;
-        case 4: hipLaunchKernelGGL((k_step<T, 4>), dim3(nitems), dim3(64, 4), 0, s, runs_dev, items_dev, parity, first); break;
-        case 8: hipLaunchKernelGGL((k_step<T, 8>), dim3(nitems), dim3(64, 8), 0, s, runs_dev, items_dev, parity, first); break;
+        case 1: hipLaunchKernelGGL((k_step<S, 1, NT>), dim3(nitems), dim3(64, 1), 0, s, runs_dev, items_dev, parity, first); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2, NT>), dim3(nitems), dim3(64, 2), 0, s, runs_dev, items_dev, parity, first); break;
+        case 4: hipLaunchKernelGGL((k_step<S, 4, NT>), dim3(nitems), dim3(64, 4), 0, s, runs_dev, items_dev, parity, first); break;
+        case 8: hipLaunchKernelGGL((k_step<S, 8, NT>), dim3(nitems), dim3(64, 8), 0, s, runs_dev, items_dev, parity, first); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_init(const RunDev<T>& h, const RunDev<T>* d, const T* rho, const T* ux,
-                       const T* uy, const T* axx, const T* axy, const T* ayy, hipStream_t s) {
-    dim3 blk(64, 4), grd((h.nx + 63) / 64, (h.ny + 3) / 4);
-    hipLaunchKernelGGL((k_init<T>), grd, blk, 0, s, d, rho, ux, uy, axx, axy, ayy);
+template <class S>
+hipError_t launch_step(const RunDev<S>* runs_dev, const Item* items_dev, int nitems, int ty,
+                       int parity, int first, int streaming, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    return streaming ? launch_step_nt<S, true>(runs_dev, items_dev, nitems, ty, parity, first, s)
+                     : launch_step_nt<S, false>(runs_dev, items_dev, nitems, ty, parity, first, s);
+}
+
+template <class S>
+hipError_t launch_fill(const RunDev<S>* runs_dev, const FillItem* items_dev, int nitems, int parity,
+                       hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill<S>), dim3(nitems), dim3(256), 0, s, runs_dev, items_dev, parity);
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_read(const RunDev<T>& h, const RunDev<T>* d, int parity, int first, T* rho,
-                       T* ux, T* uy, T* axx, T* axy, T* ayy, hipStream_t s) {
+template <class S>
+hipError_t launch_init(const RunDev<S>& h, const RunDev<S>* d, const S* rho, const S* ux,
+                       const S* uy, const S* axx, const S* axy, const S* ayy, hipStream_t s) {
     dim3 blk(64, 4), grd((h.nx + 63) / 64, (h.ny + 3) / 4);
-    hipLaunchKernelGGL((k_read<T>), grd, blk, 0, s, d, parity, first, rho, ux, uy, axx, axy, ayy);
+    hipLaunchKernelGGL((k_init<S>), grd, blk, 0, s, d, rho, ux, uy, axx, axy, ayy);
     return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_monitor(const RunDev<T>& h, const RunDev<T>* d, int parity, int first,
-                          T* usnap, MonitorAcc* acc, hipStream_t s) {
+template <class S>
+hipError_t launch_read(const RunDev<S>& h, const RunDev<S>* d, int parity, int first, S* rho,
+                       S* ux, S* uy, S* axx, S* axy, S* ayy, hipStream_t s) {
+    dim3 blk(64, 4), grd((h.nx + 63) / 64, (h.ny + 3) / 4);
+    hipLaunchKernelGGL((k_read<S>), grd, blk, 0, s, d, parity, first, rho, ux, uy, axx, axy, ayy);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_monitor(const RunDev<S>& h, const RunDev<S>* d, int parity, int first,
+                          S* usnap, MonitorAcc* acc, hipStream_t s) {
     dim3 blk(256), grd((h.nx + 63) / 64, (h.ny + 3) / 4);
-    hipLaunchKernelGGL((k_monitor<T>), grd, blk, 0, s, d, parity, first, usnap, acc);
+    hipLaunchKernelGGL((k_monitor<S>), grd, blk, 0, s, d, parity, first, usnap, acc);
     return hipGetLastError();
 }
 
@@ -727,16 +757,18 @@ hipError_t launch_write_words(unsigned long long* dst, unsigned long long w0,
     return hipGetLastError();
 }
 
-#define VLB_INSTANTIATE(T)                                                                   \
-    template hipError_t launch_step<T>(const RunDev<T>*, const Item*, int, int, int, int,  \
+#define VLB_INSTANTIATE(S)                                                                   \
+    template hipError_t launch_step<S>(const RunDev<S>*, const Item*, int, int, int, int,  \
+                                       int, hipStream_t);                                  \
+    template hipError_t launch_fill<S>(const RunDev<S>*, const FillItem*, int, int,        \
                                        hipStream_t);                                       \
-    template hipError_t launch_init<T>(const RunDev<T>&, const RunDev<T>*, const T*,       \
-                                       const T*, const T*, const T*, const T*, const T*,  \
+    template hipError_t launch_init<S>(const RunDev<S>&, const RunDev<S>*, const S*,       \
+                                       const S*, const S*, const S*, const S*, const S*,  \
                                        hipStream_t);                                       \
-    template hipError_t launch_read<T>(const RunDev<T>&, const RunDev<T>*, int, int, T*,   \
-                                       T*, T*, T*, T*, T*, hipStream_t);                   \
-    template hipError_t launch_monitor<T>(const RunDev<T>&, const RunDev<T>*, int, int,    \
-                                          T*, MonitorAcc*, hipStream_t);
+    template hipError_t launch_read<S>(const RunDev<S>&, const RunDev<S>*, int, int, S*,   \
+                                       S*, S*, S*, S*, S*, hipStream_t);                   \
+    template hipError_t launch_monitor<S>(const RunDev<S>&, const RunDev<S>*, int, int,    \
+                                          S*, MonitorAcc*, hipStream_t);
 VLB_INSTANTIATE(float)
 VLB_INSTANTIATE(double)
 

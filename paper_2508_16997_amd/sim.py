@@ -198,6 +198,10 @@ class Simulation:
     def set_tile(self, ty: int):
         L.check(self.lib.vlb_set_tile(self._h, int(ty)), "vlb_set_tile")
 
+    def set_store_mode(self, mode: int):
+        """0 automatic, 1 cached, 2 non-temporal stores of the post-collision state."""
+        L.check(self.lib.vlb_set_store_mode(self._h, int(mode)), "vlb_set_store_mode")
+
     def set_graph_chunk(self, chunk: int):
         L.check(self.lib.vlb_set_graph_chunk(self._h, int(chunk)), "vlb_set_graph_chunk")
 

@@ -94,11 +94,41 @@ def test_four_roll_fp32_128():
 
 
 def test_four_roll_fp32_512_full_size():
-    """Four-roll mill at its full 512^2 size in the benchmark's launch configuration."""
-    pr = synth.four_roll_mill(N=512, steps=200)
+    """Four-roll mill at its full 512^2 size in the benchmark's launch configuration.
+
+    600 steps: A_xy starts at zero and grows quadratically (the four-roll shear terms
+    cancel), so earlier its relative error is dominated by FP32 storage noise of a field
+    of rms ~1e-5; the other fields agree to ~1e-8 at any time.
+    """
+    pr = synth.four_roll_mill(N=512, steps=600)
     say("four-roll fp32 512", pr.steps)
-    g, o = run_pair(pr, pr.steps, sim_kw=dict(graph_chunk=16))
+    g, o = run_pair(pr, pr.steps, sim_kw=dict(graph_chunk=50, tile=4))
     err = parity(g, o, pr.fluid_mask())
+    assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
+
+
+def test_four_roll_fp32_512_20k_steps_golden():
+    """Full workload: 512^2 four-roll mill, FP32 storage, 20k steps (the stated steps).
+
+    Compared on a stride-8 sample against oracle fields written by
+    tests/golden/make_four_roll_512.py (oracle only).
+    """
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "four_roll_512_20k.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    ref = np.load(path)
+    stride = int(ref["stride"])
+    pr = synth.four_roll_mill(N=512, steps=int(ref["steps"]))
+    say("four-roll fp32 512 golden", pr.steps)
+    from paper_2508_16997_amd import Simulation
+
+    sim = Simulation.from_problem(pr, graph_chunk=50, tile=4)
+    sim.step(pr.steps)
+    g = {k: v[::stride, ::stride] for k, v in gpu_fields(sim).items()}
+    o = {k: ref[k] for k in FIELDS}
+    err = parity(g, o, np.ones_like(g["ux"], dtype=bool))
     assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
 
 
