@@ -54,6 +54,27 @@ def bytes_per_node(pr, esz):
     return b
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes (GB/s)."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    return 2.0 * nbytes / s / 1e9
+
+
 def cpu_baseline(pr, seconds):
     import oracle
 
@@ -90,6 +111,8 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -100,6 +123,10 @@ def main():
         return 2
 
     import torch
+
+    if args.copy_only:
+        print(json.dumps({"copy_GBs": round(copy_bandwidth(), 1), "bytes": 2 * (1 << 30)}))
+        return 0
 
     from paper_2508_16997_amd import Simulation
 
@@ -127,6 +154,7 @@ def main():
     if mon["nonfinite"]:
         print("non-finite fields after the timed steps", file=sys.stderr)
         return 3
+    copy_gbs = copy_bandwidth()
 
     mlups = nodes * args.steps / wall / 1e6
     bpn = bytes_per_node(pr, esz)
@@ -144,16 +172,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64",
+        "dtype": "f64",  # arithmetic type; storage below
+
         "data": "synthetic",
-        "config": {"workload": desc, "nx": pr.nx, "ny": pr.ny, "fluid_nodes": nodes,
+        "config": {"workload": desc, "storage": "f32" if prec == "fp32" else "f64",
+                   "nx": pr.nx, "ny": pr.ny, "fluid_nodes": nodes,
                    "bytes_per_node": bpn, "tile": f"64x{args.tile}",
                    "graph_chunk_steps": 2 * args.graph_chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "kernel": "k_step",
                      "avg_launch_us": round(launch_s * 1e6, 3),
-                     "bytes_per_launch": bytes_launch},
+                     "bytes_per_launch": bytes_launch,
+                     "copy_ceiling_GBs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
