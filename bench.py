@@ -75,6 +75,46 @@ def copy_bandwidth(nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / s / 1e9
 
 
+def batched_leg(steps, warmup, tile, chunk):
+    """Batched workload (256 uneven runs, one launch per step) vs the same runs one by one.
+
+    Both legs run the same simulations on the same stream with hipGraph replay; the
+    sequential leg steps each run alone for the same number of steps, back to back.
+    """
+    import torch
+    import synth
+    from paper_2508_16997_amd import Batch, Simulation
+
+    runs = synth.batch_c4()
+    stream = torch.cuda.Stream()
+    sims = [Simulation.from_problem(r, stream=stream, tile=tile, graph_chunk=chunk) for r in runs]
+    nodes = sum(int(r.fluid_mask().sum()) for r in runs)
+    b = Batch(sims, tile=tile, graph_chunk=chunk)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for s in sims:  # warm the per-run graphs
+        s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    bad = sum(s.monitors(raise_on_nonfinite=False)["nonfinite"] > 0 for s in sims)
+    b.close()
+    for s in sims:
+        s.close()
+    return {"runs": len(runs), "nodes": nodes, "steps": steps,
+            "batched_MLUPS": round(nodes * steps / t_batch / 1e6, 2),
+            "sequential_MLUPS": round(nodes * steps / t_seq / 1e6, 2),
+            "batched_vs_sequential": round(t_seq / t_batch, 3),
+            "runs_nonfinite": int(bad)}
+
+
 def cpu_baseline(pr, seconds):
     import oracle
 
@@ -111,6 +151,9 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-sequential leg (256 uneven runs)")
+    ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -187,6 +230,10 @@ def main():
                      "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
+    if not args.no_batched:
+        sim.close()
+        out["batched"] = batched_leg(args.batched_steps, 2 * args.graph_chunk + 1, args.tile,
+                                     args.graph_chunk)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -184,6 +184,34 @@ int vlb_set_store_mode(vlb_sim* sim, int mode);
 /* Use hipGraph replay for runs of nsteps >= 2 * chunk (chunk 0 disables graphs). */
 int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
 
+/* ---- batches ----------------------------------------------------------------------- */
+
+/* Many independent simulations of one precision (uneven sizes, parameters, boundary
+ * kinds) advanced together: one step launch and one boundary launch per time step
+ * cover every member's tiles (a concatenated, XCD-ordered tile list), replayed from a
+ * hipGraph.  This is the batched form of the coupled step of Sec. 3 (Eqs. 31-51); each
+ * member computes exactly what vlb_step computes for it, bit for bit.
+ *
+ * sims: n >= 1 handles, all bound, parameterised and initialised, of one precision, on
+ * one stream and at the same step; the caller keeps them alive until the batch is
+ * destroyed and may read them (vlb_read_fields, vlb_monitors, ...) between batch steps.
+ * ty: tile height 1, 2, 4 or 8 for the batch's launches.  workspace_dev: device
+ * memory of at least vlb_batch_workspace_bytes, 256-byte aligned, owned by the
+ * caller, holding the work lists and member descriptors.  A member's new parameters,
+ * force field or inlet are picked up at the next vlb_batch_step.  Errors:
+ * VLB_E_INVALID_ARG (null/mixed members, bad ty), VLB_E_STATE (member not ready,
+ * steps differ, or a member was stepped or reloaded outside the batch),
+ * VLB_E_WORKSPACE, VLB_E_HIP. */
+typedef struct vlb_batch vlb_batch;
+int vlb_batch_workspace_bytes(vlb_sim* const* sims, int n, int ty, size_t* bytes);
+int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* workspace_dev, size_t bytes,
+                     vlb_batch** out);
+/* Advances every member nsteps steps (async on the shared stream). */
+int vlb_batch_step(vlb_batch* batch, int64_t nsteps);
+/* hipGraph replay in chunks of 2 * chunk steps (0 disables). */
+int vlb_batch_set_graph_chunk(vlb_batch* batch, int chunk);
+void vlb_batch_destroy(vlb_batch* batch);
+
 /* ---- errors ------------------------------------------------------------------------ */
 const char* vlb_error_string(int status);
 const char* vlb_last_error_detail(void);

@@ -30,7 +30,9 @@ EXPORTS = [
     "vlb_set_params", "vlb_set_force_field", "vlb_set_inlet", "vlb_init_equilibrium",
     "vlb_step", "vlb_get_step", "vlb_read_fields", "vlb_read_history", "vlb_monitors",
     "vlb_state_bytes", "vlb_save_state", "vlb_load_state", "vlb_set_tile",
-    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_error_string", "vlb_last_error_detail",
+    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_batch_workspace_bytes",
+    "vlb_batch_create", "vlb_batch_step", "vlb_batch_set_graph_chunk", "vlb_batch_destroy",
+    "vlb_error_string", "vlb_last_error_detail",
 ]
 
 
@@ -92,12 +94,19 @@ def load():
     lib.vlb_set_tile.argtypes = [P, I]
     lib.vlb_set_graph_chunk.argtypes = [P, I]
     lib.vlb_set_store_mode.argtypes = [P, I]
+    lib.vlb_batch_workspace_bytes.argtypes = [P, I, I, C.POINTER(C.c_size_t)]
+    lib.vlb_batch_create.argtypes = [P, I, I, P, C.c_size_t, C.POINTER(P)]
+    lib.vlb_batch_step.argtypes = [P, C.c_int64]
+    lib.vlb_batch_set_graph_chunk.argtypes = [P, I]
+    lib.vlb_batch_destroy.argtypes = [P]
+    lib.vlb_batch_destroy.restype = None
     lib.vlb_error_string.argtypes = [I]
     lib.vlb_error_string.restype = C.c_char_p
     lib.vlb_last_error_detail.argtypes = []
     lib.vlb_last_error_detail.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("vlb_destroy", "vlb_error_string", "vlb_last_error_detail"):
+        if name not in ("vlb_destroy", "vlb_batch_destroy", "vlb_error_string",
+                        "vlb_last_error_detail"):
             getattr(lib, name).restype = I
     _lib = lib
     return lib

@@ -85,12 +85,30 @@ struct vlb_sim {
     int parity = 0, first = 1;
     int64_t step = 0;
 
+    uint64_t version = 0;  // bumped whenever the device descriptor is rewritten
     int graph_chunk = 0;
     int store_mode = 0;  // 0 auto (by working-set size), 1 cached stores, 2 streaming stores
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 
     template <class T>
     T* dptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+// A batch: many bound simulations of one precision advanced by one step launch and one
+// fill launch per time step over the concatenated work lists.
+struct vlb_batch {
+    std::vector<vlb_sim*> sims;
+    int prec = 0, ty = 4, streaming = 0;
+    char* ws = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    size_t off_runs = 0, off_items = 0, off_fill_items = 0, total = 0;
+    std::vector<vlb::Item> items;
+    std::vector<vlb::FillItem> fill_items;
+    int graph_chunk = 0;
+    int64_t step = 0;  // step count of every member, as advanced by the batch
+    std::vector<uint64_t> versions;  // member descriptor versions last copied
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -355,6 +373,7 @@ __global__ void k_store_run(Run<T> v, Run<T>* dst) {
 }
 
 int upload_run(vlb_sim* s) {
+    ++s->version;
     if (s->prec == VLB_FP32) {
         hipLaunchKernelGGL((k_store_run<float>), dim3(1), dim3(64), 0, s->stream, make_run<float>(s),
                            s->dptr<Run<float>>(s->off_run));
@@ -815,6 +834,226 @@ int vlb_set_tile(vlb_sim* s, int ty) {
     drop_graphs(s);
     if (s->bound) return upload_items(s);
     return VLB_OK;
+}
+
+}  // extern "C"
+
+// ---- batches --------------------------------------------------------------------
+
+namespace {
+
+void batch_layout(vlb_batch* b) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + bytes); return r; };
+    const size_t rsz = b->prec == VLB_FP32 ? sizeof(Run<float>) : sizeof(Run<double>);
+    b->off_runs = take(b->sims.size() * rsz);
+    b->off_items = take(std::max<size_t>(1, b->items.size()) * sizeof(vlb::Item));
+    b->off_fill_items = take(std::max<size_t>(1, b->fill_items.size()) * sizeof(vlb::FillItem));
+    b->total = o;
+}
+
+int batch_lists(vlb_batch* b, vlb_sim* const* sims, int n, int ty) {
+    if (!sims || n < 1) return fail(VLB_E_INVALID_ARG, "batch needs at least one simulation");
+    if (ty != 1 && ty != 2 && ty != 4 && ty != 8) return fail(VLB_E_INVALID_ARG, "ty must be 1, 2, 4 or 8");
+    b->sims.assign(sims, sims + n);
+    b->ty = ty;
+    b->prec = sims[0]->prec;
+    double state_bytes = 0;
+    std::vector<vlb::Item> tiles;
+    for (int r = 0; r < n; ++r) {
+        const vlb_sim* s = sims[r];
+        if (!s) return fail(VLB_E_INVALID_ARG, "null simulation in batch");
+        if (s->prec != b->prec) return fail(VLB_E_INVALID_ARG, "batch mixes precisions");
+        const int ntx = (s->nx + 63) / 64, nty = (s->ny + ty - 1) / ty;
+        for (int t = 0; t < ntx * nty; ++t) tiles.push_back(vlb::Item{r, t % ntx, t / ntx, 0});
+        for (const vlb::FillItem& fi : s->fill_items)
+            b->fill_items.push_back(vlb::FillItem{r, fi.first, fi.count, 0});
+        state_bytes += 2.0 * 36.0 * (double)s->nx * (double)s->ny * (double)s->esz;
+    }
+    // XCD-aware order over the concatenated tiles (as for a single run)
+    const int nt = (int)tiles.size(), nxcd = 8;
+    std::vector<int> start(nxcd + 1, 0);
+    for (int k = 0; k < nxcd; ++k) start[k + 1] = start[k] + nt / nxcd + (k < nt % nxcd ? 1 : 0);
+    b->items.resize(nt);
+    for (int i = 0; i < nt; ++i) b->items[i] = tiles[start[i % nxcd] + i / nxcd];
+    b->streaming = state_bytes > 192.0 * 1024 * 1024 ? 1 : 0;
+    batch_layout(b);
+    return VLB_OK;
+}
+
+// Copies member r's descriptor into the batch's array, ordered on the shared stream.
+template <class T>
+int batch_store_run(vlb_batch* b, int r) {
+    Run<T>* dst = reinterpret_cast<Run<T>*>(b->ws + b->off_runs) + r;
+    hipLaunchKernelGGL((k_store_run<T>), dim3(1), dim3(64), 0, b->stream, make_run<T>(b->sims[r]), dst);
+    VLB_HIP(hipGetLastError());
+    b->versions[r] = b->sims[r]->version;
+    return VLB_OK;
+}
+
+template <class T>
+int batch_upload(vlb_batch* b) {
+    b->versions.assign(b->sims.size(), 0);
+    for (int r = 0; r < (int)b->sims.size(); ++r) {
+        int rc = batch_store_run<T>(b, r);
+        if (rc) return rc;
+    }
+    VLB_HIP(hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(vlb::Item),
+                           hipMemcpyHostToDevice, b->stream));
+    if (!b->fill_items.empty())
+        VLB_HIP(hipMemcpyAsync(b->ws + b->off_fill_items, b->fill_items.data(),
+                               b->fill_items.size() * sizeof(vlb::FillItem), hipMemcpyHostToDevice,
+                               b->stream));
+    VLB_HIP(hipStreamSynchronize(b->stream));
+    return VLB_OK;
+}
+
+// Re-copies the descriptors of members whose parameters, force or inlet changed.
+template <class T>
+int batch_refresh(vlb_batch* b) {
+    for (int r = 0; r < (int)b->sims.size(); ++r)
+        if (b->versions[r] != b->sims[r]->version) {
+            int rc = batch_store_run<T>(b, r);
+            if (rc) return rc;
+        }
+    return VLB_OK;
+}
+
+void batch_drop_graphs(vlb_batch* b) {
+    for (auto& g : b->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+template <class T>
+int batch_launch(vlb_batch* b, int par, int first) {
+    const Run<T>* rd = reinterpret_cast<const Run<T>*>(b->ws + b->off_runs);
+    const vlb::Item* it = reinterpret_cast<const vlb::Item*>(b->ws + b->off_items);
+    const vlb::FillItem* fi = reinterpret_cast<const vlb::FillItem*>(b->ws + b->off_fill_items);
+    VLB_HIP(vlb::launch_step<T>(rd, it, (int)b->items.size(), b->ty, par, first, b->streaming, b->stream));
+    VLB_HIP(vlb::launch_fill<T>(rd, fi, (int)b->fill_items.size(), par ^ 1, b->stream));
+    return VLB_OK;
+}
+
+template <class T>
+int batch_step(vlb_batch* b, int64_t n) {
+    int rc0 = batch_refresh<T>(b);
+    if (rc0) return rc0;
+    vlb_sim* s0 = b->sims[0];
+    auto advance = [&](int64_t k) {
+        b->step += k;
+        for (vlb_sim* s : b->sims) {
+            s->step += k;
+            if (k % 2) s->parity ^= 1;
+            if (k > 0) s->first = 0;
+        }
+    };
+    if (s0->first && n > 0) {
+        int rc = batch_launch<T>(b, s0->parity, 1);
+        if (rc) return rc;
+        advance(1);
+        --n;
+    }
+    if (b->graph_chunk > 0 && b->stream != nullptr) {
+        const int64_t per = 2 * (int64_t)b->graph_chunk;
+        while (n >= per) {
+            const int par = s0->parity;
+            if (!b->graph[par]) {
+                hipGraph_t g = nullptr;
+                VLB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                int rc = VLB_OK;
+                int p = par;
+                for (int k = 0; k < per && rc == VLB_OK; ++k) {
+                    rc = batch_launch<T>(b, p, 0);
+                    p ^= 1;
+                }
+                hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+                if (rc || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc ? rc : fail(VLB_E_HIP, std::string("batch graph capture: ") + hipGetErrorString(e2));
+                }
+                hipError_t e3 = hipGraphInstantiate(&b->graph[par], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e3 != hipSuccess) return fail(VLB_E_HIP, std::string("batch graph: ") + hipGetErrorString(e3));
+            }
+            VLB_HIP(hipGraphLaunch(b->graph[par], b->stream));
+            advance(per);
+            n -= per;
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = batch_launch<T>(b, s0->parity, 0);
+        if (rc) return rc;
+        advance(1);
+    }
+    return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vlb_batch_workspace_bytes(vlb_sim* const* sims, int n, int ty, size_t* bytes) {
+    if (!bytes) return fail(VLB_E_INVALID_ARG, "null output");
+    vlb_batch tmp;
+    int rc = batch_lists(&tmp, sims, n, ty);
+    if (rc) return rc;
+    *bytes = tmp.total;
+    return VLB_OK;
+}
+
+int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* ws, size_t bytes, vlb_batch** out) {
+    if (!out) return fail(VLB_E_INVALID_ARG, "null output");
+    *out = nullptr;
+    vlb_batch* b = new (std::nothrow) vlb_batch();
+    if (!b) return fail(VLB_E_INVALID_ARG, "out of host memory");
+    int rc = batch_lists(b, sims, n, ty);
+    if (rc) { delete b; return rc; }
+    for (vlb_sim* s : b->sims) {
+        rc = check_ready(s);
+        if (rc) { delete b; return rc; }
+        if (s->stream != sims[0]->stream) { delete b; return fail(VLB_E_INVALID_ARG, "batch members must share one stream"); }
+        if (s->step != sims[0]->step || s->parity != sims[0]->parity || s->first != sims[0]->first) {
+            delete b;
+            return fail(VLB_E_STATE, "batch members must be at the same step");
+        }
+    }
+    if (!ws || ((uintptr_t)ws & 255u) || bytes < b->total) {
+        delete b;
+        return fail(VLB_E_WORKSPACE, "batch workspace missing, misaligned or smaller than " +
+                                         std::to_string(b->total) + " bytes");
+    }
+    b->ws = static_cast<char*>(ws);
+    b->bytes = bytes;
+    b->stream = sims[0]->stream;
+    b->step = sims[0]->step;
+    rc = b->prec == VLB_FP32 ? batch_upload<float>(b) : batch_upload<double>(b);
+    if (rc) { delete b; return rc; }
+    *out = b;
+    return VLB_OK;
+}
+
+int vlb_batch_step(vlb_batch* b, int64_t n) {
+    if (!b) return fail(VLB_E_INVALID_ARG, "null batch");
+    if (n < 0) return fail(VLB_E_INVALID_ARG, "negative step count");
+    for (vlb_sim* s : b->sims)
+        if (s->step != b->step || s->parity != b->sims[0]->parity || s->first != b->sims[0]->first)
+            return fail(VLB_E_STATE, "batch member was stepped or reloaded outside the batch");
+    return b->prec == VLB_FP32 ? batch_step<float>(b, n) : batch_step<double>(b, n);
+}
+
+int vlb_batch_set_graph_chunk(vlb_batch* b, int chunk) {
+    if (!b || chunk < 0 || chunk > 4096) return fail(VLB_E_INVALID_ARG, "chunk out of range");
+    batch_drop_graphs(b);
+    b->graph_chunk = chunk;
+    return VLB_OK;
+}
+
+void vlb_batch_destroy(vlb_batch* b) {
+    if (!b) return;
+    batch_drop_graphs(b);
+    delete b;
 }
 
 int vlb_set_store_mode(vlb_sim* s, int mode) {

@@ -218,6 +218,56 @@ class Simulation:
             pass
 
 
+class Batch:
+    """Many simulations advanced together by one step and one boundary launch per step.
+
+    The members must share one stream, one precision and one step count and be fully
+    set up (parameters, force, inlet, initial state) before the batch is made; the batch
+    takes their descriptors at creation.  Each member stays readable through its own
+    :class:`Simulation` methods.
+    """
+
+    def __init__(self, sims, tile: int = 4, graph_chunk: int = 0):
+        self.lib = L.load()
+        self.sims = list(sims)
+        if not self.sims:
+            raise ValueError("a batch needs at least one simulation")
+        self.stream = self.sims[0].stream
+        self.device = self.sims[0].device
+        arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        nbytes = C.c_size_t()
+        L.check(self.lib.vlb_batch_workspace_bytes(arr, len(self.sims), int(tile),
+                                                   C.byref(nbytes)), "vlb_batch_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        h = C.c_void_p()
+        self.sims[0]._order_after_torch()
+        L.check(self.lib.vlb_batch_create(arr, len(self.sims), int(tile), C.c_void_p(ptr),
+                                          self.workspace_bytes, C.byref(h)), "vlb_batch_create")
+        self._h = h
+        if graph_chunk:
+            L.check(self.lib.vlb_batch_set_graph_chunk(h, int(graph_chunk)),
+                    "vlb_batch_set_graph_chunk")
+
+    def step(self, n: int = 1):
+        self.sims[0]._order_after_torch()
+        L.check(self.lib.vlb_batch_step(self._h, int(n)), "vlb_batch_step")
+        self.sims[0]._order_before_torch()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.stream.synchronize()
+            self.lib.vlb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def host_geometry(nx, ny, xmode="periodic", ymode="periodic", solid=None, circles=()):
     """Node classes and boundary links from the library's host builder (no GPU needed)."""
     lib = L.load()

@@ -1,0 +1,201 @@
+"""Batched form: many runs advanced by one step launch and one boundary launch per step.
+
+Every batched run must be bit-identical to the same run stepped alone (the kernels are
+the same; only the work list differs), and a sample of runs is checked against the FP64
+oracle at the FP32 bar (relative L2 <= 1e-5).  The run set follows the batched workload:
+half Poiseuille channels, half four-roll mills, side N ~ U{32..512}, Wi = 10^U(-1, 2),
+beta ~ U(0.1, 0.9), all drawn from one seeded generator.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import FIELDS, gpu_fields, parity, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+
+    oracle.build(force=False)
+    oracle.set_threads(min(16, oracle.max_threads()))
+
+
+def _mixed_set(precision):
+    """Small uneven runs of every boundary kind the step supports."""
+    mask = np.zeros((37, 70), np.uint8)
+    mask[10:15, 20:24] = 1
+    runs = [r.with_(precision=precision)
+            for r in synth.batch_c4(seed=5, nruns=8, steps=0, nmin=20, nmax=140)]
+    runs += [
+        synth.random_periodic(40, 24, seed=1, precision=precision),
+        synth.random_periodic(70, 37, seed=2, ymode="wall", solid=mask, precision=precision),
+        synth.random_periodic(90, 30, seed=3, xmode="wall", circles=[(45.0, 15.0, 6.7)],
+                              precision=precision),
+        synth.random_periodic(130, 33, seed=4, xmode="open", ymode="wall",
+                              circles=[(50.0, 16.0, 7.2)], precision=precision),
+    ]
+    return runs
+
+
+def _make(runs, stream, **kw):
+    from paper_2508_16997_amd import Simulation
+
+    return [Simulation.from_problem(r, stream=stream, **kw) for r in runs]
+
+
+def _read_exact(sim):
+    import torch
+
+    r = sim.read()
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("ty,chunk", [(4, 20), (2, 0)])
+def test_batch_bit_identical_to_single(precision, ty, chunk):
+    import torch
+    from paper_2508_16997_amd import Batch
+
+    runs = _mixed_set(precision)
+    stream = torch.cuda.Stream()
+    say("batch bit-identity", precision, "ty", ty, "chunk", chunk, "runs", len(runs))
+    batched = _make(runs, stream)
+    single = _make(runs, stream)
+    b = Batch(batched, tile=ty, graph_chunk=chunk)
+    for n in (1, 129):  # first step, then graph replays and an eager tail
+        b.step(n)
+        for s in single:
+            s.step(n)
+    stream.synchronize()
+    for r, sb, ss in zip(runs, batched, single):
+        assert sb.time == ss.time == 130
+        gb, gs = _read_exact(sb), _read_exact(ss)
+        for k in FIELDS:
+            assert np.array_equal(gb[k], gs[k]), (r.name, k)
+        hb, hs = sb.history(), ss.history()
+        for k in hb:
+            assert torch.equal(hb[k], hs[k]), (r.name, "history", k)
+    b.close()
+    for s in batched + single:
+        s.close()
+
+
+def test_batch_oracle_sample():
+    """Eight runs of the full-size batched set (Wi <= 10) against the oracle."""
+    import torch
+    import oracle
+    from paper_2508_16997_amd import Batch
+
+    runs = synth.batch_c4()
+    pick = [i for i, r in enumerate(runs) if r.meta["Wi"] <= 10.0]
+    rng = np.random.default_rng(7)
+    pick = sorted(rng.choice(pick, size=8, replace=False).tolist())
+    sample = [runs[i] for i in pick]
+    stream = torch.cuda.Stream()
+    say("batch oracle sample", pick, [r.nx for r in sample])
+    sims = _make(sample, stream)
+    b = Batch(sims, graph_chunk=50)
+    steps = 500
+    b.step(steps)
+    stream.synchronize()
+    for i, r, s in zip(pick, sample, sims):
+        o = oracle.OracleSim(r)
+        o.step(steps)
+        err = parity(gpu_fields(s), o.read(), r.fluid_mask())
+        assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, (i, r.name, err)
+    b.close()
+    for s in sims:
+        s.close()
+
+
+def test_batch_full_set_bit_identical():
+    """All 256 runs of the batched workload at full size, 20 steps, batched vs alone."""
+    import torch
+    from paper_2508_16997_amd import Batch
+
+    runs = synth.batch_c4()
+    stream = torch.cuda.Stream()
+    say("batch full set", len(runs), "runs", sum(r.nx * r.ny for r in runs), "nodes")
+    batched = _make(runs, stream)
+    b = Batch(batched, graph_chunk=5)
+    b.step(21)
+    stream.synchronize()
+    for r, sb in zip(runs, batched):
+        ss = _make([r], stream)[0]
+        ss.step(21)
+        gb, gs = _read_exact(sb), _read_exact(ss)
+        for k in FIELDS:
+            assert np.array_equal(gb[k], gs[k]), (r.name, k)
+        assert np.isfinite(gb["ux"]).all(), r.name
+        ss.close()
+    b.close()
+    for s in batched:
+        s.close()
+
+
+def test_batch_picks_up_new_parameters():
+    """set_params / set_force_field on a member between batch steps reach the batch."""
+    import torch
+    from paper_2508_16997_amd import Batch
+
+    runs = [synth.random_periodic(70, 37, seed=8, ymode="wall", precision="fp32"),
+            synth.random_periodic(40, 24, seed=9, precision="fp32")]
+    stream = torch.cuda.Stream()
+    say("batch parameter refresh")
+    batched = _make(runs, stream)
+    single = _make(runs, stream)
+    b = Batch(batched, graph_chunk=4)
+    b.step(11)
+    for s in single:
+        s.step(11)
+    for s in (batched[0], single[0]):
+        s.set_params(0.12, 0.05, 30.0, 0.02, 0.25, 0.05, 1e-5, -2e-6)
+        s.set_force_field(None, None)
+    b.step(20)
+    for s in single:
+        s.step(20)
+    stream.synchronize()
+    for sb, ss in zip(batched, single):
+        gb, gs = _read_exact(sb), _read_exact(ss)
+        for k in FIELDS:
+            assert np.array_equal(gb[k], gs[k]), k
+    b.close()
+    for s in batched + single:
+        s.close()
+
+
+def test_batch_rejects_mismatched_members():
+    import torch
+    from paper_2508_16997_amd import Batch, VlbError
+
+    stream = torch.cuda.Stream()
+    a = _make([synth.random_periodic(40, 24, seed=1, precision="fp32")], stream)[0]
+    c = _make([synth.random_periodic(40, 24, seed=1, precision="fp64")], stream)[0]
+    say("batch errors")
+    with pytest.raises(VlbError):
+        Batch([a, c])  # mixed precisions
+    d = _make([synth.random_periodic(40, 24, seed=2, precision="fp32")], stream)[0]
+    d.step(3)
+    with pytest.raises(VlbError):
+        Batch([a, d])  # different step counts
+    e = _make([synth.random_periodic(40, 24, seed=3, precision="fp32")], torch.cuda.Stream())[0]
+    with pytest.raises(VlbError):
+        Batch([a, e])  # different streams
+    with pytest.raises(VlbError):
+        Batch([a], tile=3)
+    b = Batch([a])
+    b.step(2)
+    a.step(1)  # stepped outside the batch: the batch refuses to continue
+    with pytest.raises(VlbError):
+        b.step(1)
+    b.close()
+    for s in (a, c, d, e):
+        s.close()
