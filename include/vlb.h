@@ -184,6 +184,38 @@ int vlb_set_store_mode(vlb_sim* sim, int mode);
 /* Use hipGraph replay for runs of nsteps >= 2 * chunk (chunk 0 disables graphs). */
 int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
 
+/* ---- adjoint ------------------------------------------------------------------------ */
+
+/* Discrete adjoint of nsteps coupled steps (Sec. 3, Eqs. 31-51, differentiated step by
+ * step in reverse order) for fully periodic domains without solid nodes.  The
+ * differentiated quantities are the relaxation time lambda, the polymer viscosity
+ * eta_p and the per-node body force F(x) (held fixed over the steps; with a uniform
+ * force the gradient is still returned per node).  Memory: sqrt(N) checkpointing --
+ * the forward pass saves the state every `stride` steps; the backward pass recomputes
+ * each segment into `stride` state slots and sweeps it in reverse.  All memory is the
+ * caller's 256-byte aligned device workspace of vlb_adjoint_workspace_bytes (it holds
+ * ceil(nsteps / stride) + stride states of vlb_state_bytes each, plus adjoint buffers).
+ *
+ * vlb_adjoint_forward: from the current state, advances nsteps steps (exactly as
+ *   vlb_step) and records checkpoints in the workspace.
+ * vlb_adjoint_backward: after vlb_adjoint_forward (the simulation not stepped, reloaded
+ *   or re-parameterised since), given dL/du of the velocity read out at the last step
+ *   (device, [ny][nx], simulation precision), returns dL/dlambda and dL/deta_p (host)
+ *   and dL/dF_x, dL/dF_y (device, [ny][nx], double; NULL to skip).  Synchronizes.
+ * vlb_adjoint: both, for the loss L = (1 / 2N) sum_x |u(x, T) - u*(x)|^2 over the N
+ *   nodes, with the target u* (device, [ny][nx], simulation precision); *loss gets L.
+ * Errors: VLB_E_UNSUPPORTED (walls, open ends or solids), VLB_E_INVALID_ARG,
+ * VLB_E_WORKSPACE, VLB_E_STATE (backward without a matching forward), VLB_E_HIP. */
+int vlb_adjoint_workspace_bytes(const vlb_sim* sim, int64_t nsteps, int stride, size_t* bytes);
+int vlb_adjoint_forward(vlb_sim* sim, int64_t nsteps, int stride, void* workspace_dev,
+                        size_t bytes);
+int vlb_adjoint_backward(vlb_sim* sim, const void* dL_dux_dev, const void* dL_duy_dev,
+                         double* dL_dlambda, double* dL_detap, void* dL_dFx_dev,
+                         void* dL_dFy_dev, void* workspace_dev, size_t bytes);
+int vlb_adjoint(vlb_sim* sim, int64_t nsteps, int stride, const void* ux_target_dev,
+                const void* uy_target_dev, double* loss, double* dL_dlambda, double* dL_detap,
+                void* dL_dFx_dev, void* dL_dFy_dev, void* workspace_dev, size_t bytes);
+
 /* ---- batches ----------------------------------------------------------------------- */
 
 /* Many independent simulations of one precision (uneven sizes, parameters, boundary

@@ -30,7 +30,8 @@ EXPORTS = [
     "vlb_set_params", "vlb_set_force_field", "vlb_set_inlet", "vlb_init_equilibrium",
     "vlb_step", "vlb_get_step", "vlb_read_fields", "vlb_read_history", "vlb_monitors",
     "vlb_state_bytes", "vlb_save_state", "vlb_load_state", "vlb_set_tile",
-    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_batch_workspace_bytes",
+    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_adjoint_workspace_bytes",
+    "vlb_adjoint_forward", "vlb_adjoint_backward", "vlb_adjoint", "vlb_batch_workspace_bytes",
     "vlb_batch_create", "vlb_batch_step", "vlb_batch_set_graph_chunk", "vlb_batch_destroy",
     "vlb_error_string", "vlb_last_error_detail",
 ]
@@ -94,6 +95,11 @@ def load():
     lib.vlb_set_tile.argtypes = [P, I]
     lib.vlb_set_graph_chunk.argtypes = [P, I]
     lib.vlb_set_store_mode.argtypes = [P, I]
+    D = C.POINTER(C.c_double)
+    lib.vlb_adjoint_workspace_bytes.argtypes = [P, C.c_int64, I, C.POINTER(C.c_size_t)]
+    lib.vlb_adjoint_forward.argtypes = [P, C.c_int64, I, P, C.c_size_t]
+    lib.vlb_adjoint_backward.argtypes = [P, P, P, D, D, P, P, P, C.c_size_t]
+    lib.vlb_adjoint.argtypes = [P, C.c_int64, I, P, P, D, D, D, P, P, P, C.c_size_t]
     lib.vlb_batch_workspace_bytes.argtypes = [P, I, I, C.POINTER(C.c_size_t)]
     lib.vlb_batch_create.argtypes = [P, I, I, P, C.c_size_t, C.POINTER(P)]
     lib.vlb_batch_step.argtypes = [P, C.c_int64]

@@ -86,6 +86,16 @@ struct vlb_sim {
     int64_t step = 0;
 
     uint64_t version = 0;  // bumped whenever the device descriptor is rewritten
+
+    // record of the last vlb_adjoint_forward (checkpoints live in the caller's workspace)
+    struct {
+        bool valid = false;
+        char* ws = nullptr;
+        size_t bytes = 0;
+        int64_t nsteps = 0, step0 = 0;
+        int stride = 0, first0 = 0;
+        uint64_t version = 0;
+    } adj;
     int graph_chunk = 0;
     int store_mode = 0;  // 0 auto (by working-set size), 1 cached stores, 2 streaming stores
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -340,6 +350,7 @@ Run<T> make_run(const vlb_sim* s) {
     r.pop[0] = s->dptr<T>(s->off_pop[0]);
     r.pop[1] = s->dptr<T>(s->off_pop[1]);
     r.hist = s->dptr<T>(s->off_hist);
+    r.hist_out = r.hist;
     r.force = s->dptr<T>(s->off_force);
     r.bits = s->dptr<uint16_t>(s->off_bits);
     r.bidx = s->has_curved ? s->dptr<int>(s->off_bidx) : nullptr;
@@ -834,6 +845,226 @@ int vlb_set_tile(vlb_sim* s, int ty) {
     drop_graphs(s);
     if (s->bound) return upload_items(s);
     return VLB_OK;
+}
+
+}  // extern "C"
+
+// ---- adjoint (periodic domains) ------------------------------------------------------
+
+namespace {
+
+template <class V>
+__global__ void k_store_value(V v, V* dst) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+struct AdjLayout {
+    size_t state = 0;  // bytes of one saved state (vlb_save_state layout), 256-aligned
+    int K = 1, nseg = 0;
+    size_t off_desc = 0, off_adjdev = 0, off_ckpt = 0, off_slot = 0, off_a[2] = {0, 0},
+           off_scr = 0, off_gF = 0, off_part = 0, off_loss = 0, total = 0;
+};
+
+AdjLayout adj_layout(const vlb_sim* s, int64_t nsteps, int stride) {
+    AdjLayout L;
+    L.K = stride;
+    L.nseg = (int)((nsteps + stride - 1) / stride);
+    L.state = align256(256 + 41 * (size_t)s->plane * s->esz);
+    const size_t pb = (size_t)s->plane * s->esz;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + bytes); return r; };
+    const size_t rsz = s->prec == VLB_FP32 ? sizeof(Run<float>) : sizeof(Run<double>);
+    const size_t asz = s->prec == VLB_FP32 ? sizeof(vlb::AdjDev<float>) : sizeof(vlb::AdjDev<double>);
+    L.off_desc = take((size_t)L.K * rsz);
+    L.off_adjdev = take(asz);
+    L.off_ckpt = take((size_t)L.nseg * L.state);
+    L.off_slot = take((size_t)L.K * L.state);
+    L.off_a[0] = take(41 * pb);
+    L.off_a[1] = take(41 * pb);
+    L.off_scr = take(22 * pb);
+    L.off_gF = take(2 * (size_t)s->plane * sizeof(double));
+    L.off_part = take(2 * (size_t)std::max(1, s->nitems) * sizeof(double));
+    L.off_loss = take((size_t)std::max(1, s->nitems) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+int adj_check(const vlb_sim* s, int64_t nsteps, int stride) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (s->xmode != VLB_PERIODIC || s->ymode != VLB_PERIODIC || s->has_bits)
+        return fail(VLB_E_UNSUPPORTED, "the adjoint covers fully periodic domains without solids");
+    if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
+    return VLB_OK;
+}
+
+// Descriptor k of the recompute: reads state slot k, writes slot k + 1 (history too).
+template <class T>
+int adj_upload_desc(vlb_sim* s, const AdjLayout& L, char* ws) {
+    const size_t pb = (size_t)s->plane * s->esz;
+    Run<T>* d = reinterpret_cast<Run<T>*>(ws + L.off_desc);
+    for (int k = 0; k < L.K; ++k) {
+        char* sk = ws + L.off_slot + (size_t)k * L.state;
+        char* sn = k + 1 < L.K ? sk + L.state : sk;
+        Run<T> r = make_run<T>(s);
+        r.pop[0] = reinterpret_cast<T*>(sk + 256);
+        r.pop[1] = reinterpret_cast<T*>(sn + 256);
+        r.hist = reinterpret_cast<T*>(sk + 256 + 36 * pb);
+        r.hist_out = reinterpret_cast<T*>(sn + 256 + 36 * pb);
+        hipLaunchKernelGGL((k_store_value<Run<T>>), dim3(1), dim3(64), 0, s->stream, r, d + k);
+        VLB_HIP(hipGetLastError());
+    }
+    return VLB_OK;
+}
+
+template <class T>
+int adj_forward(vlb_sim* s, int64_t nsteps, int stride, char* ws, size_t bytes) {
+    const AdjLayout L = adj_layout(s, nsteps, stride);
+    s->adj.valid = false;
+    s->adj.ws = ws;
+    s->adj.bytes = bytes;
+    s->adj.nsteps = nsteps;
+    s->adj.stride = stride;
+    s->adj.step0 = s->step;
+    s->adj.first0 = s->first;
+    for (int g = 0; g < L.nseg; ++g) {
+        char* ck = ws + L.off_ckpt + (size_t)g * L.state;
+        int rc = vlb_save_state(s, ck, L.state);
+        if (rc) return rc;
+        const int64_t len = std::min<int64_t>(stride, nsteps - (int64_t)g * stride);
+        rc = do_step<T>(s, len);
+        if (rc) return rc;
+    }
+    s->adj.version = s->version;
+    s->adj.valid = true;
+    return VLB_OK;
+}
+
+template <class T>
+int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, double* loss,
+                 double* dlam, double* deta, void* dFx, void* dFy) {
+    const int64_t nsteps = s->adj.nsteps;
+    const int stride = s->adj.stride;
+    char* ws = s->adj.ws;
+    const AdjLayout L = adj_layout(s, nsteps, stride);
+    int rc = adj_upload_desc<T>(s, L, ws);
+    if (rc) return rc;
+    vlb::AdjDev<T> a{};
+    a.nx = s->nx; a.ny = s->ny; a.pitch = s->pitch; a.off0 = s->off0; a.plane = s->plane;
+    a.scr = reinterpret_cast<T*>(ws + L.off_scr);
+    a.gF = reinterpret_cast<double*>(ws + L.off_gF);
+    a.part = reinterpret_cast<double*>(ws + L.off_part);
+    a.lossp = reinterpret_cast<double*>(ws + L.off_loss);
+    a.seed_x = static_cast<const T*>(gx);
+    a.seed_y = static_cast<const T*>(gy);
+    a.seed_is_target = is_target;
+    a.inv_nfluid = 1.0 / ((double)s->nx * (double)s->ny);
+    vlb::AdjDev<T>* ad = reinterpret_cast<vlb::AdjDev<T>*>(ws + L.off_adjdev);
+    hipLaunchKernelGGL((k_store_value<vlb::AdjDev<T>>), dim3(1), dim3(64), 0, s->stream, a, ad);
+    VLB_HIP(hipGetLastError());
+    const vlb::Item* items = s->dptr<vlb::Item>(s->off_items);
+    T* abuf[2] = {reinterpret_cast<T*>(ws + L.off_a[0]), reinterpret_cast<T*>(ws + L.off_a[1])};
+    const Run<T>* rs = s->dptr<Run<T>>(s->off_run);
+    VLB_HIP(vlb::launch_adj_seed<T>(rs, ad, items, s->nitems, s->ty, s->dptr<T>(s->off_pop[s->parity]),
+                                    s->first ? 0 : 1, abuf[0], s->stream));
+    int cur = 0;
+    const Run<T>* desc = reinterpret_cast<const Run<T>*>(ws + L.off_desc);
+    for (int g = L.nseg - 1; g >= 0; --g) {
+        const int64_t len = std::min<int64_t>(stride, nsteps - (int64_t)g * stride);
+        VLB_HIP(hipMemcpyAsync(ws + L.off_slot, ws + L.off_ckpt + (size_t)g * L.state, L.state,
+                               hipMemcpyDeviceToDevice, s->stream));
+        for (int64_t k = 0; k + 1 < len; ++k) {
+            const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
+            VLB_HIP(vlb::launch_step<T>(desc + k, items, s->nitems, s->ty, 0, first, 0, s->stream));
+        }
+        for (int64_t k = len - 1; k >= 0; --k) {
+            const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
+            VLB_HIP(vlb::launch_adj_step<T>(desc + k, ad, items, s->nitems, s->ty, first, abuf[cur],
+                                            abuf[cur ^ 1], s->stream));
+            cur ^= 1;
+        }
+    }
+    const size_t row = (size_t)s->nx * sizeof(double);
+    const size_t pitchb = (size_t)s->pitch * sizeof(double);
+    const double* gF = reinterpret_cast<const double*>(ws + L.off_gF) + s->off0;
+    if (dFx) VLB_HIP(hipMemcpy2DAsync(dFx, row, gF, pitchb, row, s->ny, hipMemcpyDeviceToDevice, s->stream));
+    if (dFy) VLB_HIP(hipMemcpy2DAsync(dFy, row, gF + s->plane, pitchb, row, s->ny, hipMemcpyDeviceToDevice, s->stream));
+    std::vector<double> part(2 * (size_t)s->nitems), lossp((size_t)s->nitems);
+    VLB_HIP(hipMemcpyAsync(part.data(), ws + L.off_part, part.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream));
+    VLB_HIP(hipMemcpyAsync(lossp.data(), ws + L.off_loss, lossp.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    double sl = 0.0, se = 0.0, sloss = 0.0;
+    for (int b = 0; b < s->nitems; ++b) {
+        sl += part[2 * b];
+        se += part[2 * b + 1];
+        sloss += lossp[b];
+    }
+    if (dlam) *dlam = sl;
+    if (deta) *deta = se;
+    if (loss) *loss = is_target ? sloss : 0.0;
+    return VLB_OK;
+}
+
+int adj_ws_check(const vlb_sim* s, int64_t nsteps, int stride, void* ws, size_t bytes) {
+    const AdjLayout L = adj_layout(s, nsteps, stride);
+    if (!ws || ((uintptr_t)ws & 255u) || bytes < L.total)
+        return fail(VLB_E_WORKSPACE, "adjoint workspace missing, misaligned or smaller than " +
+                                         std::to_string(L.total) + " bytes");
+    return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vlb_adjoint_workspace_bytes(const vlb_sim* s, int64_t nsteps, int stride, size_t* bytes) {
+    if (!s || !bytes) return fail(VLB_E_INVALID_ARG, "null argument");
+    if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
+    *bytes = adj_layout(s, nsteps, stride).total;
+    return VLB_OK;
+}
+
+int vlb_adjoint_forward(vlb_sim* s, int64_t nsteps, int stride, void* ws, size_t bytes) {
+    int rc = adj_check(s, nsteps, stride);
+    if (rc) return rc;
+    rc = adj_ws_check(s, nsteps, stride, ws, bytes);
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    return s->prec == VLB_FP32 ? adj_forward<float>(s, nsteps, stride, w, bytes)
+                               : adj_forward<double>(s, nsteps, stride, w, bytes);
+}
+
+static int adj_backward_checked(vlb_sim* s, const void* gx, const void* gy, int is_target,
+                                double* loss, double* dlam, double* deta, void* dFx, void* dFy,
+                                void* ws, size_t bytes) {
+    int rc = adj_check(s, 0, 1);
+    if (rc) return rc;
+    if (!gx || !gy) return fail(VLB_E_INVALID_ARG, "null velocity seed");
+    if (!s->adj.valid || s->adj.ws != ws || s->adj.bytes != bytes)
+        return fail(VLB_E_STATE, "no vlb_adjoint_forward recorded in this workspace");
+    if (s->step != s->adj.step0 + s->adj.nsteps || s->adj.version != s->version)
+        return fail(VLB_E_STATE, "simulation changed since vlb_adjoint_forward");
+    return s->prec == VLB_FP32
+               ? adj_backward<float>(s, gx, gy, is_target, loss, dlam, deta, dFx, dFy)
+               : adj_backward<double>(s, gx, gy, is_target, loss, dlam, deta, dFx, dFy);
+}
+
+int vlb_adjoint_backward(vlb_sim* s, const void* dL_dux, const void* dL_duy, double* dL_dlambda,
+                         double* dL_detap, void* dL_dFx, void* dL_dFy, void* ws, size_t bytes) {
+    return adj_backward_checked(s, dL_dux, dL_duy, 0, nullptr, dL_dlambda, dL_detap, dL_dFx,
+                                dL_dFy, ws, bytes);
+}
+
+int vlb_adjoint(vlb_sim* s, int64_t nsteps, int stride, const void* ux_tgt, const void* uy_tgt,
+                double* loss, double* dL_dlambda, double* dL_detap, void* dL_dFx, void* dL_dFy,
+                void* ws, size_t bytes) {
+    if (!ux_tgt || !uy_tgt) return fail(VLB_E_INVALID_ARG, "null target velocity");
+    int rc = vlb_adjoint_forward(s, nsteps, stride, ws, bytes);
+    if (rc) return rc;
+    return adj_backward_checked(s, ux_tgt, uy_tgt, 1, loss, dL_dlambda, dL_detap, dL_dFx, dL_dFy,
+                                ws, bytes);
 }
 
 }  // extern "C"

@@ -50,6 +50,8 @@ struct RunDev {
     long long plane;    // elements per plane ((ny + 2) * pitch)
     S* pop[2];          // two population buffers of 36 planes: f (9), g_xx, g_xy, g_yy (9 each)
     S* hist;            // 5 planes: S_xx, S_xy, S_yy, u_x, u_y of the previous step
+    S* hist_out;        // where the step writes this step's S and u (hist, except when an
+                        // adjoint segment is recomputed into separate state slots)
     const S* force;     // 2 planes (F_x, F_y) when !uniform_force
     const uint16_t* bits;  // per node, see BIT_SELF_SOLID
     const int* bidx;    // per node: row of bq for nodes with curved links, else -1
@@ -73,6 +75,23 @@ struct Item {
 // Work item of the fill kernel: run index and a chunk of that run's ops.
 struct FillItem {
     int run, first, count, pad;
+};
+
+// Adjoint buffers (periodic domains).  Adjoint planes use the padded layout of the
+// forward state; periodic neighbours are reached by wrapping indices.
+template <class S>
+struct AdjDev {
+    int nx, ny, pitch, off0;
+    long long plane;
+    S* scr;          // 22 planes of per-node intermediates written by the local pass
+    double* gF;      // 2 planes: accumulated dL/dF_x, dL/dF_y
+    double* part;    // 2 per work item: accumulated dL/dlambda, dL/deta_p partials
+    double* lossp;   // 1 per work item: loss partials of the seed
+    const S* seed_x;  // [ny][nx] (unpadded): dL/du_x or the target u_x
+    const S* seed_y;  // [ny][nx]: dL/du_y or the target u_y
+    int seed_is_target;  // 1: dL/du = (u - target) / nfluid and the loss is formed
+    int pad;
+    double inv_nfluid;
 };
 
 struct MonitorAcc {
@@ -101,6 +120,12 @@ hipError_t launch_read(const RunDev<S>& run_host, const RunDev<S>* run_dev, int 
 template <class S>
 hipError_t launch_monitor(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,
                           int first, S* usnap, MonitorAcc* acc, hipStream_t s);
+template <class S>
+hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                           int nitems, int ty, const S* src, int pull, S* aout, hipStream_t s);
+template <class S>
+hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                           int nitems, int ty, int first, const S* ain, S* aout, hipStream_t s);
 hipError_t launch_fill_bytes(void* dst, size_t bytes, unsigned char v, hipStream_t s);
 hipError_t launch_write_words(unsigned long long* dst, unsigned long long w0,
                               unsigned long long w1, unsigned long long w2,

@@ -22,9 +22,7 @@
 // single-precision arithmetic lets rounding drift accumulate over many steps.
 // The collision is the paper's regularized TRT operator rewritten in Hermite-moment
 // space (algebraically identical to the per-direction form).
-#include "vlb_internal.h"
-
-#define VLB_GLOBAL __attribute__((address_space(1)))
+#include "vlb_device.h"
 
 // Register budget of the step kernel: single-precision storage fits four waves per
 // SIMD (a few spilled registers cost less than the lost latency hiding); double
@@ -37,283 +35,6 @@ struct StepBounds {
 
 namespace vlb {
 namespace {
-
-using T = double;  // arithmetic type
-
-// load/store with a uniform base pointer and a non-negative 32-bit element offset
-template <class S>
-__device__ __forceinline__ T ldu(const S* base, unsigned off) {
-    return (T)((const VLB_GLOBAL S*)base)[off];
-}
-template <class S>
-__device__ __forceinline__ void stu(S* base, unsigned off, T v) {
-    ((VLB_GLOBAL S*)base)[off] = (S)v;
-}
-// store of a streamed value, read by other workgroups in the next step only: a
-// non-temporal store when the working set exceeds the last-level cache, a plain one
-// when the whole state stays cache resident
-template <bool NT, class S>
-__device__ __forceinline__ void st_stream(S* base, unsigned off, T v) {
-    if (NT) __builtin_nontemporal_store((S)v, (VLB_GLOBAL S*)base + off);
-    else ((VLB_GLOBAL S*)base)[off] = (S)v;
-}
-
-// D2Q9 velocities in the paper's order (Sec. 3.1), their opposites and weights.
-__host__ __device__ constexpr int ex(int i) {
-    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
-}
-__host__ __device__ constexpr int ey(int i) {
-    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
-}
-__host__ __device__ constexpr int opp(int i) {
-    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
-}
-__device__ __forceinline__ constexpr T wgt(int i) {
-    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
-}
-constexpr T R3 = 1.0 / 3.0;
-
-static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
-static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
-
-template <class S>
-__device__ __forceinline__ int node_index(const RunDev<S>& R, int x, int y) {
-    return R.off0 + y * R.pitch + x;
-}
-
-// Deviation of the third-order Hermite hydrodynamic equilibrium (Sec. 3.1):
-// f_i^eq - w_i = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u + 13.5 h3_i(u))].
-__device__ __forceinline__ T dfeq(int i, T drho, T rho, T ux, T uy) {
-    const T eu = T(ex(i)) * ux + T(ey(i)) * uy;
-    const T hxxy = (T(ex(i) * ex(i)) - R3) * T(ey(i));
-    const T hxyy = (T(ey(i) * ey(i)) - R3) * T(ex(i));
-    const T h3 = hxxy * ux * ux * uy + hxyy * ux * uy * uy;
-    return wgt(i) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy) + 13.5 * h3));
-}
-
-// Deviation of the second-order convection-diffusion equilibrium (Sec. 3.2).
-__device__ __forceinline__ T dgeq(int i, T dphi, T phi, T ux, T uy) {
-    const T eu = T(ex(i)) * ux + T(ey(i)) * uy;
-    return wgt(i) * (dphi + phi * (3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy)));
-}
-
-__device__ __forceinline__ constexpr T phi0(int k) { return k == 1 ? 0.0 : 1.0; }
-
-template <class S>
-__device__ __forceinline__ T link_q(const RunDev<S>& R, int bi, int i) {
-    return bi >= 0 ? R.bq[bi * 8 + (i - 1)] : 0.5;
-}
-
-template <class S>
-__device__ __forceinline__ unsigned node_bits(const RunDev<S>& R, int p) {
-    return R.has_bits ? (unsigned)((const VLB_GLOBAL uint16_t*)R.bits)[p] : 0u;
-}
-
-template <class S>
-__device__ __forceinline__ void node_force(const RunDev<S>& R, int p, T& Fx, T& Fy) {
-    if (R.uniform_force) {
-        Fx = R.Fx;
-        Fy = R.Fy;
-    } else {
-        Fx = ldu(R.force, (unsigned)p);
-        Fy = ldu(R.force + R.plane, (unsigned)p);
-    }
-}
-
-// The nine populations of lattice L (0 hydro, 1..3 conformation) that arrive at slot
-// p: pulled from p - e_i, or the node's own values on the first step.  Kept in storage
-// precision until their moments are taken.
-template <class S>
-__device__ __forceinline__ void pull9(const RunDev<S>& R, const S* src, int L, int p, bool pull,
-                                      S v[9]) {
-    const long long plane = R.plane;
-    const S* base = src + (long long)(9 * L) * plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int off = pull ? p - ex(i) - ey(i) * R.pitch : p;
-        v[i] = ((const VLB_GLOBAL S*)(base + i * plane))[(unsigned)off];
-    }
-}
-
-// rho, u with the half-force shift (Sec. 3.1).
-template <class V>
-__device__ __forceinline__ void hydro_macros(const V f[9], T Fx, T Fy, T& drho, T& rho, T& ux,
-                                             T& uy) {
-    const T s13 = T(f[1]) + T(f[3]), s24 = T(f[2]) + T(f[4]);
-    const T s57 = T(f[5]) + T(f[7]), s68 = T(f[6]) + T(f[8]);
-    const T d13 = T(f[1]) - T(f[3]), d24 = T(f[2]) - T(f[4]);
-    const T d57 = T(f[5]) - T(f[7]), d68 = T(f[6]) - T(f[8]);
-    drho = T(f[0]) + (s13 + s24) + (s57 + s68);
-    const T jx = d13 + (d57 - d68), jy = d24 + (d57 + d68);
-    rho = 1.0 + drho;
-    const T inv = 1.0 / rho;
-    ux = (jx + 0.5 * Fx) * inv;
-    uy = (jy + 0.5 * Fy) * inv;
-}
-
-// Conservative non-equilibrium bounce-back for one lattice at a boundary node
-// (Sec. 3.3).  On entry g holds the known post-streaming populations and, on wall
-// links, the post-collision populations that moved toward the wall; phi_b is their
-// sum.  Unknowns are rebuilt from the equilibrium at (phi_b, u_b) plus the
-// non-equilibrium part of the known opposite population (the equilibrium alone when
-// the opposite is unknown too); g_0 restores phi_b exactly.
-// An unknown is never read as the known opposite of another unknown, so the update is
-// done in place.
-__device__ __forceinline__ void cnebb(unsigned solid, int k, T ux, T uy, T g[9]) {
-    T sum = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) sum += g[i];
-    const T phi = phi0(k) + sum;
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        if (!((solid >> i) & 1u)) continue;
-        const int o = opp(i);
-        T v = dgeq(i, sum, phi, ux, uy);
-        if (!((solid >> o) & 1u)) v += g[o] - dgeq(o, sum, phi, ux, uy);
-        g[i] = v;
-    }
-    T rest = sum;
-#pragma unroll
-    for (int i = 1; i < 9; ++i) rest -= g[i];
-    g[0] = rest;
-}
-
-// Finite-difference derivative along one axis: central difference, or the quadratic
-// through the no-slip wall value 0 at fraction q when a neighbour is a wall.
-__device__ __forceinline__ T dgrad(bool lo_wall, T qlo, T vlo, T v0, bool hi_wall, T qhi, T vhi) {
-    if (!lo_wall && !hi_wall) return 0.5 * (vhi - vlo);
-    if (lo_wall && !hi_wall) return qlo / (1.0 + qlo) * vhi + (1.0 - qlo) / qlo * v0;
-    if (!lo_wall) return -(qhi / (1.0 + qhi) * vlo + (1.0 - qhi) / qhi * v0);
-    return v0 * (qhi - qlo) / (qlo * qhi);
-}
-
-// Moments of one D2Q9 population set via opposite-pair sums and differences:
-// zeroth, first (x, y), second (xx, yy, xy) and the two third-order ones (xxy, xyy).
-struct Mom {
-    T m0, mx, my, pxx, pyy, pxy, qxxy, qxyy;
-};
-template <class V>
-__device__ __forceinline__ Mom moments(const V v[9]) {
-    const T s13 = T(v[1]) + T(v[3]), d13 = T(v[1]) - T(v[3]);
-    const T s24 = T(v[2]) + T(v[4]), d24 = T(v[2]) - T(v[4]);
-    const T s57 = T(v[5]) + T(v[7]), d57 = T(v[5]) - T(v[7]);
-    const T s68 = T(v[6]) + T(v[8]), d68 = T(v[6]) - T(v[8]);
-    Mom m;
-    m.m0 = T(v[0]) + (s13 + s24) + (s57 + s68);
-    m.mx = d13 + (d57 - d68);
-    m.my = d24 + (d57 + d68);
-    m.pxx = s13 + (s57 + s68);
-    m.pyy = s24 + (s57 + s68);
-    m.pxy = s57 - s68;
-    m.qxxy = d57 + d68;
-    m.qxyy = d57 - d68;
-    return m;
-}
-
-// Populations w_i [e0 + 3 e.M1 + 4.5 H2:M2 + 13.5 H3:M3] rebuilt pairwise: for the
-// opposite directions i and i' the even part is shared and the odd part changes sign.
-__device__ __forceinline__ void rebuild(T e0, T m1x, T m1y, T m2xx, T m2yy, T m2xy, T m3xxy,
-                                        T m3xyy, T out[9]) {
-    constexpr T w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
-    const T tr = m2xx + m2yy;
-    out[0] = w0 * (e0 - 1.5 * tr);
-    const T e13 = e0 + 3.0 * m2xx - 1.5 * m2yy, o13 = 3.0 * m1x - 4.5 * m3xyy;
-    out[1] = w1 * (e13 + o13);
-    out[3] = w1 * (e13 - o13);
-    const T e24 = e0 + 3.0 * m2yy - 1.5 * m2xx, o24 = 3.0 * m1y - 4.5 * m3xxy;
-    out[2] = w1 * (e24 + o24);
-    out[4] = w1 * (e24 - o24);
-    const T ed = e0 + 3.0 * tr;
-    const T e57 = ed + 9.0 * m2xy, o57 = 3.0 * (m1x + m1y) + 9.0 * (m3xxy + m3xyy);
-    out[5] = w5 * (e57 + o57);
-    out[7] = w5 * (e57 - o57);
-    const T e68 = ed - 9.0 * m2xy, o68 = 3.0 * (m1y - m1x) + 9.0 * (m3xxy - m3xyy);
-    out[6] = w5 * (e68 + o68);
-    out[8] = w5 * (e68 - o68);
-}
-
-// Hydrodynamic TRT regularized collision in Hermite-moment form (Sec. 3.1): the
-// post-collision populations are w_i [drho + 3 e.M1 + 4.5 H2:M2 + 13.5 H3:M3] with
-//   M1 = rho u + (1 - 1/tau_s1) a_1 + (1 - 1/(2 tau_s1)) F                      (F_i)
-//   M2 = rho uu + (1 - 1/tau_s1) a_2 - (1 - 1/(2 tau_s1)) diag(Dx, Dy) - tau/tau_s1
-//        (G_i and T_i)
-//   M3 = rho uuu + (1 - 1/tau_s2) a_3   (xxy and xyy; H_xxx = H_yyy = 0 on D2Q9)
-// where a_n are the off-equilibrium Hermite moments of f (a_0 = 0 identically).
-template <class S>
-__device__ __forceinline__ void collide_hydro(const RunDev<S>& R, const Mom& m, T rho, T ux, T uy,
-                                              T Fx, T Fy, T txx, T txy, T tyy, T Dx, T Dy,
-                                              T out[9]) {
-    const T drho = m.m0;
-    const T ruxx = rho * ux * ux, ruyy = rho * uy * uy, ruxy = rho * ux * uy;
-    const T ax = m.mx - rho * ux, ay = m.my - rho * uy;
-    const T axx = m.pxx - R3 * drho - ruxx;
-    const T ayy = m.pyy - R3 * drho - ruyy;
-    const T axy = m.pxy - ruxy;
-    const T axxy = m.qxxy - R3 * m.my - ruxx * uy;
-    const T axyy = m.qxyy - R3 * m.mx - ruyy * ux;
-    const T m1x = rho * ux + R.c1 * ax + R.h1 * Fx;
-    const T m1y = rho * uy + R.c1 * ay + R.h1 * Fy;
-    const T m2xx = ruxx + R.c1 * axx - R.h1 * Dx - R.inv_ts1 * txx;
-    const T m2yy = ruyy + R.c1 * ayy - R.h1 * Dy - R.inv_ts1 * tyy;
-    const T m2xy = ruxy + R.c1 * axy - R.inv_ts1 * txy;
-    const T m3xxy = ruxx * uy + R.c2 * axxy;
-    const T m3xyy = ruyy * ux + R.c2 * axyy;
-    rebuild(drho, m1x, m1y, m2xx, m2yy, m2xy, m3xxy, m3xyy, out);
-}
-
-// Convection-diffusion TRT regularized collision in moment form (Sec. 3.2):
-// w_i [dphi + 1.5 S - 0.5 S_prev + 3 e.N1 + 4.5 H2:N2] with
-//   N1 = phi u + (1 - 1/tau_p1) b_1 + (1 - 1/(2 tau_p1)) (F phi/rho + 1.5 S u - 0.5 S_prev u_prev)
-//   N2 = phi uu + (1 - 1/tau_p2) b_2,
-// i.e. the equilibrium, the regularized non-equilibrium part, G~_i, F~_i and half the
-// backward time difference of F~_i.
-template <class S>
-__device__ __forceinline__ void collide_cde(const RunDev<S>& R, const Mom& m, T phi, T ux, T uy,
-                                            T fr, T Fx, T Fy, T Sk, T Sp, T uxp, T uyp,
-                                            T out[9]) {
-    const T dphi = m.m0;
-    const T pux = phi * ux, puy = phi * uy;
-    const T bx = m.mx - pux, by = m.my - puy;
-    const T bxx = m.pxx - R3 * dphi - pux * ux;
-    const T byy = m.pyy - R3 * dphi - puy * uy;
-    const T bxy = m.pxy - pux * uy;
-    const T s0 = dphi + 1.5 * Sk - 0.5 * Sp;
-    const T n1x = pux + R.p1 * bx + R.h2 * (Fx * fr + 1.5 * Sk * ux - 0.5 * Sp * uxp);
-    const T n1y = puy + R.p1 * by + R.h2 * (Fy * fr + 1.5 * Sk * uy - 0.5 * Sp * uyp);
-    const T n2xx = pux * ux + R.p2 * bxx;
-    const T n2yy = puy * uy + R.p2 * byy;
-    const T n2xy = pux * uy + R.p2 * bxy;
-    rebuild(s0, n1x, n1y, n2xx, n2yy, n2xy, 0.0, 0.0, out);
-}
-
-// Periodic image of a tile/ring cell; false when it lies beyond a wall or open end.
-template <class S>
-__device__ __forceinline__ bool wrap_cell(const RunDev<S>& R, int& xx, int& yy) {
-    if (yy < 0 || yy >= R.ny) {
-        if (R.ymode != XM_PERIODIC) return false;
-        yy = ((yy % R.ny) + R.ny) % R.ny;
-    }
-    if (xx < 0 || xx >= R.nx) {
-        if (R.xmode != XM_PERIODIC) return false;
-        xx = ((xx % R.nx) + R.nx) % R.nx;
-    }
-    return true;
-}
-
-// rho and u of one tile/ring cell (hydrodynamic pull + moments); false if not fluid.
-template <class S>
-__device__ __forceinline__ bool cell_macros(const RunDev<S>& R, const S* src, int cx, int cy,
-                                            bool pull, T& rho, T& ux, T& uy) {
-    if (!wrap_cell(R, cx, cy)) return false;
-    const int p = node_index(R, cx, cy);
-    if (node_bits(R, p) & BIT_SELF_SOLID) return false;
-    S f[9];
-    pull9(R, src, 0, p, pull, f);
-    T Fx, Fy, drho;
-    node_force(R, p, Fx, Fy);
-    hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
-    return true;
-}
 
 template <class S, int TY, bool NT>
 __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::min_waves_per_eu)) void k_step(
@@ -487,9 +208,9 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
         }
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) st_stream<NT>(R.hist + k * plane, (unsigned)p, Sc[k]);
-    st_stream<NT>(R.hist + 3 * plane, (unsigned)p, ux);
-    st_stream<NT>(R.hist + 4 * plane, (unsigned)p, uy);
+    for (int k = 0; k < 3; ++k) st_stream<NT>(R.hist_out + k * plane, (unsigned)p, Sc[k]);
+    st_stream<NT>(R.hist_out + 3 * plane, (unsigned)p, ux);
+    st_stream<NT>(R.hist_out + 4 * plane, (unsigned)p, uy);
 }
 
 // Boundary links of the buffer just written: write into each ghost or solid slot the

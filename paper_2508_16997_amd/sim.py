@@ -103,6 +103,9 @@ class Simulation:
         p = L.VlbParams(float(nu_s), float(eta_p), float(lam), float(kappa), float(Lambda_s),
                         float(Lambda_p), float(Fx), float(Fy), int(flags))
         L.check(self.lib.vlb_set_params(self._h, C.byref(p)), "vlb_set_params")
+        self.params = dict(nu_s=float(nu_s), eta_p=float(eta_p), lam=float(lam),
+                           kappa=float(kappa), Lambda_s=float(Lambda_s),
+                           Lambda_p=float(Lambda_p), Fx=float(Fx), Fy=float(Fy), flags=int(flags))
 
     def set_force_field(self, fx, fy):
         if fx is None and fy is None:
@@ -204,6 +207,71 @@ class Simulation:
 
     def set_graph_chunk(self, chunk: int):
         L.check(self.lib.vlb_set_graph_chunk(self._h, int(chunk)), "vlb_set_graph_chunk")
+
+    # ------------------------------------------------------------------ adjoint
+    @staticmethod
+    def default_stride(nsteps: int) -> int:
+        """Checkpoint stride ceil(sqrt(nsteps)): O(sqrt N) states held at once."""
+        return max(1, int(np.ceil(np.sqrt(max(1, int(nsteps))))))
+
+    def adjoint_workspace_bytes(self, nsteps: int, stride: Optional[int] = None) -> int:
+        stride = stride or self.default_stride(nsteps)
+        v = C.c_size_t()
+        L.check(self.lib.vlb_adjoint_workspace_bytes(self._h, int(nsteps), int(stride),
+                                                     C.byref(v)), "vlb_adjoint_workspace_bytes")
+        return int(v.value)
+
+    def _adjoint_ws(self, nsteps, stride):
+        need = self.adjoint_workspace_bytes(nsteps, stride)
+        buf = getattr(self, "_adj_buf", None)
+        if buf is None or buf.numel() < need + 256:
+            self._adj_buf = buf = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ptr = (buf.data_ptr() + 255) // 256 * 256
+        return ptr, buf.numel() - (ptr - buf.data_ptr())
+
+    def adjoint_forward(self, nsteps: int, stride: Optional[int] = None):
+        """Advance nsteps steps, saving checkpoints for :meth:`adjoint_backward`."""
+        stride = stride or self.default_stride(nsteps)
+        ptr, nbytes = self._adjoint_ws(nsteps, stride)
+        self._order_after_torch()
+        L.check(self.lib.vlb_adjoint_forward(self._h, int(nsteps), int(stride), C.c_void_p(ptr),
+                                             nbytes), "vlb_adjoint_forward")
+        self._adj_rec = (ptr, nbytes)
+
+    def adjoint_backward(self, dL_dux, dL_duy) -> dict:
+        """Gradients of L given dL/du of the last readout: dlambda, deta_p, dFx, dFy."""
+        if getattr(self, "_adj_rec", None) is None:
+            raise RuntimeError("adjoint_backward needs adjoint_forward first")
+        ptr, nbytes = self._adj_rec
+        gx, gy = self._dev(dL_dux), self._dev(dL_duy)
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for k in ("dFx", "dFy")}
+        dl, de = C.c_double(), C.c_double()
+        self._order_after_torch()
+        L.check(self.lib.vlb_adjoint_backward(self._h, _ptr(gx), _ptr(gy), C.byref(dl), C.byref(de),
+                                              _ptr(out["dFx"]), _ptr(out["dFy"]), C.c_void_p(ptr),
+                                              nbytes), "vlb_adjoint_backward")
+        self._order_before_torch()
+        out["dlambda"] = dl.value
+        out["deta_p"] = de.value
+        return out
+
+    def adjoint(self, nsteps: int, ux_target, uy_target, stride: Optional[int] = None) -> dict:
+        """Loss (1/2N) sum |u(T) - u*|^2 after nsteps steps and its gradients."""
+        stride = stride or self.default_stride(nsteps)
+        ptr, nbytes = self._adjoint_ws(nsteps, stride)
+        tx, ty = self._dev(ux_target), self._dev(uy_target)
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for k in ("dFx", "dFy")}
+        loss, dl, de = C.c_double(), C.c_double(), C.c_double()
+        self._order_after_torch()
+        L.check(self.lib.vlb_adjoint(self._h, int(nsteps), int(stride), _ptr(tx), _ptr(ty),
+                                     C.byref(loss), C.byref(dl), C.byref(de), _ptr(out["dFx"]),
+                                     _ptr(out["dFy"]), C.c_void_p(ptr), nbytes), "vlb_adjoint")
+        self._order_before_torch()
+        self._adj_rec = (ptr, nbytes)
+        out.update(loss=loss.value, dlambda=dl.value, deta_p=de.value)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

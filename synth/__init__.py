@@ -14,6 +14,7 @@ from .workloads import (  # noqa: F401
     cylinder,
     batch_c4,
     adjoint_c5,
+    smooth_force_perturbation,
     rest_state,
     random_periodic,
     waves,
