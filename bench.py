@@ -26,6 +26,33 @@ if ROOT not in sys.path:
 METRIC = "coupled MLUPS (FP32) & % HBM roofline; batched vs single; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_step launch on a workload, from rocprofv3 counters (per dispatch, KiB):
+# FETCH_SIZE counts half of the bytes a plain 1 GiB copy reads and WRITE_SIZE all it
+# writes, so traffic = 2 * FETCH + WRITE.  Valid only for the kernel sources they were
+# taken with (hash below); otherwise the bench reports null.
+MEASURED_TRAFFIC = {
+    "four_roll_512": {"sources": "d82f5449f4f46b8a", "fetch_KiB": 27432.1, "write_KiB": 45493.8,
+                      "profile": "profiles/k_step_k_adj_four_roll_512_fp32_fetch_write.md"},
+}
+KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_kernels.hip")
+
+
+def kernel_sources_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_16997_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    rec = MEASURED_TRAFFIC.get(workload_name)
+    if rec is None or rec["sources"] != kernel_sources_hash():
+        return None
+    return int(round((2.0 * rec["fetch_KiB"] + rec["write_KiB"]) * 1024))
+
 
 def workload(name):
     import synth
@@ -115,6 +142,64 @@ def batched_leg(steps, warmup, tile, chunk):
             "runs_nonfinite": int(bad)}
 
 
+def adjoint_leg(steps, stride, tile, chunk):
+    """Adjoint workload: gradients of the velocity misfit after `steps` steps.
+
+    Times the plain forward, the checkpointed forward and the backward pass (seed,
+    segment recompute, reverse sweep).  The per-step adjoint cost is the backward time
+    less the recompute (steps - segments forward steps at the measured forward rate).
+    """
+    import math
+
+    import torch
+    import synth
+    from paper_2508_16997_amd import Simulation
+
+    pr, hidden = synth.adjoint_c5(steps=steps)
+    stream = torch.cuda.Stream()
+    tgt_sim = Simulation.from_problem(
+        pr.with_(lam=hidden["lam"], eta_p=hidden["eta_p"], Fx=hidden["Fx"], Fy=hidden["Fy"]),
+        stream=stream, tile=tile, graph_chunk=chunk)
+    tgt_sim.step(steps)
+    tgt = tgt_sim.read()
+    tx, ty = tgt["ux"].clone(), tgt["uy"].clone()
+    tgt_sim.close()
+    sim = Simulation.from_problem(pr, stream=stream, tile=tile, graph_chunk=chunk)
+    s0 = sim.save_state()
+    sim.adjoint(min(steps, 2 * stride), tx, ty, stride=stride)  # warm-up (graphs, workspace)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        sim.load_state(s0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    t_fwd, _ = timed(lambda: sim.step(steps))
+    t_afwd, _ = timed(lambda: sim.adjoint_forward(steps, stride))
+    t_all, g = timed(lambda: sim.adjoint(steps, tx, ty, stride=stride))
+    nseg = math.ceil(steps / stride)
+    step_s = t_fwd / steps
+    t_bwd = t_all - t_afwd
+    recompute = (steps - nseg) * step_s
+    adj_step = (t_bwd - recompute) / steps
+    ws = sim.adjoint_workspace_bytes(steps, stride)
+    sim.close()
+    return {"workload": f"four-roll mill {pr.nx}x{pr.ny} FP32, hidden-parameter target",
+            "steps": steps, "stride": stride, "workspace_GB": round(ws / 1e9, 3),
+            "forward_ms": round(t_fwd * 1e3, 3),
+            "checkpointed_forward_ms": round(t_afwd * 1e3, 3),
+            "backward_ms": round(t_bwd * 1e3, 3),
+            "forward_step_us": round(step_s * 1e6, 3),
+            "adjoint_step_us": round(adj_step * 1e6, 3),
+            "adjoint_vs_forward": round(adj_step / step_s, 3),
+            "recompute_fraction_of_backward": round(recompute / t_bwd, 3),
+            "gradient_vs_forward_wall": round((t_afwd + t_bwd) / t_fwd, 3),
+            "loss": g["loss"], "dL_dlambda": g["dlambda"], "dL_deta_p": g["deta_p"]}
+
+
 def cpu_baseline(pr, seconds):
     import oracle
 
@@ -154,6 +239,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-sequential leg (256 uneven runs)")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint leg (512x512, gradient of a velocity misfit)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-stride", type=int, default=45)
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -224,7 +313,7 @@ def main():
                    "graph_chunk_steps": 2 * args.graph_chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_step",
+                     "traffic": measured_traffic(args.workload), "kernel": "k_step",
                      "avg_launch_us": round(launch_s * 1e6, 3),
                      "bytes_per_launch": bytes_launch,
                      "copy_ceiling_GBs": round(copy_gbs, 1),
@@ -233,6 +322,9 @@ def main():
     if not args.no_batched:
         sim.close()
         out["batched"] = batched_leg(args.batched_steps, 2 * args.graph_chunk + 1, args.tile,
+                                     args.graph_chunk)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_stride, args.tile,
                                      args.graph_chunk)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
