@@ -102,6 +102,39 @@ def copy_bandwidth(nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / s / 1e9
 
 
+def cylinder_leg(steps, warmup, tile, chunk):
+    """Channel flow past a cylinder, 4096 x 1024, FP32 storage: a working set (1.4 GB)
+    far beyond the last-level cache, so its rate is an HBM rate."""
+    import torch
+    import synth
+    from paper_2508_16997_amd import Simulation
+
+    pr = synth.cylinder(Wi=1.0)
+    stream = torch.cuda.Stream()
+    sim = Simulation.from_problem(pr, stream=stream, tile=tile, graph_chunk=chunk)
+    nodes = int(pr.fluid_mask().sum())
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_s = ev0.elapsed_time(ev1) / 1e3 / steps
+    bad = sim.monitors(raise_on_nonfinite=False)["nonfinite"]
+    sim.close()
+    bpn = bytes_per_node(pr, 4)
+    achieved = bpn * nodes / step_s / 1e9
+    return {"workload": "channel flow past a cylinder 4096x1024, R=128, FP32 storage, Wi=1",
+            "fluid_nodes": nodes, "steps": steps, "MLUPS": round(nodes * steps / wall / 1e6, 2),
+            "us_per_step": round(step_s * 1e6, 3), "bytes_per_node": bpn,
+            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "nonfinite": int(bad)}
+
+
 def batched_leg(steps, warmup, tile, chunk):
     """Batched workload (256 uneven runs, one launch per step) vs the same runs one by one.
 
@@ -132,6 +165,7 @@ def batched_leg(steps, warmup, tile, chunk):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     bad = sum(s.monitors(raise_on_nonfinite=False)["nonfinite"] > 0 for s in sims)
+    step_bytes = sum(bytes_per_node(r, 4) * int(r.fluid_mask().sum()) for r in runs)
     b.close()
     for s in sims:
         s.close()
@@ -139,6 +173,8 @@ def batched_leg(steps, warmup, tile, chunk):
             "batched_MLUPS": round(nodes * steps / t_batch / 1e6, 2),
             "sequential_MLUPS": round(nodes * steps / t_seq / 1e6, 2),
             "batched_vs_sequential": round(t_seq / t_batch, 3),
+            "batched_GBs": round(step_bytes * steps / t_batch / 1e9, 1),
+            "batched_frac": round(step_bytes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
             "runs_nonfinite": int(bad)}
 
 
@@ -239,6 +275,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-sequential leg (256 uneven runs)")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--no-cylinder", action="store_true",
+                    help="skip the 4096x1024 cylinder leg")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint leg (512x512, gradient of a velocity misfit)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
@@ -319,8 +357,10 @@ def main():
                      "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
+    sim.close()
+    if not args.no_cylinder:
+        out["cylinder"] = cylinder_leg(1000, 100, args.tile, args.graph_chunk)
     if not args.no_batched:
-        sim.close()
         out["batched"] = batched_leg(args.batched_steps, 2 * args.graph_chunk + 1, args.tile,
                                      args.graph_chunk)
     if not args.no_adjoint:

@@ -126,6 +126,15 @@ int vlb_bind(vlb_sim* sim, void* workspace_dev, size_t bytes, void* hip_stream);
 /* Validates and stores the parameters (tau_s1, tau_p1 > 1/2 follow from nu_s, kappa > 0). */
 int vlb_set_params(vlb_sim* sim, const vlb_params* p);
 
+/* Lattice-unit parameters from the dimensionless groups of Sec. 2.4-2.5 (rho0 = 1,
+ * c_s^2 = 1/3): U_c = Ma c_s, nu_0 = U_c L_c / Re, nu_s = beta nu_0,
+ * eta_p = (1 - beta) nu_0, lambda = Wi L_c / U_c, kappa = nu_s / Sc.  Fills *out
+ * (force zero, flags 0) and, if uc is non-null, the characteristic speed U_c.
+ * Host only.  Errors: VLB_E_INVALID_ARG for Re, Wi, Sc, Ma, L_c, Lambda_s, Lambda_p
+ * <= 0 or beta outside (0, 1]. */
+int vlb_params_from_groups(double Re, double Wi, double beta, double Sc, double Ma, double Lc,
+                           double Lambda_s, double Lambda_p, vlb_params* out, double* uc);
+
 /* Per-node body force: device arrays [ny][nx] in the simulation precision, copied into
  * the workspace on the stream.  Both null: back to the uniform force of vlb_params. */
 int vlb_set_force_field(vlb_sim* sim, const void* fx_dev, const void* fy_dev);
@@ -240,6 +249,9 @@ int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* workspace_dev, s
                      vlb_batch** out);
 /* Advances every member nsteps steps (async on the shared stream). */
 int vlb_batch_step(vlb_batch* batch, int64_t nsteps);
+/* vlb_read_fields of member `run` (0-based, in creation order). */
+int vlb_batch_read_fields(vlb_batch* batch, int run, void* rho, void* ux, void* uy, void* axx,
+                          void* axy, void* ayy);
 /* hipGraph replay in chunks of 2 * chunk steps (0 disables). */
 int vlb_batch_set_graph_chunk(vlb_batch* batch, int chunk);
 void vlb_batch_destroy(vlb_batch* batch);

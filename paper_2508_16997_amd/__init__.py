@@ -5,11 +5,11 @@ package only marshals arguments and provides device memory and streams via PyTor
 """
 from ._lib import EXPORTS, LIB_PATH, VlbError, load  # noqa: F401
 
-__all__ = ["Simulation", "Batch", "host_geometry", "load", "VlbError", "EXPORTS", "LIB_PATH"]
+__all__ = ["Simulation", "Batch", "host_geometry", "params_from_groups", "load", "VlbError", "EXPORTS", "LIB_PATH"]
 
 
 def __getattr__(name):
-    if name in ("Simulation", "Batch", "host_geometry"):
+    if name in ("Simulation", "Batch", "host_geometry", "params_from_groups"):
         from . import sim
 
         return getattr(sim, name)

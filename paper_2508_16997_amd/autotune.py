@@ -1,0 +1,90 @@
+"""Launch-shape autotuner for the step kernel.
+
+For a simulation it times every tile height (64 x TY threads, TY in 1, 2, 4, 8) and both
+store modes (cached, non-temporal) with HIP events on the simulation's stream, keeps the
+fastest, and caches the choice per size class in a JSON file (``VLB_AUTOTUNE_CACHE`` or
+``~/.cache/paper_2508_16997_amd/autotune.json``).  The simulation's state is saved
+before and restored after the sweep, so tuning does not advance it.  The register
+budget (waves per SIMD) is a compile-time choice of the library and is not swept here.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Optional
+
+import torch
+
+TILES = (1, 2, 4, 8)
+STORE_MODES = {1: "cached", 2: "streaming"}
+
+
+def cache_path() -> str:
+    p = os.environ.get("VLB_AUTOTUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "paper_2508_16997_amd", "autotune.json")
+
+
+def size_class(sim) -> str:
+    """Key of the cache: precision, grid, boundary kinds, solids."""
+    solid = "solid" if (sim._mask is not None and sim._mask.any()) or sim._circ.size else "open"
+    return f"{sim.precision}:{sim.nx}x{sim.ny}:{sim.xmode}/{sim.ymode}:{solid}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_step(sim, steps: int) -> float:
+    """Average device time of one step (seconds) over ``steps`` steps."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def tune(sim, steps: int = 60, warmup: int = 10, cache: Optional[str] = None,
+         force: bool = False) -> dict:
+    """Pick and apply the fastest (tile, store mode) for ``sim``; returns the record."""
+    path = cache or cache_path()
+    data = _load(path)
+    key = size_class(sim)
+    if not force and key in data:
+        rec = data[key]
+        sim.set_tile(rec["tile"])
+        sim.set_store_mode(rec["store_mode"])
+        return rec
+    state = sim.save_state()
+    timings = {}
+    for ty in TILES:
+        for mode in STORE_MODES:
+            sim.load_state(state)
+            sim.set_tile(ty)
+            sim.set_store_mode(mode)
+            sim.step(warmup)
+            timings[(ty, mode)] = time_step(sim, steps)
+    (ty, mode), best = min(timings.items(), key=lambda kv: kv[1])
+    sim.load_state(state)
+    sim.set_tile(ty)
+    sim.set_store_mode(mode)
+    rec = {"tile": ty, "store_mode": mode, "us_per_step": round(best * 1e6, 3),
+           "sweep_us": {f"{t}/{STORE_MODES[m]}": round(v * 1e6, 3) for (t, m), v in timings.items()}}
+    data[key] = rec
+    _store(path, data)
+    return rec

@@ -71,7 +71,7 @@ struct vlb_sim {
     hipStream_t stream = nullptr;
     bool bound = false;
     size_t off_pop[2] = {0, 0}, off_hist = 0, off_force = 0, off_usnap = 0, off_inlet = 0,
-           off_bq = 0, off_bits = 0, off_bidx = 0, off_run = 0, off_items = 0, off_mon = 0,
+           off_bq = 0, off_bits = 0, off_bidx = 0, off_run = 0, off_items = 0, off_mon = 0, off_monpart = 0,
            off_fill = 0, off_fill_items = 0, total = 0;
 
     std::vector<vlb::Item> items;
@@ -93,7 +93,7 @@ struct vlb_sim {
         char* ws = nullptr;
         size_t bytes = 0;
         int64_t nsteps = 0, step0 = 0;
-        int stride = 0, first0 = 0;
+        int stride = 0, first0 = 0, ty = 0;
         uint64_t version = 0;
     } adj;
     int graph_chunk = 0;
@@ -332,6 +332,7 @@ void layout(vlb_sim* s) {
     s->items_cap = ((s->nx + 63) / 64) * s->ny;  // enough for any tile height >= 1
     s->off_items = take((size_t)s->items_cap * sizeof(vlb::Item));
     s->off_mon = take(sizeof(vlb::MonitorAcc));
+    s->off_monpart = take(8 * sizeof(double) * (size_t)((s->nx + 63) / 64) * (size_t)((s->ny + 3) / 4));
     s->off_fill = take(std::max<size_t>(1, s->fill.size()) * sizeof(vlb::FillOp));
     s->off_fill_items = take(std::max<size_t>(1, s->fill_items.size()) * sizeof(vlb::FillItem));
     s->total = o;
@@ -762,15 +763,15 @@ int vlb_monitors(vlb_sim* s, vlb_monitor* out) {
     if (rc) return rc;
     if (!out) return fail(VLB_E_INVALID_ARG, "null output");
     vlb::MonitorAcc* acc = s->dptr<vlb::MonitorAcc>(s->off_mon);
-    VLB_HIP(vlb::launch_fill_bytes(acc, sizeof(vlb::MonitorAcc), 0, s->stream));
+    double* part = s->dptr<double>(s->off_monpart);
     if (s->prec == VLB_FP32) {
         VLB_HIP(vlb::launch_monitor<float>(make_run<float>(s), s->dptr<Run<float>>(s->off_run),
-                                           s->parity, s->first, s->dptr<float>(s->off_usnap), acc,
-                                           s->stream));
+                                           s->parity, s->first, s->dptr<float>(s->off_usnap), part,
+                                           acc, s->stream));
     } else {
         VLB_HIP(vlb::launch_monitor<double>(make_run<double>(s), s->dptr<Run<double>>(s->off_run),
                                             s->parity, s->first, s->dptr<double>(s->off_usnap),
-                                            acc, s->stream));
+                                            part, acc, s->stream));
     }
     vlb::MonitorAcc h{};
     VLB_HIP(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, s->stream));
@@ -927,6 +928,7 @@ int adj_forward(vlb_sim* s, int64_t nsteps, int stride, char* ws, size_t bytes) 
     s->adj.stride = stride;
     s->adj.step0 = s->step;
     s->adj.first0 = s->first;
+    s->adj.ty = s->ty;
     for (int g = 0; g < L.nseg; ++g) {
         char* ck = ws + L.off_ckpt + (size_t)g * L.state;
         int rc = vlb_save_state(s, ck, L.state);
@@ -1019,6 +1021,26 @@ int adj_ws_check(const vlb_sim* s, int64_t nsteps, int stride, void* ws, size_t 
 
 extern "C" {
 
+int vlb_params_from_groups(double Re, double Wi, double beta, double Sc, double Ma, double Lc,
+                           double Lambda_s, double Lambda_p, vlb_params* out, double* uc) {
+    if (!out) return fail(VLB_E_INVALID_ARG, "null output");
+    if (!(Re > 0) || !(Wi > 0) || !(Sc > 0) || !(Ma > 0) || !(Lc > 0) || !(Lambda_s > 0) ||
+        !(Lambda_p > 0) || !(beta > 0) || !(beta <= 1))
+        return fail(VLB_E_INVALID_ARG, "groups must be positive and 0 < beta <= 1");
+    const double Uc = Ma * std::sqrt(1.0 / 3.0);
+    const double nu0 = Uc * Lc / Re;
+    vlb_params p{};
+    p.nu_s = beta * nu0;
+    p.eta_p = (1.0 - beta) * nu0;
+    p.lambda = Wi * Lc / Uc;
+    p.kappa = p.nu_s / Sc;
+    p.Lambda_s = Lambda_s;
+    p.Lambda_p = Lambda_p;
+    *out = p;
+    if (uc) *uc = Uc;
+    return VLB_OK;
+}
+
 int vlb_adjoint_workspace_bytes(const vlb_sim* s, int64_t nsteps, int stride, size_t* bytes) {
     if (!s || !bytes) return fail(VLB_E_INVALID_ARG, "null argument");
     if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
@@ -1044,7 +1066,8 @@ static int adj_backward_checked(vlb_sim* s, const void* gx, const void* gy, int 
     if (!gx || !gy) return fail(VLB_E_INVALID_ARG, "null velocity seed");
     if (!s->adj.valid || s->adj.ws != ws || s->adj.bytes != bytes)
         return fail(VLB_E_STATE, "no vlb_adjoint_forward recorded in this workspace");
-    if (s->step != s->adj.step0 + s->adj.nsteps || s->adj.version != s->version)
+    if (s->step != s->adj.step0 + s->adj.nsteps || s->adj.version != s->version ||
+        s->ty != s->adj.ty)
         return fail(VLB_E_STATE, "simulation changed since vlb_adjoint_forward");
     return s->prec == VLB_FP32
                ? adj_backward<float>(s, gx, gy, is_target, loss, dlam, deta, dFx, dFy)
@@ -1272,6 +1295,12 @@ int vlb_batch_step(vlb_batch* b, int64_t n) {
         if (s->step != b->step || s->parity != b->sims[0]->parity || s->first != b->sims[0]->first)
             return fail(VLB_E_STATE, "batch member was stepped or reloaded outside the batch");
     return b->prec == VLB_FP32 ? batch_step<float>(b, n) : batch_step<double>(b, n);
+}
+
+int vlb_batch_read_fields(vlb_batch* b, int run, void* rho, void* ux, void* uy, void* axx,
+                          void* axy, void* ayy) {
+    if (!b || run < 0 || run >= (int)b->sims.size()) return fail(VLB_E_INVALID_ARG, "run index out of range");
+    return vlb_read_fields(b->sims[run], rho, ux, uy, axx, axy, ayy);
 }
 
 int vlb_batch_set_graph_chunk(vlb_batch* b, int chunk) {

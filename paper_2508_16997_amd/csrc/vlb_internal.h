@@ -117,9 +117,10 @@ hipError_t launch_init(const RunDev<S>& run_host, const RunDev<S>* run_dev, cons
 template <class S>
 hipError_t launch_read(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,
                        int first, S* rho, S* ux, S* uy, S* axx, S* axy, S* ayy, hipStream_t s);
+// Deterministic two-pass reduction; part holds 8 doubles per 64 x 4 block of nodes.
 template <class S>
 hipError_t launch_monitor(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,
-                          int first, S* usnap, MonitorAcc* acc, hipStream_t s);
+                          int first, S* usnap, double* part, MonitorAcc* acc, hipStream_t s);
 template <class S>
 hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
                            int nitems, int ty, const S* src, int pull, S* aout, hipStream_t s);

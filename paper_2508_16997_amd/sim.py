@@ -31,6 +31,7 @@ class Simulation:
         if precision not in _DT:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         self.nx, self.ny, self.precision = int(nx), int(ny), precision
+        self.xmode, self.ymode = xmode, ymode
         self.dtype = _DT[precision]
         self.device = torch.device(device)
         self._mask = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
@@ -323,6 +324,18 @@ class Batch:
         L.check(self.lib.vlb_batch_step(self._h, int(n)), "vlb_batch_step")
         self.sims[0]._order_before_torch()
 
+    def read(self, run: int) -> dict:
+        """Fields of member ``run`` through the batch (vlb_batch_read_fields)."""
+        s = self.sims[run]
+        out = {k: torch.empty((s.ny, s.nx), dtype=s.dtype, device=s.device)
+               for k in ("rho", "ux", "uy", "axx", "axy", "ayy")}
+        s._order_after_torch()
+        L.check(self.lib.vlb_batch_read_fields(self._h, int(run), *[_ptr(out[k]) for k in
+                                               ("rho", "ux", "uy", "axx", "axy", "ayy")]),
+                "vlb_batch_read_fields")
+        s._order_before_torch()
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             self.stream.synchronize()
@@ -334,6 +347,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def params_from_groups(Re, Wi, beta, Sc, Ma, Lc, Lambda_s=0.25, Lambda_p=1e-6) -> dict:
+    """Lattice-unit parameters from the dimensionless groups (library host routine)."""
+    lib = L.load()
+    p = L.VlbParams()
+    uc = C.c_double()
+    L.check(lib.vlb_params_from_groups(float(Re), float(Wi), float(beta), float(Sc), float(Ma),
+                                       float(Lc), float(Lambda_s), float(Lambda_p), C.byref(p),
+                                       C.byref(uc)), "vlb_params_from_groups")
+    return dict(nu_s=p.nu_s, eta_p=p.eta_p, lam=p.lambda_, kappa=p.kappa, Lambda_s=p.Lambda_s,
+                Lambda_p=p.Lambda_p, Uc=uc.value)
 
 
 def host_geometry(nx, ny, xmode="periodic", ymode="periodic", solid=None, circles=()):

@@ -135,3 +135,44 @@ def test_workspace_size_accounts_for_layout(vlb):
         assert n.value >= (2 * 36 + 5 + 2) * pitch * 50 * 4
     finally:
         lib.vlb_destroy(h)
+
+
+def test_params_from_groups(vlb):
+    """Group -> lattice conversion of Sec. 2.4-2.5 on the three single-run set-ups.
+
+    Expected values are the definitions evaluated by hand: Poiseuille (Re 1, Wi 1,
+    beta 1/2, Ma 0.1, L_c = 32), four-roll mill (Wi 5, Ma 0.01, L_c = 512 / 2 pi) and
+    cylinder (Wi 1, beta 0.59, Ma 0.01, L_c = R = 128).
+    """
+    import math
+
+    import synth
+    from paper_2508_16997_amd import params_from_groups
+
+    cs = math.sqrt(1.0 / 3.0)
+    for (Re, Wi, beta, Sc, Ma, Lc) in ((1.0, 1.0, 0.5, 1e6, 0.1, 32.0),
+                                       (1.0, 5.0, 0.5, 1e5, 0.01, 512 / (2 * math.pi)),
+                                       (1.0, 1.0, 0.59, 1e6, 0.01, 128.0)):
+        p = params_from_groups(Re, Wi, beta, Sc, Ma, Lc)
+        Uc = Ma * cs
+        nu0 = Uc * Lc / Re
+        assert p["Uc"] == pytest.approx(Uc, rel=1e-15)
+        assert p["nu_s"] == pytest.approx(beta * nu0, rel=1e-15)
+        assert p["eta_p"] == pytest.approx((1 - beta) * nu0, rel=1e-14)
+        assert p["lam"] == pytest.approx(Wi * Lc / Uc, rel=1e-15)
+        assert p["kappa"] == pytest.approx(beta * nu0 / Sc, rel=1e-15)
+        ref = synth.lattice_units(Re, Wi, beta, Sc, Ma, Lc)
+        for k in ("nu_s", "eta_p", "lam", "kappa"):
+            assert p[k] == pytest.approx(ref[k], rel=1e-14)
+    # printed values of the Poiseuille set-up: U_c = 5.7735e-2, nu_s = eta_p = 0.92376,
+    # lambda = 554.256
+    p = params_from_groups(1.0, 1.0, 0.5, 1e6, 0.1, 32.0)
+    assert abs(p["Uc"] - 5.7735e-2) < 1e-6 and abs(p["nu_s"] - 0.92376) < 1e-5
+    assert abs(p["lam"] - 554.256) < 1e-3
+    from paper_2508_16997_amd import VlbError
+
+    for bad in (dict(Re=0.0), dict(beta=0.0), dict(beta=1.5), dict(Sc=-1.0)):
+        kw = dict(Re=1.0, Wi=1.0, beta=0.5, Sc=1e6, Ma=0.1, Lc=32.0)
+        kw.update(bad)
+        with pytest.raises(VlbError):
+            params_from_groups(**kw)

@@ -253,4 +253,8 @@ def test_adjoint_rejects_misuse():
     sim.step(1)  # stepped after the recorded forward pass
     with pytest.raises(VlbError):
         sim.adjoint_backward(z, z)
+    sim.adjoint_forward(4, 2)
+    sim.set_tile(1)  # a different work list than the recorded forward pass
+    with pytest.raises(VlbError):
+        sim.adjoint_backward(z, z)
     sim.close()

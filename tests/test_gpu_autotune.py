@@ -1,0 +1,60 @@
+"""Autotuner: sweeps tile height and store mode, leaves the state untouched, caches."""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import FIELDS, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _exact(sim):
+    import torch
+
+    r = sim.read()
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def test_autotune_sweeps_restores_and_caches(tmp_path):
+    from paper_2508_16997_amd import Simulation
+    from paper_2508_16997_amd.autotune import size_class, tune
+
+    pr = synth.random_periodic(150, 70, seed=9, ymode="wall", precision="fp32")
+    say("autotune", pr.nx, pr.ny)
+    sim = Simulation.from_problem(pr, graph_chunk=10)
+    ref = Simulation.from_problem(pr, graph_chunk=10)
+    sim.step(7)
+    ref.step(7)
+    before = _exact(sim)
+    cache = str(tmp_path / "tune.json")
+    rec = tune(sim, steps=20, warmup=3, cache=cache)
+    assert rec["tile"] in (1, 2, 4, 8) and rec["store_mode"] in (1, 2)
+    assert len(rec["sweep_us"]) == 8 and min(rec["sweep_us"].values()) == rec["us_per_step"]
+    after = _exact(sim)
+    for k in FIELDS:
+        assert np.array_equal(before[k], after[k]), k
+    assert sim.time == 7
+    # tuned and untuned runs agree bit for bit
+    sim.step(33)
+    ref.step(33)
+    a, b = _exact(sim), _exact(ref)
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k
+    data = json.load(open(cache))
+    assert data[size_class(sim)]["tile"] == rec["tile"]
+    # a cached class is applied without a sweep
+    again = tune(sim, cache=cache)
+    assert again == data[size_class(sim)]
+    sim.close()
+    ref.close()

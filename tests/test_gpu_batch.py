@@ -163,10 +163,12 @@ def test_batch_picks_up_new_parameters():
     for s in single:
         s.step(20)
     stream.synchronize()
-    for sb, ss in zip(batched, single):
+    for i, (sb, ss) in enumerate(zip(batched, single)):
         gb, gs = _read_exact(sb), _read_exact(ss)
+        rb = {k: v.cpu().numpy() for k, v in b.read(i).items()}
         for k in FIELDS:
             assert np.array_equal(gb[k], gs[k]), k
+            assert np.array_equal(rb[k], gs[k]), ("batch read", k)
     b.close()
     for s in batched + single:
         s.close()

@@ -132,6 +132,38 @@ def test_four_roll_fp32_512_20k_steps_golden():
     assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
 
 
+def test_cylinder_fp32_full_size_1000_steps_golden():
+    """Full cylinder workload (4096 x 1024, R = 128, FP32 storage) after 1,000 steps.
+
+    Compared against oracle values written by tests/golden/make_cylinder_1000.py (oracle
+    only) at a stride-32 sample, every fluid node within two units of the cylinder (curved
+    links, CNEBB), and samples of the wall rows and the inlet/outlet columns; in the
+    launch configuration the benchmark times.
+    """
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "cylinder_1000.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    ref = np.load(path)
+    pr = synth.cylinder(Wi=float(ref["wi"]))
+    ys, xs = ref["ys"], ref["xs"]
+    say("cylinder fp32 golden", int(ref["steps"]), len(ys), "nodes")
+    from paper_2508_16997_amd import Simulation
+
+    sim = Simulation.from_problem(pr, graph_chunk=50, tile=4)
+    sim.step(int(ref["steps"]))
+    g = {k: v[ys, xs] for k, v in gpu_fields(sim).items()}
+    sim.close()
+    o = {k: ref[k] for k in FIELDS}
+    err = parity(g, o, np.ones_like(g["ux"], dtype=bool))
+    assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
+    near = np.sqrt((xs - 2048.0) ** 2 + (ys - 512.0) ** 2) <= 130.0
+    err_near = parity({k: v[near] for k, v in g.items()}, {k: v[near] for k, v in o.items()},
+                      np.ones(int(near.sum()), dtype=bool))
+    assert max(err_near["u"], err_near["axx"], err_near["axy"], err_near["ayy"]) < 1e-5, err_near
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_results_independent_of_tiling_and_graphs(prec):
     """Bit-identical fields for every tile height, with and without hipGraph replay."""
