@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # writes, so traffic = 2 * FETCH + WRITE.  Valid only for the kernel sources they were
 # taken with (hash below); otherwise the bench reports null.
 MEASURED_TRAFFIC = {
-    "four_roll_512": {"sources": "d82f5449f4f46b8a", "fetch_KiB": 27432.1, "write_KiB": 45493.8,
-                      "profile": "profiles/k_step_k_adj_four_roll_512_fp32_fetch_write.md"},
+    "four_roll_512": {"sources": "fd8ff90e28c10402", "fetch_KiB": 27539.3, "write_KiB": 45495.0,
+                      "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
 }
 KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_kernels.hip")
 
@@ -236,16 +236,10 @@ def adjoint_leg(steps, stride, tile, chunk):
             "loss": g["loss"], "dL_dlambda": g["dlambda"], "dL_deta_p": g["deta_p"]}
 
 
-def cpu_baseline(pr, seconds):
+def _oracle_rate(pr, seconds, threads):
     import oracle
 
-    oracle.build(force=False)
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    oracle.set_threads(cores)
+    oracle.set_threads(threads)
     o = oracle.OracleSim(pr)
     t0 = time.perf_counter()
     o.step(1)
@@ -255,10 +249,25 @@ def cpu_baseline(pr, seconds):
     o.step(n)
     dt = time.perf_counter() - t0
     nodes = int(pr.fluid_mask().sum())
-    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.max_threads(),
-            "kind": "oracle",
+    return nodes * n / dt / 1e6, n, dt, oracle.max_threads()
+
+
+def cpu_baseline(pr, seconds):
+    """The FP64 oracle as it stands, on all host cores (up to 16) and on one core."""
+    import oracle
+
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    v, n, dt, used = _oracle_rate(pr, seconds, cores)
+    v1, n1, dt1, _ = _oracle_rate(pr, seconds / 3.0, 1)
+    return {"value": v, "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{n} coupled FP64 steps of the same {pr.nx}x{pr.ny} workload "
-                      f"(after 1 untimed step), {dt:.1f} s"}
+                      f"(after 1 untimed step), {dt:.1f} s; one core: {n1} steps, {dt1:.1f} s",
+            "value_1_core": v1}
 
 
 def main():
