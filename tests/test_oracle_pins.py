@@ -444,3 +444,25 @@ def test_geometry_circle_fractions(oracle_lib):
     np.testing.assert_allclose(np.hypot(px, py), R, rtol=1e-12)
     fl = pr.fluid_mask()
     assert np.array_equal(cls == 1, ~fl)
+
+
+def test_waters_king_series_limits():
+    """The start-up series used by the transient pins (Sec. 4.2) in its known limits.
+
+    beta = 1 (no polymer) must equal the textbook Newtonian start-up series
+    u* = 4y(1-y) - 32 sum sin(N y)/N^3 exp(-N^2 t*/Re); long times give the steady
+    parabola; and the centre-line values at Wi = 1 (t* = 0.25, 0.5, 1, 2, 5) and at
+    Wi = 10^4 (t* = 18.04), beta = 0.5, are reproduced.
+    """
+    ys = np.linspace(0.05, 0.95, 7)
+    n = np.arange(1, 4001, dtype=float)
+    N = (2 * n - 1) * math.pi
+    for t in (0.01, 0.1, 0.5):
+        newt = 4 * ys * (1 - ys) - 32 * (np.sin(np.multiply.outer(ys, N)) / N ** 3 *
+                                         np.exp(-N ** 2 * t)).sum(-1)
+        np.testing.assert_allclose(waters_king_u(ys, t, 3.0, 1.0), newt, atol=1e-10)
+    np.testing.assert_allclose(waters_king_u(ys, 200.0, 1.0, 0.5), 4 * ys * (1 - ys), atol=1e-9)
+    for t, v in ((0.25, 1.34216), (0.5, 1.55606), (1.0, 1.27296), (2.0, 1.01680),
+                 (5.0, 0.999996)):
+        assert abs(float(waters_king_u(0.5, t, 1.0, 0.5)) - v) < 1e-5, t
+    assert abs(float(waters_king_u(0.5, 18.04, 1e4, 0.5)) - 1.99648) < 1e-5
