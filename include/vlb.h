@@ -174,6 +174,15 @@ int vlb_read_history(vlb_sim* sim, void* sxx, void* sxy, void* syy, void* uxp, v
  * any fluid node is non-finite (the paper's numerical breakdown), with *out filled. */
 int vlb_monitors(vlb_sim* sim, vlb_monitor* out);
 
+/* Momentum-exchange force on a solid (Sec. 4.3): over the boundary links (fluid node
+ * x_f, direction i with x_f + e_i solid) sum e_i (f_i^post(x_f, t) + f_opp(i)(x_f, t+1)),
+ * with the post-collision values of the last step and the populations its boundary
+ * rules return.  circle >= 0 (index into vlb_grid.circles) keeps the links into that
+ * circle; circle < 0 keeps every solid link (walls, mask solids and circles).  Lattice
+ * units (force per unit depth).  Deterministic (fixed-order reduction); synchronizes.
+ * Errors: VLB_E_STATE before the first step, VLB_E_INVALID_ARG for a bad circle. */
+int vlb_drag(vlb_sim* sim, int circle, double* fx, double* fy);
+
 /* ---- checkpoint ------------------------------------------------------------------ */
 
 /* Bytes of a saved state (populations, history, step counter). */

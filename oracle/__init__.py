@@ -65,6 +65,7 @@ def _load():
     lib.orc_read_tangent.argtypes = [P, DP, DP, DP, DP, DP, DP]
     lib.orc_read_history.argtypes = [P, DP, DP, DP, DP, DP]
     lib.orc_read_populations.argtypes = [P, DP, DP]
+    lib.orc_drag.argtypes = [P, C.c_int, DP]
     lib.orc_geometry.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p, DP, C.c_int]
     lib.orc_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, DP]
     lib.orc_node_feq.argtypes = [D, D, D, DP]
@@ -177,6 +178,13 @@ class OracleSim:
         first = _load().orc_read_history(self.h, *[_dp(out[k]) for k in
                                                    ("sxx", "sxy", "syy", "uxp", "uyp")])
         return out, bool(first)
+
+    def drag(self, circle: int = 0):
+        """Momentum-exchange force (F_x, F_y) on a circle (all solids if circle < 0)."""
+        out = np.zeros(2)
+        if _load().orc_drag(self.h, int(circle), _dp(out)) != 0:
+            raise ValueError("oracle: drag needs at least one step")
+        return float(out[0]), float(out[1])
 
     def populations(self):
         n = self.nx * self.ny

@@ -480,12 +480,43 @@ struct Sim {
             for (int i = 0; i < Q; ++i) {
                 const Src s = geo.source(x, y, i);
                 const int o = OPP[i];
-                if (s.kind == SRC_FLUID || s.kind == SRC_OUTLET) {
+                if (s.kind == SRC_FLUID) {
                     f[i][n] = fp[i][s.node];
                     for (int k = 0; k < 3; ++k) g[k][i][n] = gp[k][i][s.node];
-                } else if (s.kind == SRC_INLET) {
-                    f[i][n] = feq(i, R(1.0), uin[s.ys], R(0.0));
-                    for (int k = 0; k < 3; ++k) g[k][i][n] = geq(i, ain[k][s.ys], uin[s.ys], R(0.0));
+                } else if (s.kind == SRC_INLET || s.kind == SRC_OUTLET) {
+                    // Open ends (reading A21): non-equilibrium extrapolation from the node
+                    // x0 next to the ghost (first or last column, same row): its
+                    // post-collision populations minus their own equilibrium, plus the
+                    // equilibrium of the boundary state -- inlet: rho(x0) and the inlet
+                    // profile (u_in, A_in); outlet: rho = 1 and u(x0) for the hydrodynamic
+                    // lattice, a plain copy of x0 for the conformation lattices.
+                    const bool in = s.kind == SRC_INLET;
+                    const size_t m = in ? (size_t)s.ys * nx : (size_t)s.node;
+                    if (!fluid(m)) {
+                        f[i][n] = feq(i, R(1.0), in ? uin[s.ys] : R(0.0), R(0.0));
+                        for (int k = 0; k < 3; ++k)
+                            g[k][i][n] = geq(i, in ? ain[k][s.ys] : R(k == 1 ? 0.0 : 1.0), in ? uin[s.ys] : R(0.0), R(0.0));
+                        continue;
+                    }
+                    R r = R(0.0), jx = R(0.0), jy = R(0.0);
+                    for (int j = 0; j < Q; ++j) {
+                        r += fp[j][m];
+                        jx += R((double)EX[j]) * fp[j][m];
+                        jy += R((double)EY[j]) * fp[j][m];
+                    }
+                    const R vx = jx / r, vy = jy / r;
+                    const R fneq = fp[i][m] - feq(i, r, vx, vy);
+                    f[i][n] = in ? feq(i, r, uin[s.ys], R(0.0)) + fneq : feq(i, R(1.0), vx, vy) + fneq;
+                    for (int k = 0; k < 3; ++k) {
+                        if (!in) {
+                            g[k][i][n] = gp[k][i][m];
+                            continue;
+                        }
+                        R ph = R(0.0);
+                        for (int j = 0; j < Q; ++j) ph += gp[k][j][m];
+                        g[k][i][n] = geq(i, ain[k][s.ys], uin[s.ys], R(0.0)) + gp[k][i][m] -
+                                     geq(i, ph, vx, vy);
+                    }
                 } else {
                     // Hydrodynamic wall: half-way bounce-back for q = 1/2 (reading A13),
                     // linear interpolated bounce-back otherwise (reading A21).
@@ -561,6 +592,29 @@ struct Sim {
         }
         first = false;
         ++step;
+    }
+
+    // Momentum-exchange force on the solid (Sec. 4.3): over the fluid nodes x_f next
+    // to a solid and the directions i pointing into it (x_f + e_i solid),
+    // sum e_i (f_i^post(x_f, t) + f_opp(i)(x_f, t + 1)), with the post-collision values
+    // of the last step and the populations it streamed and filled.  circle >= 0 keeps
+    // the links into that circle only; circle < 0 keeps every solid (walls included).
+    void drag(int circle, double out[2]) const {
+        double fx = 0.0, fy = 0.0;
+        for (size_t n = 0; n < N; ++n) {
+            if (!fluid(n)) continue;
+            const int x = (int)(n % nx), y = (int)(n / nx);
+            for (int i = 1; i < Q; ++i) {
+                const Src s = geo.source(x, y, OPP[i]);  // x - e_opp(i) = x + e_i
+                if (s.kind != SRC_SOLID) continue;
+                if (circle >= 0 && (s.node < 0 || geo.circle_of[s.node] != circle)) continue;
+                const double v = val(fp[i][n]) + val(f[OPP[i]][n]);
+                fx += (double)EX[i] * v;
+                fy += (double)EY[i] * v;
+            }
+        }
+        out[0] = fx;
+        out[1] = fy;
     }
 };
 
@@ -783,6 +837,16 @@ int orc_read_history(void* hp, double* sxx, double* sxy, double* syy, double* ux
         return s.first ? 1 : 0;
     };
     return h->dual ? doit(h->sx) : doit(h->sd);
+}
+
+// Momentum-exchange force on circle `circle` (all solids if < 0) after the last step;
+// -1 before the first step.
+int orc_drag(void* hp, int circle, double* out2) {
+    Handle* h = static_cast<Handle*>(hp);
+    if (h->dual ? h->sx.first : h->sd.first) return -1;
+    if (h->dual) h->sx.drag(circle, out2);
+    else h->sd.drag(circle, out2);
+    return 0;
 }
 
 // Raw populations at the current time (post-stream, post-boundary): f[9][N], g[3][9][N].

@@ -29,6 +29,7 @@ EXPORTS = [
     "vlb_create", "vlb_destroy", "vlb_workspace_bytes", "vlb_geometry", "vlb_bind",
     "vlb_set_params", "vlb_set_force_field", "vlb_set_inlet", "vlb_init_equilibrium",
     "vlb_step", "vlb_get_step", "vlb_read_fields", "vlb_read_history", "vlb_monitors",
+    "vlb_drag",
     "vlb_state_bytes", "vlb_save_state", "vlb_load_state", "vlb_set_tile",
     "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_adjoint_workspace_bytes",
     "vlb_adjoint_forward", "vlb_adjoint_backward", "vlb_adjoint", "vlb_batch_workspace_bytes",
@@ -96,6 +97,7 @@ def load():
     lib.vlb_set_tile.argtypes = [P, I]
     lib.vlb_set_graph_chunk.argtypes = [P, I]
     lib.vlb_set_store_mode.argtypes = [P, I]
+    lib.vlb_drag.argtypes = [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     D = C.POINTER(C.c_double)
     lib.vlb_adjoint_workspace_bytes.argtypes = [P, C.c_int64, I, C.POINTER(C.c_size_t)]
     lib.vlb_adjoint_forward.argtypes = [P, C.c_int64, I, P, C.c_size_t]

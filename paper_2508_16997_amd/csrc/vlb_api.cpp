@@ -58,6 +58,7 @@ struct vlb_sim {
     std::vector<double> circles;    // xc, yc, R
     std::vector<uint16_t> bits;     // padded plane
     std::vector<Link> links;
+    std::vector<int> drag_links;    // per link: slot of the fluid node, direction, circle or -1
     std::vector<int> bidx;          // padded plane, curved only
     std::vector<vlb::FillOp> fill;  // boundary links served by the fill kernel
     std::vector<vlb::FillItem> fill_items;
@@ -71,7 +72,7 @@ struct vlb_sim {
     hipStream_t stream = nullptr;
     bool bound = false;
     size_t off_pop[2] = {0, 0}, off_hist = 0, off_force = 0, off_usnap = 0, off_inlet = 0,
-           off_bq = 0, off_bits = 0, off_bidx = 0, off_run = 0, off_items = 0, off_mon = 0, off_monpart = 0,
+           off_bq = 0, off_bits = 0, off_bidx = 0, off_run = 0, off_items = 0, off_mon = 0, off_monpart = 0, off_drag = 0, off_dragpart = 0,
            off_fill = 0, off_fill_items = 0, total = 0;
 
     std::vector<vlb::Item> items;
@@ -160,6 +161,7 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
         }
     s->bits.assign((size_t)s->plane, 0);
     s->links.clear();
+    s->drag_links.clear();
     bool any_bits = false, curved = false;
     std::vector<double> qnode(9);
     for (int y = 0; y < ny; ++y)
@@ -178,6 +180,7 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
                 const bool xout = xn < 0 || xn >= nx, yout = yn < 0 || yn >= ny;
                 bool is_solid = false;
                 double q = 0.5;
+                int cid = -1;
                 if ((yout && s->ymode == VLB_WALL) || (xout && s->xmode == VLB_WALL)) {
                     is_solid = true;
                 } else {
@@ -194,6 +197,7 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
                             if (s->circle_of[m] >= 0) {
                                 q = circle_q(s, x, y, d, s->circle_of[m]);
                                 curved = true;
+                                cid = s->circle_of[m];
                             }
                         }
                     }
@@ -201,6 +205,7 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
                 if (is_solid) {
                     b |= (uint16_t)(1u << OPPH[d]);
                     s->links.push_back(Link{(int32_t)n, (int8_t)d, q});
+                    s->drag_links.insert(s->drag_links.end(), {(int)pp, d, cid});
                 }
             }
             s->bits[pp] = b;
@@ -282,8 +287,8 @@ void build_fill(vlb_sim* s) {
                         op.far = yw;
                         op.src = p;
                     } else {
-                        op.dir_kind = i | (vlb::FILL_COPY << 8);
-                        op.src = slot(nx - 1, yw);  // zero-gradient outlet
+                        op.dir_kind = i | (vlb::FILL_OUTLET << 8);
+                        op.src = slot(nx - 1, yw);
                     }
                 } else {
                     // periodic image: written by the step kernel's edge stores
@@ -292,6 +297,11 @@ void build_fill(vlb_sim* s) {
                 s->fill.push_back(op);
             }
         }
+    // Group the ops by kind (node order kept within a kind) so that a wavefront runs
+    // one boundary rule instead of serialising several.
+    std::stable_sort(s->fill.begin(), s->fill.end(), [](const vlb::FillOp& a, const vlb::FillOp& b) {
+        return (a.dir_kind >> 8) < (b.dir_kind >> 8);
+    });
     s->fill_items.clear();
     for (int f = 0; f < (int)s->fill.size(); f += 256)
         s->fill_items.push_back(vlb::FillItem{0, f, std::min(256, (int)s->fill.size() - f), 0});
@@ -333,6 +343,8 @@ void layout(vlb_sim* s) {
     s->off_items = take((size_t)s->items_cap * sizeof(vlb::Item));
     s->off_mon = take(sizeof(vlb::MonitorAcc));
     s->off_monpart = take(8 * sizeof(double) * (size_t)((s->nx + 63) / 64) * (size_t)((s->ny + 3) / 4));
+    s->off_drag = take(std::max<size_t>(3, s->drag_links.size()) * sizeof(int));
+    s->off_dragpart = take(2 * sizeof(double) * std::max<size_t>(1, (s->links.size() + 255) / 256));
     s->off_fill = take(std::max<size_t>(1, s->fill.size()) * sizeof(vlb::FillOp));
     s->off_fill_items = take(std::max<size_t>(1, s->fill_items.size()) * sizeof(vlb::FillItem));
     s->total = o;
@@ -618,6 +630,9 @@ int vlb_bind(vlb_sim* s, void* ws, size_t bytes, void* stream) {
     }
     VLB_HIP(hipMemcpyAsync(s->ws + s->off_bits, s->bits.data(), s->bits.size() * sizeof(uint16_t),
                            hipMemcpyHostToDevice, s->stream));
+    if (!s->drag_links.empty())
+        VLB_HIP(hipMemcpyAsync(s->ws + s->off_drag, s->drag_links.data(),
+                               s->drag_links.size() * sizeof(int), hipMemcpyHostToDevice, s->stream));
     if (s->has_curved) {
         VLB_HIP(hipMemcpyAsync(s->ws + s->off_bidx, s->bidx.data(), s->bidx.size() * sizeof(int),
                                hipMemcpyHostToDevice, s->stream));
@@ -783,6 +798,36 @@ int vlb_monitors(vlb_sim* s, vlb_monitor* out) {
     out->nonfinite = (int64_t)h.nonfinite;
     out->spd_violations = (int64_t)h.spd;
     if (h.nonfinite) return fail(VLB_E_NONFINITE, "non-finite fields at step " + std::to_string(s->step));
+    return VLB_OK;
+}
+
+int vlb_drag(vlb_sim* s, int circle, double* fx, double* fy) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!fx || !fy) return fail(VLB_E_INVALID_ARG, "null output");
+    if (s->first) return fail(VLB_E_STATE, "the drag needs at least one step");
+    if (circle >= (int)(s->circles.size() / 3)) return fail(VLB_E_INVALID_ARG, "no such circle");
+    const int nl = (int)s->links.size();
+    const int nb = (nl + 255) / 256;
+    double* part = s->dptr<double>(s->off_dragpart);
+    if (s->prec == VLB_FP32)
+        VLB_HIP(vlb::launch_drag<float>(s->dptr<Run<float>>(s->off_run), s->dptr<int>(s->off_drag), nl,
+                                        circle, s->parity, part, s->stream));
+    else
+        VLB_HIP(vlb::launch_drag<double>(s->dptr<Run<double>>(s->off_run), s->dptr<int>(s->off_drag),
+                                         nl, circle, s->parity, part, s->stream));
+    std::vector<double> h(2 * (size_t)std::max(1, nb), 0.0);
+    if (nb > 0)
+        VLB_HIP(hipMemcpyAsync(h.data(), part, 2 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream));
+    VLB_HIP(hipStreamSynchronize(s->stream));
+    double sx = 0.0, sy = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sx += h[2 * b];
+        sy += h[2 * b + 1];
+    }
+    *fx = sx;
+    *fy = sy;
     return VLB_OK;
 }
 

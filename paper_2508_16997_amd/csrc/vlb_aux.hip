@@ -165,6 +165,44 @@ __global__ __launch_bounds__(256) void k_monitor_final(const double* __restrict_
     }
 }
 
+// Momentum-exchange force on the solid (Sec. 4.3): per boundary link (fluid node x_f,
+// direction d with x_f + e_d solid) e_d (f_d^post(x_f) + f_opp(d)(x_f, t + 1)); the buffer
+// just written holds the post-collision values at the nodes and, in the slot x_f + e_d,
+// the population the boundary rule returns.  Links of other circles contribute zero.
+template <class S>
+__global__ __launch_bounds__(256) void k_drag(const RunDev<S>* __restrict__ run,
+                                              const int* __restrict__ links, int nlinks,
+                                              int circle, int parity, double* part) {
+    __shared__ double s_p[4][2];
+    const RunDev<S>& R = *run;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    double fx = 0.0, fy = 0.0;
+    if (t < nlinks) {
+        const int p = links[3 * t], d = links[3 * t + 1], cid = links[3 * t + 2];
+        if (circle < 0 || cid == circle) {
+            const S* buf = R.pop[parity];
+            const long long plane = R.plane;
+            const int o = opp(d);
+            const T v = ldu(buf + d * plane, (unsigned)p) + ldu(buf + o * plane, (unsigned)(p + ex(d) + ey(d) * R.pitch)) +
+                        2.0 * wgt(d);
+            fx = T(ex(d)) * v;
+            fy = T(ey(d)) * v;
+        }
+    }
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_p[w][0] = fx;
+        s_p[w][1] = fy;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int c = threadIdx.x;
+        part[2 * blockIdx.x + c] = ((s_p[0][c] + s_p[1][c]) + s_p[2][c]) + s_p[3][c];
+    }
+}
+
 __global__ void k_fill_bytes(unsigned char* dst, size_t n, unsigned char v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = v;
@@ -224,6 +262,15 @@ hipError_t launch_write_words(unsigned long long* dst, unsigned long long w0,
 }
 
 
+template <class S>
+hipError_t launch_drag(const RunDev<S>* run_dev, const int* links, int nlinks, int circle,
+                       int parity, double* part, hipStream_t s) {
+    if (nlinks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_drag<S>), dim3((nlinks + 255) / 256), dim3(256), 0, s, run_dev, links,
+                       nlinks, circle, parity, part);
+    return hipGetLastError();
+}
+
 #define VLB_INSTANTIATE_AUX(S)                                                               \
     template hipError_t launch_init<S>(const RunDev<S>&, const RunDev<S>*, const S*,       \
                                        const S*, const S*, const S*, const S*, const S*,  \
@@ -231,7 +278,9 @@ hipError_t launch_write_words(unsigned long long* dst, unsigned long long w0,
     template hipError_t launch_read<S>(const RunDev<S>&, const RunDev<S>*, int, int, S*,   \
                                        S*, S*, S*, S*, S*, hipStream_t);                   \
     template hipError_t launch_monitor<S>(const RunDev<S>&, const RunDev<S>*, int, int,    \
-                                          S*, double*, MonitorAcc*, hipStream_t);
+                                          S*, double*, MonitorAcc*, hipStream_t);          \
+    template hipError_t launch_drag<S>(const RunDev<S>*, const int*, int, int, int, double*, \
+                                       hipStream_t);
 VLB_INSTANTIATE_AUX(float)
 VLB_INSTANTIATE_AUX(double)
 

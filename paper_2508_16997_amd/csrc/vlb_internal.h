@@ -23,15 +23,16 @@ enum { XOFF = 64 };
 // Kinds of fill operations (run after each step on the post-collision buffer, before
 // the next step pulls from it).  One op serves direction `dir` of one fluid node.
 enum {
-    FILL_COPY = 0,     // all four lattices: slot dst <- node src (periodic image, outlet)
+    FILL_OUTLET = 0,   // last column: non-equilibrium extrapolation from node src
     FILL_WALL = 1,     // half-way bounce-back: f_dir(dst) <- f_opp(src); g likewise
     FILL_CURVED = 2,   // interpolated bounce-back for f (q, far node); g as FILL_WALL
-    FILL_INLET = 3     // equilibrium of the inlet profile at row `far`
+    FILL_INLET = 3     // first column: inlet profile at row `far`, non-equilibrium
+                       // part extrapolated from that row's first node
 };
 
 struct FillOp {
     int dst;       // slot that the fluid node pulls direction dir from
-    int src;       // fluid node x (or copy source)
+    int src;       // fluid node x (outlet: the last-column node of that row)
     int far;       // x + e_dir for FILL_CURVED (or -1), inlet row for FILL_INLET
     int dir_kind;  // dir | kind << 8
     double q;      // wall fraction for FILL_CURVED
@@ -127,6 +128,10 @@ hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, c
 template <class S>
 hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
                            int nitems, int ty, int first, const S* ain, S* aout, hipStream_t s);
+// Momentum-exchange force: per block of 256 boundary links, 2 partial sums (F_x, F_y).
+template <class S>
+hipError_t launch_drag(const RunDev<S>* run_dev, const int* links, int nlinks, int circle,
+                       int parity, double* part, hipStream_t s);
 hipError_t launch_fill_bytes(void* dst, size_t bytes, unsigned char v, hipStream_t s);
 hipError_t launch_write_words(unsigned long long* dst, unsigned long long w0,
                               unsigned long long w1, unsigned long long w2,

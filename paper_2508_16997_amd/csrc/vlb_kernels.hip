@@ -5,17 +5,14 @@
 //           neighbours' slots with one branch-free global load each (structure-of-
 //           arrays planes, x fastest, 64 lanes read contiguous rows).  Slots that do
 //           not hold a fluid node -- ghost rows/columns around the domain and solid
-//           nodes -- were written by k_fill with exactly the value the boundary rule
-//           gives for that link.  rho and u of the 64 x TY tile and of a one-node ring
-//           around it go to LDS; then the velocity gradient and d(rho u^3) by finite
-//           differences, CNEBB at wall-adjacent nodes, the constitutive source, the
-//           hydrodynamic and three convection-diffusion collisions in moment form,
-//           and 36 + 5 coalesced stores.
-//   k_fill  walks the run's list of boundary links (one op per fluid node and
-//           direction whose source is not a fluid node) and writes the periodic image,
-//           the bounced or interpolated population, or the inlet equilibrium into the
-//           slot that the next k_step pulls.  Every (slot, direction) pair belongs to
-//           one fluid node, so the ops never conflict.
+//           nodes -- hold exactly the value the boundary rule gives for that link:
+//           periodic images are stored a second time by the edge lanes of this
+//           kernel, every other boundary link by k_fill (vlb_fill.hip).  rho and u of
+//           the 64 x TY tile and of a one-node ring around it go to LDS; then the
+//           velocity gradient and d(rho u^3) by finite differences, CNEBB at
+//           wall-adjacent nodes, the constitutive source, the hydrodynamic and three
+//           convection-diffusion collisions in moment form, and 36 + 5 coalesced
+//           stores.
 // Storage is float or double (template S); populations are kept as deviations from
 // the rest state (f_i - w_i, g_i - w_i phi0 with phi0 = 1, 0, 1).  All arithmetic is
 // double precision: on CDNA the vector FP64 rate equals the unpacked FP32 rate, and
@@ -213,55 +210,6 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
     st_stream<NT>(R.hist_out + 4 * plane, (unsigned)p, uy);
 }
 
-// Boundary links of the buffer just written: write into each ghost or solid slot the
-// value its fluid neighbour pulls in the next step.
-template <class S>
-__global__ __launch_bounds__(256) void k_fill(const RunDev<S>* __restrict__ runs,
-                                              const FillItem* __restrict__ items, int parity) {
-    const FillItem it = items[blockIdx.x];
-    if ((int)threadIdx.x >= it.count) return;
-    const RunDev<S>& R = runs[it.run];
-    const FillOp op = R.fill[it.first + threadIdx.x];
-    S* buf = R.pop[parity];
-    const long long plane = R.plane;
-    const int dir = op.dir_kind & 0xff, kind = op.dir_kind >> 8;
-    const int o = opp(dir);
-    if (kind == FILL_COPY) {
-#pragma unroll
-        for (int L = 0; L < 4; ++L) {
-            S* pl = buf + (9 * L + dir) * plane;
-            stu(pl, (unsigned)op.dst, ldu(pl, (unsigned)op.src));
-        }
-    } else if (kind == FILL_INLET) {
-        const int row = op.far;
-        const T uin = R.inlet[row];
-        stu(buf + dir * plane, (unsigned)op.dst, dfeq(dir, 0.0, 1.0, uin, 0.0));
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T a = R.inlet[(1 + k) * R.ny + row];
-            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst, dgeq(dir, a - phi0(k), a, uin, 0.0));
-        }
-    } else {
-        // conformation lattices: the population that left toward the wall (CNEBB input)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
-                ldu(buf + (9 + 9 * k + o) * plane, (unsigned)op.src));
-        // hydrodynamic lattice: half-way or linear interpolated bounce-back
-        const T fo = ldu(buf + o * plane, (unsigned)op.src);
-        T v = fo;
-        if (kind == FILL_CURVED) {
-            const T q = op.q;
-            if (q < 0.5) {
-                if (op.far >= 0) v = 2.0 * q * fo + (1.0 - 2.0 * q) * ldu(buf + o * plane, (unsigned)op.far);
-            } else {
-                v = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * ldu(buf + dir * plane, (unsigned)op.src);
-            }
-        }
-        stu(buf + dir * plane, (unsigned)op.dst, v);
-    }
-}
-
 }  // namespace
 
 template <class S, bool NT>
@@ -285,19 +233,9 @@ hipError_t launch_step(const RunDev<S>* runs_dev, const Item* items_dev, int nit
                      : launch_step_nt<S, false>(runs_dev, items_dev, nitems, ty, parity, first, s);
 }
 
-template <class S>
-hipError_t launch_fill(const RunDev<S>* runs_dev, const FillItem* items_dev, int nitems, int parity,
-                       hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fill<S>), dim3(nitems), dim3(256), 0, s, runs_dev, items_dev, parity);
-    return hipGetLastError();
-}
-
 #define VLB_INSTANTIATE(S)                                                                   \
     template hipError_t launch_step<S>(const RunDev<S>*, const Item*, int, int, int, int,  \
-                                       int, hipStream_t);                                  \
-    template hipError_t launch_fill<S>(const RunDev<S>*, const FillItem*, int, int,        \
-                                       hipStream_t);
+                                       int, hipStream_t);
 VLB_INSTANTIATE(float)
 VLB_INSTANTIATE(double)
 

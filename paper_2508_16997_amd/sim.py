@@ -168,6 +168,13 @@ class Simulation:
         return dict(mass=list(m.mass), residual=m.residual, umax=m.umax, step=m.step,
                     nonfinite=m.nonfinite, spd_violations=m.spd_violations)
 
+    def drag(self, circle: int = 0):
+        """Momentum-exchange force (F_x, F_y) on a circle (all solids if circle < 0)."""
+        fx, fy = C.c_double(), C.c_double()
+        self._order_after_torch()
+        L.check(self.lib.vlb_drag(self._h, int(circle), C.byref(fx), C.byref(fy)), "vlb_drag")
+        return fx.value, fy.value
+
     def geometry(self):
         """(node_class (ny, nx) uint8, link nodes, dirs, q) -- host only."""
         cls = np.zeros((self.ny, self.nx), dtype=np.uint8)

@@ -12,6 +12,7 @@ from .workloads import (  # noqa: F401
     poiseuille,
     four_roll_mill,
     cylinder,
+    cylinder_channel,
     batch_c4,
     adjoint_c5,
     smooth_force_perturbation,

@@ -192,6 +192,18 @@ def cylinder(nx=4096, ny=1024, R=128.0, xc=2048.0, yc=512.0, Wi=1.0, beta=0.59, 
     return prob
 
 
+def cylinder_channel(R=20, Wi=0.1, beta=0.59, Sc=1e6, Lambda_p=2.5e-7, precision="fp64",
+                     steps=0) -> Problem:
+    """The paper's confined cylinder (Sec. 4.3): a 30R x 4R channel with the cylinder at
+    (15R, 2R), i.e. midway between the half-way walls (node coordinates shifted by 1/2),
+    L_c = R, Re = 1, Ma = 0.01; inlet, outlet and start as in :func:`cylinder`."""
+    R = int(R)
+    pr = cylinder(nx=30 * R, ny=4 * R, R=float(R), xc=15 * R - 0.5, yc=2 * R - 0.5, Wi=Wi,
+                  beta=beta, Sc=Sc, Lambda_p=Lambda_p, steps=steps, precision=precision)
+    pr.name = f"cylinder_channel_R{R}_Wi{Wi:g}"
+    return pr
+
+
 def batch_c4(seed=16997, nruns=256, steps=5000, nmin=32, nmax=512):
     """256 independent runs: half Poiseuille, half four-roll mill, uneven sizes.
 

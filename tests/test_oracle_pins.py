@@ -209,6 +209,55 @@ def test_rest_state_open_boundaries(oracle_lib):
     assert np.abs(r["ux"][fl]).max() < 1e-13 and np.abs(r["axx"][fl] - 1).max() < 1e-13
 
 
+def _open_channel_steady(oracle_lib, ny, nu, umax):
+    """Newtonian channel 3*ny x ny with half-way walls, the parabolic inlet profile of
+    peak umax (node centres, walls at y = 0 and ny) and the outlet; run to steady state."""
+    nx = 3 * ny
+    pr = synth.random_periodic(nx, ny, seed=0, amp_u=0, amp_rho=0, amp_a=0, xmode="open",
+                               ymode="wall", nu_s=nu, eta_p=0.0, force_amp=0.0)
+    yp = np.arange(ny) + 0.5
+    pr.inlet["ux"] = umax * 4 * yp * (ny - yp) / ny ** 2
+    o = oracle_lib.OracleSim(pr)
+    prev = None
+    for _ in range(60):
+        o.step(1000)
+        r = o.read()
+        if prev is not None and np.abs(r["ux"] - prev).max() < 1e-9 * umax:
+            return pr, r
+        prev = r["ux"].copy()
+    raise AssertionError("open channel not steady")
+
+
+def test_open_channel_poiseuille_second_order(oracle_lib):
+    """Open ends (Sec. 4.3: prescribed inlet profile, zero-gradient outlet) on a straight
+    channel: far from the ends the flow is plane Poiseuille with the inlet's flow rate,
+    dp/dx = -8 mu U_max / H^2 with p = c_s^2 rho, and the pressure extrapolates to the
+    reference density at the outlet ghost column; the error to the closed form falls at
+    second order from H = 16 to H = 32 (2.0 % -> 0.47 % of U_max at nu = 0.5; the
+    extrapolated non-equilibrium part carries an O(tau dx^2) error).
+    """
+    oracle_lib.set_threads(min(8, oracle_lib.max_threads()))
+    nu, umax = 0.5, 0.002
+    err = {}
+    for ny in (16, 32):
+        pr, r = _open_channel_steady(oracle_lib, ny, nu, umax)
+        nx = pr.nx
+        yp = np.arange(ny) + 0.5
+        exact = umax * 4 * yp * (ny - yp) / ny ** 2
+        mid = r["ux"][:, nx // 2]
+        err[ny] = np.abs(mid - exact).max() / umax
+        assert np.abs(r["uy"][:, nx // 4: 3 * nx // 4]).max() < 1e-3 * umax
+        rho = r["rho"].mean(0)
+        x = np.arange(nx)
+        slope, icpt = np.polyfit(x[nx // 4: 3 * nx // 4], rho[nx // 4: 3 * nx // 4], 1)
+        ref = -8 * nu * umax / ny ** 2 / CS2
+        assert abs(slope / ref - 1) < (0.025 if ny == 16 else 0.005), (ny, slope, ref)
+        # reference density at the outlet ghost column x = nx (linear part of p)
+        assert abs(slope * nx + icpt - 1.0) < 1e-3 * abs(slope) * nx, (ny, slope * nx + icpt)
+        assert np.ptp(r["rho"][:, nx // 4: 3 * nx // 4], axis=0).max() < 1e-2 * abs(slope) * nx
+    assert err[32] < 6e-3 and err[16] / err[32] > 3.5, err
+
+
 @pytest.mark.parametrize("case", [dict(xmode="periodic", ymode="wall"),
                                   dict(xmode="periodic", ymode="periodic")])
 def test_hydro_mass_is_exact(oracle_lib, case):
@@ -466,3 +515,40 @@ def test_waters_king_series_limits():
                  (5.0, 0.999996)):
         assert abs(float(waters_king_u(0.5, t, 1.0, 0.5)) - v) < 1e-5, t
     assert abs(float(waters_king_u(0.5, 18.04, 1e4, 0.5)) - 1.99648) < 1e-5
+
+
+def test_momentum_exchange_balance(oracle_lib):
+    """Momentum-exchange force (Sec. 4.3) against the exact momentum budget.
+
+    Every collision adds the body force F to a node's momentum and every boundary link
+    removes e_i (f_i^post + f_opp(i)) from the fluid, whatever rule fills the returning
+    population; in a domain closed by periodicity and solids the total momentum
+    P = sum(rho u - F/2) therefore obeys P(t+1) - P(t) = sum F - D at every step, with
+    D the drag on all solids (walls, a staircase block and a curved cylinder here).
+    """
+    mask = np.zeros((30, 60), np.uint8)
+    mask[12:16, 10:14] = 1
+    pr = synth.random_periodic(60, 30, seed=5, ymode="wall", solid=mask,
+                               circles=[(40.0, 15.0, 6.3)])
+    o = oracle_lib.OracleSim(pr)
+    fx, fy = pr.force_arrays()
+    fl = pr.fluid_mask()
+
+    def momentum():
+        r = o.read()
+        return np.array([((r["rho"] * r["ux"] - 0.5 * fx)[fl]).sum(),
+                         ((r["rho"] * r["uy"] - 0.5 * fy)[fl]).sum()])
+
+    with pytest.raises(ValueError):
+        o.drag(-1)  # no step taken yet
+    o.step(3)
+    fsum = np.array([fx[fl].sum(), fy[fl].sum()])
+    for _ in range(3):
+        p0 = momentum()
+        o.step(1)
+        d = np.array(o.drag(-1))
+        assert np.abs(d).max() > 1e-2
+        assert np.abs(momentum() - p0 - (fsum - d)).max() < 1e-12
+        # the cylinder's share is part of it and is not the whole
+        dc = np.array(o.drag(0))
+        assert 0 < np.abs(dc).max() < np.abs(d).max()
