@@ -75,10 +75,22 @@ typedef struct {
     int ncircles;
 } vlb_grid;
 
+/* Constitutive closures (Sec. 2.2: the model function F(A) enters the conformation
+ * equation as the relaxation term -(1/lambda) F and the Kramers relation as the stress
+ * (eta_p / lambda) F).  The paper's runs use Oldroyd-B, F = A - I.  The others, in
+ * conformation form with the 2-D trace tr A (2 at rest), relaxation function F_r and
+ * stress function F_s:
+ *   VLB_GIESEKUS  model_param = alpha in [0, 1]:  F_r = (A - I) + alpha (A - I)^2,  F_s = A - I
+ *   VLB_LPTT      model_param = eps >= 0:   F_r = [1 + eps (tr A - 2)] (A - I),  F_s = A - I
+ *   VLB_EPTT      model_param = eps >= 0:   F_r = exp[eps (tr A - 2)] (A - I),   F_s = A - I
+ *   VLB_FENE_P    model_param = L^2 > 2:    F_r = F_s = f A - I, f = (L^2 - 2) / (L^2 - tr A) */
+enum { VLB_OLDROYD_B = 0, VLB_GIESEKUS = 1, VLB_LPTT = 2, VLB_EPTT = 3, VLB_FENE_P = 4 };
+
 /* Lattice-unit parameters (rho0 = 1).  The library derives the relaxation times of
  * Sec. 3.1-3.2: tau_s1 = nu_s / c_s^2 + 1/2, tau_s2 = Lambda_s / (tau_s1 - 1/2) + 1/2,
- * tau_p1 = kappa / c_s^2 + 1/2, tau_p2 = Lambda_p / (tau_p1 - 1/2) + 1/2, and uses the
- * Oldroyd-B closure tau_ab = (eta_p / lambda)(A_ab - delta_ab). */
+ * tau_p1 = kappa / c_s^2 + 1/2, tau_p2 = Lambda_p / (tau_p1 - 1/2) + 1/2, and the
+ * polymer stress tau_ab = (eta_p / lambda) F_s(A)_ab of the chosen closure (zero
+ * initialisation gives Oldroyd-B). */
 typedef struct {
     double nu_s;      /* solvent kinematic viscosity, > 0                  */
     double eta_p;     /* polymer viscosity, >= 0                           */
@@ -88,6 +100,8 @@ typedef struct {
     double Lambda_p;  /* conformation magic parameter, > 0                 */
     double Fx, Fy;    /* uniform body force (used until a force field is set) */
     int flags;        /* VLB_FLAG_*                                        */
+    int model;        /* VLB_OLDROYD_B (0) ... VLB_FENE_P                  */
+    double model_param; /* alpha, eps or L^2 (see above); ignored for Oldroyd-B */
 } vlb_params;
 
 typedef struct {

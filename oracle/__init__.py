@@ -24,6 +24,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 MODES = {"periodic": 0, "wall": 1, "open": 2}
+# constitutive closures (model function F(A), Sec. 2.2) and the meaning of model_param
+MODELS = {"oldroyd_b": 0, "giesekus": 1, "lptt": 2, "eptt": 3, "fene_p": 4}
 FLAG_NO_SOURCE = 1
 
 
@@ -73,6 +75,8 @@ def _load():
     lib.orc_node_hydro.argtypes = [DP, D, D, D, D, D, D, D, D, D, DP]
     lib.orc_node_cde.argtypes = [DP, D, D, D, D, D, D, D, D, D, D, D, DP]
     lib.orc_node_source.argtypes = [DP, DP, D, DP]
+    lib.orc_node_source_model.argtypes = [DP, DP, D, C.c_int, D, DP]
+    lib.orc_set_model.argtypes = [P, C.c_int, D]
     lib.orc_node_fd.restype = D
     lib.orc_node_fd.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
     _lib = lib
@@ -120,6 +124,9 @@ class OracleSim:
                                 prob.Lambda_s, prob.Lambda_p, flags)
         if rc != 0:
             raise ValueError("oracle: invalid parameters")
+        model = getattr(prob, "model", "oldroyd_b")
+        if lib.orc_set_model(self.h, MODELS[model], float(getattr(prob, "model_param", 0.0))) != 0:
+            raise ValueError(f"oracle: invalid model parameter for {model}")
         self.set_force(prob.Fx, prob.Fy)
         if prob.inlet is not None:
             i = prob.inlet
@@ -242,11 +249,17 @@ def node_cde(g9, rho, ux, uy, Fx, Fy, S, Sp, uxp, uyp, tau_p1, tau_p2):
     return out
 
 
-def node_source(A3, L4, lam):
+def node_source(A3, L4, lam, model=None, mpar=0.0):
+    """Constitutive source (S_xx, S_xy, S_yy) at one node; L4 = (d_x u_x, d_x u_y,
+    d_y u_x, d_y u_y).  Without a model: the Oldroyd-B entry point."""
     A3 = _c64(A3)
     L4 = _c64(L4)
     out = np.zeros(3)
-    _load().orc_node_source(_dp(A3), _dp(L4), lam, _dp(out))
+    if model is None:
+        _load().orc_node_source(_dp(A3), _dp(L4), lam, _dp(out))
+    else:
+        _load().orc_node_source_model(_dp(A3), _dp(L4), lam, MODELS[model], float(mpar),
+                                      _dp(out))
     return out
 
 

@@ -13,16 +13,19 @@
  * over the grid per stage, state stored as absolute populations:
  *
  *   1. macroscopic density and velocity with the half-force shift    (Sec. 3.1)
- *   2. conformation components and polymer stress (Kramers, Oldroyd-B) (Sec. 2.2-2.3)
+ *   2. conformation components and polymer stress (Kramers relation with the
+ *      model function F(A): Oldroyd-B, Giesekus, PTT, FENE-P)           (Sec. 2.2-2.3)
  *   3. velocity gradient and d(rho u^3) by finite differences           (reading A6/A7)
  *   4. constitutive source Phi_ab                                         (Sec. 3.2)
  *   5. hydrodynamic TRT regularized collision with G_i, F_i, T_i         (Sec. 3.1)
  *   6. three convection-diffusion TRT regularized collisions with
  *      the auxiliary source, the source term and its time derivative   (Sec. 3.2)
  *   7. streaming; half-way / linearly interpolated bounce-back for f;
- *      equilibrium inlet and zero-gradient outlet ghosts               (readings A13, A21)
+ *      non-equilibrium extrapolation at the inlet and outlet ghosts    (readings A13, A21)
  *   8. conservative non-equilibrium bounce-back for every g lattice     (Sec. 3.3)
  *   9. history of S and u for the backward time difference             (Sec. 3.2)
+ *
+ * plus the momentum-exchange force on solids (Sec. 4.3).
  *
  * Readings of points the paper leaves open are listed in the repository's design
  * notes under the same labels (A5 ... A25) and are marked where they are used.
@@ -238,14 +241,68 @@ void collide_cde(const R g[Q], R phi, R rho, R ux, R uy, R Fx, R Fy, R S, R Sp, 
     }
 }
 
-// Constitutive source Phi_ab for the Oldroyd-B closure (Sec. 3.2), with
-// L[g][b] = d_g u_b:  -(A - I)/lambda + A_ag L_gb + A_gb L_ga + A_ab L_gg.
+// Constitutive models enter only through the model function F(A) (Sec. 2.2: the
+// conformation equation relaxes with -(1/lambda) F and the Kramers relation gives the
+// polymer stress (eta_p / lambda) F).  The paper runs the Oldroyd-B closure
+// F = A - I.  The other closures it names are written here in the conformation form:
+// a relaxation function F_r (in the transport equation) and a stress function F_s (in
+// the Kramers relation), with the 2-D trace tr A (equal to 2 at rest):
+//   Giesekus (alpha):    F_r = (A - I) + alpha (A - I)^2,           F_s = A - I
+//   linear PTT (eps):    F_r = [1 + eps (tr A - 2)] (A - I),        F_s = A - I
+//   exponential PTT:     F_r = exp[eps (tr A - 2)] (A - I),         F_s = A - I
+//   FENE-P (L^2):        F_r = F_s = f A - I,  f = (L^2 - 2) / (L^2 - tr A)
+enum { MODEL_OLDROYD_B = 0, MODEL_GIESEKUS = 1, MODEL_LPTT = 2, MODEL_EPTT = 3, MODEL_FENE_P = 4 };
+
+inline double exp_(double a) { return std::exp(a); }
+inline Dual exp_(Dual a) {
+    const double e = std::exp(a.v);
+    return Dual(e, e * a.d);
+}
+
 template <class R>
-void constitutive_source(const R A[2][2], const R L[2][2], R lam, R S[2][2]) {
+void model_functions(const R A[2][2], int model, double mp, R Fr[2][2], R Fs[2][2]) {
+    R B[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) B[a][b] = A[a][b] - R(kd(a, b));
+    const R trA = A[0][0] + A[1][1];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            Fs[a][b] = B[a][b];
+            Fr[a][b] = B[a][b];
+        }
+    if (model == MODEL_GIESEKUS) {
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                R bb = R(0.0);
+                for (int g = 0; g < 2; ++g) bb += B[a][g] * B[g][b];
+                Fr[a][b] = B[a][b] + R(mp) * bb;
+            }
+    } else if (model == MODEL_LPTT || model == MODEL_EPTT) {
+        const R x = R(mp) * (trA - R(2.0));
+        const R Y = model == MODEL_LPTT ? R(1.0) + x : exp_(x);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) Fr[a][b] = Y * B[a][b];
+    } else if (model == MODEL_FENE_P) {
+        const R f = R(mp - 2.0) / (R(mp) - trA);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                Fr[a][b] = f * A[a][b] - R(kd(a, b));
+                Fs[a][b] = Fr[a][b];
+            }
+    }
+}
+
+// Constitutive source Phi_ab (Sec. 3.2), with L[g][b] = d_g u_b:
+// -F_r(A)/lambda + A_ag L_gb + A_gb L_ga + A_ab L_gg.
+template <class R>
+void constitutive_source(const R A[2][2], const R L[2][2], R lam, int model, double mp,
+                         R S[2][2]) {
+    R Fr[2][2], Fs[2][2];
+    model_functions(A, model, mp, Fr, Fs);
     const R trL = L[0][0] + L[1][1];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-            R s = -(A[a][b] - R(kd(a, b))) / lam;
+            R s = -Fr[a][b] / lam;
             for (int g = 0; g < 2; ++g) s += A[a][g] * L[g][b] + A[g][b] * L[g][a];
             s += A[a][b] * trL;
             S[a][b] = s;
@@ -353,6 +410,8 @@ struct Sim {
     size_t N = 0;
     Relax<R> p{};
     int flags = 0;
+    int model = MODEL_OLDROYD_B;  // constitutive closure and its parameter
+    double mpar = 0.0;
     std::vector<R> Fx, Fy;
     std::vector<R> uin, ain[3];
     std::vector<R> f[Q], fp[Q], g[3][Q], gp[3][Q];
@@ -443,13 +502,14 @@ struct Sim {
                            uinl * uinl * uinl, R(0.0));
             const R Dy = D(syl, syh, py_at, rho[n] * uy[n] * uy[n] * uy[n], R(0.0), R(0.0));
 
-            // Conformation tensor and polymer stress tau = (eta_p / lambda)(A - I).
+            // Conformation tensor and polymer stress tau = (eta_p / lambda) F_s(A).
             const R Am[2][2] = {{A[0][n], A[1][n]}, {A[1][n], A[2][n]}};
-            R tau_ab[2][2];
+            R Fr[2][2], Fs[2][2], tau_ab[2][2];
+            model_functions(Am, model, mpar, Fr, Fs);
             for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) tau_ab[a][b] = p.eta_p / p.lam * (Am[a][b] - R(kd(a, b)));
+                for (int b = 0; b < 2; ++b) tau_ab[a][b] = p.eta_p / p.lam * Fs[a][b];
             R Sm[2][2];
-            constitutive_source(Am, L, p.lam, Sm);
+            constitutive_source(Am, L, p.lam, model, mpar, Sm);
             R S[3] = {Sm[0][0], Sm[0][1], Sm[1][1]};
             if (flags & FLAG_NO_SOURCE) S[0] = S[1] = S[2] = R(0.0);
             // First step: F~(t - 1) := F~(t) (reading A9).
@@ -736,6 +796,20 @@ int orc_set_params(void* hp, double nu_s, double eta_p, double lam, double kappa
     return 0;
 }
 
+// Constitutive closure (MODEL_*) and its parameter: Giesekus alpha in [0, 1], PTT
+// epsilon >= 0, FENE-P L^2 > 2; ignored for Oldroyd-B.
+int orc_set_model(void* hp, int model, double mpar) {
+    Handle* h = static_cast<Handle*>(hp);
+    if (model < MODEL_OLDROYD_B || model > MODEL_FENE_P) return -1;
+    if (model == MODEL_GIESEKUS && !(mpar >= 0.0 && mpar <= 1.0)) return -1;
+    if ((model == MODEL_LPTT || model == MODEL_EPTT) && !(mpar >= 0.0)) return -1;
+    if (model == MODEL_FENE_P && !(mpar > 2.0)) return -1;
+    if (model == MODEL_OLDROYD_B) mpar = 0.0;
+    if (h->dual) { h->sx.model = model; h->sx.mpar = mpar; }
+    else { h->sd.model = model; h->sd.mpar = mpar; }
+    return 0;
+}
+
 // Uniform force when fx/fy are null (values fx0, fy0).
 int orc_set_force(void* hp, double fx0, double fy0, const double* fx, const double* fy) {
     Handle* h = static_cast<Handle*>(hp);
@@ -922,12 +996,16 @@ void orc_node_cde(const double* g9, double rho, double ux, double uy, double Fx,
     Relax<double> p{1.0, 1.0, tau_p1, tau_p2, 1.0, 0.0};
     collide_cde(g9, phi, rho, ux, uy, Fx, Fy, S, Sp, uxp, uyp, p, out9);
 }
-void orc_node_source(const double* A3, const double* L4, double lam, double* S3) {
+void orc_node_source_model(const double* A3, const double* L4, double lam, int model,
+                           double mpar, double* S3) {
     const double A[2][2] = {{A3[0], A3[1]}, {A3[1], A3[2]}};
     const double L[2][2] = {{L4[0], L4[1]}, {L4[2], L4[3]}};
     double S[2][2];
-    constitutive_source(A, L, lam, S);
+    constitutive_source(A, L, lam, model, mpar, S);
     S3[0] = S[0][0]; S3[1] = S[0][1]; S3[2] = S[1][1];
+}
+void orc_node_source(const double* A3, const double* L4, double lam, double* S3) {
+    orc_node_source_model(A3, L4, lam, MODEL_OLDROYD_B, 0.0, S3);
 }
 double orc_node_fd(int lo_solid, double qlo, double plo, double p0, int hi_solid, double qhi,
                    double phi) {

@@ -48,7 +48,12 @@ class VlbGrid(C.Structure):
 class VlbParams(C.Structure):
     _fields_ = [("nu_s", C.c_double), ("eta_p", C.c_double), ("lambda_", C.c_double),
                 ("kappa", C.c_double), ("Lambda_s", C.c_double), ("Lambda_p", C.c_double),
-                ("Fx", C.c_double), ("Fy", C.c_double), ("flags", C.c_int)]
+                ("Fx", C.c_double), ("Fy", C.c_double), ("flags", C.c_int),
+                ("model", C.c_int), ("model_param", C.c_double)]
+
+
+# constitutive closures (VLB_OLDROYD_B ... VLB_FENE_P) by name
+MODELS = {"oldroyd_b": 0, "giesekus": 1, "lptt": 2, "eptt": 3, "fene_p": 4}
 
 
 class VlbMonitor(C.Structure):

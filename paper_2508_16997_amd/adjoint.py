@@ -27,7 +27,8 @@ class VlbFunction(torch.autograd.Function):
         p = dict(sim.params)
         p.update(lam=float(lam), eta_p=float(eta_p))
         sim.set_params(p["nu_s"], p["eta_p"], p["lam"], p["kappa"], p["Lambda_s"], p["Lambda_p"],
-                       0.0, 0.0, p["flags"])
+                       0.0, 0.0, p["flags"], model=p.get("model", "oldroyd_b"),
+                       model_param=p.get("model_param", 0.0))
         sim.set_force_field(Fx.detach(), Fy.detach())
         sim.adjoint_forward(int(nsteps), stride)
         r = sim.read()

@@ -49,6 +49,10 @@ using Run = vlb::RunDev<T>;
 
 }  // namespace
 
+static_assert(vlb::MODEL_GIESEKUS == VLB_GIESEKUS && vlb::MODEL_LPTT == VLB_LPTT &&
+                  vlb::MODEL_EPTT == VLB_EPTT && vlb::MODEL_FENE_P == VLB_FENE_P,
+              "closure codes of the ABI and the kernels differ");
+
 struct vlb_sim {
     int nx = 0, ny = 0, xmode = 0, ymode = 0, prec = 0, pitch = 0, off0 = 0;
     long long plane = 0;
@@ -386,6 +390,8 @@ Run<T> make_run(const vlb_sim* s) {
     r.h2 = (3.0 * p.kappa) / tp1;
     r.inv_lam = 1.0 / p.lambda;
     r.eta_over_lam = p.eta_p / p.lambda;
+    r.model = p.model;
+    r.mpar = p.model == VLB_FENE_P ? p.model_param - 2.0 : (p.model == VLB_OLDROYD_B ? 0.0 : p.model_param);
     r.Fx = p.Fx;
     r.Fy = p.Fy;
     return r;
@@ -663,6 +669,16 @@ int vlb_set_params(vlb_sim* s, const vlb_params* p) {
     if (!(p->Lambda_s > 0) || !(p->Lambda_p > 0))
         return fail(VLB_E_INVALID_ARG, "magic parameters must be > 0");
     if (p->flags & ~VLB_FLAG_NO_SOURCE) return fail(VLB_E_INVALID_ARG, "unknown flag");
+    if (p->model < VLB_OLDROYD_B || p->model > VLB_FENE_P)
+        return fail(VLB_E_INVALID_ARG, "unknown constitutive model");
+    if (p->model != VLB_OLDROYD_B && !std::isfinite(p->model_param))
+        return fail(VLB_E_INVALID_ARG, "non-finite model parameter");
+    if (p->model == VLB_GIESEKUS && !(p->model_param >= 0.0 && p->model_param <= 1.0))
+        return fail(VLB_E_INVALID_ARG, "Giesekus alpha must lie in [0, 1]");
+    if ((p->model == VLB_LPTT || p->model == VLB_EPTT) && !(p->model_param >= 0.0))
+        return fail(VLB_E_INVALID_ARG, "PTT epsilon must be >= 0");
+    if (p->model == VLB_FENE_P && !(p->model_param > 2.0))
+        return fail(VLB_E_INVALID_ARG, "FENE-P L^2 must be > 2");
     s->params = *p;
     s->params_set = true;
     if (s->bound) return upload_run(s);
@@ -940,6 +956,8 @@ int adj_check(const vlb_sim* s, int64_t nsteps, int stride) {
     if (rc) return rc;
     if (s->xmode != VLB_PERIODIC || s->ymode != VLB_PERIODIC || s->has_bits)
         return fail(VLB_E_UNSUPPORTED, "the adjoint covers fully periodic domains without solids");
+    if (s->params.model != VLB_OLDROYD_B)
+        return fail(VLB_E_UNSUPPORTED, "the adjoint covers the Oldroyd-B closure");
     if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
     return VLB_OK;
 }

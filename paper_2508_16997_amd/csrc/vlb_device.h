@@ -159,6 +159,34 @@ __device__ __forceinline__ T dgrad(bool lo_wall, T qlo, T vlo, T v0, bool hi_wal
     return v0 * (qhi - qlo) / (qlo * qhi);
 }
 
+// Constitutive closure at one node from B = A - I (b0 = B_xx, b1 = B_xy, b2 = B_yy):
+// the relaxation function F_r of the conformation equation and the stress function
+// F_s of the Kramers relation (Sec. 2.2); Oldroyd-B is F_r = F_s = B.  The model is
+// uniform per run, so the branch is too.  mp: alpha (Giesekus), eps (PTT), L^2 - 2
+// (FENE-P, written as f A - I = (f - 1)(I + B) + B with f - 1 = tr B / (L^2 - 2 - tr B)).
+__device__ __forceinline__ void closure(int model, T mp, T b0, T b1, T b2, T r[3], T s[3]) {
+    r[0] = s[0] = b0;
+    r[1] = s[1] = b1;
+    r[2] = s[2] = b2;
+    if (model == MODEL_GIESEKUS) {
+        r[0] = b0 + mp * (b0 * b0 + b1 * b1);
+        r[1] = b1 + mp * b1 * (b0 + b2);
+        r[2] = b2 + mp * (b1 * b1 + b2 * b2);
+    } else if (model == MODEL_LPTT || model == MODEL_EPTT) {
+        const T x = mp * (b0 + b2);
+        const T Y = model == MODEL_LPTT ? 1.0 + x : exp(x);
+        r[0] = Y * b0;
+        r[1] = Y * b1;
+        r[2] = Y * b2;
+    } else if (model == MODEL_FENE_P) {
+        const T tr = b0 + b2;
+        const T fm1 = tr / (mp - tr);
+        r[0] = s[0] = fm1 * (1.0 + b0) + b0;
+        r[1] = s[1] = (1.0 + fm1) * b1;
+        r[2] = s[2] = fm1 * (1.0 + b2) + b2;
+    }
+}
+
 // Moments of one D2Q9 population set via opposite-pair sums and differences:
 // zeroth, first (x, y), second (xx, yy, xy) and the two third-order ones (xxy, xyy).
 struct Mom {

@@ -30,6 +30,9 @@ enum {
                        // part extrapolated from that row's first node
 };
 
+// Constitutive closures (same values as VLB_OLDROYD_B ... VLB_FENE_P of the ABI).
+enum { MODEL_OLDROYD_B = 0, MODEL_GIESEKUS = 1, MODEL_LPTT = 2, MODEL_EPTT = 3, MODEL_FENE_P = 4 };
+
 struct FillOp {
     int dst;       // slot that the fluid node pulls direction dir from
     int src;       // fluid node x (outlet: the last-column node of that row)
@@ -48,6 +51,8 @@ struct RunDev {
     int has_curved;     // curved links present (bidx / bq valid)
     int uniform_force;  // 1: use Fx, Fy below; 0: force planes
     int no_source;      // constitutive source forced to zero
+    int model;          // constitutive closure (VLB_OLDROYD_B ... VLB_FENE_P)
+    int pad0;
     long long plane;    // elements per plane ((ny + 2) * pitch)
     S* pop[2];          // two population buffers of 36 planes: f (9), g_xx, g_xy, g_yy (9 each)
     S* hist;            // 5 planes: S_xx, S_xy, S_yy, u_x, u_y of the previous step
@@ -65,6 +70,7 @@ struct RunDev {
     double c1, c2, h1, inv_ts1;  // 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
     double p1, p2, h2;           // 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)
     double inv_lam, eta_over_lam;
+    double mpar;                 // closure parameter: alpha, eps or L^2 - 2 (FENE-P)
     double Fx, Fy;
 };
 

@@ -148,15 +148,17 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
     }
     const T d0 = gm[0].m0, d1 = gm[1].m0, d2 = gm[2].m0;
     const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
-    const T txx = R.eta_over_lam * d0, txy = R.eta_over_lam * d1, tyy = R.eta_over_lam * d2;
+    T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
+    if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
+    const T txx = R.eta_over_lam * sf[0], txy = R.eta_over_lam * sf[1], tyy = R.eta_over_lam * sf[2];
     T Sc[3];
     if (R.no_source) {
         Sc[0] = Sc[1] = Sc[2] = 0.0;
     } else {
         const T d = Lxx + Lyy;
-        Sc[0] = -R.inv_lam * d0 + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
-        Sc[1] = -R.inv_lam * d1 + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
-        Sc[2] = -R.inv_lam * d2 + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
+        Sc[0] = -R.inv_lam * rf[0] + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
+        Sc[1] = -R.inv_lam * rf[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
+        Sc[2] = -R.inv_lam * rf[2] + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
     }
     if (!pull) {  // first step: F~(t - 1) := F~(t)
         hS[0] = Sc[0]; hS[1] = Sc[1]; hS[2] = Sc[2];

@@ -70,7 +70,9 @@ class Simulation:
         sim = cls(prob.nx, prob.ny, prob.xmode, prob.ymode, precision or prob.precision,
                   solid=prob.solid, circles=prob.circles, **kw)
         sim.set_params(prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s, prob.Lambda_p,
-                       *(((float(prob.Fx), float(prob.Fy)) if prob.uniform_force() else (0.0, 0.0))))
+                       *(((float(prob.Fx), float(prob.Fy)) if prob.uniform_force() else (0.0, 0.0))),
+                       model=getattr(prob, "model", "oldroyd_b"),
+                       model_param=getattr(prob, "model_param", 0.0))
         if not prob.uniform_force():
             fx, fy = prob.force_arrays()
             sim.set_force_field(fx, fy)
@@ -100,13 +102,20 @@ class Simulation:
         return t
 
     def set_params(self, nu_s, eta_p, lam, kappa, Lambda_s=0.25, Lambda_p=1e-6, Fx=0.0, Fy=0.0,
-                   flags=0):
+                   flags=0, model="oldroyd_b", model_param=0.0):
+        """Lattice-unit parameters; ``model`` names the constitutive closure ('oldroyd_b',
+        'giesekus' with model_param = alpha, 'lptt' / 'eptt' with epsilon, 'fene_p' with
+        L^2)."""
+        if model not in L.MODELS:
+            raise ValueError(f"unknown constitutive model {model!r}")
         p = L.VlbParams(float(nu_s), float(eta_p), float(lam), float(kappa), float(Lambda_s),
-                        float(Lambda_p), float(Fx), float(Fy), int(flags))
+                        float(Lambda_p), float(Fx), float(Fy), int(flags), L.MODELS[model],
+                        float(model_param))
         L.check(self.lib.vlb_set_params(self._h, C.byref(p)), "vlb_set_params")
         self.params = dict(nu_s=float(nu_s), eta_p=float(eta_p), lam=float(lam),
                            kappa=float(kappa), Lambda_s=float(Lambda_s),
-                           Lambda_p=float(Lambda_p), Fx=float(Fx), Fy=float(Fy), flags=int(flags))
+                           Lambda_p=float(Lambda_p), Fx=float(Fx), Fy=float(Fy), flags=int(flags),
+                           model=model, model_param=float(model_param))
 
     def set_force_field(self, fx, fy):
         if fx is None and fy is None:

@@ -46,6 +46,11 @@ class Problem:
     steps: int = 0
     precision: str = "fp32"
     meta: dict = field(default_factory=dict)
+    # constitutive closure: 'oldroyd_b' (the paper's), 'giesekus' (model_param = alpha),
+    # 'lptt' / 'eptt' (linear / exponential Phan-Thien-Tanner, model_param = epsilon),
+    # 'fene_p' (model_param = L^2)
+    model: str = "oldroyd_b"
+    model_param: float = 0.0
 
     @property
     def nodes(self) -> int:

@@ -66,3 +66,94 @@ def four_roll_newtonian(N, Uc):
     xs = 2.0 * math.pi * np.arange(N) / N
     X, Y = np.meshgrid(xs, xs, indexing="xy")
     return -Uc * np.sin(X) * np.cos(Y), Uc * np.cos(X) * np.sin(Y)
+
+
+# ---------------------------------------------------------------------------------
+# Steady homogeneous simple shear u_x = gdot y of the constitutive closures (model
+# function F(A), Sec. 2.2), Wi = lambda gdot.  With B = A - I the steady conformation
+# equation reads, component by component,
+#   F_r,xx = 2 Wi A_xy,   F_r,xy = Wi A_yy,   F_r,yy = 0,
+# solved here in closed form or as one scalar equation per closure.
+# ---------------------------------------------------------------------------------
+def shear_conformation(model, mp, Wi):
+    """(A_xx, A_xy, A_yy) of steady simple shear at Weissenberg number Wi (any sign)."""
+    from scipy.optimize import brentq
+
+    s = 1.0 if Wi >= 0 else -1.0
+    W = abs(Wi)
+    if W == 0.0:
+        return 1.0, 0.0, 1.0
+    if model == "oldroyd_b":
+        axx, axy, ayy = 1 + 2 * W * W, W, 1.0
+    elif model == "giesekus":
+        # Giesekus' analytic solution: chi^2 = [sqrt(1 + 16 a (1 - a) Wi^2) - 1] /
+        # [8 a (1 - a) Wi^2], f = (1 - chi) / (1 + (1 - 2a) chi); A_yy = 1 - f,
+        # A_xy = Wi (1 - f)^2 / (1 + (1 - 2a) f), A_xx - A_yy = 2 f (1 - a f) / (a (1 - f)).
+        a = mp
+        if a == 0.0:
+            return shear_conformation("oldroyd_b", 0.0, Wi)
+        chi = math.sqrt((math.sqrt(1 + 16 * a * (1 - a) * W * W) - 1) / (8 * a * (1 - a) * W * W))
+        f = (1 - chi) / (1 + (1 - 2 * a) * chi)
+        ayy = 1 - f
+        axy = W * (1 - f) ** 2 / (1 + (1 - 2 * a) * f)
+        axx = ayy + 2 * f * (1 - a * f) / (a * (1 - f))
+    elif model in ("lptt", "eptt"):
+        # F_r = Y(tr A - 2) B: B_yy = 0, B_xy = Wi / Y, B_xx = 2 Wi^2 / Y^2 and
+        # Y = 1 + eps B_xx (linear) or exp(eps B_xx) (exponential).
+        e = mp
+
+        def g(Y):
+            bxx = 2 * W * W / (Y * Y)
+            return (1 + e * bxx if model == "lptt" else math.exp(e * bxx)) - Y
+
+        Y = brentq(g, 1.0, 1.0 + 2 * e * W * W + 1.0, xtol=1e-15, rtol=1e-15)
+        axx, axy, ayy = 1 + 2 * W * W / (Y * Y), W / Y, 1.0
+    elif model == "fene_p":
+        # F_r = f A - I: A_yy = 1/f, A_xy = Wi / f^2, A_xx = (1 + 2 Wi^2 / f^2) / f with
+        # f = (L^2 - 2) / (L^2 - tr A).
+        L2 = mp
+
+        def g(f):
+            tr = (1 + 2 * W * W / (f * f)) / f + 1 / f
+            return f * (L2 - tr) - (L2 - 2)
+
+        f = brentq(g, 1.0, 1e6, xtol=1e-15, rtol=1e-15)
+        axx, axy, ayy = (1 + 2 * W * W / (f * f)) / f, W / (f * f), 1 / f
+    else:
+        raise ValueError(model)
+    return axx, s * axy, ayy
+
+
+def shear_stress_function(model, mp, Wi):
+    """F_s,xy of steady simple shear: the polymer shear stress is (eta_p / lambda) F_s,xy."""
+    axx, axy, ayy = shear_conformation(model, mp, Wi)
+    if model == "fene_p":
+        f = (mp - 2) / (mp - axx - ayy)
+        return f * axy
+    return axy
+
+
+def poiseuille_steady_model(ny, G, nu_s, eta_p, lam, model, mp):
+    """Steady force-driven channel flow of a closure at the node centres y = j + 1/2
+    between walls at y = 0 and y = ny (body force G along x, rho0 = 1, no diffusion of
+    A).  The flow is locally simple shear, so the total shear stress
+    nu_s gdot + (eta_p / lambda) F_s,xy(lambda gdot) = G (ny/2 - y) fixes gdot(y);
+    u(y) is its integral from the wall and A(y) the shear conformation at gdot(y)."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+
+    H = float(ny)
+
+    def gdot(y):
+        sig = G * (H / 2 - y)
+        if sig == 0.0:
+            return 0.0
+        h = lambda g: nu_s * g + eta_p / lam * shear_stress_function(model, mp, lam * g) - sig  # noqa: E731
+        hi = sig / nu_s
+        return brentq(h, 0.0, hi, xtol=1e-17, rtol=1e-15) if sig > 0 else \
+            brentq(h, hi, 0.0, xtol=1e-17, rtol=1e-15)
+
+    ys = np.arange(ny) + 0.5
+    u = np.array([quad(gdot, 0.0, y, epsabs=1e-14, epsrel=1e-12, limit=200)[0] for y in ys])
+    A = np.array([shear_conformation(model, mp, lam * gdot(y)) for y in ys])
+    return dict(ux=u, axx=A[:, 0], axy=A[:, 1], ayy=A[:, 2])

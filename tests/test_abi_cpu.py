@@ -110,12 +110,18 @@ def test_invalid_params_rejected_before_launch(vlb):
     assert st == L.VLB_OK
     try:
         bad = [dict(nu_s=0.0), dict(kappa=-1.0), dict(lambda_=0.0), dict(eta_p=-0.1),
-               dict(Lambda_p=0.0), dict(nu_s=float("nan"))]
+               dict(Lambda_p=0.0), dict(nu_s=float("nan")), dict(model=7),
+               dict(model=1, model_param=1.5), dict(model=2, model_param=-0.1),
+               dict(model=3, model_param=float("inf")), dict(model=4, model_param=2.0)]
         for b in bad:
             p = dict(nu_s=0.1, eta_p=0.1, lambda_=10.0, kappa=0.01, Lambda_s=0.25, Lambda_p=1e-6,
                      Fx=0.0, Fy=0.0, flags=0)
             p.update(b)
             assert lib.vlb_set_params(h, C.byref(L.VlbParams(**p))) == L.VLB_E_INVALID_ARG
+        for model, mp in ((0, 0.0), (1, 0.3), (2, 0.25), (3, 0.0), (4, 50.0)):
+            p = dict(nu_s=0.1, eta_p=0.1, lambda_=10.0, kappa=0.01, Lambda_s=0.25, Lambda_p=1e-6,
+                     Fx=0.0, Fy=0.0, flags=0, model=model, model_param=mp)
+            assert lib.vlb_set_params(h, C.byref(L.VlbParams(**p))) == L.VLB_OK
         # stepping an unbound simulation is a state error, not a crash
         assert lib.vlb_step(h, 1) == L.VLB_E_STATE
         assert b"bind" in lib.vlb_last_error_detail()

@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import synth
-from analytic import four_roll_newtonian, gre, poiseuille_steady, waters_king_u
+from analytic import (four_roll_newtonian, gre, poiseuille_steady, poiseuille_steady_model,
+                      shear_conformation, waters_king_u)
 
 CS2 = 1.0 / 3.0
 
@@ -150,6 +151,63 @@ def test_source_planar_extension(oracle_lib):
     A = _steady_A(oracle_lib, [eps, 0.0, 0.0, eps], lam)
     np.testing.assert_allclose(A, [1 / (1 - 4 * lam * eps), 0.0, 1 / (1 - 4 * lam * eps)],
                                rtol=1e-13, atol=1e-15)
+
+
+MODEL_CASES = [("giesekus", 0.2), ("giesekus", 0.5), ("lptt", 0.25), ("eptt", 0.25),
+               ("fene_p", 20.0), ("fene_p", 100.0)]
+
+
+@pytest.mark.parametrize("model,mp", MODEL_CASES)
+def test_source_simple_shear_closures(oracle_lib, model, mp):
+    """Other closures through the model function F(A) (Sec. 2.2): the steady conformation
+    of simple shear (Giesekus' analytic solution; the PTT and FENE-P scalar equations)
+    zeroes the oracle's constitutive source, for both shear directions and several Wi.
+    The planar solution of a transposed flow u_y = gdot x swaps xx and yy."""
+    lam = 5.0
+    for Wi in (0.3, 1.5, -1.5, 4.0):
+        gd = Wi / lam
+        A = np.array(shear_conformation(model, mp, Wi))
+        S = oracle_lib.node_source(A, [0.0, 0.0, gd, 0.0], lam, model, mp)
+        assert np.abs(S).max() < 1e-14 * max(1.0, np.abs(A).max()), (Wi, A, S)
+        At = A[[2, 1, 0]]
+        S = oracle_lib.node_source(At, [0.0, gd, 0.0, 0.0], lam, model, mp)
+        assert np.abs(S).max() < 1e-14 * max(1.0, np.abs(A).max()), (Wi, At, S)
+        # and it is not the Oldroyd-B state
+        assert np.abs(A - shear_conformation("oldroyd_b", 0.0, Wi)).max() > 1e-3
+
+
+def test_closures_reduce_to_oldroyd_b(oracle_lib):
+    """alpha = 0, eps = 0 and L^2 -> infinity give the Oldroyd-B source."""
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        A = np.array([1.3, 0.2, 0.9]) + 0.1 * rng.standard_normal(3)
+        L = 0.05 * rng.standard_normal(4)
+        ob = oracle_lib.node_source(A, L, 7.0)
+        for model, mp, tol in (("giesekus", 0.0, 0.0), ("lptt", 0.0, 0.0), ("eptt", 0.0, 0.0),
+                               ("fene_p", 1e12, 1e-11)):
+            S = oracle_lib.node_source(A, L, 7.0, model, mp)
+            assert np.abs(S - ob).max() <= tol * np.abs(ob).max(), model
+
+
+@pytest.mark.parametrize("model,mp", [("giesekus", 0.2), ("lptt", 0.25), ("eptt", 0.25),
+                                      ("fene_p", 20.0)])
+def test_poiseuille_closures_second_order(oracle_lib, model, mp):
+    """Steady channel flow of each closure (Wi = 1, beta = 0.5 as Sec. 4.2) against the
+    semi-analytic solution (the local simple-shear stress balances G (H/2 - y)): u and
+    A converge at second order from Ny = 16 to 32 to profiles that differ from the
+    Oldroyd-B ones by 19-48 % in u."""
+    oracle_lib.set_threads(min(8, oracle_lib.max_threads()))
+    err = {}
+    for ny, steps in ((16, 24000), (32, 40000)):
+        pr = synth.poiseuille(nx=4, ny=ny).with_(model=model, model_param=mp)
+        ref = poiseuille_steady_model(ny, pr.Fx, pr.nu_s, pr.eta_p, pr.lam, model, mp)
+        o = oracle_lib.OracleSim(pr)
+        o.step(steps)
+        r = o.read()
+        err[ny] = (gre(r["ux"][:, 0], ref["ux"]), gre(r["axy"][:, 0], ref["axy"]),
+                   gre(r["axx"][:, 0] - 1, ref["axx"] - 1))
+    assert err[32][0] < 1.2e-3 and err[32][1] < 2e-3 and err[32][2] < 2.5e-3, err
+    assert err[16][0] / err[32][0] > 3.5, err
 
 
 def test_finite_difference_exact_on_quadratics(oracle_lib):
