@@ -44,9 +44,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build(force=True)
-    lib = C.CDLL(_LIB)
+    path = os.environ.get("ORACLE_LIBRARY")  # an instrumented build (sanitizer tests)
+    if not path:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        path = _LIB
+    lib = C.CDLL(path)
     P = C.c_void_p
     D = C.c_double
     DP = C.POINTER(C.c_double)

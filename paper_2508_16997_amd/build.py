@@ -18,6 +18,7 @@ SOURCES = ["vlb_kernels.hip", "vlb_fill.hip", "vlb_aux.hip", "vlb_adjoint.hip", 
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VLB_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(HIPCC)), "lib")
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -57,7 +58,9 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = out + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           # roctx ranges around the entry points that enqueue device work
+           f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -12,10 +12,21 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "vlb.h"
 #include "vlb_internal.h"
 
 namespace {
+
+// roctx range around an entry point that enqueues device work: shows up as a named
+// region in rocprofv3 --marker-trace timelines, costs one call when no tool listens.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 thread_local std::string g_detail;
 
@@ -750,6 +761,7 @@ int vlb_step(vlb_sim* s, int64_t n) {
     int rc = check_ready(s);
     if (rc) return rc;
     if (n < 0) return fail(VLB_E_INVALID_ARG, "negative step count");
+    Range r("vlb_step");
     return s->prec == VLB_FP32 ? do_step<float>(s, n) : do_step<double>(s, n);
 }
 
@@ -1117,6 +1129,7 @@ int vlb_adjoint_forward(vlb_sim* s, int64_t nsteps, int stride, void* ws, size_t
     rc = adj_ws_check(s, nsteps, stride, ws, bytes);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
+    Range r("vlb_adjoint_forward");
     return s->prec == VLB_FP32 ? adj_forward<float>(s, nsteps, stride, w, bytes)
                                : adj_forward<double>(s, nsteps, stride, w, bytes);
 }
@@ -1132,6 +1145,7 @@ static int adj_backward_checked(vlb_sim* s, const void* gx, const void* gy, int 
     if (s->step != s->adj.step0 + s->adj.nsteps || s->adj.version != s->version ||
         s->ty != s->adj.ty)
         return fail(VLB_E_STATE, "simulation changed since vlb_adjoint_forward");
+    Range r("vlb_adjoint_backward");
     return s->prec == VLB_FP32
                ? adj_backward<float>(s, gx, gy, is_target, loss, dlam, deta, dFx, dFy)
                : adj_backward<double>(s, gx, gy, is_target, loss, dlam, deta, dFx, dFy);
@@ -1357,6 +1371,7 @@ int vlb_batch_step(vlb_batch* b, int64_t n) {
     for (vlb_sim* s : b->sims)
         if (s->step != b->step || s->parity != b->sims[0]->parity || s->first != b->sims[0]->first)
             return fail(VLB_E_STATE, "batch member was stepped or reloaded outside the batch");
+    Range r("vlb_batch_step");
     return b->prec == VLB_FP32 ? batch_step<float>(b, n) : batch_step<double>(b, n);
 }
 

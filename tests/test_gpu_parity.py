@@ -204,6 +204,44 @@ def test_checkpoint_resume_bit_exact():
         assert np.array_equal(ga[k], gb[k]), k
 
 
+def test_breakdown_detected_and_recovered_from_checkpoint():
+    """A non-finite population (the paper's "NaN" breakdown) makes vlb_monitors return
+    VLB_E_NONFINITE with a node count; reloading the last clean checkpoint recovers the
+    run bit for bit.  The NaN is planted from the host into a saved state, so every kernel
+    runs on ordinary data and exits normally."""
+    import torch
+    from paper_2508_16997_amd import Simulation, VlbError
+    from paper_2508_16997_amd import _lib as L
+
+    pr = synth.random_periodic(80, 40, seed=9, ymode="wall")
+    say("breakdown and recovery")
+    ref = Simulation.from_problem(pr, precision="fp32")
+    ref.step(20)
+    gr = gpu_fields(ref)
+    sim = Simulation.from_problem(pr, precision="fp32")
+    sim.step(10)
+    assert sim.monitors()["nonfinite"] == 0
+    clean = sim.save_state()
+    bad = clean.clone()
+    pb = (bad.numel() - 256) // 41  # header, then 41 planes of populations and history
+    start = 256 + pb // 2  # middle rows of the first population plane
+    bad[start:start + 2048].view(torch.float32).fill_(float("nan"))
+    sim.load_state(bad)
+    sim.step(1)
+    with pytest.raises(VlbError) as e:
+        sim.monitors()
+    assert e.value.status == L.VLB_E_NONFINITE
+    assert sim.monitors(raise_on_nonfinite=False)["nonfinite"] > 0
+    sim.load_state(clean)
+    sim.step(10)
+    assert sim.monitors()["nonfinite"] == 0
+    g = gpu_fields(sim)
+    for k in FIELDS:
+        assert np.array_equal(g[k], gr[k]), k
+    sim.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("case", [dict(xmode="periodic", ymode="wall"),
                                   dict(xmode="periodic", ymode="periodic", circles=[(30.0, 20.0, 7.5)]),
                                   dict(xmode="open", ymode="wall", circles=[(30.0, 20.0, 5.5)])])
