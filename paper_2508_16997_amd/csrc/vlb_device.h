@@ -192,6 +192,12 @@ __device__ __forceinline__ void closure(int model, T mp, T b0, T b1, T b2, T r[3
 struct Mom {
     T m0, mx, my, pxx, pyy, pxy, qxxy, qxyy;
 };
+// Zeroth moment with the same pairing and rounding as Mom::m0 below.
+template <class V>
+__device__ __forceinline__ T zeroth(const V v[9]) {
+    return T(v[0]) + ((T(v[1]) + T(v[3])) + (T(v[2]) + T(v[4]))) +
+           ((T(v[5]) + T(v[7])) + (T(v[6]) + T(v[8])));
+}
 template <class V>
 __device__ __forceinline__ Mom moments(const V v[9]) {
     const T s13 = T(v[1]) + T(v[3]), d13 = T(v[1]) - T(v[3]);

@@ -58,10 +58,16 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
     const bool active = in_dom && !(b & BIT_SELF_SOLID);
     S f[9], g[3][9];
     T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
+    // conformation deviations A - I: the zeroth moments of the pulled g lattices (CNEBB
+    // keeps them, so they are final before the wall reconstruction)
+    T dk[3] = {0.0, 0.0, 0.0};
     if (active) {
         pull9(R, src, 0, p, pull, f);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) pull9(R, src, 1 + k, p, pull, g[k]);
+        for (int k = 0; k < 3; ++k) {
+            pull9(R, src, 1 + k, p, pull, g[k]);
+            dk[k] = zeroth(g[k]);
+        }
         node_force(R, p, Fx, Fy);
         if (pull) {
 #pragma unroll
@@ -131,22 +137,7 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
     const T Dy = dgrad(wyl, qyl, rd * uyd * uyd * uyd, rho * uy * uy * uy, wyh, qyh,
                        ru * uyu * uyu * uyu);
 
-    // conformation: CNEBB at wall-adjacent nodes, then the moments of each lattice
-    const unsigned solid = pull ? (b & 0x1FEu) : 0u;
-    Mom gm[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (solid) {
-            T gg[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) gg[i] = T(g[k][i]);
-            cnebb(solid, k, ux, uy, gg);
-            gm[k] = moments(gg);
-        } else {
-            gm[k] = moments(g[k]);
-        }
-    }
-    const T d0 = gm[0].m0, d1 = gm[1].m0, d2 = gm[2].m0;
+    const T d0 = dk[0], d1 = dk[1], d2 = dk[2];
     const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
     T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
     if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
@@ -191,11 +182,26 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
             if (gs >= 0) stu(dst + i * plane, (unsigned)gs, out[i]);
         }
     }
+    // conformation lattices one at a time after the hydrodynamic one (keeps the
+    // register budget of four waves per SIMD): CNEBB at wall-adjacent nodes, moments,
+    // collision, stores
+    const unsigned solid = pull ? (b & 0x1FEu) : 0u;
     const T inv_rho = 1.0 / rho;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const T phi = phi0(k) + gm[k].m0;
-        collide_cde(R, gm[k], phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], hS[k], hux, huy, out);
+        Mom gm;
+        if (solid) {
+            T gg[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gg[i] = T(g[k][i]);
+            cnebb(solid, k, ux, uy, gg);
+            gm = moments(gg);
+        } else {
+            gm = moments(g[k]);
+        }
+        gm.m0 = dk[k];
+        const T phi = phi0(k) + dk[k];
+        collide_cde(R, gm, phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], hS[k], hux, huy, out);
 #pragma unroll
         for (int i = 0; i < 9; ++i) st_stream<NT>(dst + (9 + 9 * k + i) * plane, (unsigned)p, out[i]);
         if (edge) {
