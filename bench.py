@@ -29,10 +29,17 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per k_step launch on a workload, from rocprofv3 counters (per dispatch, KiB):
 # FETCH_SIZE counts half of the bytes a plain 1 GiB copy reads and WRITE_SIZE all it
 # writes, so traffic = 2 * FETCH + WRITE.  Valid only for the kernel sources they were
-# taken with (hash below); otherwise the bench reports null.
+# taken with (hash below) and the launch shape (tile height, store mode) the bench
+# times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
-    "four_roll_512": {"sources": "26df4b66c98f9978", "fetch_KiB": 25611.0, "write_KiB": 42416.0,
-                      "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
+    "four_roll_512": [
+        {"sources": "26df4b66c98f9978", "tile": 8, "store_mode": "streaming",
+         "fetch_KiB": 24921.7, "write_KiB": 42416.3,
+         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
+        {"sources": "26df4b66c98f9978", "tile": 4, "store_mode": "cached",
+         "fetch_KiB": 25611.0, "write_KiB": 42416.0,
+         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
+    ],
 }
 KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_kernels.hip")
 
@@ -47,11 +54,32 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name):
-    rec = MEASURED_TRAFFIC.get(workload_name)
-    if rec is None or rec["sources"] != kernel_sources_hash():
-        return None
-    return int(round((2.0 * rec["fetch_KiB"] + rec["write_KiB"]) * 1024))
+def auto_store_mode(pr, esz):
+    """The library's automatic choice: streaming (non-temporal) stores once the two
+    population buffers exceed 192 MiB, cached stores below."""
+    return "streaming" if 2.0 * 36 * pr.nx * pr.ny * esz > 192.0 * 1024 * 1024 else "cached"
+
+
+def autotuned_tile(sim):
+    """Tile height picked (and applied, with its store mode) by the library's autotuner
+    for this simulation: a sweep of tile heights and store modes outside any timed
+    region, state saved and restored."""
+    import tempfile
+
+    from paper_2508_16997_amd.autotune import tune
+
+    with tempfile.TemporaryDirectory() as d:
+        rec = tune(sim, cache=os.path.join(d, "autotune.json"), force=True)
+    sim.store_mode_name = "cached" if rec["store_mode"] == 1 else "streaming"
+    return int(rec["tile"])
+
+
+def measured_traffic(workload_name, tile, store_mode):
+    for rec in MEASURED_TRAFFIC.get(workload_name, []):
+        if (rec["sources"] == kernel_sources_hash() and rec["tile"] == tile
+                and rec["store_mode"] == store_mode):
+            return int(round((2.0 * rec["fetch_KiB"] + rec["write_KiB"]) * 1024))
+    return None
 
 
 def workload(name):
@@ -111,7 +139,8 @@ def cylinder_leg(steps, warmup, tile, chunk):
 
     pr = synth.cylinder(Wi=1.0)
     stream = torch.cuda.Stream()
-    sim = Simulation.from_problem(pr, stream=stream, tile=tile, graph_chunk=chunk)
+    sim = Simulation.from_problem(pr, stream=stream, tile=tile or 4, graph_chunk=chunk)
+    tile = tile or autotuned_tile(sim)
     nodes = int(pr.fluid_mask().sum())
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -132,7 +161,7 @@ def cylinder_leg(steps, warmup, tile, chunk):
             "fluid_nodes": nodes, "steps": steps, "MLUPS": round(nodes * steps / wall / 1e6, 2),
             "us_per_step": round(step_s * 1e6, 3), "bytes_per_node": bpn,
             "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "nonfinite": int(bad)}
+            "tile": f"64x{tile}", "nonfinite": int(bad)}
 
 
 def batched_leg(steps, warmup, tile, chunk):
@@ -147,8 +176,13 @@ def batched_leg(steps, warmup, tile, chunk):
 
     runs = synth.batch_c4()
     stream = torch.cuda.Stream()
-    sims = [Simulation.from_problem(r, stream=stream, tile=tile, graph_chunk=chunk) for r in runs]
+    sims = [Simulation.from_problem(r, stream=stream, tile=tile or 4, graph_chunk=chunk)
+            for r in runs]
     nodes = sum(int(r.fluid_mask().sum()) for r in runs)
+    if not tile:
+        from paper_2508_16997_amd.autotune import tune_batch
+
+        tile, _ = tune_batch(sims, tiles=(2, 4, 8), graph_chunk=chunk)
     b = Batch(sims, tile=tile, graph_chunk=chunk)
     b.step(warmup)
     torch.cuda.synchronize()
@@ -175,7 +209,7 @@ def batched_leg(steps, warmup, tile, chunk):
             "batched_vs_sequential": round(t_seq / t_batch, 3),
             "batched_GBs": round(step_bytes * steps / t_batch / 1e9, 1),
             "batched_frac": round(step_bytes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
-            "runs_nonfinite": int(bad)}
+            "tile": f"64x{tile}", "runs_nonfinite": int(bad)}
 
 
 def adjoint_leg(steps, stride, tile, chunk):
@@ -277,7 +311,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="four_roll_512",
                     choices=["four_roll_512", "cylinder_4096x1024", "poiseuille_64x32_fp64"])
-    ap.add_argument("--tile", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile height of the step kernel (64 x TY threads); 0 = autotune "
+                         "each leg before its timed region")
+    ap.add_argument("--store-mode", choices=["auto", "cached", "streaming"], default="auto",
+                    help="stores of the step kernel when --tile is fixed (the autotuner picks "
+                         "its own)")
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -313,7 +352,13 @@ def main():
     prec = pr.precision
     esz = 4 if prec == "fp32" else 8
     stream = torch.cuda.Stream()
-    sim = Simulation.from_problem(pr, stream=stream, tile=args.tile, graph_chunk=args.graph_chunk)
+    sim = Simulation.from_problem(pr, stream=stream, tile=args.tile or 4,
+                                  graph_chunk=args.graph_chunk)
+    tile = args.tile or autotuned_tile(sim)
+    if args.tile and args.store_mode != "auto":
+        sim.set_store_mode(1 if args.store_mode == "cached" else 2)
+        sim.store_mode_name = args.store_mode
+    store_mode = getattr(sim, "store_mode_name", None) or auto_store_mode(pr, esz)
     nodes = int(pr.fluid_mask().sum())
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -356,11 +401,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "storage": "f32" if prec == "fp32" else "f64",
                    "nx": pr.nx, "ny": pr.ny, "fluid_nodes": nodes,
-                   "bytes_per_node": bpn, "tile": f"64x{args.tile}",
+                   "bytes_per_node": bpn, "tile": f"64x{tile}",
+                   "store_mode": store_mode,
+                   "tile_choice": "fixed" if args.tile else "autotuned",
                    "graph_chunk_steps": 2 * args.graph_chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload), "kernel": "k_step",
+                     "traffic": measured_traffic(args.workload, tile, store_mode),
+                     "kernel": "k_step",
                      "avg_launch_us": round(launch_s * 1e6, 3),
                      "bytes_per_launch": bytes_launch,
                      "copy_ceiling_GBs": round(copy_gbs, 1),
@@ -373,7 +421,7 @@ def main():
         out["batched"] = batched_leg(args.batched_steps, 2 * args.graph_chunk + 1, args.tile,
                                      args.graph_chunk)
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_stride, args.tile,
+        out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_stride, tile,
                                      args.graph_chunk)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)

@@ -88,3 +88,25 @@ def tune(sim, steps: int = 60, warmup: int = 10, cache: Optional[str] = None,
     data[key] = rec
     _store(path, data)
     return rec
+
+
+def tune_batch(sims, tiles=TILES, steps: int = 20, warmup: int = 5, graph_chunk: int = 0):
+    """Time one batch per tile height over the same members and return
+    (fastest tile, {tile: seconds per step}).  The members advance by
+    len(tiles) * (warmup + steps) steps; results do not depend on the tile."""
+    from .sim import Batch
+
+    timings = {}
+    for ty in tiles:
+        b = Batch(sims, tile=ty, graph_chunk=graph_chunk)
+        b.step(warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        b.step(steps)
+        e1.record(b.stream)
+        e1.synchronize()
+        timings[ty] = e0.elapsed_time(e1) / 1e3 / steps
+        b.close()
+    best = min(timings, key=timings.get)
+    return best, timings
