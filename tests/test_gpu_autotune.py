@@ -58,3 +58,34 @@ def test_autotune_sweeps_restores_and_caches(tmp_path):
     assert again == data[size_class(sim)]
     sim.close()
     ref.close()
+
+
+def test_tune_batch_picks_a_tile_and_members_stay_exact():
+    """tune_batch times one batch per tile height over the same members; the members
+    then continue in a batch of the chosen tile bit-identically to runs stepped alone."""
+    import torch
+    from paper_2508_16997_amd import Batch, Simulation
+    from paper_2508_16997_amd.autotune import tune_batch
+
+    runs = [synth.random_periodic(70, 37, seed=3, ymode="wall", precision="fp32"),
+            synth.random_periodic(40, 24, seed=4, precision="fp32")]
+    stream = torch.cuda.Stream()
+    say("tune_batch")
+    members = [Simulation.from_problem(r, stream=stream) for r in runs]
+    alone = [Simulation.from_problem(r, stream=stream) for r in runs]
+    ty, timings = tune_batch(members, tiles=(2, 4, 8), steps=6, warmup=2, graph_chunk=2)
+    assert ty in (2, 4, 8) and set(timings) == {2, 4, 8} and timings[ty] == min(timings.values())
+    done = 3 * (2 + 6)
+    b = Batch(members, tile=ty, graph_chunk=2)
+    b.step(11)
+    for s in alone:
+        s.step(done + 11)
+    stream.synchronize()
+    for sb, ss in zip(members, alone):
+        assert sb.time == ss.time == done + 11
+        gb, gs = _exact(sb), _exact(ss)
+        for k in FIELDS:
+            assert np.array_equal(gb[k], gs[k]), k
+    b.close()
+    for s in members + alone:
+        s.close()
