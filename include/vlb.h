@@ -219,7 +219,8 @@ int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
 /* ---- adjoint ------------------------------------------------------------------------ */
 
 /* Discrete adjoint of nsteps coupled steps (Sec. 3, Eqs. 31-51, differentiated step by
- * step in reverse order) for fully periodic domains without solid nodes.  The
+ * step in reverse order) for fully periodic domains without solid nodes, with any of
+ * the constitutive closures above.  The
  * differentiated quantities are the relaxation time lambda, the polymer viscosity
  * eta_p and the per-node body force F(x) (held fixed over the steps; with a uniform
  * force the gradient is still returned per node).  Memory: sqrt(N) checkpointing --

@@ -263,12 +263,14 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
         for (int k = 0; k < 3; ++k) gm[k] = moments(g[k]);
         const T d0 = gm[0].m0, d1 = gm[1].m0, d2 = gm[2].m0;
         const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
+        T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
+        if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
         T Sc[3] = {0.0, 0.0, 0.0};
         if (!R.no_source) {
             const T d = Lxx + Lyy;
-            Sc[0] = -R.inv_lam * d0 + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
-            Sc[1] = -R.inv_lam * d1 + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
-            Sc[2] = -R.inv_lam * d2 + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
+            Sc[0] = -R.inv_lam * rf[0] + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
+            Sc[1] = -R.inv_lam * rf[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
+            Sc[2] = -R.inv_lam * rf[2] + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
         }
         if (!pull) {
             hS[0] = Sc[0]; hS[1] = Sc[1]; hS[2] = Sc[2];
@@ -327,24 +329,29 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
             a_uyp = 0.0;
         }
 
-        // constitutive source S(A, L, lambda)
+        // constitutive source S(A, L, lambda) = -F_r(A)/lambda + upper-convected terms,
+        // polymer stress tau = (eta_p / lambda) F_s(A)
         T a_Lxx = 0.0, a_Lxy = 0.0, a_Lyx = 0.0, a_Lyy = 0.0;
+        T wr[3] = {0.0, 0.0, 0.0};
         if (!R.no_source) {
             const T d = Lxx + Lyy;
-            a_d[0] += a_S[0] * (-R.inv_lam + 2.0 * Lxx + d) + a_S[1] * Lxy;
-            a_d[1] += a_S[0] * (2.0 * Lyx) + a_S[1] * (-R.inv_lam + Lyy + Lxx + d) + a_S[2] * (2.0 * Lxy);
-            a_d[2] += a_S[1] * Lyx + a_S[2] * (-R.inv_lam + 2.0 * Lyy + d);
+            a_d[0] += a_S[0] * (2.0 * Lxx + d) + a_S[1] * Lxy;
+            a_d[1] += a_S[0] * (2.0 * Lyx) + a_S[1] * (Lyy + Lxx + d) + a_S[2] * (2.0 * Lxy);
+            a_d[2] += a_S[1] * Lyx + a_S[2] * (2.0 * Lyy + d);
             a_Lxx = 3.0 * axx * a_S[0] + 2.0 * axy * a_S[1] + ayy * a_S[2];
             a_Lyy = axx * a_S[0] + 2.0 * axy * a_S[1] + 3.0 * ayy * a_S[2];
             a_Lxy = axx * a_S[1] + 2.0 * axy * a_S[2];
             a_Lyx = 2.0 * axy * a_S[0] + ayy * a_S[1];
-            glam += R.inv_lam * R.inv_lam * (d0 * a_S[0] + d1 * a_S[1] + d2 * a_S[2]);
+            glam += R.inv_lam * R.inv_lam * (rf[0] * a_S[0] + rf[1] * a_S[1] + rf[2] * a_S[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) wr[k] = -R.inv_lam * a_S[k];
         }
-        // polymer stress tau = (eta_p / lambda)(A - I)
-        const T td = d0 * ha.txx + d1 * ha.txy + d2 * ha.tyy;
-        a_d[0] += R.eta_over_lam * ha.txx;
-        a_d[1] += R.eta_over_lam * ha.txy;
-        a_d[2] += R.eta_over_lam * ha.tyy;
+        const T td = sf[0] * ha.txx + sf[1] * ha.txy + sf[2] * ha.tyy;
+        const T ws[3] = {R.eta_over_lam * ha.txx, R.eta_over_lam * ha.txy, R.eta_over_lam * ha.tyy};
+        T a_b[3];
+        closure_adj(R.model, R.mpar, d0, d1, d2, wr, ws, a_b);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a_d[k] += a_b[k];
         geta += R.inv_lam * td;
         glam -= R.eta_over_lam * R.inv_lam * td;
 

@@ -968,8 +968,6 @@ int adj_check(const vlb_sim* s, int64_t nsteps, int stride) {
     if (rc) return rc;
     if (s->xmode != VLB_PERIODIC || s->ymode != VLB_PERIODIC || s->has_bits)
         return fail(VLB_E_UNSUPPORTED, "the adjoint covers fully periodic domains without solids");
-    if (s->params.model != VLB_OLDROYD_B)
-        return fail(VLB_E_UNSUPPORTED, "the adjoint covers the Oldroyd-B closure");
     if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
     return VLB_OK;
 }

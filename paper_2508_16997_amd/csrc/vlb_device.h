@@ -192,6 +192,39 @@ __device__ __forceinline__ void closure(int model, T mp, T b0, T b1, T b2, T r[3
 struct Mom {
     T m0, mx, my, pxx, pyy, pxy, qxxy, qxyy;
 };
+// Transpose of the closure's Jacobian (the adjoint of closure() above): for weights wr
+// on F_r and ws on F_s, out_j = sum_i wr_i dF_r,i/db_j + ws_i dF_s,i/db_j with
+// b = (B_xx, B_xy, B_yy) as closure() takes it.
+__device__ __forceinline__ void closure_adj(int model, T mp, T b0, T b1, T b2, const T wr[3],
+                                            const T ws[3], T out[3]) {
+    out[0] = wr[0] + ws[0];
+    out[1] = wr[1] + ws[1];
+    out[2] = wr[2] + ws[2];
+    if (model == MODEL_GIESEKUS) {
+        out[0] = wr[0] * (1.0 + 2.0 * mp * b0) + wr[1] * (mp * b1) + ws[0];
+        out[1] = (wr[0] + wr[2]) * (2.0 * mp * b1) + wr[1] * (1.0 + mp * (b0 + b2)) + ws[1];
+        out[2] = wr[1] * (mp * b1) + wr[2] * (1.0 + 2.0 * mp * b2) + ws[2];
+    } else if (model == MODEL_LPTT || model == MODEL_EPTT) {
+        const T x = mp * (b0 + b2);
+        const T Y = model == MODEL_LPTT ? 1.0 + x : exp(x);
+        const T dY = model == MODEL_LPTT ? mp : mp * Y;  // dY/db_xx = dY/db_yy
+        const T wb = wr[0] * b0 + wr[1] * b1 + wr[2] * b2;
+        out[0] = Y * wr[0] + dY * wb + ws[0];
+        out[1] = Y * wr[1] + ws[1];
+        out[2] = Y * wr[2] + dY * wb + ws[2];
+    } else if (model == MODEL_FENE_P) {
+        const T tr = b0 + b2;
+        const T den = mp - tr;
+        const T fm1 = tr / den;
+        const T dfm = mp / (den * den);  // d(f - 1)/db_xx = d(f - 1)/db_yy
+        const T w0 = wr[0] + ws[0], w1 = wr[1] + ws[1], w2 = wr[2] + ws[2];
+        const T wI = w0 * (1.0 + b0) + w1 * b1 + w2 * (1.0 + b2);
+        out[0] = (1.0 + fm1) * w0 + dfm * wI;
+        out[1] = (1.0 + fm1) * w1;
+        out[2] = (1.0 + fm1) * w2 + dfm * wI;
+    }
+}
+
 // Zeroth moment with the same pairing and rounding as Mom::m0 below.
 template <class V>
 __device__ __forceinline__ T zeroth(const V v[9]) {

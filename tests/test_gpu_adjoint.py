@@ -1,7 +1,7 @@
 """Discrete adjoint (HIP) against derivatives computed without it.
 
 * 8 x 8 periodic, FP64: the full gradient (lambda, eta_p and all 128 force components)
-  against central differences of the FP64 oracle.
+  against central differences of the FP64 oracle, for Oldroyd-B and the other closures.
 * 128 x 128, 200 steps: directional derivatives along lambda, eta_p and a random smooth
   force direction against the oracle's forward-mode (dual-number) derivatives.
 * The adjoint workload at full size (512 x 512, FP32, 2000 steps, checkpoint stride 45,
@@ -69,12 +69,16 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_adjoint_bruteforce_8x8_fp64():
-    """All 130 gradient components against oracle central differences."""
-    pr = synth.random_periodic(8, 8, seed=3, precision="fp64")
+@pytest.mark.parametrize("model,mp", [("oldroyd_b", 0.0), ("giesekus", 0.3), ("lptt", 0.25),
+                                      ("eptt", 0.25), ("fene_p", 20.0)])
+def test_adjoint_bruteforce_8x8_fp64(model, mp):
+    """All 130 gradient components against oracle central differences, for every
+    constitutive closure (the transpose of each closure's Jacobian)."""
+    pr = synth.random_periodic(8, 8, seed=3, precision="fp64").with_(model=model,
+                                                                     model_param=mp)
     steps, stride = 12, 5  # three segments, the last one partial
     tgt = _target(pr, 11)
-    say("adjoint 8x8 brute force", steps, stride)
+    say("adjoint 8x8 brute force", model, steps, stride)
     g = _gpu_adjoint(pr, steps, tgt, "fp64", stride)
     assert abs(g["loss"] - _oracle_loss(pr, steps, tgt)) < 1e-12 * abs(g["loss"]) + 1e-18
 
