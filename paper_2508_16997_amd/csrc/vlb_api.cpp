@@ -297,6 +297,11 @@ void build_fill(vlb_sim* s) {
                 if (!xout && !yout) continue;  // ordinary pull from a fluid node
                 const int yw = yout ? wrap(ys, ny) : ys;
                 if (xout && s->xmode == VLB_OPEN) {
+                    // the extrapolation node x0 (same row as the ghost, first or last
+                    // column) writes this ghost itself in the step kernel; only ghosts of
+                    // a solid x0 (constant equilibrium values) stay in the fill list
+                    const int x0c = xs < 0 ? 0 : nx - 1;
+                    if (!s->solid[(size_t)yw * nx + x0c]) continue;
                     if (xs < 0) {
                         op.dir_kind = i | (vlb::FILL_INLET << 8);
                         op.far = yw;

@@ -23,11 +23,11 @@ enum { XOFF = 64 };
 // Kinds of fill operations (run after each step on the post-collision buffer, before
 // the next step pulls from it).  One op serves direction `dir` of one fluid node.
 enum {
-    FILL_OUTLET = 0,   // last column: non-equilibrium extrapolation from node src
+    FILL_OUTLET = 0,   // last column, solid x0: rest equilibrium (constant)
     FILL_WALL = 1,     // half-way bounce-back: f_dir(dst) <- f_opp(src); g likewise
     FILL_CURVED = 2,   // interpolated bounce-back for f (q, far node); g as FILL_WALL
-    FILL_INLET = 3     // first column: inlet profile at row `far`, non-equilibrium
-                       // part extrapolated from that row's first node
+    FILL_INLET = 3     // first column, solid x0: equilibrium of the inlet profile at
+                       // row `far` (constant)
 };
 
 // Constitutive closures (same values as VLB_OLDROYD_B ... VLB_FENE_P of the ABI).

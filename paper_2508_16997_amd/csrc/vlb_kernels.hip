@@ -33,6 +33,26 @@ struct StepBounds {
 namespace vlb {
 namespace {
 
+// Ghost slots that the inlet (outlet) links of row y pull from: direction i with
+// e_x = +1 (-1) is pulled by node (x, y + e_y) from (gx, y), gx = -1 (nx); at a periodic
+// y edge the puller wraps and the slot is the corner ghost it pulls from.  Calls
+// fn(i, slot) for each.
+template <class S, class F>
+__device__ __forceinline__ void open_end_slots(const RunDev<S>& R, int y, bool in, F fn) {
+    const int gx = in ? -1 : R.nx;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        if (ex(i) != (in ? 1 : -1)) continue;
+        const int yp = y + ey(i);
+        int gy = y;
+        if (yp < 0 || yp >= R.ny) {
+            if (R.ymode != XM_PERIODIC) continue;  // beyond a wall: nobody pulls it
+            gy = (yp < 0 ? yp + R.ny : yp - R.ny) - ey(i);
+        }
+        fn(i, (unsigned)(R.off0 + gy * R.pitch + gx));
+    }
+}
+
 template <class S, int TY, bool NT>
 __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::min_waves_per_eu)) void k_step(
     const RunDev<S>* __restrict__ runs, const Item* __restrict__ items, int parity, int first) {
@@ -175,6 +195,26 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
     collide_hydro(R, moments(f), rho, ux, uy, Fx, Fy, txx, txy, tyy, Dx, Dy, out);
 #pragma unroll
     for (int i = 0; i < 9; ++i) st_stream<NT>(dst + i * plane, (unsigned)p, out[i]);
+    // Open ends (Sec. 4.3): the first (last) column node writes the ghosts its row's
+    // inlet (outlet) links pull next step by non-equilibrium extrapolation from its own
+    // post-collision populations (as stored): f_i = f_i^eq(rho_b, u_b) + f_i -
+    // f_i^eq(rho, u) with rho, u their moments; inlet rho_b = rho, u_b = profile;
+    // outlet rho_b = 1, u_b = u.  The conformation ghosts follow below.
+    const bool oend = R.xmode == XM_OPEN && (x == 0 || x == R.nx - 1);
+    const bool oin = x == 0;
+    T oux = 0.0, ouy = 0.0;
+    if (oend) {
+        S so[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) so[i] = S(out[i]);
+        T odr, orho;
+        hydro_macros(so, 0.0, 0.0, odr, orho, oux, ouy);
+        const T uin = oin ? T(R.inlet[y]) : 0.0;
+        open_end_slots(R, y, oin, [&](int i, unsigned gs) {
+            const T fneq = T(so[i]) - dfeq(i, odr, orho, oux, ouy);
+            stu(dst + i * plane, gs, (oin ? dfeq(i, odr, orho, uin, 0.0) : dfeq(i, 0.0, 1.0, oux, ouy)) + fneq);
+        });
+    }
     if (edge) {
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -204,6 +244,22 @@ __global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::m
         collide_cde(R, gm, phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], hS[k], hux, huy, out);
 #pragma unroll
         for (int i = 0; i < 9; ++i) st_stream<NT>(dst + (9 + 9 * k + i) * plane, (unsigned)p, out[i]);
+        if (oend) {  // inlet: extrapolation around A_in, u_in; outlet: copy
+            S so[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) so[i] = S(out[i]);
+            T dphi = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dphi += T(so[i]);
+            const T uin = oin ? T(R.inlet[y]) : 0.0;
+            const T a = oin ? T(R.inlet[(1 + k) * R.ny + y]) : 0.0;
+            open_end_slots(R, y, oin, [&](int i, unsigned gs) {
+                stu(dst + (9 + 9 * k + i) * plane, gs,
+                    oin ? dgeq(i, a - phi0(k), a, uin, 0.0) + T(so[i]) -
+                              dgeq(i, dphi, phi0(k) + dphi, oux, ouy)
+                        : T(so[i]));
+            });
+        }
         if (edge) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
