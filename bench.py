@@ -33,11 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
     "four_roll_512": [
-        {"sources": "26df4b66c98f9978", "tile": 8, "store_mode": "streaming",
-         "fetch_KiB": 24921.7, "write_KiB": 42416.3,
-         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
-        {"sources": "26df4b66c98f9978", "tile": 4, "store_mode": "cached",
-         "fetch_KiB": 25611.0, "write_KiB": 42416.0,
+        {"sources": "61146c7b4ec7953c", "tile": 8, "store_mode": "streaming",
+         "fetch_KiB": 25079.8, "write_KiB": 42418.6,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
     ],
 }
