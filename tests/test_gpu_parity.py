@@ -30,12 +30,21 @@ def _cases():
     mask = np.zeros((37, 70), np.uint8)
     mask[10:15, 20:24] = 1
     mask[25, 50] = 1
+    end_mask = np.zeros((37, 90), np.uint8)
+    end_mask[5:8, 0] = 1
+    end_mask[20:22, 89] = 1
+    end_mask[0, 0] = 1
     return {
         "periodic_ragged": dict(nx=40, ny=24),
         "periodic_multi_tile": dict(nx=150, ny=21),
         "channel_walls": dict(nx=70, ny=37, ymode="wall", solid=mask),
         "x_walls_circle": dict(nx=90, ny=30, xmode="wall", circles=[(45.0, 15.0, 6.7)]),
         "open_circle": dict(nx=130, ny=33, xmode="open", ymode="wall", circles=[(50.0, 16.0, 7.2)]),
+        # open ends on a periodic y edge (corner ghosts) and solid nodes in the first and
+        # last columns (constant ghosts of a solid extrapolation node)
+        "open_periodic_y": dict(nx=100, ny=26, xmode="open", ymode="periodic",
+                                circles=[(40.0, 13.0, 5.2)]),
+        "open_solid_ends": dict(nx=90, ny=37, xmode="open", ymode="wall", solid=end_mask),
     }
 
 
