@@ -38,7 +38,7 @@ MEASURED_TRAFFIC = {
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
     ],
 }
-KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_kernels.hip")
+KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_step.h", "vlb_kernels.hip")
 
 
 def kernel_sources_hash():
@@ -162,10 +162,12 @@ def cylinder_leg(steps, warmup, tile, chunk):
 
 
 def batched_leg(steps, warmup, tile, chunk):
-    """Batched workload (256 uneven runs, one launch per step) vs the same runs one by one.
+    """Batched workload (256 uneven runs advanced together) vs the same runs one by one.
 
-    Both legs run the same simulations on the same stream with hipGraph replay; the
-    sequential leg steps each run alone for the same number of steps, back to back.
+    The batch is timed in both forms (one step launch and one fill launch per step under
+    hipGraph replay, or the persistent cooperative launch of up to 256 steps), each at
+    its autotuned tile; the faster is the batched figure.  The sequential leg steps each
+    run alone for the same number of steps, back to back, with hipGraph replay.
     """
     import torch
     import synth
@@ -176,17 +178,27 @@ def batched_leg(steps, warmup, tile, chunk):
     sims = [Simulation.from_problem(r, stream=stream, tile=tile or 4, graph_chunk=chunk)
             for r in runs]
     nodes = sum(int(r.fluid_mask().sum()) for r in runs)
-    if not tile:
-        from paper_2508_16997_amd.autotune import tune_batch
+    from paper_2508_16997_amd.autotune import tune_batch
 
-        tile, _ = tune_batch(sims, tiles=(2, 4, 8), graph_chunk=chunk)
-    b = Batch(sims, tile=tile, graph_chunk=chunk)
-    b.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    # both batched forms, each at its fastest tile (or the tile given); the faster one
+    # is the batched figure, the other is reported beside it
+    (tile, pers), tuned = tune_batch(sims, tiles=(tile,) if tile else (2, 4, 8),
+                                     graph_chunk=chunk, forms=(False, True))
+
+    def timed_batch(ty, persistent):
+        b = Batch(sims, tile=ty, graph_chunk=0 if persistent else chunk, persistent=persistent)
+        b.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        b.close()
+        return t
+
+    t_batch = timed_batch(tile, pers)
+    other = min((k for k in tuned if k[1] != pers), key=tuned.get)
+    t_other = timed_batch(*other)
     for s in sims:  # warm the per-run graphs
         s.step(warmup)
     torch.cuda.synchronize()
@@ -197,7 +209,6 @@ def batched_leg(steps, warmup, tile, chunk):
     t_seq = time.perf_counter() - t0
     bad = sum(s.monitors(raise_on_nonfinite=False)["nonfinite"] > 0 for s in sims)
     step_bytes = sum(bytes_per_node(r, 4) * int(r.fluid_mask().sum()) for r in runs)
-    b.close()
     for s in sims:
         s.close()
     return {"runs": len(runs), "nodes": nodes, "steps": steps,
@@ -206,7 +217,11 @@ def batched_leg(steps, warmup, tile, chunk):
             "batched_vs_sequential": round(t_seq / t_batch, 3),
             "batched_GBs": round(step_bytes * steps / t_batch / 1e9, 1),
             "batched_frac": round(step_bytes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
-            "tile": f"64x{tile}", "runs_nonfinite": int(bad)}
+            "tile": f"64x{tile}", "form": "persistent" if pers else "per-step launches",
+            "other_form": {"form": "persistent" if other[1] else "per-step launches",
+                           "tile": f"64x{other[0]}",
+                           "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
+            "runs_nonfinite": int(bad)}
 
 
 def adjoint_leg(steps, stride, tile, chunk):

@@ -262,8 +262,9 @@ int vlb_adjoint(vlb_sim* sim, int64_t nsteps, int stride, const void* ux_target_
  * destroyed and may read them (vlb_read_fields, vlb_monitors, ...) between batch steps.
  * ty: tile height 1, 2, 4 or 8 for the batch's launches.  workspace_dev: device
  * memory of at least vlb_batch_workspace_bytes, 256-byte aligned, owned by the
- * caller, holding the work lists and member descriptors.  A member's new parameters,
- * force field or inlet are picked up at the next vlb_batch_step.  Errors:
+ * caller, holding the work lists, member descriptors and the persistent form's work
+ * counters.  A member's new parameters, force field or inlet are picked up at the next
+ * vlb_batch_step.  Errors:
  * VLB_E_INVALID_ARG (null/mixed members, bad ty), VLB_E_STATE (member not ready,
  * steps differ, or a member was stepped or reloaded outside the batch),
  * VLB_E_WORKSPACE, VLB_E_HIP. */
@@ -278,6 +279,14 @@ int vlb_batch_read_fields(vlb_batch* batch, int run, void* rho, void* ux, void* 
                           void* axy, void* ayy);
 /* hipGraph replay in chunks of 2 * chunk steps (0 disables). */
 int vlb_batch_set_graph_chunk(vlb_batch* batch, int chunk);
+/* on = 1: persistent form -- one cooperative launch advances every member up to 256
+ * steps (all tiles of a step, a grid-wide barrier, all boundary fills, a barrier, next
+ * step).  The grid is as many workgroups as stay resident together; they draw tiles
+ * from per-XCD queues (atomic counters in the batch workspace).  Results are
+ * bit-identical to the per-step launches (on = 0, the default; also hipGraph-captured
+ * when a graph chunk is set).  Errors: VLB_E_UNSUPPORTED without cooperative launch
+ * support. */
+int vlb_batch_set_persistent(vlb_batch* batch, int on);
 void vlb_batch_destroy(vlb_batch* batch);
 
 /* ---- errors ------------------------------------------------------------------------ */

@@ -90,23 +90,28 @@ def tune(sim, steps: int = 60, warmup: int = 10, cache: Optional[str] = None,
     return rec
 
 
-def tune_batch(sims, tiles=TILES, steps: int = 20, warmup: int = 5, graph_chunk: int = 0):
-    """Time one batch per tile height over the same members and return
-    (fastest tile, {tile: seconds per step}).  The members advance by
-    len(tiles) * (warmup + steps) steps; results do not depend on the tile."""
+def tune_batch(sims, tiles=TILES, steps: int = 20, warmup: int = 5, graph_chunk: int = 0,
+               forms=(False,)):
+    """Time one batch per (tile height, form) over the same members and return
+    (fastest (tile, persistent), {(tile, persistent): seconds per step}).  ``forms``
+    lists the forms to try: False = one step launch and one fill launch per step
+    (hipGraph replay when graph_chunk > 0), True = the persistent cooperative launch.
+    The members advance by len(tiles) * len(forms) * (warmup + steps) steps; results do
+    not depend on the choice."""
     from .sim import Batch
 
     timings = {}
     for ty in tiles:
-        b = Batch(sims, tile=ty, graph_chunk=graph_chunk)
-        b.step(warmup)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(b.stream)
-        b.step(steps)
-        e1.record(b.stream)
-        e1.synchronize()
-        timings[ty] = e0.elapsed_time(e1) / 1e3 / steps
-        b.close()
+        for pers in forms:
+            b = Batch(sims, tile=ty, graph_chunk=0 if pers else graph_chunk, persistent=pers)
+            b.step(warmup)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(b.stream)
+            b.step(steps)
+            e1.record(b.stream)
+            e1.synchronize()
+            timings[(ty, bool(pers))] = e0.elapsed_time(e1) / 1e3 / steps
+            b.close()
     best = min(timings, key=timings.get)
     return best, timings

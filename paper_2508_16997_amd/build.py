@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvlb.so")
-SOURCES = ["vlb_kernels.hip", "vlb_fill.hip", "vlb_aux.hip", "vlb_adjoint.hip", "vlb_api.cpp"]
+SOURCES = ["vlb_kernels.hip", "vlb_batch.hip", "vlb_fill.hip", "vlb_aux.hip", "vlb_adjoint.hip", "vlb_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VLB_OFFLOAD_ARCH", "gfx950")
@@ -32,6 +32,9 @@ PER_FILE = {
     # contraction decided per source expression, so every inlined copy of a device
     # function rounds identically (results independent of the tiling)
     "vlb_kernels.hip": ["-ffp-contract=on"],
+    # machine-level loop-invariant code motion would hoist the FP64 constants of the
+    # tile body out of the persistent tile loop and keep them live across it (spills)
+    "vlb_batch.hip": ["-ffp-contract=on", "-mllvm", "-disable-machine-licm"],
     "vlb_fill.hip": ["-ffp-contract=on"],
     "vlb_adjoint.hip": ["-ffp-contract=on"],
     "vlb_aux.hip": ["-ffp-contract=on"],

@@ -128,10 +128,11 @@ struct vlb_batch {
     char* ws = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
-    size_t off_runs = 0, off_items = 0, off_fill_items = 0, total = 0;
+    size_t off_runs = 0, off_items = 0, off_fill_items = 0, off_queues = 0, total = 0;
     std::vector<vlb::Item> items;
     std::vector<vlb::FillItem> fill_items;
     int graph_chunk = 0;
+    int persistent = 0;  // 1: cooperative persistent launches (launch_batch)
     int64_t step = 0;  // step count of every member, as advanced by the batch
     std::vector<uint64_t> versions;  // member descriptor versions last copied
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -1183,6 +1184,7 @@ void batch_layout(vlb_batch* b) {
     b->off_runs = take(b->sims.size() * rsz);
     b->off_items = take(std::max<size_t>(1, b->items.size()) * sizeof(vlb::Item));
     b->off_fill_items = take(std::max<size_t>(1, b->fill_items.size()) * sizeof(vlb::FillItem));
+    b->off_queues = take(2 * vlb::kBatchQueues * sizeof(int));  // persistent form's counters
     b->total = o;
 }
 
@@ -1234,6 +1236,7 @@ int batch_upload(vlb_batch* b) {
     }
     VLB_HIP(hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(vlb::Item),
                            hipMemcpyHostToDevice, b->stream));
+    VLB_HIP(hipMemsetAsync(b->ws + b->off_queues, 0, 2 * vlb::kBatchQueues * sizeof(int), b->stream));
     if (!b->fill_items.empty())
         VLB_HIP(hipMemcpyAsync(b->ws + b->off_fill_items, b->fill_items.data(),
                                b->fill_items.size() * sizeof(vlb::FillItem), hipMemcpyHostToDevice,
@@ -1260,6 +1263,9 @@ void batch_drop_graphs(vlb_batch* b) {
     }
 }
 
+// Steps per cooperative launch of the persistent batch kernel.
+constexpr int64_t kPersistentChunk = 256;
+
 template <class T>
 int batch_launch(vlb_batch* b, int par, int first) {
     const Run<T>* rd = reinterpret_cast<const Run<T>*>(b->ws + b->off_runs);
@@ -1283,6 +1289,22 @@ int batch_step(vlb_batch* b, int64_t n) {
             if (k > 0) s->first = 0;
         }
     };
+    if (b->persistent) {
+        // one cooperative launch per chunk of at most kPersistentChunk steps (bounded
+        // kernel duration); the first step of the members is the chunk's first
+        const Run<T>* rd = reinterpret_cast<const Run<T>*>(b->ws + b->off_runs);
+        const vlb::Item* it = reinterpret_cast<const vlb::Item*>(b->ws + b->off_items);
+        const vlb::FillItem* fi = reinterpret_cast<const vlb::FillItem*>(b->ws + b->off_fill_items);
+        while (n > 0) {
+            const int k = (int)std::min<int64_t>(n, kPersistentChunk);
+            VLB_HIP(vlb::launch_batch<T>(rd, it, (int)b->items.size(), fi, (int)b->fill_items.size(),
+                                         k, b->ty, s0->parity, s0->first, b->streaming,
+                                         reinterpret_cast<int*>(b->ws + b->off_queues), b->stream));
+            advance(k);
+            n -= k;
+        }
+        return VLB_OK;
+    }
     if (s0->first && n > 0) {
         int rc = batch_launch<T>(b, s0->parity, 1);
         if (rc) return rc;
@@ -1365,6 +1387,19 @@ int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* ws, size_t bytes
     rc = b->prec == VLB_FP32 ? batch_upload<float>(b) : batch_upload<double>(b);
     if (rc) { delete b; return rc; }
     *out = b;
+    return VLB_OK;
+}
+
+int vlb_batch_set_persistent(vlb_batch* b, int on) {
+    if (!b) return fail(VLB_E_INVALID_ARG, "null batch");
+    if (on != 0 && on != 1) return fail(VLB_E_INVALID_ARG, "persistent must be 0 or 1");
+    if (on) {
+        int dev = 0, coop = 0;
+        VLB_HIP(hipGetDevice(&dev));
+        VLB_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        if (!coop) return fail(VLB_E_UNSUPPORTED, "device has no cooperative launch");
+    }
+    b->persistent = on;
     return VLB_OK;
 }
 

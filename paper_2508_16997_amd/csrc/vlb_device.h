@@ -225,6 +225,49 @@ __device__ __forceinline__ void closure_adj(int model, T mp, T b0, T b1, T b2, c
     }
 }
 
+// One boundary-fill op on the post-collision buffer buf (see FillOp): write into the
+// ghost or solid slot op.dst the value that the fluid node op.src pulls in direction
+// dir next step.
+template <class S>
+__device__ __forceinline__ void apply_fill_op(const RunDev<S>& R, const FillOp& op, S* buf) {
+    const long long plane = R.plane;
+    const int dir = op.dir_kind & 0xff, kind = op.dir_kind >> 8;
+    const int o = opp(dir);
+    if (kind == FILL_OUTLET || kind == FILL_INLET) {
+        // Open-end ghosts whose extrapolation node x0 (first or last column, row `far`)
+        // is solid: the equilibrium of the boundary state (inlet profile, or rest at the
+        // outlet), constant in time.  Ghosts of fluid x0 are written by the step kernel
+        // itself.
+        const bool in = kind == FILL_INLET;
+        const T uin = in ? T(R.inlet[op.far]) : 0.0;
+        stu(buf + dir * plane, (unsigned)op.dst, in ? dfeq(dir, 0.0, 1.0, uin, 0.0) : 0.0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T a = in ? T(R.inlet[(1 + k) * R.ny + op.far]) : phi0(k);
+            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
+                in ? dgeq(dir, a - phi0(k), a, uin, 0.0) : 0.0);
+        }
+    } else {
+        // conformation lattices: the population that left toward the wall (CNEBB input)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
+                ldu(buf + (9 + 9 * k + o) * plane, (unsigned)op.src));
+        // hydrodynamic lattice: half-way or linear interpolated bounce-back
+        const T fo = ldu(buf + o * plane, (unsigned)op.src);
+        T v = fo;
+        if (kind == FILL_CURVED) {
+            const T q = op.q;
+            if (q < 0.5) {
+                if (op.far >= 0) v = 2.0 * q * fo + (1.0 - 2.0 * q) * ldu(buf + o * plane, (unsigned)op.far);
+            } else {
+                v = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * ldu(buf + dir * plane, (unsigned)op.src);
+            }
+        }
+        stu(buf + dir * plane, (unsigned)op.dst, v);
+    }
+}
+
 // Zeroth moment with the same pairing and rounding as Mom::m0 below.
 template <class V>
 __device__ __forceinline__ T zeroth(const V v[9]) {

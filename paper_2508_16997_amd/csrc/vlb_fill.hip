@@ -24,43 +24,7 @@ __global__ __launch_bounds__(256) void k_fill(const RunDev<S>* __restrict__ runs
     if ((int)threadIdx.x >= it.count) return;
     const RunDev<S>& R = runs[it.run];
     const FillOp op = R.fill[it.first + threadIdx.x];
-    S* buf = R.pop[parity];
-    const long long plane = R.plane;
-    const int dir = op.dir_kind & 0xff, kind = op.dir_kind >> 8;
-    const int o = opp(dir);
-    if (kind == FILL_OUTLET || kind == FILL_INLET) {
-        // Open-end ghosts whose extrapolation node x0 (first or last column, row `far`)
-        // is solid: the equilibrium of the boundary state (inlet profile, or rest at the
-        // outlet), constant in time.  Ghosts of fluid x0 are written by the step kernel
-        // itself.
-        const bool in = kind == FILL_INLET;
-        const T uin = in ? T(R.inlet[op.far]) : 0.0;
-        stu(buf + dir * plane, (unsigned)op.dst, in ? dfeq(dir, 0.0, 1.0, uin, 0.0) : 0.0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T a = in ? T(R.inlet[(1 + k) * R.ny + op.far]) : phi0(k);
-            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
-                in ? dgeq(dir, a - phi0(k), a, uin, 0.0) : 0.0);
-        }
-    } else {
-        // conformation lattices: the population that left toward the wall (CNEBB input)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
-                ldu(buf + (9 + 9 * k + o) * plane, (unsigned)op.src));
-        // hydrodynamic lattice: half-way or linear interpolated bounce-back
-        const T fo = ldu(buf + o * plane, (unsigned)op.src);
-        T v = fo;
-        if (kind == FILL_CURVED) {
-            const T q = op.q;
-            if (q < 0.5) {
-                if (op.far >= 0) v = 2.0 * q * fo + (1.0 - 2.0 * q) * ldu(buf + o * plane, (unsigned)op.far);
-            } else {
-                v = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * ldu(buf + dir * plane, (unsigned)op.src);
-            }
-        }
-        stu(buf + dir * plane, (unsigned)op.dst, v);
-    }
+    apply_fill_op(R, op, R.pop[parity]);
 }
 
 }  // namespace

@@ -114,6 +114,14 @@ struct MonitorAcc {
 template <class S>
 hipError_t launch_step(const RunDev<S>* runs_dev, const Item* items_dev, int nitems, int ty,
                        int parity, int first, int streaming, hipStream_t s);
+// Persistent batch form (vlb_batch.hip): one cooperative launch runs nsteps steps (step,
+// grid barrier, fills, grid barrier) over the same work and fill lists.  queues: device
+// array of 2 * kBatchQueues ints, zero before the first launch and left zero by each.
+constexpr int kBatchQueues = 8;
+template <class S>
+hipError_t launch_batch(const RunDev<S>* runs_dev, const Item* items_dev, int nitems,
+                        const FillItem* fitems_dev, int nfitems, int nsteps, int ty, int parity,
+                        int first, int streaming, int* queues, hipStream_t s);
 template <class S>
 hipError_t launch_fill(const RunDev<S>* runs_dev, const FillItem* items_dev, int nitems,
                        int parity, hipStream_t s);

@@ -1,0 +1,285 @@
+// vlb_step.h -- one coupled lattice Boltzmann step of a 64 x TY tile: the device code
+// shared by the per-step kernel (k_step, vlb_kernels.hip) and the persistent batch kernel
+// (k_batch, vlb_batch.hip), so both round identically.
+//
+// Every lane pulls its node's 36 post-collision populations from the neighbours' slots
+// with one branch-free global load each (structure-of-arrays planes, x fastest, 64 lanes
+// read contiguous rows).  Slots that do not hold a fluid node -- ghost rows/columns
+// around the domain and solid nodes -- hold exactly the value the boundary rule gives for
+// that link: periodic images and open-end ghosts are stored a second time by the edge
+// lanes of the step, every other boundary link by the fill list (apply_fill_op).  rho
+// and u of the tile and of a one-node ring around it go to LDS; then the velocity
+// gradient and d(rho u^3) by finite differences, CNEBB at wall-adjacent nodes, the
+// constitutive source, the hydrodynamic and three convection-diffusion collisions in
+// moment form, and 36 + 5 coalesced stores.
+// Storage is float or double (template S); populations are kept as deviations from
+// the rest state (f_i - w_i, g_i - w_i phi0 with phi0 = 1, 0, 1).  All arithmetic is
+// double precision: on CDNA the vector FP64 rate equals the unpacked FP32 rate, and
+// single-precision arithmetic lets rounding drift accumulate over many steps.
+// The collision is the paper's regularized TRT operator rewritten in Hermite-moment
+// space (algebraically identical to the per-direction form).
+#pragma once
+
+#include "vlb_device.h"
+
+// Register budget of the step kernel: single-precision storage fits four waves per
+// SIMD without spilling; double precision keeps its natural allocation.
+template <class S, int TY>
+struct StepBounds {
+    static constexpr int threads = 64 * TY;
+    static constexpr int min_waves_per_eu = sizeof(S) == 4 ? 4 : 1;
+    // the persistent batch kernel loops over tiles and keeps a few more values live:
+    // four waves per SIMD (FP32 storage) spill 28-32 bytes per lane, touched once per
+    // tile, and still run faster than three without spills; FP64 fits three
+    static constexpr int batch_waves_per_eu = sizeof(S) == 4 ? 4 : 2;
+};
+
+namespace vlb {
+namespace {
+
+// Ghost slots that the inlet (outlet) links of row y pull from: direction i with
+// e_x = +1 (-1) is pulled by node (x, y + e_y) from (gx, y), gx = -1 (nx); at a periodic
+// y edge the puller wraps and the slot is the corner ghost it pulls from.  Calls
+// fn(i, slot) for each.
+template <class S, class F>
+__device__ __forceinline__ void open_end_slots(const RunDev<S>& R, int y, bool in, F fn) {
+    const int gx = in ? -1 : R.nx;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        if (ex(i) != (in ? 1 : -1)) continue;
+        const int yp = y + ey(i);
+        int gy = y;
+        if (yp < 0 || yp >= R.ny) {
+            if (R.ymode != XM_PERIODIC) continue;  // beyond a wall: nobody pulls it
+            gy = (yp < 0 ? yp + R.ny : yp - R.ny) - ey(i);
+        }
+        fn(i, (unsigned)(R.off0 + gy * R.pitch + gx));
+    }
+}
+
+// One coupled step of the 64 x TY tile `it` (the whole body of k_step; also the unit of
+// work of the persistent batch kernel).  lane0 is zero: the persistent kernel passes an
+// opaque zero so that the lane-index arithmetic stays inside its tile loop instead of
+// being hoisted (and held in registers) across it.
+template <class S, int TY, bool NT>
+__device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, const Item it,
+                                          int parity, int first, int lane0) {
+    __shared__ T s_rho[TY + 2][66];
+    __shared__ T s_ux[TY + 2][66];
+    __shared__ T s_uy[TY + 2][66];
+    const RunDev<S>& R = runs[it.run];
+    const S* src = R.pop[parity];
+    S* dst = R.pop[parity ^ 1];
+    const long long plane = R.plane;
+    const bool pull = first == 0;
+    const int lx = threadIdx.x + lane0, ly = threadIdx.y + lane0;
+    const int tid = ly * 64 + lx;
+    const int x0 = it.tx * 64, y0 = it.ty * TY;
+    const int x = x0 + lx, y = y0 + ly;
+
+    // ---- phase 1: own node (36 pulls, history, force) ----
+    const bool in_dom = x < R.nx && y < R.ny;
+    const int p = node_index(R, x, y);
+    unsigned b = 0u;
+    if (in_dom) b = node_bits(R, p);
+    const bool active = in_dom && !(b & BIT_SELF_SOLID);
+    S f[9], g[3][9];
+    T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
+    // conformation deviations A - I: the zeroth moments of the pulled g lattices (CNEBB
+    // keeps them, so they are final before the wall reconstruction)
+    T dk[3] = {0.0, 0.0, 0.0};
+    if (active) {
+        pull9(R, src, 0, p, pull, f);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            pull9(R, src, 1 + k, p, pull, g[k]);
+            dk[k] = zeroth(g[k]);
+        }
+        node_force(R, p, Fx, Fy);
+        if (pull) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) hS[k] = ldu(R.hist + k * plane, (unsigned)p);
+            hux = ldu(R.hist + 3 * plane, (unsigned)p);
+            huy = ldu(R.hist + 4 * plane, (unsigned)p);
+        }
+    }
+    // ring cells: rows above/below the tile, columns left/right of it
+    for (int r = tid; r < 128 + 2 * TY; r += 64 * TY) {
+        int cx, cy, lcx, lcy;
+        if (r < 64) { cx = x0 + r; cy = y0 - 1; lcx = r + 1; lcy = 0; }
+        else if (r < 128) { cx = x0 + r - 64; cy = y0 + TY; lcx = r - 63; lcy = TY + 1; }
+        else if (r < 128 + TY) { cx = x0 - 1; cy = y0 + r - 128; lcx = 0; lcy = r - 127; }
+        else { cx = x0 + 64; cy = y0 + r - 128 - TY; lcx = 65; lcy = r - 127 - TY; }
+        T rr, vx, vy;
+        if (cell_macros(R, src, cx, cy, pull, rr, vx, vy)) {
+            s_rho[lcy][lcx] = rr;
+            s_ux[lcy][lcx] = vx;
+            s_uy[lcy][lcx] = vy;
+        }
+    }
+    T drho = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
+    if (active) {
+        hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
+        s_rho[ly + 1][lx + 1] = rho;
+        s_ux[ly + 1][lx + 1] = ux;
+        s_uy[ly + 1][lx + 1] = uy;
+    } else if (!in_dom) {
+        // out-of-domain tile cell: periodic image for the neighbours' differences
+        T rr, vx, vy;
+        if (cell_macros(R, src, x, y, pull, rr, vx, vy)) {
+            s_rho[ly + 1][lx + 1] = rr;
+            s_ux[ly + 1][lx + 1] = vx;
+            s_uy[ly + 1][lx + 1] = vy;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // ---- phase 2 ----
+    // neighbour values for the differences: LDS for fluid neighbours, the wall formula
+    // at walls, inlet/outlet ghost values at open ends.
+    const bool wxl = (b >> 1) & 1u, wxh = (b >> 3) & 1u, wyl = (b >> 2) & 1u, wyh = (b >> 4) & 1u;
+    T qxl = 0.5, qxh = 0.5, qyl = 0.5, qyh = 0.5;
+    if (R.has_curved && (b & 0x1Eu)) {
+        const int bi = R.bidx[p];
+        qxl = link_q(R, bi, 1); qxh = link_q(R, bi, 3);
+        qyl = link_q(R, bi, 2); qyh = link_q(R, bi, 4);
+    }
+    const bool open_l = R.xmode == XM_OPEN && x == 0;
+    const bool open_h = R.xmode == XM_OPEN && x == R.nx - 1;
+    T rl = 0.0, uxl = 0.0, uyl = 0.0, rh = 0.0, uxh = 0.0, uyh = 0.0;
+    if (open_l) { rl = 1.0; uxl = R.inlet[y]; }
+    else if (!wxl) { rl = s_rho[ly + 1][lx]; uxl = s_ux[ly + 1][lx]; uyl = s_uy[ly + 1][lx]; }
+    if (open_h) { rh = rho; uxh = ux; uyh = uy; }
+    else if (!wxh) { rh = s_rho[ly + 1][lx + 2]; uxh = s_ux[ly + 1][lx + 2]; uyh = s_uy[ly + 1][lx + 2]; }
+    T rd = 0.0, uxd = 0.0, uyd = 0.0, ru = 0.0, uxu = 0.0, uyu = 0.0;
+    if (!wyl) { rd = s_rho[ly][lx + 1]; uxd = s_ux[ly][lx + 1]; uyd = s_uy[ly][lx + 1]; }
+    if (!wyh) { ru = s_rho[ly + 2][lx + 1]; uxu = s_ux[ly + 2][lx + 1]; uyu = s_uy[ly + 2][lx + 1]; }
+    const T Lxx = dgrad(wxl, qxl, uxl, ux, wxh, qxh, uxh);
+    const T Lxy = dgrad(wxl, qxl, uyl, uy, wxh, qxh, uyh);
+    const T Lyx = dgrad(wyl, qyl, uxd, ux, wyh, qyh, uxu);
+    const T Lyy = dgrad(wyl, qyl, uyd, uy, wyh, qyh, uyu);
+    const T Dx = dgrad(wxl, qxl, rl * uxl * uxl * uxl, rho * ux * ux * ux, wxh, qxh,
+                       rh * uxh * uxh * uxh);
+    const T Dy = dgrad(wyl, qyl, rd * uyd * uyd * uyd, rho * uy * uy * uy, wyh, qyh,
+                       ru * uyu * uyu * uyu);
+
+    const T d0 = dk[0], d1 = dk[1], d2 = dk[2];
+    const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
+    T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
+    if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
+    const T txx = R.eta_over_lam * sf[0], txy = R.eta_over_lam * sf[1], tyy = R.eta_over_lam * sf[2];
+    T Sc[3];
+    if (R.no_source) {
+        Sc[0] = Sc[1] = Sc[2] = 0.0;
+    } else {
+        const T d = Lxx + Lyy;
+        Sc[0] = -R.inv_lam * rf[0] + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
+        Sc[1] = -R.inv_lam * rf[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
+        Sc[2] = -R.inv_lam * rf[2] + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
+    }
+    if (!pull) {  // first step: F~(t - 1) := F~(t)
+        hS[0] = Sc[0]; hS[1] = Sc[1]; hS[2] = Sc[2];
+        hux = ux; huy = uy;
+    }
+
+    // Periodic images: an edge node also writes the populations that leave the domain
+    // into the ghost slots its periodic neighbours pull from (no fill op needed).
+    const bool px_per = R.xmode == XM_PERIODIC, py_per = R.ymode == XM_PERIODIC;
+    const int gxo = (px_per && x == R.nx - 1) ? -R.nx : ((px_per && x == 0) ? R.nx : 0);
+    const int gyo = (py_per && y == R.ny - 1) ? -R.ny : ((py_per && y == 0) ? R.ny : 0);
+    const bool edge = (gxo | gyo) != 0;
+    // ghost slot of direction i for this node, or -1: a population moving in direction
+    // i leaves through the edge it points at
+    auto ghost = [&](int i) -> int {
+        const int sx = (gxo != 0 && ex(i) == (gxo < 0 ? 1 : -1)) ? gxo : 0;
+        const int sy = (gyo != 0 && ey(i) == (gyo < 0 ? 1 : -1)) ? gyo : 0;
+        if (sx == 0 && sy == 0) return -1;
+        return p + sx + sy * R.pitch;
+    };
+
+    T out[9];
+    collide_hydro(R, moments(f), rho, ux, uy, Fx, Fy, txx, txy, tyy, Dx, Dy, out);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st_stream<NT>(dst + i * plane, (unsigned)p, out[i]);
+    // Open ends (Sec. 4.3): the first (last) column node writes the ghosts its row's
+    // inlet (outlet) links pull next step by non-equilibrium extrapolation from its own
+    // post-collision populations (as stored): f_i = f_i^eq(rho_b, u_b) + f_i -
+    // f_i^eq(rho, u) with rho, u their moments; inlet rho_b = rho, u_b = profile;
+    // outlet rho_b = 1, u_b = u.  The conformation ghosts follow below.
+    const bool oend = R.xmode == XM_OPEN && (x == 0 || x == R.nx - 1);
+    const bool oin = x == 0;
+    T oux = 0.0, ouy = 0.0;
+    if (oend) {
+        S so[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) so[i] = S(out[i]);
+        T odr, orho;
+        hydro_macros(so, 0.0, 0.0, odr, orho, oux, ouy);
+        const T uin = oin ? T(R.inlet[y]) : 0.0;
+        open_end_slots(R, y, oin, [&](int i, unsigned gs) {
+            const T fneq = T(so[i]) - dfeq(i, odr, orho, oux, ouy);
+            stu(dst + i * plane, gs, (oin ? dfeq(i, odr, orho, uin, 0.0) : dfeq(i, 0.0, 1.0, oux, ouy)) + fneq);
+        });
+    }
+    if (edge) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int gs = ghost(i);
+            if (gs >= 0) stu(dst + i * plane, (unsigned)gs, out[i]);
+        }
+    }
+    // conformation lattices one at a time after the hydrodynamic one (keeps the
+    // register budget of four waves per SIMD): CNEBB at wall-adjacent nodes, moments,
+    // collision, stores
+    const unsigned solid = pull ? (b & 0x1FEu) : 0u;
+    const T inv_rho = 1.0 / rho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Mom gm;
+        if (solid) {
+            T gg[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gg[i] = T(g[k][i]);
+            cnebb(solid, k, ux, uy, gg);
+            gm = moments(gg);
+        } else {
+            gm = moments(g[k]);
+        }
+        gm.m0 = dk[k];
+        const T phi = phi0(k) + dk[k];
+        collide_cde(R, gm, phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], hS[k], hux, huy, out);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_stream<NT>(dst + (9 + 9 * k + i) * plane, (unsigned)p, out[i]);
+        if (oend) {  // inlet: extrapolation around A_in, u_in; outlet: copy
+            S so[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) so[i] = S(out[i]);
+            T dphi = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dphi += T(so[i]);
+            const T uin = oin ? T(R.inlet[y]) : 0.0;
+            const T a = oin ? T(R.inlet[(1 + k) * R.ny + y]) : 0.0;
+            open_end_slots(R, y, oin, [&](int i, unsigned gs) {
+                stu(dst + (9 + 9 * k + i) * plane, gs,
+                    oin ? dgeq(i, a - phi0(k), a, uin, 0.0) + T(so[i]) -
+                              dgeq(i, dphi, phi0(k) + dphi, oux, ouy)
+                        : T(so[i]));
+            });
+        }
+        if (edge) {
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int gs = ghost(i);
+                if (gs >= 0) stu(dst + (9 + 9 * k + i) * plane, (unsigned)gs, out[i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st_stream<NT>(R.hist_out + k * plane, (unsigned)p, Sc[k]);
+    st_stream<NT>(R.hist_out + 3 * plane, (unsigned)p, ux);
+    st_stream<NT>(R.hist_out + 4 * plane, (unsigned)p, uy);
+}
+
+}  // namespace
+}  // namespace vlb

@@ -312,7 +312,7 @@ class Batch:
     :class:`Simulation` methods.
     """
 
-    def __init__(self, sims, tile: int = 4, graph_chunk: int = 0):
+    def __init__(self, sims, tile: int = 4, graph_chunk: int = 0, persistent: bool = False):
         self.lib = L.load()
         self.sims = list(sims)
         if not self.sims:
@@ -334,6 +334,8 @@ class Batch:
         if graph_chunk:
             L.check(self.lib.vlb_batch_set_graph_chunk(h, int(graph_chunk)),
                     "vlb_batch_set_graph_chunk")
+        if persistent:
+            L.check(self.lib.vlb_batch_set_persistent(h, 1), "vlb_batch_set_persistent")
 
     def step(self, n: int = 1):
         self.sims[0]._order_after_torch()

@@ -61,8 +61,9 @@ def test_autotune_sweeps_restores_and_caches(tmp_path):
 
 
 def test_tune_batch_picks_a_tile_and_members_stay_exact():
-    """tune_batch times one batch per tile height over the same members; the members
-    then continue in a batch of the chosen tile bit-identically to runs stepped alone."""
+    """tune_batch times one batch per tile height and form over the same members; the
+    members then continue in a batch of the chosen shape bit-identically to runs stepped
+    alone."""
     import torch
     from paper_2508_16997_amd import Batch, Simulation
     from paper_2508_16997_amd.autotune import tune_batch
@@ -73,10 +74,13 @@ def test_tune_batch_picks_a_tile_and_members_stay_exact():
     say("tune_batch")
     members = [Simulation.from_problem(r, stream=stream) for r in runs]
     alone = [Simulation.from_problem(r, stream=stream) for r in runs]
-    ty, timings = tune_batch(members, tiles=(2, 4, 8), steps=6, warmup=2, graph_chunk=2)
-    assert ty in (2, 4, 8) and set(timings) == {2, 4, 8} and timings[ty] == min(timings.values())
-    done = 3 * (2 + 6)
-    b = Batch(members, tile=ty, graph_chunk=2)
+    best, timings = tune_batch(members, tiles=(2, 4, 8), steps=6, warmup=2, graph_chunk=2,
+                               forms=(False, True))
+    ty, pers = best
+    assert set(timings) == {(t, f) for t in (2, 4, 8) for f in (False, True)}
+    assert timings[best] == min(timings.values())
+    done = 6 * (2 + 6)
+    b = Batch(members, tile=ty, graph_chunk=2, persistent=pers)
     b.step(11)
     for s in alone:
         s.step(done + 11)

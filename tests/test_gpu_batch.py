@@ -88,6 +88,62 @@ def test_batch_bit_identical_to_single(precision, ty, chunk):
         s.close()
 
 
+@pytest.mark.parametrize("precision,ty", [("fp32", 4), ("fp32", 8), ("fp64", 2)])
+def test_persistent_batch_bit_identical(precision, ty):
+    """One cooperative launch per chunk of at most 256 steps, grid-wide barriers between
+    the tiles and the fills: same bits as the runs stepped alone, across the first step
+    and a chunk boundary (1 + 300 steps = launches of 1, 256 and 44 steps)."""
+    import torch
+    from paper_2508_16997_amd import Batch
+
+    runs = _mixed_set(precision)
+    stream = torch.cuda.Stream()
+    say("persistent batch", precision, "ty", ty, "runs", len(runs))
+    batched = _make(runs, stream)
+    single = _make(runs, stream)
+    b = Batch(batched, tile=ty, persistent=True)
+    for n in (1, 300):
+        b.step(n)
+        for s in single:
+            s.step(n)
+    stream.synchronize()
+    for r, sb, ss in zip(runs, batched, single):
+        assert sb.time == ss.time == 301
+        gb, gs = _read_exact(sb), _read_exact(ss)
+        for k in FIELDS:
+            assert np.array_equal(gb[k], gs[k]), (r.name, k)
+        hb, hs = sb.history(), ss.history()
+        for k in hb:
+            assert torch.equal(hb[k], hs[k]), (r.name, "history", k)
+    b.close()
+    for s in batched + single:
+        s.close()
+
+
+def test_persistent_batch_full_set_matches_per_step():
+    """The 256-run batched workload: persistent and per-step batches agree bit for bit."""
+    import torch
+    from paper_2508_16997_amd import Batch
+
+    runs = synth.batch_c4()
+    stream = torch.cuda.Stream()
+    say("persistent batch full set", len(runs))
+    a, p = _make(runs, stream), _make(runs, stream)
+    ba = Batch(a, graph_chunk=5)
+    bp = Batch(p, persistent=True)
+    ba.step(21)
+    bp.step(21)
+    stream.synchronize()
+    for r, sa, sp in zip(runs, a, p):
+        ga, gp = _read_exact(sa), _read_exact(sp)
+        for k in FIELDS:
+            assert np.array_equal(ga[k], gp[k]), (r.name, k)
+    ba.close()
+    bp.close()
+    for s in a + p:
+        s.close()
+
+
 def test_batch_oracle_sample():
     """Eight runs of the full-size batched set (Wi <= 10) against the oracle."""
     import torch
