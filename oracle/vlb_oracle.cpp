@@ -22,6 +22,8 @@
  *      the auxiliary source, the source term and its time derivative   (Sec. 3.2)
  *   7. streaming; half-way / linearly interpolated bounce-back for f;
  *      non-equilibrium extrapolation at the inlet and outlet ghosts    (readings A13, A21)
+ *      or, for wet-node walls, non-equilibrium bounce-back of f at the wall nodes
+ *      themselves (Sec. 4.2-4.3, reading A29)
  *   8. conservative non-equilibrium bounce-back for every g lattice     (Sec. 3.3)
  *   9. history of S and u for the backward time difference             (Sec. 3.2)
  *
@@ -322,7 +324,9 @@ R fd_axis(bool lo_solid, double qlo, R plo, R p0, bool hi_solid, double qhi, R p
     return p0 * R((qhi - qlo) / (qlo * qhi));
 }
 
-enum { MODE_PERIODIC = 0, MODE_WALL = 1, MODE_OPEN = 2 };
+// MODE_WET (y only): the first and last rows are wall nodes (wet-node walls, u = 0 on
+// them, channel height ny - 1; reading A29).
+enum { MODE_PERIODIC = 0, MODE_WALL = 1, MODE_OPEN = 2, MODE_WET = 3 };
 enum { SRC_FLUID = 0, SRC_SOLID = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
 enum { FLAG_NO_SOURCE = 1 };
 
@@ -383,7 +387,7 @@ struct Geometry {
     Src source(int x, int y, int i) const {
         int xs = x - EX[i], ys = y - EY[i];
         const bool xout = xs < 0 || xs >= nx, yout = ys < 0 || ys >= ny;
-        if ((yout && ymode == MODE_WALL) || (xout && xmode == MODE_WALL))
+        if ((yout && (ymode == MODE_WALL || ymode == MODE_WET)) || (xout && xmode == MODE_WALL))
             return Src{SRC_SOLID, -1, -1, 0.5};
         if (yout) ys = wrap(ys, ny);
         if (xout) {
@@ -395,6 +399,9 @@ struct Geometry {
         if (solid[s]) return Src{SRC_SOLID, s, ys, link_q(x, y, i, s)};
         return Src{SRC_FLUID, s, ys, 0.0};
     }
+
+    // Wall node of a wet-node wall: first or last row.
+    bool wet_row(int y) const { return ymode == MODE_WET && (y == 0 || y == ny - 1); }
 
     bool is_boundary(int x, int y) const {
         for (int i = 1; i < Q; ++i)
@@ -451,6 +458,10 @@ struct Sim {
             rho[n] = r;
             ux[n] = (jx + R(0.5) * Fx[n]) / r;
             uy[n] = (jy + R(0.5) * Fy[n]) / r;
+            if (geo.wet_row((int)(n / nx))) {  // wall node: the wall velocity (reading A29)
+                ux[n] = R(0.0);
+                uy[n] = R(0.0);
+            }
             for (int k = 0; k < 3; ++k) {
                 R s = R(0.0);
                 for (int i = 0; i < Q; ++i) s += g[k][i][n];
@@ -500,7 +511,20 @@ struct Sim {
             L[1][1] = D(syl, syh, uy_at, uy[n], R(0.0), R(0.0));
             const R Dx = D(sxl, sxh, px_at, rho[n] * ux[n] * ux[n] * ux[n],
                            uinl * uinl * uinl, R(0.0));
-            const R Dy = D(syl, syh, py_at, rho[n] * uy[n] * uy[n] * uy[n], R(0.0), R(0.0));
+            R Dy = D(syl, syh, py_at, rho[n] * uy[n] * uy[n] * uy[n], R(0.0), R(0.0));
+            if (geo.wet_row(y)) {
+                // Wall node of a wet-node wall: wall-normal derivatives by the one-sided
+                // second-order difference through the node and the next two rows into the
+                // fluid (reading A29).
+                const int s1 = y == 0 ? 1 : -1;
+                const size_t n1 = (size_t)(y + s1) * nx + x, n2 = (size_t)(y + 2 * s1) * nx + x;
+                auto one_sided = [&](auto fn, R p0) {
+                    return R((double)s1) * (R(-1.5) * p0 + R(2.0) * fn(n1) - R(0.5) * fn(n2));
+                };
+                L[1][0] = one_sided(ux_at, ux[n]);
+                L[1][1] = one_sided(uy_at, uy[n]);
+                Dy = one_sided(py_at, rho[n] * uy[n] * uy[n] * uy[n]);
+            }
 
             // Conformation tensor and polymer stress tau = (eta_p / lambda) F_s(A).
             const R Am[2][2] = {{A[0][n], A[1][n]}, {A[1][n], A[2][n]}};
@@ -599,6 +623,30 @@ struct Sim {
                 }
             }
         }
+        // Stage 7b: wet-node walls -- the populations the wall nodes would receive from
+        // beyond the wall, by non-equilibrium bounce-back with zero wall velocity (the
+        // Zou-He closure; the momentum of the streamed populations is rho u - F / 2 with
+        // the half-force shift, so zero velocity means -F / 2; reading A29).
+        if (geo.ymode == MODE_WET) {
+#pragma omp parallel for schedule(static)
+            for (long long xx = 0; xx < (long long)nx; ++xx) {
+                for (int y : {0, ny - 1}) {
+                    const size_t n = (size_t)y * nx + (size_t)xx;
+                    if (!fluid(n)) continue;
+                    const R jx = R(-0.5) * Fx[n], jy = R(-0.5) * Fy[n];
+                    const R d13 = f[1][n] - f[3][n];
+                    if (y == 0) {  // unknown: directions with e_y = +1
+                        f[2][n] = f[4][n] + R(2.0 / 3.0) * jy;
+                        f[5][n] = f[7][n] - R(0.5) * d13 + R(1.0 / 6.0) * jy + R(0.5) * jx;
+                        f[6][n] = f[8][n] + R(0.5) * d13 + R(1.0 / 6.0) * jy - R(0.5) * jx;
+                    } else {  // unknown: directions with e_y = -1
+                        f[4][n] = f[2][n] - R(2.0 / 3.0) * jy;
+                        f[7][n] = f[5][n] + R(0.5) * d13 - R(1.0 / 6.0) * jy - R(0.5) * jx;
+                        f[8][n] = f[6][n] - R(0.5) * d13 - R(1.0 / 6.0) * jy + R(0.5) * jx;
+                    }
+                }
+            }
+        }
         // Stage 8: conservative non-equilibrium bounce-back at every boundary node
         // (Sec. 3.3), with u(x_b, t+1) from the filled hydrodynamic populations
         // (reading A11); unknowns whose opposite is also unknown take the equilibrium
@@ -621,8 +669,9 @@ struct Sim {
                 jx += R((double)EX[i]) * f[i][n];
                 jy += R((double)EY[i]) * f[i][n];
             }
-            const R ubx = (jx + R(0.5) * Fx[n]) / r;
-            const R uby = (jy + R(0.5) * Fy[n]) / r;
+            R ubx = (jx + R(0.5) * Fx[n]) / r;
+            R uby = (jy + R(0.5) * Fy[n]) / r;
+            if (geo.wet_row(y)) ubx = uby = R(0.0);  // wall node: the wall velocity
             for (int k = 0; k < 3; ++k) {
                 // phi(x_b, t+1): known post-streaming populations plus the post-collision
                 // populations that moved toward the solid.
@@ -756,15 +805,28 @@ extern "C" {
 
 void* orc_create(int nx, int ny, int xmode, int ymode, const uint8_t* mask,
                  const double* circles, int ncircles, int dual) {
-    if (nx < 1 || ny < 1 || xmode < 0 || xmode > 2 || ymode < 0 || ymode > 1) return nullptr;
+    if (nx < 1 || ny < 1 || xmode < 0 || xmode > 2 || ymode < 0 || ymode > 3 || ymode == 2)
+        return nullptr;
+    if (ymode == MODE_WET && ny < 5) return nullptr;
     Handle* h = new Handle();
     h->dual = dual;
     auto setup = [&](auto& s) {
         s.nx = nx; s.ny = ny;
         s.geo.build(nx, ny, xmode, ymode, mask, circles, ncircles);
         s.alloc();
+        // wet-node walls: the wall rows and the two rows next to each (the one-sided
+        // differences at the wall nodes) must be fluid
+        bool ok = true;
+        if (ymode == MODE_WET)
+            for (int y : {0, 1, 2, ny - 3, ny - 2, ny - 1})
+                for (int x = 0; x < nx; ++x) ok = ok && !s.geo.solid[(size_t)y * nx + x];
+        return ok;
     };
-    if (dual) setup(h->sx); else setup(h->sd);
+    const bool ok = dual ? setup(h->sx) : setup(h->sd);
+    if (!ok) {
+        delete h;
+        return nullptr;
+    }
     return h;
 }
 

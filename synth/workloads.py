@@ -30,7 +30,7 @@ class Problem:
     nx: int
     ny: int
     xmode: str  # 'periodic' | 'wall' | 'open' (open: inlet at x = -1, outlet at x = nx)
-    ymode: str  # 'periodic' | 'wall'
+    ymode: str  # 'periodic' | 'wall' | 'wet' (wet: rows 0 and ny - 1 are wall nodes)
     nu_s: float  # solvent kinematic viscosity (lattice units)
     eta_p: float  # polymer viscosity (rho0 = 1)
     lam: float  # polymer relaxation time lambda
@@ -110,18 +110,21 @@ def lattice_units(Re: float, Wi: float, beta: float, Sc: float, Ma: float, Lc: f
 
 
 def poiseuille(nx=64, ny=32, Re=1.0, Wi=1.0, beta=0.5, Ma=0.1, Sc=1e6,
-               Lambda_s=0.25, Lambda_p=1e-6, steps=10000, precision="fp64") -> Problem:
+               Lambda_s=0.25, Lambda_p=1e-6, steps=10000, precision="fp64",
+               wet=False) -> Problem:
     """Force-driven plane Poiseuille flow (Sec. 4.2).
 
     Periodic in x, no-slip walls half a spacing outside rows 0 and ny-1 (channel height
-    H = L_c = ny).  Driving force F_x = 8 (nu_s + nu_p) U_c / L_c^2; start from unit
+    H = L_c = ny), or with ``wet`` on rows 0 and ny - 1 themselves (wet-node walls,
+    H = L_c = ny - 1).  Driving force F_x = 8 (nu_s + nu_p) U_c / L_c^2; start from unit
     density, zero velocity and identity conformation.
     """
-    Lc = float(ny)
+    Lc = float(ny - 1 if wet else ny)
     p = lattice_units(Re, Wi, beta, Sc, Ma, Lc)
     Fx = 8.0 * p["nu0"] * p["Uc"] / (Lc * Lc)
     return Problem(
-        name=f"poiseuille_{nx}x{ny}_Wi{Wi:g}", nx=nx, ny=ny, xmode="periodic", ymode="wall",
+        name=f"poiseuille_{nx}x{ny}_Wi{Wi:g}{'_wet' if wet else ''}", nx=nx, ny=ny,
+        xmode="periodic", ymode="wet" if wet else "wall",
         nu_s=p["nu_s"], eta_p=p["eta_p"], lam=p["lam"], kappa=p["kappa"],
         Lambda_s=Lambda_s, Lambda_p=Lambda_p, Fx=Fx, Fy=0.0, steps=steps,
         precision=precision,

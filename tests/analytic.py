@@ -39,14 +39,16 @@ def waters_king_u(ystar, tstar, Wi, beta, Re=1.0, nterms=20000):
     return out - 32.0 * terms.sum(axis=-1)
 
 
-def poiseuille_steady(ny, Uc, lam):
-    """Steady Oldroyd-B Poiseuille flow between half-way walls, height H = ny (Sec. 4.2).
+def poiseuille_steady(ny, Uc, lam, wet=False):
+    """Steady Oldroyd-B Poiseuille flow between half-way walls, height H = ny (Sec. 4.2),
+    or between wet-node walls on rows 0 and ny - 1, height H = ny - 1.
 
-    u = 4 U_c y'(H - y')/H^2 at y' = j + 1/2; A_xy = lambda u', A_xx = 1 + 2 (lambda u')^2,
-    A_yy = 1 (Kramers relation with tau_xy = eta_p u', tau_xx = 2 lambda eta_p u'^2).
+    u = 4 U_c y'(H - y')/H^2 at y' = j + 1/2 (wet: y' = j); A_xy = lambda u',
+    A_xx = 1 + 2 (lambda u')^2, A_yy = 1 (Kramers relation with tau_xy = eta_p u',
+    tau_xx = 2 lambda eta_p u'^2).
     """
-    H = float(ny)
-    yp = np.arange(ny, dtype=np.float64) + 0.5
+    H = float(ny - 1 if wet else ny)
+    yp = np.arange(ny, dtype=np.float64) + (0.0 if wet else 0.5)
     u = 4.0 * Uc * yp * (H - yp) / H ** 2
     du = 4.0 * Uc * (H - 2.0 * yp) / H ** 2
     return dict(ux=u, axy=lam * du, axx=1.0 + 2.0 * (lam * du) ** 2, ayy=np.ones(ny), dudy=du)

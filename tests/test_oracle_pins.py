@@ -240,6 +240,8 @@ def _wall_cases():
         dict(xmode="wall", ymode="periodic"),
         dict(xmode="periodic", ymode="periodic", circles=[(11.5, 8.0, 3.7)]),
         dict(xmode="periodic", ymode="wall", circles=[(10.0, 7.5, 4.2)]),
+        dict(xmode="periodic", ymode="wet"),
+        dict(xmode="periodic", ymode="wet", circles=[(10.0, 7.5, 3.2)]),
     ]
 
 
@@ -450,6 +452,68 @@ def test_poiseuille_second_order(oracle_lib):
     errs = np.array(errs)
     order = np.log2(errs[0] / errs[2]) / 2
     assert np.all(order > 1.8), order
+
+
+# ---------------------------------------------------------------------------------
+# Wet-node walls (non-equilibrium bounce-back at the wall nodes, reading A29)
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("ny", [9, 17])
+def test_wet_walls_newtonian_poiseuille_is_exact(oracle_lib, ny):
+    """Newtonian channel flow between wet-node walls reaches the parabola
+    u = 4 U_c y (H - y) / H^2, H = ny - 1, to round-off (pin P12).
+
+    A closed form the scheme reproduces exactly: non-equilibrium bounce-back with the
+    half-force momentum and a second-order collision hold the wall nodes at u = 0 and
+    the interior on the parabola.  A missing -F/2 in the wall momentum (slip F/2),
+    a wrong sign or weight of the tangential correction or of the normal term, or a
+    wrong wall row, each leave an O(1e-3) error or more.
+    """
+    pr = synth.poiseuille(nx=2, ny=ny, beta=1.0, wet=True)
+    o = oracle_lib.OracleSim(pr)
+    o.step(int(30 * pr.meta["Tc"]))
+    r = o.read()
+    ref = poiseuille_steady(ny, pr.meta["Uc"], pr.lam, wet=True)
+    assert np.abs(r["ux"][:, 0] - ref["ux"]).max() < 1e-12 * ref["ux"].max()
+    assert np.abs(r["uy"]).max() < 1e-14
+    # the populations the wall nodes hold carry zero velocity: sum e f + F/2 = 0
+    f, _ = o.populations()
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    jx = np.tensordot(ex, f, axes=1) + 0.5 * pr.Fx
+    assert np.abs(jx[[0, -1], :]).max() < 1e-15
+
+
+def test_wet_walls_oldroyd_b_poiseuille(oracle_lib):
+    """Steady Oldroyd-B channel flow between wet-node walls (Wi = 1, beta = 0.5, Sec. 4.2):
+    the closed form at H = 16, 32, 64 with errors falling at close to second order.
+
+    The wall nodes take their wall-normal velocity gradient from the one-sided
+    second-order difference; a first-order difference there would leave A_xy and A_xx
+    at first order.
+    """
+    errs = []
+    for ny in (17, 33, 65):
+        pr = synth.poiseuille(nx=2, ny=ny, wet=True)
+        o = oracle_lib.OracleSim(pr)
+        o.step(int(round(18 * pr.meta["Tc"])))
+        r = o.read()
+        ref = poiseuille_steady(ny, pr.meta["Uc"], pr.lam, wet=True)
+        errs.append([gre(r["ux"][:, 0], ref["ux"]), gre(r["axy"][:, 0], ref["axy"]),
+                     gre(r["axx"][:, 0], ref["axx"])])
+        assert np.abs(r["ayy"] - 1).max() < 1e-10
+    errs = np.array(errs)
+    assert errs[1, 0] < 1e-4 and errs[1, 1] < 3e-3 and errs[1, 2] < 8e-3, errs
+    order = np.log2(errs[0] / errs[2]) / 2
+    assert np.all(order > 1.6), order
+
+
+def test_wet_walls_reject_solids_next_to_the_wall(oracle_lib):
+    """The one-sided differences at wall nodes need two fluid rows: solids there are
+    refused (as by the library)."""
+    mask = np.zeros((12, 10), np.uint8)
+    mask[2, 4] = 1
+    pr = synth.random_periodic(10, 12, seed=1, ymode="wet", solid=mask)
+    with pytest.raises(Exception):
+        oracle_lib.OracleSim(pr)
 
 
 def test_waters_king_transient(oracle_lib):
