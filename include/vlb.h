@@ -49,11 +49,17 @@ enum {
 };
 
 enum { VLB_FP32 = 0, VLB_FP64 = 1 };
-/* Boundary kind of an axis.  VLB_OPEN (x only): inlet ghost column at x = -1 carrying
- * the prescribed profile (vlb_set_inlet) at equilibrium, zero-gradient outlet ghost at
- * x = nx.  VLB_WALL: no-slip wall half a spacing outside the first and last rows
- * (columns). */
-enum { VLB_PERIODIC = 0, VLB_WALL = 1, VLB_OPEN = 2 };
+/* Boundary kind of an axis.  VLB_OPEN (x only): inlet ghost column at x = -1 and outlet
+ * ghost column at x = nx, filled by non-equilibrium extrapolation from the first / last
+ * column (inlet: the prescribed profile of vlb_set_inlet; outlet: rho = 1, zero-gradient
+ * u and A).  VLB_WALL: no-slip wall half a spacing outside the first and last rows
+ * (columns), half-way bounce-back for f.  VLB_WET (y only): wet-node walls -- rows 0 and
+ * ny - 1 are wall nodes with u = 0 (channel height ny - 1), f rebuilt there by
+ * non-equilibrium bounce-back (Zou-He closure with the half-force momentum; the wall
+ * setting of the paper's channel flows, Sec. 4.2-4.3), CNEBB for the conformation
+ * lattices at the wall nodes, one-sided second-order wall-normal differences; needs
+ * ny >= 5 and fluid nodes on rows 0-2 and ny-3..ny-1. */
+enum { VLB_PERIODIC = 0, VLB_WALL = 1, VLB_OPEN = 2, VLB_WET = 3 };
 /* Node classes returned by vlb_geometry. */
 enum { VLB_NODE_FLUID = 0, VLB_NODE_SOLID = 1, VLB_NODE_BOUNDARY = 2 };
 /* Parameter flags. */
@@ -68,7 +74,8 @@ typedef struct vlb_sim vlb_sim;
  * q = 1/2. */
 typedef struct {
     int nx, ny;               /* 1 <= nx, ny; nx * ny < 2^31                           */
-    int xmode, ymode;         /* VLB_PERIODIC / VLB_WALL / VLB_OPEN (xmode only)       */
+    int xmode, ymode;         /* VLB_PERIODIC / VLB_WALL / VLB_OPEN (xmode only) /
+                                 VLB_WET (ymode only)                                 */
     int precision;            /* VLB_FP32 or VLB_FP64                                  */
     const uint8_t* solid_mask;/* host, ny*nx, nullable                                 */
     const double* circles;    /* host, 3 per circle (xc, yc, R), nullable              */
@@ -194,7 +201,8 @@ int vlb_monitors(vlb_sim* sim, vlb_monitor* out);
  * rules return.  circle >= 0 (index into vlb_grid.circles) keeps the links into that
  * circle; circle < 0 keeps every solid link (walls, mask solids and circles).  Lattice
  * units (force per unit depth).  Deterministic (fixed-order reduction); synchronizes.
- * Errors: VLB_E_STATE before the first step, VLB_E_INVALID_ARG for a bad circle. */
+ * Errors: VLB_E_STATE before the first step, VLB_E_INVALID_ARG for a bad circle,
+ * VLB_E_UNSUPPORTED for circle < 0 with wet-node walls (circles only there). */
 int vlb_drag(vlb_sim* sim, int circle, double* fx, double* fy);
 
 /* ---- checkpoint ------------------------------------------------------------------ */

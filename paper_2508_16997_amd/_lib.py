@@ -20,9 +20,9 @@ VLB_E_NONFINITE = -4
 VLB_E_STATE = -5
 VLB_E_UNSUPPORTED = -6
 VLB_FP32, VLB_FP64 = 0, 1
-VLB_PERIODIC, VLB_WALL, VLB_OPEN = 0, 1, 2
+VLB_PERIODIC, VLB_WALL, VLB_OPEN, VLB_WET = 0, 1, 2, 3
 VLB_FLAG_NO_SOURCE = 1
-MODES = {"periodic": VLB_PERIODIC, "wall": VLB_WALL, "open": VLB_OPEN}
+MODES = {"periodic": VLB_PERIODIC, "wall": VLB_WALL, "open": VLB_OPEN, "wet": VLB_WET}
 
 # Every symbol declared in include/vlb.h.
 EXPORTS = [

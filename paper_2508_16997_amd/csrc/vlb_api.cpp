@@ -197,7 +197,8 @@ void build_geometry(vlb_sim* s, const uint8_t* mask) {
                 bool is_solid = false;
                 double q = 0.5;
                 int cid = -1;
-                if ((yout && s->ymode == VLB_WALL) || (xout && s->xmode == VLB_WALL)) {
+                if ((yout && (s->ymode == VLB_WALL || s->ymode == VLB_WET)) ||
+                    (xout && s->xmode == VLB_WALL)) {
                     is_solid = true;
                 } else {
                     if (yout) yn = wrap(yn, ny);
@@ -376,6 +377,7 @@ Run<T> make_run(const vlb_sim* s) {
     Run<T> r{};
     r.nx = s->nx; r.ny = s->ny; r.pitch = s->pitch; r.off0 = s->off0;
     r.xmode = s->xmode; r.ymode = s->ymode;
+    r.wet_y = s->ymode == VLB_WET ? 1 : 0;
     r.has_bits = s->has_bits ? 1 : 0;
     r.has_curved = s->has_curved ? 1 : 0;
     r.uniform_force = s->force_field ? 0 : 1;
@@ -563,8 +565,11 @@ int vlb_create(const vlb_grid* g, vlb_sim** out) {
     if (g->nx < 1 || g->ny < 1 || ((long long)g->nx + 129) * (g->ny + 2) >= (1LL << 31) / 64)
         return fail(VLB_E_INVALID_ARG, "grid size out of range");
     if (g->xmode < VLB_PERIODIC || g->xmode > VLB_OPEN || g->ymode < VLB_PERIODIC ||
-        g->ymode > VLB_WALL)
-        return fail(VLB_E_INVALID_ARG, "boundary mode out of range (ymode cannot be open)");
+        g->ymode > VLB_WET || g->ymode == VLB_OPEN)
+        return fail(VLB_E_INVALID_ARG,
+                    "boundary mode out of range (ymode cannot be open, xmode cannot be wet)");
+    if (g->ymode == VLB_WET && g->ny < 5)
+        return fail(VLB_E_INVALID_ARG, "wet-node walls need ny >= 5");
     if (g->precision != VLB_FP32 && g->precision != VLB_FP64)
         return fail(VLB_E_INVALID_ARG, "precision must be VLB_FP32 or VLB_FP64");
     if (g->ncircles < 0 || (g->ncircles > 0 && !g->circles))
@@ -586,6 +591,17 @@ int vlb_create(const vlb_grid* g, vlb_sim** out) {
     s->plane = (long long)s->pitch * (g->ny + 2);
     if (g->ncircles) s->circles.assign(g->circles, g->circles + 3 * g->ncircles);
     build_geometry(s, g->solid_mask);
+    if (s->ymode == VLB_WET) {
+        // the wall rows and the two rows next to each (one-sided differences at the
+        // wall nodes) must be fluid
+        for (int y : {0, 1, 2, s->ny - 3, s->ny - 2, s->ny - 1})
+            for (int x = 0; x < s->nx; ++x)
+                if (s->solid[(size_t)y * s->nx + x]) {
+                    delete s;
+                    return fail(VLB_E_INVALID_ARG,
+                                "wet-node walls: rows 0-2 and ny-3..ny-1 must be fluid");
+                }
+    }
     build_fill(s);
     s->inlet.assign(4 * (size_t)g->ny, 0.0);
     for (int y = 0; y < g->ny; ++y) { s->inlet[g->ny + y] = 1.0; s->inlet[3 * g->ny + y] = 1.0; }
@@ -841,6 +857,8 @@ int vlb_drag(vlb_sim* s, int circle, double* fx, double* fy) {
     if (!fx || !fy) return fail(VLB_E_INVALID_ARG, "null output");
     if (s->first) return fail(VLB_E_STATE, "the drag needs at least one step");
     if (circle >= (int)(s->circles.size() / 3)) return fail(VLB_E_INVALID_ARG, "no such circle");
+    if (circle < 0 && s->ymode == VLB_WET)
+        return fail(VLB_E_UNSUPPORTED, "the drag on wet-node walls is not built (circles only)");
     const int nl = (int)s->links.size();
     const int nb = (nl + 255) / 256;
     double* part = s->dptr<double>(s->off_dragpart);

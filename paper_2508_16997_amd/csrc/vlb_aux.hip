@@ -48,7 +48,10 @@ __device__ __forceinline__ bool node_fields(const RunDev<S>& R, const S* src, in
     pull9(R, src, 0, p, pull, f);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
+    const bool wet = wet_row(R, y);
+    if (wet && pull) zou_he(f, y == 0, Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
+    if (wet) ux = uy = 0.0;  // wall node: the wall velocity
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         S g[9];

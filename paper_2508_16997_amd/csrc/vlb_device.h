@@ -123,6 +123,40 @@ __device__ __forceinline__ void hydro_macros(const V f[9], T Fx, T Fy, T& drho, 
     uy = (jy + 0.5 * Fy) * inv;
 }
 
+// Wall node of a wet-node wall (first or last row).
+template <class S>
+__device__ __forceinline__ bool wet_row(const RunDev<S>& R, int y) {
+    return R.wet_y && (y == 0 || y == R.ny - 1);
+}
+
+// Non-equilibrium bounce-back of the hydrodynamic populations at a wet-node wall node
+// (Zou-He closure with zero wall velocity): the three populations that would arrive
+// from beyond the wall are set so that the node keeps the normal non-equilibrium part
+// of its opposite and the streamed momentum equals -F/2 (zero velocity with the
+// half-force shift).  The relations are differences of equally weighted populations,
+// so they hold for the deviations f_i - w_i as stored.
+// (Both candidate sets are formed and selected per entry, so that every array index
+// stays a compile-time constant and f stays in registers.)
+template <class V>
+__device__ __forceinline__ void zou_he(V f[9], bool bottom, T Fx, T Fy) {
+    const T jx = -0.5 * Fx, jy = -0.5 * Fy;
+    const T d13 = T(f[1]) - T(f[3]);
+    // bottom wall, unknown e_y = +1
+    const V b2 = V(T(f[4]) + (2.0 / 3.0) * jy);
+    const V b5 = V(T(f[7]) - 0.5 * d13 + (1.0 / 6.0) * jy + 0.5 * jx);
+    const V b6 = V(T(f[8]) + 0.5 * d13 + (1.0 / 6.0) * jy - 0.5 * jx);
+    // top wall, unknown e_y = -1
+    const V t4 = V(T(f[2]) - (2.0 / 3.0) * jy);
+    const V t7 = V(T(f[5]) + 0.5 * d13 - (1.0 / 6.0) * jy - 0.5 * jx);
+    const V t8 = V(T(f[6]) - 0.5 * d13 - (1.0 / 6.0) * jy + 0.5 * jx);
+    f[2] = bottom ? b2 : f[2];
+    f[5] = bottom ? b5 : f[5];
+    f[6] = bottom ? b6 : f[6];
+    f[4] = bottom ? f[4] : t4;
+    f[7] = bottom ? f[7] : t7;
+    f[8] = bottom ? f[8] : t8;
+}
+
 // Conservative non-equilibrium bounce-back for one lattice at a boundary node
 // (Sec. 3.3).  On entry g holds the known post-streaming populations and, on wall
 // links, the post-collision populations that moved toward the wall; phi_b is their
@@ -393,7 +427,10 @@ __device__ __forceinline__ bool cell_macros(const RunDev<S>& R, const S* src, in
     pull9(R, src, 0, p, pull, f);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
+    const bool wet = wet_row(R, cy);
+    if (wet && pull) zou_he(f, cy == 0, Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
+    if (wet) ux = uy = 0.0;  // wall node: the wall velocity
     return true;
 }
 

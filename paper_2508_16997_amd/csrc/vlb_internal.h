@@ -8,7 +8,8 @@
 
 namespace vlb {
 
-enum { XM_PERIODIC = 0, XM_WALL = 1, XM_OPEN = 2 };
+// XM_WET (y only): the first and last rows are wall nodes (wet-node walls).
+enum { XM_PERIODIC = 0, XM_WALL = 1, XM_OPEN = 2, XM_WET = 3 };
 
 // Per-node geometry word: bit 0 = the node itself is solid; bit i (1..8) = the source
 // x - e_i of direction i is solid (domain wall or solid node).
@@ -52,7 +53,7 @@ struct RunDev {
     int uniform_force;  // 1: use Fx, Fy below; 0: force planes
     int no_source;      // constitutive source forced to zero
     int model;          // constitutive closure (VLB_OLDROYD_B ... VLB_FENE_P)
-    int pad0;
+    int wet_y;          // 1: rows 0 and ny - 1 are wet-node wall nodes (u = 0 there)
     long long plane;    // elements per plane ((ny + 2) * pitch)
     S* pop[2];          // two population buffers of 36 planes: f (9), g_xx, g_xy, g_yy (9 each)
     S* hist;            // 5 planes: S_xx, S_xy, S_yy, u_x, u_y of the previous step

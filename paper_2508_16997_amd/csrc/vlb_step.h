@@ -29,9 +29,9 @@ struct StepBounds {
     static constexpr int threads = 64 * TY;
     static constexpr int min_waves_per_eu = sizeof(S) == 4 ? 4 : 1;
     // the persistent batch kernel loops over tiles and keeps a few more values live:
-    // four waves per SIMD (FP32 storage) spill 28-32 bytes per lane, touched once per
-    // tile, and still run faster than three without spills; FP64 fits three
-    static constexpr int batch_waves_per_eu = sizeof(S) == 4 ? 4 : 2;
+    // four waves per SIMD (FP32 storage) spill about 40 bytes per lane, touched once
+    // per tile, and ran faster than three without spills; FP64 at three spills 12
+    static constexpr int batch_waves_per_eu = sizeof(S) == 4 ? 4 : 3;
 };
 
 namespace vlb {
@@ -67,6 +67,9 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     __shared__ T s_rho[TY + 2][66];
     __shared__ T s_ux[TY + 2][66];
     __shared__ T s_uy[TY + 2][66];
+    // wet-node walls: u_x, u_y and rho u_y^3 two rows into the fluid from the wall nodes
+    // of the tile ([0] bottom wall, [1] top wall), for their one-sided differences
+    __shared__ T s_w2[2][3][64];
     const RunDev<S>& R = runs[it.run];
     const S* src = R.pop[parity];
     S* dst = R.pop[parity ^ 1];
@@ -83,6 +86,16 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     unsigned b = 0u;
     if (in_dom) b = node_bits(R, p);
     const bool active = in_dom && !(b & BIT_SELF_SOLID);
+    if (active && wet_row(R, y)) {
+        // recomputed from its pulled populations before this node's own pulls, so that
+        // nothing extra stays live across them
+        T r2 = 1.0, ux2 = 0.0, uy2 = 0.0;
+        cell_macros(R, src, x, y == 0 ? 2 : y - 2, pull, r2, ux2, uy2);
+        const int w = y == 0 ? 0 : 1;
+        s_w2[w][0][lx] = ux2;
+        s_w2[w][1][lx] = uy2;
+        s_w2[w][2][lx] = r2 * uy2 * uy2 * uy2;
+    }
     S f[9], g[3][9];
     T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
     // conformation deviations A - I: the zeroth moments of the pulled g lattices (CNEBB
@@ -96,6 +109,9 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
             dk[k] = zeroth(g[k]);
         }
         node_force(R, p, Fx, Fy);
+        // wet-node wall: the populations from beyond the wall by non-equilibrium
+        // bounce-back (the pulled ghost values are discarded)
+        if (pull && wet_row(R, y)) zou_he(f, y == 0, Fx, Fy);
         if (pull) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) hS[k] = ldu(R.hist + k * plane, (unsigned)p);
@@ -120,6 +136,7 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     T drho = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
     if (active) {
         hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
+        if (wet_row(R, y)) ux = uy = 0.0;  // wall node: the wall velocity
         s_rho[ly + 1][lx + 1] = rho;
         s_ux[ly + 1][lx + 1] = ux;
         s_uy[ly + 1][lx + 1] = uy;
@@ -157,12 +174,25 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     if (!wyh) { ru = s_rho[ly + 2][lx + 1]; uxu = s_ux[ly + 2][lx + 1]; uyu = s_uy[ly + 2][lx + 1]; }
     const T Lxx = dgrad(wxl, qxl, uxl, ux, wxh, qxh, uxh);
     const T Lxy = dgrad(wxl, qxl, uyl, uy, wxh, qxh, uyh);
-    const T Lyx = dgrad(wyl, qyl, uxd, ux, wyh, qyh, uxu);
-    const T Lyy = dgrad(wyl, qyl, uyd, uy, wyh, qyh, uyu);
+    T Lyx = dgrad(wyl, qyl, uxd, ux, wyh, qyh, uxu);
+    T Lyy = dgrad(wyl, qyl, uyd, uy, wyh, qyh, uyu);
     const T Dx = dgrad(wxl, qxl, rl * uxl * uxl * uxl, rho * ux * ux * ux, wxh, qxh,
                        rh * uxh * uxh * uxh);
-    const T Dy = dgrad(wyl, qyl, rd * uyd * uyd * uyd, rho * uy * uy * uy, wyh, qyh,
-                       ru * uyu * uyu * uyu);
+    T Dy = dgrad(wyl, qyl, rd * uyd * uyd * uyd, rho * uy * uy * uy, wyh, qyh,
+                 ru * uyu * uyu * uyu);
+    if (wet_row(R, y)) {
+        // wall node of a wet-node wall: wall-normal derivatives by the one-sided
+        // second-order difference through the node and the next two rows (the nearer
+        // from the tile's LDS, the farther from s_w2)
+        const bool bot = y == 0;
+        const int w = bot ? 0 : 1;
+        const T s1 = bot ? 1.0 : -1.0;
+        const T r1 = bot ? ru : rd, ux1 = bot ? uxu : uxd, uy1 = bot ? uyu : uyd;
+        Lyx = s1 * (-1.5 * ux + 2.0 * ux1 - 0.5 * s_w2[w][0][lx]);
+        Lyy = s1 * (-1.5 * uy + 2.0 * uy1 - 0.5 * s_w2[w][1][lx]);
+        Dy = s1 * (-1.5 * (rho * uy * uy * uy) + 2.0 * (r1 * uy1 * uy1 * uy1) -
+                   0.5 * s_w2[w][2][lx]);
+    }
 
     const T d0 = dk[0], d1 = dk[1], d2 = dk[2];
     const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
