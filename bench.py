@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
     "four_roll_512": [
-        {"sources": "9cced523001b14ad", "tile": 8, "store_mode": "streaming",
-         "fetch_KiB": 24849.3, "write_KiB": 42416.5,
+        {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "streaming",
+         "fetch_KiB": 24953.2, "write_KiB": 42417.8,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
     ],
 }
