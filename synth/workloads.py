@@ -165,19 +165,20 @@ def four_roll_mill(N=512, Re=1.0, Wi=5.0, beta=0.5, Ma=0.01, Sc=1e5, Lambda_s=0.
 
 def cylinder(nx=4096, ny=1024, R=128.0, xc=2048.0, yc=512.0, Wi=1.0, beta=0.59, Re=1.0,
              Ma=0.01, Sc=1e6, Lambda_s=0.25, Lambda_p=2.5e-7, steps=2000,
-             precision="fp32") -> Problem:
+             precision="fp32", wet=False) -> Problem:
     """Channel flow past a circular cylinder (Sec. 4.3), L_c = R.
 
-    Half-way no-slip walls outside rows 0 and ny-1 (H = ny); inlet column at x = -1
-    carries the fully developed profile u_x = 1.5 * 4 U_c y'(H - y')/H^2 (y' = y + 1/2)
-    with the steady Oldroyd-B conformation of that shear, A_xy = lambda u',
-    A_xx = 1 + 2 (lambda u')^2, A_yy = 1; zero-gradient outlet at x = nx.  The flow
-    starts from the inlet profile everywhere (zero inside the cylinder).
+    Half-way no-slip walls outside rows 0 and ny-1 (H = ny; with ``wet``, wet-node walls
+    on rows 0 and ny - 1, H = ny - 1); inlet column at x = -1 carries the fully developed
+    profile u_x = 1.5 * 4 U_c y'(H - y')/H^2 (y' = y + 1/2, wet: y' = y) with the steady
+    Oldroyd-B conformation of that shear, A_xy = lambda u', A_xx = 1 + 2 (lambda u')^2,
+    A_yy = 1; zero-gradient outlet at x = nx.  The flow starts from the inlet profile
+    everywhere (zero inside the cylinder).
     """
     Lc = float(R)
     p = lattice_units(Re, Wi, beta, Sc, Ma, Lc)
-    H = float(ny)
-    yp = np.arange(ny, dtype=np.float64) + 0.5
+    H = float(ny - 1 if wet else ny)
+    yp = np.arange(ny, dtype=np.float64) + (0.0 if wet else 0.5)
     Umax_scale = 1.5 * 4.0 * p["Uc"] / (H * H)
     ux_in = Umax_scale * yp * (H - yp)
     dudy = Umax_scale * (H - 2.0 * yp)
@@ -186,13 +187,14 @@ def cylinder(nx=4096, ny=1024, R=128.0, xc=2048.0, yc=512.0, Wi=1.0, beta=0.59, 
     axx_in = 1.0 + 2.0 * (lam * dudy) ** 2
     ayy_in = np.ones(ny)
     prob = Problem(
-        name=f"cylinder_{nx}x{ny}_R{R:g}_Wi{Wi:g}", nx=nx, ny=ny, xmode="open", ymode="wall",
+        name=f"cylinder_{nx}x{ny}_R{R:g}_Wi{Wi:g}", nx=nx, ny=ny, xmode="open",
+        ymode="wet" if wet else "wall",
         nu_s=p["nu_s"], eta_p=p["eta_p"], lam=lam, kappa=p["kappa"],
         Lambda_s=Lambda_s, Lambda_p=Lambda_p, Fx=0.0, Fy=0.0, circles=[(xc, yc, R)],
         inlet=dict(ux=ux_in, axx=axx_in, axy=axy_in, ayy=ayy_in), steps=steps,
         precision=precision,
         meta=dict(Re=Re, Wi=Wi, beta=beta, Sc=Sc, Ma=Ma, Uc=p["Uc"], Lc=Lc,
-                  Tc=Lc / p["Uc"], blockage=2 * R / ny))
+                  Tc=Lc / p["Uc"], blockage=2 * R / H))
     fluid = prob.fluid_mask()
     ux0 = np.where(fluid, ux_in[:, None], 0.0)
     prob.init = dict(ux=ux0, axx=np.where(fluid, axx_in[:, None], 1.0),
@@ -201,14 +203,16 @@ def cylinder(nx=4096, ny=1024, R=128.0, xc=2048.0, yc=512.0, Wi=1.0, beta=0.59, 
 
 
 def cylinder_channel(R=20, Wi=0.1, beta=0.59, Sc=1e6, Lambda_p=2.5e-7, precision="fp64",
-                     steps=0) -> Problem:
+                     steps=0, wet=False) -> Problem:
     """The paper's confined cylinder (Sec. 4.3): a 30R x 4R channel with the cylinder at
-    (15R, 2R), i.e. midway between the half-way walls (node coordinates shifted by 1/2),
+    (15R, 2R), i.e. midway between the half-way walls (node coordinates shifted by 1/2;
+    with ``wet``, between wet-node walls on rows 0 and 4R, cylinder centre on row 2R),
     L_c = R, Re = 1, Ma = 0.01; inlet, outlet and start as in :func:`cylinder`."""
     R = int(R)
-    pr = cylinder(nx=30 * R, ny=4 * R, R=float(R), xc=15 * R - 0.5, yc=2 * R - 0.5, Wi=Wi,
-                  beta=beta, Sc=Sc, Lambda_p=Lambda_p, steps=steps, precision=precision)
-    pr.name = f"cylinder_channel_R{R}_Wi{Wi:g}"
+    pr = cylinder(nx=30 * R, ny=4 * R + (1 if wet else 0), R=float(R), xc=15 * R - 0.5,
+                  yc=2 * R - (0.0 if wet else 0.5), Wi=Wi, beta=beta, Sc=Sc,
+                  Lambda_p=Lambda_p, steps=steps, precision=precision, wet=wet)
+    pr.name = f"cylinder_channel_R{R}_Wi{Wi:g}{'_wet' if wet else ''}"
     return pr
 
 
