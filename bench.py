@@ -36,6 +36,18 @@ MEASURED_TRAFFIC = {
         {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "streaming",
          "fetch_KiB": 24953.2, "write_KiB": 42417.8,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
+        {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "cached",
+         "fetch_KiB": 25170.2, "write_KiB": 42416.0,
+         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
+        {"sources": "6c52ea7c87ecb45a", "tile": 4, "store_mode": "streaming",
+         "fetch_KiB": 25549.2, "write_KiB": 42416.2,
+         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
+        {"sources": "6c52ea7c87ecb45a", "tile": 4, "store_mode": "cached",
+         "fetch_KiB": 25537.6, "write_KiB": 42416.0,
+         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
+        {"sources": "6c52ea7c87ecb45a", "tile": 2, "store_mode": "streaming",
+         "fetch_KiB": 26260.7, "write_KiB": 42418.2,
+         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
     ],
 }
 KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_step.h", "vlb_kernels.hip")
