@@ -336,3 +336,43 @@ def test_invalid_params_fail_loudly():
         sim.set_params(nu_s=-1.0, eta_p=0.1, lam=10.0, kappa=0.01)
     with pytest.raises(VlbError):
         sim.step(1)  # no parameters / state yet
+
+
+def test_largest_grid_matches_its_one_row_problem():
+    """Near the largest grid the library accepts ((nx + 129)(ny + 2) < 2^31 / 64): a state
+    that does not depend on y evolves row by row like the same columns on a 4-row grid
+    (translation invariance of the periodic step), bit for bit, and the 4-row grid
+    matches the oracle.  Exercises the index arithmetic at about 33 million nodes
+    (FP32, about 10 GB of state)."""
+    import torch
+    from paper_2508_16997_amd import Simulation
+
+    nx, ny = 8064, 4093
+    assert (nx + 129) * (ny + 2) < 2 ** 31 // 64 <= (nx + 129) * (ny + 3)
+    k = 2 * np.pi / nx
+    x = np.arange(nx, dtype=np.float64)
+    init = dict(uy=0.01 * np.sin(k * x), axx=1.0 + 0.1 * np.cos(k * x),
+                axy=0.05 * np.sin(2 * k * x))
+    small = synth.Problem(name="rows4", nx=nx, ny=4, xmode="periodic", ymode="periodic",
+                          nu_s=0.1, eta_p=0.07, lam=40.0, kappa=0.02, Lambda_s=0.25,
+                          Lambda_p=0.05, init=init, precision="fp32")
+    big = small.with_(name="largest", ny=ny)
+    say("largest grid", nx, ny)
+    sb = Simulation.from_problem(big, tile=8)
+    ss = Simulation.from_problem(small, tile=8)
+    sb.step(5)
+    ss.step(5)
+    gb, gs = sb.read(), ss.read()
+    torch.cuda.synchronize()
+    for key in FIELDS:
+        assert torch.equal(gb[key], gs[key][:1].expand(ny, nx)), key
+    del gb
+    sb.close()
+    g = gpu_fields(ss)
+    ss.close()
+    import oracle
+
+    o = oracle.OracleSim(small)
+    o.step(5)
+    err = parity(g, o.read(), small.fluid_mask())
+    assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
