@@ -376,3 +376,19 @@ def test_largest_grid_matches_its_one_row_problem():
     o.step(5)
     err = parity(g, o.read(), small.fluid_mask())
     assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
+
+
+@pytest.mark.parametrize("nx,ny,xmode,ymode,precision", [
+    (1, 12, "periodic", "periodic", "fp64"), (12, 1, "periodic", "periodic", "fp64"),
+    (1, 1, "periodic", "periodic", "fp64"), (1, 16, "periodic", "wall", "fp64"),
+    (2, 9, "open", "wall", "fp64"), (1, 12, "periodic", "periodic", "fp32")])
+def test_one_node_axes(nx, ny, xmode, ymode, precision):
+    """Degenerate grids: a periodic axis with one node (every neighbour along it is the
+    node itself, both periodic images written by the one edge node), the narrowest open
+    channel; against the oracle."""
+    pr = synth.random_periodic(nx, ny, seed=41, xmode=xmode, ymode=ymode, precision=precision)
+    say("one-node axes", nx, ny, xmode, ymode, precision)
+    g, o = run_pair(pr, 30, dual_chunks=[1, 29], sim_kw=dict(tile=4))
+    e = parity(g, o, pr.fluid_mask())
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert max(e["u"], e["axx"], e["axy"], e["ayy"]) < tol, e
