@@ -33,20 +33,20 @@ HBM_PEAK_GBS = 8000.0
 # times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
     "four_roll_512": [
-        {"sources": "951da35d18096f16", "tile": 8, "store_mode": "streaming",
-         "fetch_KiB": 24881.0, "write_KiB": 42416.9,
+        {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "streaming",
+         "fetch_KiB": 24953.2, "write_KiB": 42417.8,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
-        {"sources": "951da35d18096f16", "tile": 8, "store_mode": "cached",
-         "fetch_KiB": 25088.2, "write_KiB": 42416.0,
+        {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "cached",
+         "fetch_KiB": 25170.2, "write_KiB": 42416.0,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
-        {"sources": "951da35d18096f16", "tile": 4, "store_mode": "streaming",
-         "fetch_KiB": 25529.2, "write_KiB": 42416.3,
+        {"sources": "6c52ea7c87ecb45a", "tile": 4, "store_mode": "streaming",
+         "fetch_KiB": 25549.2, "write_KiB": 42416.2,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
-        {"sources": "951da35d18096f16", "tile": 4, "store_mode": "cached",
-         "fetch_KiB": 25554.0, "write_KiB": 42416.0,
+        {"sources": "6c52ea7c87ecb45a", "tile": 4, "store_mode": "cached",
+         "fetch_KiB": 25537.6, "write_KiB": 42416.0,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
-        {"sources": "951da35d18096f16", "tile": 2, "store_mode": "streaming",
-         "fetch_KiB": 26436.2, "write_KiB": 42416.7,
+        {"sources": "6c52ea7c87ecb45a", "tile": 2, "store_mode": "streaming",
+         "fetch_KiB": 26260.7, "write_KiB": 42418.2,
          "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
     ],
 }

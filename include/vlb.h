@@ -74,8 +74,8 @@ typedef struct vlb_sim vlb_sim;
  * q = 1/2. */
 typedef struct {
     int nx, ny;               /* 1 <= nx, ny; (nx + 129)(ny + 2) < 2^31 / 64 (padded
-                                 plane of at most 33.5 M slots); nx >= 2 with VLB_OPEN,
-                                 ny >= 5 with VLB_WET                                 */
+                                 plane of at most 33.5 M slots); at least 2 nodes along
+                                 a periodic or open axis, ny >= 5 with VLB_WET       */
     int xmode, ymode;         /* VLB_PERIODIC / VLB_WALL / VLB_OPEN (xmode only) /
                                  VLB_WET (ymode only)                                 */
     int precision;            /* VLB_FP32 or VLB_FP64                                  */

@@ -570,8 +570,10 @@ int vlb_create(const vlb_grid* g, vlb_sim** out) {
                     "boundary mode out of range (ymode cannot be open, xmode cannot be wet)");
     if (g->ymode == VLB_WET && g->ny < 5)
         return fail(VLB_E_INVALID_ARG, "wet-node walls need ny >= 5");
-    if (g->xmode == VLB_OPEN && g->nx < 2)
-        return fail(VLB_E_INVALID_ARG, "open ends need nx >= 2 (distinct inlet and outlet columns)");
+    if ((g->xmode == VLB_OPEN || g->xmode == VLB_PERIODIC) && g->nx < 2)
+        return fail(VLB_E_INVALID_ARG, "periodic or open x needs nx >= 2");
+    if (g->ymode == VLB_PERIODIC && g->ny < 2)
+        return fail(VLB_E_INVALID_ARG, "periodic y needs ny >= 2");
     if (g->precision != VLB_FP32 && g->precision != VLB_FP64)
         return fail(VLB_E_INVALID_ARG, "precision must be VLB_FP32 or VLB_FP64");
     if (g->ncircles < 0 || (g->ncircles > 0 && !g->circles))

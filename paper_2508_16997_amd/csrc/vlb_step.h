@@ -216,14 +216,14 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     // Periodic images: an edge node also writes the populations that leave the domain
     // into the ghost slots its periodic neighbours pull from (no fill op needed).
     const bool px_per = R.xmode == XM_PERIODIC, py_per = R.ymode == XM_PERIODIC;
-    const bool xlo = px_per && x == 0, xhi = px_per && x == R.nx - 1;
-    const bool ylo = py_per && y == 0, yhi = py_per && y == R.ny - 1;
-    const bool edge = xlo || xhi || ylo || yhi;
+    const int gxo = (px_per && x == R.nx - 1) ? -R.nx : ((px_per && x == 0) ? R.nx : 0);
+    const int gyo = (py_per && y == R.ny - 1) ? -R.ny : ((py_per && y == 0) ? R.ny : 0);
+    const bool edge = (gxo | gyo) != 0;
     // ghost slot of direction i for this node, or -1: a population moving in direction
-    // i leaves through the edge it points at (both edges when the axis has one node)
+    // i leaves through the edge it points at
     auto ghost = [&](int i) -> int {
-        const int sx = (xhi && ex(i) == 1) ? -R.nx : ((xlo && ex(i) == -1) ? R.nx : 0);
-        const int sy = (yhi && ey(i) == 1) ? -R.ny : ((ylo && ey(i) == -1) ? R.ny : 0);
+        const int sx = (gxo != 0 && ex(i) == (gxo < 0 ? 1 : -1)) ? gxo : 0;
+        const int sy = (gyo != 0 && ey(i) == (gyo < 0 ? 1 : -1)) ? gyo : 0;
         if (sx == 0 && sy == 0) return -1;
         return p + sx + sy * R.pitch;
     };

@@ -103,13 +103,16 @@ def test_invalid_grid_rejected(vlb):
     assert st == L.VLB_E_INVALID_ARG
     lib, L, st, h = _lib_and_sim(vlb, prec=7)
     assert st == L.VLB_E_INVALID_ARG
-    # open ends need distinct inlet and outlet columns; wet-node walls are y only and
-    # need ny >= 5
+    # periodic and open axes need two nodes (distinct edges: periodic images, inlet and
+    # outlet columns); wet-node walls are y only and need ny >= 5
     assert _lib_and_sim(vlb, nx=1, xmode=2)[2] == L.VLB_E_INVALID_ARG
+    assert _lib_and_sim(vlb, nx=1, xmode=0)[2] == L.VLB_E_INVALID_ARG
+    assert _lib_and_sim(vlb, ny=1, ymode=0)[2] == L.VLB_E_INVALID_ARG
     assert _lib_and_sim(vlb, xmode=3)[2] == L.VLB_E_INVALID_ARG
     assert _lib_and_sim(vlb, ny=4, ymode=3)[2] == L.VLB_E_INVALID_ARG
-    # one-node axes are fine when periodic or walled
-    for kw in (dict(nx=1, ny=1), dict(nx=1, ny=8, ymode=1), dict(nx=2, xmode=2)):
+    # one-node axes between walls, two-node periodic and open axes are fine
+    for kw in (dict(nx=1, ny=1, xmode=1, ymode=1), dict(nx=2, ny=1, ymode=1),
+               dict(nx=2, ny=2), dict(nx=2, xmode=2)):
         lib, L, st, h = _lib_and_sim(vlb, **kw)
         assert st == L.VLB_OK, kw
         lib.vlb_destroy(h)

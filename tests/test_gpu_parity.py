@@ -379,15 +379,17 @@ def test_largest_grid_matches_its_one_row_problem():
 
 
 @pytest.mark.parametrize("nx,ny,xmode,ymode,precision", [
-    (1, 12, "periodic", "periodic", "fp64"), (12, 1, "periodic", "periodic", "fp64"),
-    (1, 1, "periodic", "periodic", "fp64"), (1, 16, "periodic", "wall", "fp64"),
-    (2, 9, "open", "wall", "fp64"), (1, 12, "periodic", "periodic", "fp32")])
-def test_one_node_axes(nx, ny, xmode, ymode, precision):
-    """Degenerate grids: a periodic axis with one node (every neighbour along it is the
-    node itself, both periodic images written by the one edge node), the narrowest open
-    channel; against the oracle."""
+    (2, 12, "periodic", "periodic", "fp64"), (12, 2, "periodic", "periodic", "fp64"),
+    (2, 2, "periodic", "periodic", "fp64"), (2, 16, "periodic", "wall", "fp64"),
+    (2, 9, "open", "wall", "fp64"), (2, 12, "periodic", "periodic", "fp32"),
+    (8, 1, "periodic", "wall", "fp64"), (1, 1, "wall", "wall", "fp64"),
+    (1, 9, "wall", "periodic", "fp64")])
+def test_smallest_axes(nx, ny, xmode, ymode, precision):
+    """Degenerate grids: periodic axes of two nodes (each edge node writes the images its
+    neighbour pulls, the neighbour on both sides is the same node), one-node axes between
+    walls, the narrowest open channel; against the oracle."""
     pr = synth.random_periodic(nx, ny, seed=41, xmode=xmode, ymode=ymode, precision=precision)
-    say("one-node axes", nx, ny, xmode, ymode, precision)
+    say("smallest axes", nx, ny, xmode, ymode, precision)
     g, o = run_pair(pr, 30, dual_chunks=[1, 29], sim_kw=dict(tile=4))
     e = parity(g, o, pr.fluid_mask())
     tol = 1e-10 if precision == "fp64" else 1e-5
