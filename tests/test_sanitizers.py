@@ -85,7 +85,8 @@ specs = [
     (130, 33, L.VLB_OPEN, L.VLB_WALL, 0, None, [(50.0, 16.0, 7.2), (90.0, 10.0, 3.1)]),
     (64, 64, L.VLB_PERIODIC, L.VLB_PERIODIC, 1, None, [(0.5, 0.5, 6.0)]),
     (33, 17, L.VLB_WALL, L.VLB_WALL, 1, None, []),
-    (1, 1, L.VLB_PERIODIC, L.VLB_PERIODIC, 0, None, []),
+    (1, 1, L.VLB_WALL, L.VLB_WALL, 0, None, []),
+    (2, 2, L.VLB_PERIODIC, L.VLB_PERIODIC, 0, None, []),
 ]
 for nx, ny, xm, ym, prec, m, circ in specs:
     g, keep = grid(nx, ny, xm, ym, prec, m, circ)
