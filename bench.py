@@ -173,13 +173,14 @@ def cylinder_leg(steps, warmup, tile, chunk):
             "tile": f"64x{tile}", "nonfinite": int(bad)}
 
 
-def batched_leg(steps, warmup, tile, chunk):
+def batched_leg(steps, warmup, tile, chunk, forms=(False, True)):
     """Batched workload (256 uneven runs advanced together) vs the same runs one by one.
 
     The batch is timed in both forms (one step launch and one fill launch per step under
     hipGraph replay, or the persistent cooperative launch of up to 256 steps), each at
     its autotuned tile; the faster is the batched figure.  The sequential leg steps each
     run alone for the same number of steps, back to back, with hipGraph replay.
+    ``forms`` limits the forms (a kernel trace of the per-step form alone, say).
     """
     import torch
     import synth
@@ -195,7 +196,7 @@ def batched_leg(steps, warmup, tile, chunk):
     # both batched forms, each at its fastest tile (or the tile given); the faster one
     # is the batched figure, the other is reported beside it
     (tile, pers), tuned = tune_batch(sims, tiles=(tile,) if tile else (2, 4, 8),
-                                     graph_chunk=chunk, forms=(False, True))
+                                     graph_chunk=chunk, forms=tuple(forms))
 
     def timed_batch(ty, persistent):
         b = Batch(sims, tile=ty, graph_chunk=0 if persistent else chunk, persistent=persistent)
@@ -209,8 +210,9 @@ def batched_leg(steps, warmup, tile, chunk):
         return t
 
     t_batch = timed_batch(tile, pers)
-    other = min((k for k in tuned if k[1] != pers), key=tuned.get)
-    t_other = timed_batch(*other)
+    others = [k for k in tuned if k[1] != pers]
+    other = min(others, key=tuned.get) if others else None
+    t_other = timed_batch(*other) if other else None
     for s in sims:  # warm the per-run graphs
         s.step(warmup)
     torch.cuda.synchronize()
@@ -230,9 +232,9 @@ def batched_leg(steps, warmup, tile, chunk):
             "batched_GBs": round(step_bytes * steps / t_batch / 1e9, 1),
             "batched_frac": round(step_bytes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
             "tile": f"64x{tile}", "form": "persistent" if pers else "per-step launches",
-            "other_form": {"form": "persistent" if other[1] else "per-step launches",
-                           "tile": f"64x{other[0]}",
-                           "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
+            "other_form": None if other is None else {
+                "form": "persistent" if other[1] else "per-step launches",
+                "tile": f"64x{other[0]}", "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
             "runs_nonfinite": int(bad)}
 
 
@@ -347,6 +349,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-sequential leg (256 uneven runs)")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--batched-form", choices=["both", "per-step", "persistent"],
+                    default="both", help="batched forms to time (default both)")
     ap.add_argument("--no-cylinder", action="store_true",
                     help="skip the 4096x1024 cylinder leg")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -442,8 +446,9 @@ def main():
     if not args.no_cylinder:
         out["cylinder"] = cylinder_leg(1000, 100, args.tile, args.graph_chunk)
     if not args.no_batched:
+        forms = {"both": (False, True), "per-step": (False,), "persistent": (True,)}
         out["batched"] = batched_leg(args.batched_steps, 2 * args.graph_chunk + 1, args.tile,
-                                     args.graph_chunk)
+                                     args.graph_chunk, forms[args.batched_form])
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_stride, tile,
                                      args.graph_chunk)
