@@ -27,6 +27,7 @@ MODES = {"periodic": 0, "wall": 1, "open": 2, "wet": 3}
 # constitutive closures (model function F(A), Sec. 2.2) and the meaning of model_param
 MODELS = {"oldroyd_b": 0, "giesekus": 1, "lptt": 2, "eptt": 3, "fene_p": 4}
 FLAG_NO_SOURCE = 1
+FLAG_NO_GTILDE = 2  # planted mistake for sensitivity checks: drop G~_i
 
 
 def build(force: bool = True) -> str:

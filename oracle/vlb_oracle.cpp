@@ -328,7 +328,9 @@ R fd_axis(bool lo_solid, double qlo, R plo, R p0, bool hi_solid, double qhi, R p
 // them, channel height ny - 1; reading A29).
 enum { MODE_PERIODIC = 0, MODE_WALL = 1, MODE_OPEN = 2, MODE_WET = 3 };
 enum { SRC_FLUID = 0, SRC_SOLID = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
-enum { FLAG_NO_SOURCE = 1 };
+// FLAG_NO_GTILDE drops the auxiliary term G~_i of the convection-diffusion collision: a
+// planted mistake for the sensitivity checks of the tests, never the method.
+enum { FLAG_NO_SOURCE = 1, FLAG_NO_GTILDE = 2 };
 
 struct Src {
     int kind;
@@ -549,8 +551,11 @@ struct Sim {
             for (int k = 0; k < 3; ++k) {
                 R gl[Q];
                 for (int i = 0; i < Q; ++i) gl[i] = g[k][i][n];
-                collide_cde(gl, A[k][n], rho[n], ux[n], uy[n], Fx[n], Fy[n], S[k], Sp[k],
-                            uxprev, uyprev, p, out);
+                // (the body force enters the convection-diffusion collision only through
+                // G~_i)
+                const bool gt = !(flags & FLAG_NO_GTILDE);
+                collide_cde(gl, A[k][n], rho[n], ux[n], uy[n], gt ? Fx[n] : R(0.0),
+                            gt ? Fy[n] : R(0.0), S[k], Sp[k], uxprev, uyprev, p, out);
                 for (int i = 0; i < Q; ++i) gp[k][i][n] = out[i];
                 Snew[k][n] = S[k];
             }

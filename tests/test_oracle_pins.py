@@ -588,6 +588,40 @@ def test_conformation_diffusion(oracle_lib, lam):
     assert abs(rate / (pr.kappa * k * k + 1 / lam) - 1) < 2e-3
 
 
+@pytest.mark.parametrize("kappa", [0.1, 0.02])
+def test_auxiliary_term_cancels_the_accelerated_flux_error(oracle_lib, kappa):
+    """G~_i against the Chapman-Enskog error of the convection-diffusion scheme (Sec. 3.2).
+
+    A conformation wave A_xx = 1 + a sin(k x) carried by a uniform flow that a body force
+    F accelerates from rest.  Without G~_i the scheme's first-order error flux
+    (tau_p1 - 1/2) d_t(phi u) = (tau_p1 - 1/2) phi F / rho slows the pattern by
+    (tau_p1 - 1/2) F per step; G~_i must give back exactly that displacement.  The
+    displacement with and without it (the latter a mistake planted in the oracle) must
+    differ by (tau_p1 - 1/2) F T to 0.5 %: a prefactor 1 - 1/tau instead of
+    1 - 1/(2 tau), a flipped sign or a missing phi fails.
+    """
+    n, T, F = 128, 400, 1e-5
+    k = 2 * np.pi / n
+    x = np.arange(n)
+    disp = []
+    for flags in (0, oracle_lib.FLAG_NO_GTILDE):
+        pr = synth.waves("conformation", n=n, amp=1e-3, kappa=kappa).with_(Fx=F)
+        o = oracle_lib.OracleSim(pr, flags=flags)
+
+        def phase():
+            a = o.read()["axx"][0] - 1
+            return np.angle((a * np.exp(-1j * k * x)).sum())
+
+        p0 = phase()
+        o.step(T)
+        disp.append(-np.angle(np.exp(1j * (phase() - p0))) / k)
+    ref = 3.0 * kappa * F * T  # (tau_p1 - 1/2) F T with tau_p1 = 3 kappa + 1/2
+    assert abs((disp[0] - disp[1]) / ref - 1) < 5e-3, (disp, ref)
+    # and the pattern moves with the flow: sum of u_n = F (n + 1/2) over the steps, to
+    # within a few 1e-3
+    assert abs(disp[0] / (F * T * T / 2) - 1) < 3e-3, disp
+
+
 def _sound_decay(oracle_lib, U):
     pr = synth.waves("sound", n=64, amp=1e-4, nu_s=0.05, U=U)
     o = oracle_lib.OracleSim(pr)
