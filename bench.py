@@ -113,7 +113,7 @@ def bytes_per_node(pr, esz):
     b = 2 * 36 * esz + 2 * 5 * esz  # populations and S/u history
     if not pr.uniform_force():
         b += 2 * esz  # per-node body force (read only)
-    if pr.ymode == "wall" or pr.xmode == "wall" or pr.circles or pr.solid is not None:
+    if pr.ymode in ("wall", "wet") or pr.xmode == "wall" or pr.circles or pr.solid is not None:
         b += 2  # geometry word (read only)
     return b
 
