@@ -10,8 +10,12 @@
  *     the auxiliary term G~_i (incompressible form), the source term F~_i and its
  *     backward time difference (Sec. 2.2-2.3, 3.2);
  *   - conservative non-equilibrium bounce-back (CNEBB) for every conformation lattice
- *     at solid walls (Sec. 3.3), half-way or linearly interpolated bounce-back for the
- *     hydrodynamic lattice, equilibrium inlet and zero-gradient outlet columns.
+ *     at solid walls (Sec. 3.3), half-way or linearly interpolated bounce-back (or
+ *     wet-node non-equilibrium bounce-back walls) for the hydrodynamic lattice, and open
+ *     inlet / outlet columns whose ghost populations are set by non-equilibrium
+ *     extrapolation from the adjacent fluid column (inlet: the prescribed velocity and
+ *     conformation profile; outlet: rho = 1 with zero-gradient u and A; the channel set-up
+ *     of Sec. 4.3).
  *
  * Conventions
  *   - Every call returns an int status: VLB_OK (0) or a negative VLB_E_* code; a
@@ -158,12 +162,20 @@ int vlb_set_params(vlb_sim* sim, const vlb_params* p);
 int vlb_params_from_groups(double Re, double Wi, double beta, double Sc, double Ma, double Lc,
                            double Lambda_s, double Lambda_p, vlb_params* out, double* uc);
 
-/* Per-node body force: device arrays [ny][nx] in the simulation precision, copied into
- * the workspace on the stream.  Both null: back to the uniform force of vlb_params. */
+/* Per-node body force F(x) of the hydrodynamic lattice (the forcing term F_i and the
+ * half-force velocity shift of Sec. 3.1; the four-roll mill's force field of Sec. 4.1):
+ * device arrays [ny][nx] in the simulation precision, copied into the workspace on the
+ * stream, so the caller may free them once the stream has passed this call.  Both null:
+ * back to the uniform force of vlb_params.  Errors: VLB_E_INVALID_ARG if exactly one is
+ * null, VLB_E_STATE before vlb_bind, VLB_E_HIP. */
 int vlb_set_force_field(vlb_sim* sim, const void* fx_dev, const void* fy_dev);
 
-/* Inlet profile for VLB_OPEN x: host arrays of ny doubles (u_x, A_xx, A_xy, A_yy);
- * u_y = 0 and rho = 1 at the inlet ghost column. */
+/* Inlet profile for VLB_OPEN x (the channel inlet of Sec. 4.3: a parabolic velocity and
+ * the conformation of the steady channel solution, A_xy = lambda u', A_xx = 1 +
+ * 2 (lambda u')^2, A_yy = 1): host arrays of ny doubles (u_x, A_xx, A_xy, A_yy, row y at
+ * index y), copied before the call returns; u_y = 0 at the inlet.  The inlet ghost column
+ * is filled each step by non-equilibrium extrapolation around this profile.  Errors:
+ * VLB_E_INVALID_ARG (null array, non-finite value), VLB_E_UNSUPPORTED (x not VLB_OPEN). */
 int vlb_set_inlet(vlb_sim* sim, const double* ux, const double* axx, const double* axy,
                   const double* ayy);
 
@@ -176,15 +188,20 @@ int vlb_init_equilibrium(vlb_sim* sim, const void* rho, const void* ux, const vo
 
 /* ---- time stepping and read-out ----------------------------------------------- */
 
-/* Advances nsteps coupled time steps (async on the stream). */
+/* Advances nsteps coupled time steps (the coupled update of Sec. 3.1-3.3: streaming and
+ * the boundary rules, the hydrodynamic and the three conformation collisions with their
+ * source terms), async on the stream; nsteps = 0 does nothing.  Errors: VLB_E_STATE
+ * (not bound, parameterised and initialised), VLB_E_INVALID_ARG (nsteps < 0), VLB_E_HIP.
+ * A numerical breakdown is not detected here: vlb_monitors reports it. */
 int vlb_step(vlb_sim* sim, int64_t nsteps);
 
 /* Current step count (host-side, no synchronization). */
 int vlb_get_step(const vlb_sim* sim, int64_t* step);
 
-/* Macroscopic fields at the current time: rho, u (with the half-force shift), A.
- * Device arrays [ny][nx] in the simulation precision; any may be null; solid nodes
- * read 0. */
+/* Macroscopic fields at the current time (the moments of Sec. 3.1 and 3.2): rho = sum
+ * f_i, u = (sum e_i f_i + F/2) / rho, A_k = sum g^k_i.  Device arrays [ny][nx] in the
+ * simulation precision, written on the stream; any may be null; solid nodes read 0.
+ * Errors: VLB_E_STATE before vlb_init_equilibrium (or vlb_load_state), VLB_E_HIP. */
 int vlb_read_fields(vlb_sim* sim, void* rho, void* ux, void* uy, void* axx, void* axy,
                     void* ayy);
 
@@ -192,9 +209,14 @@ int vlb_read_fields(vlb_sim* sim, void* rho, void* ux, void* uy, void* axx, void
  * Device arrays as for vlb_read_fields. */
 int vlb_read_history(vlb_sim* sim, void* sxx, void* sxy, void* syy, void* uxp, void* uyp);
 
-/* Wavefront-reduced monitors (mass per lattice, residual since the previous call,
- * non-finite and SPD counts).  Synchronizes the stream.  Returns VLB_E_NONFINITE when
- * any fluid node is non-finite (the paper's numerical breakdown), with *out filled. */
+/* Wavefront-reduced monitors: the total of rho and of each conformation component over
+ * the fluid nodes (the quantities the CNEBB scheme of Sec. 3.3 conserves), the
+ * velocity residual max |u(now) - u(previous call)| (divided by U_c and the call interval
+ * it is the steady-state criterion of Sec. 4.1), the largest |u|, and the counts of
+ * non-finite nodes and of nodes where A is not positive definite.  Synchronizes the
+ * stream.  Returns VLB_E_NONFINITE when any fluid node is non-finite (the breakdown the
+ * paper's stability studies record), with *out filled; VLB_E_STATE before
+ * initialisation; VLB_E_HIP. */
 int vlb_monitors(vlb_sim* sim, vlb_monitor* out);
 
 /* Momentum-exchange force on a solid (Sec. 4.3): over the boundary links (fluid node
@@ -209,9 +231,17 @@ int vlb_drag(vlb_sim* sim, int circle, double* fx, double* fy);
 
 /* ---- checkpoint ------------------------------------------------------------------ */
 
-/* Bytes of a saved state (populations, history, step counter). */
+/* Checkpoint of the full time-stepping state: the post-streaming populations of the four
+ * lattices and the history the next step needs (S and u of the previous step, for the
+ * time derivative of F~_i, Sec. 3.2), plus the step counter.
+ * vlb_state_bytes: bytes of a saved state (a 256-byte header, then the state).
+ * vlb_save_state: copies the state into a caller-owned device buffer of at least that
+ *   size (async on the stream).  VLB_E_STATE before initialisation, VLB_E_WORKSPACE for a
+ *   null or short buffer.
+ * vlb_load_state: restores a state saved by a simulation of the same grid, precision and
+ *   boundary kinds (checked from the header; else VLB_E_INVALID_ARG and nothing changes);
+ *   synchronizes the stream to read the header.  VLB_E_STATE before vlb_set_params. */
 int vlb_state_bytes(const vlb_sim* sim, size_t* bytes);
-/* Copies the state into / from a caller-owned device buffer (async / synchronizing). */
 int vlb_save_state(vlb_sim* sim, void* dev, size_t bytes);
 int vlb_load_state(vlb_sim* sim, const void* dev, size_t bytes);
 

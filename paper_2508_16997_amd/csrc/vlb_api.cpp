@@ -895,6 +895,15 @@ int vlb_state_bytes(const vlb_sim* s, size_t* bytes) {
 
 static const unsigned long long kStateMagic = 0x564C425354415445ULL;  // "VLBSTATE"
 
+// Header word 3 of a saved state: nx (bits 32-55), ny (bits 0-23), precision (bit 56),
+// x and y boundary modes (bits 58-59, 60-61).  A state loads only into a simulation
+// with the same word: the same plane layout, storage type and ghost-slot meaning.
+static unsigned long long state_shape(const vlb_sim* s) {
+    return ((unsigned long long)(unsigned)s->nx << 32) | (unsigned long long)(unsigned)s->ny |
+           ((unsigned long long)(s->prec & 1) << 56) | ((unsigned long long)(s->xmode & 3) << 58) |
+           ((unsigned long long)(s->ymode & 3) << 60);
+}
+
 int vlb_save_state(vlb_sim* s, void* dev, size_t bytes) {
     int rc = check_ready(s);
     if (rc) return rc;
@@ -902,10 +911,9 @@ int vlb_save_state(vlb_sim* s, void* dev, size_t bytes) {
     vlb_state_bytes(s, &need);
     if (!dev || bytes < need) return fail(VLB_E_WORKSPACE, "state buffer too small");
     char* d = static_cast<char*>(dev);
-    const unsigned long long shape = ((unsigned long long)(unsigned)s->nx << 32) | (unsigned)s->ny;
     VLB_HIP(vlb::launch_write_words(reinterpret_cast<unsigned long long*>(d), kStateMagic,
                                     (unsigned long long)s->step, (unsigned long long)s->first,
-                                    shape, s->stream));
+                                    state_shape(s), s->stream));
     const size_t pb = (size_t)s->plane * s->esz;
     VLB_HIP(hipMemcpyAsync(d + 256, s->ws + s->off_pop[s->parity], 36 * pb,
                            hipMemcpyDeviceToDevice, s->stream));
@@ -924,9 +932,10 @@ int vlb_load_state(vlb_sim* s, const void* dev, size_t bytes) {
     unsigned long long hdr[4] = {0, 0, 0, 0};
     VLB_HIP(hipMemcpyAsync(hdr, dev, sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
     VLB_HIP(hipStreamSynchronize(s->stream));
-    const unsigned long long shape = ((unsigned long long)(unsigned)s->nx << 32) | (unsigned)s->ny;
-    if (hdr[0] != kStateMagic || hdr[3] != shape)
-        return fail(VLB_E_INVALID_ARG, "state buffer does not hold a state of this grid");
+    if (hdr[0] != kStateMagic)
+        return fail(VLB_E_INVALID_ARG, "state buffer does not hold a saved state");
+    if (hdr[3] != state_shape(s))
+        return fail(VLB_E_INVALID_ARG, "saved state is of another grid, precision or boundary kind");
     const char* d = static_cast<const char*>(dev);
     const size_t pb = (size_t)s->plane * s->esz;
     VLB_HIP(hipMemcpyAsync(s->ws + s->off_pop[0], d + 256, 36 * pb, hipMemcpyDeviceToDevice,
@@ -1222,6 +1231,10 @@ int batch_lists(vlb_batch* b, vlb_sim* const* sims, int n, int ty) {
         const vlb_sim* s = sims[r];
         if (!s) return fail(VLB_E_INVALID_ARG, "null simulation in batch");
         if (s->prec != b->prec) return fail(VLB_E_INVALID_ARG, "batch mixes precisions");
+        // a member listed twice would be advanced twice per batch step (its buffer
+        // parity flipped twice), so later reads would see the stale buffer
+        for (int q = 0; q < r; ++q)
+            if (sims[q] == s) return fail(VLB_E_INVALID_ARG, "simulation listed twice in batch");
         const int ntx = (s->nx + 63) / 64, nty = (s->ny + ty - 1) / ty;
         for (int t = 0; t < ntx * nty; ++t) tiles.push_back(vlb::Item{r, t % ntx, t / ntx, 0});
         for (const vlb::FillItem& fi : s->fill_items)

@@ -200,3 +200,28 @@ def test_params_from_groups(vlb):
         kw.update(bad)
         with pytest.raises(VlbError):
             params_from_groups(**kw)
+
+
+def test_batch_rejects_a_member_listed_twice(vlb):
+    """A simulation listed twice would be advanced twice per batch step (its buffer
+    parity flipped twice), so the batch refuses it; the list check is host-only."""
+    lib, L, st, h = _lib_and_sim(vlb, nx=40, ny=20)
+    assert st == L.VLB_OK
+    lib2, _, st2, h2 = _lib_and_sim(vlb, nx=32, ny=16)
+    assert st2 == L.VLB_OK
+    try:
+        n = C.c_size_t()
+        ok = (C.c_void_p * 2)(h, h2)
+        assert lib.vlb_batch_workspace_bytes(ok, 2, 4, C.byref(n)) == L.VLB_OK
+        assert n.value > 0
+        dup = (C.c_void_p * 3)(h, h2, h)
+        assert lib.vlb_batch_workspace_bytes(dup, 3, 4, C.byref(n)) == L.VLB_E_INVALID_ARG
+        assert b"twice" in lib.vlb_last_error_detail()
+        out = C.c_void_p()
+        assert lib.vlb_batch_create(dup, 3, 4, C.c_void_p(256), 1 << 30, C.byref(out)) \
+            == L.VLB_E_INVALID_ARG
+        assert not out.value
+    finally:
+        lib.vlb_destroy(h)
+        lib.vlb_destroy(h2)
+
