@@ -213,6 +213,40 @@ def test_checkpoint_resume_bit_exact():
         assert np.array_equal(ga[k], gb[k]), k
 
 
+def test_load_state_refuses_another_precision_or_boundary_kind():
+    """A saved state loads only into a simulation of the same grid, storage precision and
+    boundary kinds: an FP64 state of the same shape is not reinterpreted as floats."""
+    import torch
+    from paper_2508_16997_amd import Simulation, VlbError
+    from paper_2508_16997_amd import _lib as L
+
+    pr = synth.random_periodic(64, 32, seed=3, ymode="wall")
+    say("load_state header checks")
+    a64 = Simulation.from_problem(pr, precision="fp64")
+    a64.step(3)
+    s64 = a64.save_state()
+    a32 = Simulation.from_problem(pr, precision="fp32")
+    a32.step(2)
+    ref = gpu_fields(a32)
+    big = torch.zeros(max(s64.numel(), a32.state_bytes()), dtype=torch.uint8, device=s64.device)
+    big[:s64.numel()] = s64
+    with pytest.raises(VlbError) as e:
+        a32.load_state(big)
+    assert e.value.status == L.VLB_E_INVALID_ARG
+    per = Simulation.from_problem(synth.random_periodic(64, 32, seed=3), precision="fp32")
+    per.step(1)
+    with pytest.raises(VlbError) as e:
+        a32.load_state(per.save_state())
+    assert e.value.status == L.VLB_E_INVALID_ARG
+    # the refused loads left the simulation untouched
+    assert a32.time == 2
+    g = gpu_fields(a32)
+    for k in FIELDS:
+        assert np.array_equal(g[k], ref[k]), k
+    a32.load_state(a32.save_state())
+    assert a32.time == 2
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_shifted_wall_channel_parity(precision, tol):
     """Channel between two circles of radius 1e6 (flat walls at fractions 0.3 and 0.7,
