@@ -28,6 +28,9 @@ MODES = {"periodic": 0, "wall": 1, "open": 2, "wet": 3}
 MODELS = {"oldroyd_b": 0, "giesekus": 1, "lptt": 2, "eptt": 3, "fene_p": 4}
 FLAG_NO_SOURCE = 1
 FLAG_NO_GTILDE = 2  # planted mistake for sensitivity checks: drop G~_i
+# alternative readings of the CNEBB scheme (Sec. 3.3), for sensitivity measurements only:
+FLAG_CNEBB_UB_ZERO = 4  # zero wall velocity in the CNEBB equilibrium (reading A11's alternative)
+FLAG_CNEBB_PAIR_NEQ = 8  # both-unknown pairs keep a non-equilibrium part (A12's alternative)
 
 
 def build(force: bool = True) -> str:

@@ -330,7 +330,13 @@ enum { MODE_PERIODIC = 0, MODE_WALL = 1, MODE_OPEN = 2, MODE_WET = 3 };
 enum { SRC_FLUID = 0, SRC_SOLID = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
 // FLAG_NO_GTILDE drops the auxiliary term G~_i of the convection-diffusion collision: a
 // planted mistake for the sensitivity checks of the tests, never the method.
-enum { FLAG_NO_SOURCE = 1, FLAG_NO_GTILDE = 2 };
+// FLAG_CNEBB_UB_ZERO and FLAG_CNEBB_PAIR_NEQ are the alternative readings of two points
+// the boundary scheme of Sec. 3.3 leaves open, kept only to measure how much the result
+// depends on them: the velocity in the CNEBB equilibrium taken as the wall's (zero)
+// instead of the boundary node's (reading A11), and an unknown population whose opposite
+// is unknown too rebuilt with the non-equilibrium part of the population that left in
+// its own direction instead of the equilibrium alone (reading A12).
+enum { FLAG_NO_SOURCE = 1, FLAG_NO_GTILDE = 2, FLAG_CNEBB_UB_ZERO = 4, FLAG_CNEBB_PAIR_NEQ = 8 };
 
 struct Src {
     int kind;
@@ -677,6 +683,7 @@ struct Sim {
             R ubx = (jx + R(0.5) * Fx[n]) / r;
             R uby = (jy + R(0.5) * Fy[n]) / r;
             if (geo.wet_row(y)) ubx = uby = R(0.0);  // wall node: the wall velocity
+            if (flags & FLAG_CNEBB_UB_ZERO) ubx = uby = R(0.0);
             for (int k = 0; k < 3; ++k) {
                 // phi(x_b, t+1): known post-streaming populations plus the post-collision
                 // populations that moved toward the solid.
@@ -687,7 +694,9 @@ struct Sim {
                 for (int i = 1; i < Q; ++i) {
                     if (!unknown[i]) continue;
                     const int o = OPP[i];
-                    if (!unknown[o])
+                    // (known[o] of an unknown o holds the post-collision population that
+                    // left toward the solid in direction i: the alternative reading A12)
+                    if (!unknown[o] || (flags & FLAG_CNEBB_PAIR_NEQ))
                         g[k][i][n] = geq(i, phib, ubx, uby) + (known[o] - geq(o, phib, ubx, uby));
                     else
                         g[k][i][n] = geq(i, phib, ubx, uby);

@@ -363,6 +363,97 @@ def test_open_channel_poiseuille_second_order(oracle_lib):
     assert err[32] < 6e-3 and err[16] / err[32] > 3.5, err
 
 
+def _open_channel_oldroyd_b(oracle_lib, ny, steps):
+    """Oldroyd-B channel 3*ny x ny between half-way walls at Wi = 1, beta = 0.5, Ma = 0.01
+    (the Sec. 4.2 groups), driven only through its open ends: the inlet carries the
+    parabolic velocity and the conformation of the steady channel solution, the outlet
+    is the zero-gradient column.  Starts from that solution everywhere."""
+    base = synth.poiseuille(nx=3 * ny, ny=ny, Wi=1.0, Ma=0.01)
+    lam, Uc = base.lam, base.meta["Uc"]
+    yp = np.arange(ny) + 0.5
+    ux = 4 * Uc * yp * (ny - yp) / ny ** 2
+    du = 4 * Uc * (ny - 2 * yp) / ny ** 2
+    axy, axx = lam * du, 1 + 2 * (lam * du) ** 2
+    pr = base.with_(xmode="open", Fx=0.0, name="open_oldroyd_b",
+                    inlet=dict(ux=ux, axx=axx, axy=axy, ayy=np.ones(ny)))
+    full = lambda v: np.ascontiguousarray(np.broadcast_to(v[:, None], (ny, pr.nx)))
+    pr.init = dict(ux=full(ux), axx=full(axx), axy=full(axy))
+    o = oracle_lib.OracleSim(pr)
+    o.step(steps)
+    return pr, o.read(), dict(ux=ux, axy=axy, axx=axx)
+
+
+def test_open_channel_oldroyd_b_conformation_at_every_column(oracle_lib):
+    """The open ends carry the conformation of the channel solution (Sec. 4.3 set-up;
+    reading A21 with the inlet profile of reading A19): in an Oldroyd-B channel driven
+    only through its inlet and outlet, every column -- the first and the last included --
+    holds the steady closed form A_xy = lambda u', A_xx = 1 + 2 (lambda u')^2, A_yy = 1
+    within the discretisation error of the same channel with periodic ends (the same
+    walls, the same H).
+
+    Catches an inlet conformation ghost extrapolated around A = I instead of the
+    prescribed profile (first column off by about 85 %), an outlet ghost set to the rest
+    equilibrium instead of the zero-gradient copy (last column off by about 90 %), and a
+    velocity profile that does not carry through the inlet.
+    """
+    oracle_lib.set_threads(min(8, oracle_lib.max_threads()))
+    ny = 16
+    pr, r, ex = _open_channel_oldroyd_b(oracle_lib, ny, 30000)
+    # the periodic channel with the same groups, to its steady state: the error budget
+    per = synth.poiseuille(nx=2, ny=ny, Wi=1.0, Ma=0.01)
+    op = oracle_lib.OracleSim(per)
+    op.step(int(round(18 * per.meta["Tc"])))
+    rp = op.read()
+    bud_xy = np.abs(rp["axy"][:, 0] - ex["axy"]).max() / np.abs(ex["axy"]).max()
+    bud_xx = np.abs(rp["axx"][:, 0] - ex["axx"]).max() / np.abs(ex["axx"] - 1).max()
+    assert 1e-3 < bud_xy < 5e-2 and 1e-3 < bud_xx < 5e-2, (bud_xy, bud_xx)
+    e_xy = np.abs(r["axy"] - ex["axy"][:, None]).max(axis=0) / np.abs(ex["axy"]).max()
+    e_xx = np.abs(r["axx"] - ex["axx"][:, None]).max(axis=0) / np.abs(ex["axx"] - 1).max()
+    e_u = np.abs(r["ux"] - ex["ux"][:, None]).max(axis=0) / pr.meta["Uc"]
+    for c in (0, 1, pr.nx // 2, pr.nx - 2, pr.nx - 1):
+        assert e_xy[c] < 1.25 * bud_xy, (c, e_xy[c], bud_xy)
+        assert e_xx[c] < 1.25 * bud_xx, (c, e_xx[c], bud_xx)
+    assert e_xy.max() < 1.25 * bud_xy and e_xx.max() < 1.25 * bud_xx
+    assert e_u.max() < 1e-2, e_u.max()
+    assert np.abs(r["ayy"] - 1).max() < 1e-3 * np.abs(ex["axx"] - 1).max()
+
+
+@pytest.mark.parametrize("walls", ["y", "x"])
+def test_hydrostatic_channel_keeps_the_conformation_at_rest(oracle_lib, walls):
+    """A body force normal to half-way walls settles into hydrostatic equilibrium: the
+    velocity with the half-force shift (Sec. 3.1) is zero to round-off, the pressure
+    gradient balances the force density, c_s^2 d rho / dn = F, and the conformation stays
+    A = I: the only residue is the (tau_p1 - 1/2) F phi / rho first moment that G~_i
+    leaves in a forced fluid at rest, here lambda (tau_p1 - 1/2) |F| = 6e-9.
+
+    Catches a CNEBB equilibrium taken at the unshifted velocity j / rho (Sec. 3.3 uses the
+    fluid velocity, which in a forced fluid includes F / 2): the wall nodes then see a
+    spurious normal velocity -F / (2 rho), and the conformation near the walls moves off
+    I by 1e-5 here.
+    """
+    F, lam, kappa = 1e-4, 20.0, 1e-6
+    tp = 3 * kappa  # tau_p1 - 1/2
+    if walls == "y":
+        pr = synth.random_periodic(4, 16, seed=0, amp_u=0, amp_rho=0, amp_a=0, ymode="wall",
+                                   nu_s=0.5, eta_p=0.1, lam=lam, kappa=kappa, Lambda_p=1e-6,
+                                   force_amp=0.0)
+        pr.Fx, pr.Fy = 0.0, F
+    else:
+        pr = synth.random_periodic(16, 4, seed=0, amp_u=0, amp_rho=0, amp_a=0, xmode="wall",
+                                   nu_s=0.5, eta_p=0.1, lam=lam, kappa=kappa, Lambda_p=1e-6,
+                                   force_amp=0.0)
+        pr.Fx, pr.Fy = F, 0.0
+    o = oracle_lib.OracleSim(pr)
+    o.step(3000)
+    r = o.read()
+    assert np.abs(r["ux"]).max() < 1e-13 and np.abs(r["uy"]).max() < 1e-13
+    rho = r["rho"][:, 0] if walls == "y" else r["rho"][0, :]
+    assert np.abs(np.diff(rho) / (F / CS2) - 1).max() < 1e-6, np.diff(rho)
+    bound = 10 * lam * tp * F
+    for c, one in (("axx", 1.0), ("axy", 0.0), ("ayy", 1.0)):
+        assert np.abs(r[c] - one).max() < bound, (c, np.abs(r[c] - one).max(), bound)
+
+
 @pytest.mark.parametrize("case", [dict(xmode="periodic", ymode="wall"),
                                   dict(xmode="periodic", ymode="periodic")])
 def test_hydro_mass_is_exact(oracle_lib, case):
