@@ -312,6 +312,19 @@ typedef struct vlb_batch vlb_batch;
 int vlb_batch_workspace_bytes(vlb_sim* const* sims, int n, int ty, size_t* bytes);
 int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* workspace_dev, size_t bytes,
                      vlb_batch** out);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it): vlb_batch_create without a workspace.  The
+ * batch's work lists, member descriptors and persistent-form counters go into a static
+ * scratch array of 16 MiB that the library holds on each device for the life of the
+ * process (the batched 256-run workload needs about 2 MB at ty = 4, 6 MB at ty = 1).
+ * The call allocates nothing; the members' device must be current.  One such batch per
+ * device at a time: while it lives, a second call on that device fails with VLB_E_STATE
+ * (vlb_batch_destroy releases the scratch; the contents are rewritten by the next
+ * create).  Batches from vlb_batch_create are unaffected and may coexist with it.
+ * Everything else -- members, results, stepping, graphs, the persistent form -- is as
+ * for vlb_batch_create, bit for bit.  Errors: those of vlb_batch_create, and
+ * VLB_E_WORKSPACE when the lists exceed the scratch (checked before any device work). */
+int vlb_batch_create_noalloc(vlb_sim* const* sims, int n, int ty, vlb_batch** out);
 /* Advances every member nsteps steps (async on the shared stream). */
 int vlb_batch_step(vlb_batch* batch, int64_t nsteps);
 /* vlb_read_fields of member `run` (0-based, in creation order). */

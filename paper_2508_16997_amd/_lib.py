@@ -33,7 +33,7 @@ EXPORTS = [
     "vlb_state_bytes", "vlb_save_state", "vlb_load_state", "vlb_set_tile",
     "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_adjoint_workspace_bytes",
     "vlb_adjoint_forward", "vlb_adjoint_backward", "vlb_adjoint", "vlb_batch_workspace_bytes",
-    "vlb_batch_create", "vlb_batch_step", "vlb_batch_read_fields", "vlb_batch_set_graph_chunk",
+    "vlb_batch_create", "vlb_batch_create_noalloc", "vlb_batch_step", "vlb_batch_read_fields", "vlb_batch_set_graph_chunk",
     "vlb_batch_set_persistent",
     "vlb_batch_destroy", "vlb_params_from_groups",
     "vlb_error_string", "vlb_last_error_detail",
@@ -111,6 +111,7 @@ def load():
     lib.vlb_adjoint.argtypes = [P, C.c_int64, I, P, P, D, D, D, P, P, P, C.c_size_t]
     lib.vlb_batch_workspace_bytes.argtypes = [P, I, I, C.POINTER(C.c_size_t)]
     lib.vlb_batch_create.argtypes = [P, I, I, P, C.c_size_t, C.POINTER(P)]
+    lib.vlb_batch_create_noalloc.argtypes = [P, I, I, C.POINTER(P)]
     lib.vlb_batch_step.argtypes = [P, C.c_int64]
     lib.vlb_batch_set_graph_chunk.argtypes = [P, I]
     lib.vlb_batch_set_persistent.argtypes = [P, I]

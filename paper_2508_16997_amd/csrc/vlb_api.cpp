@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -136,6 +138,7 @@ struct vlb_batch {
     int64_t step = 0;  // step count of every member, as advanced by the batch
     std::vector<uint64_t> versions;  // member descriptor versions last copied
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int scratch_dev = -1;  // >= 0: lists live in that device's static scratch (noalloc form)
 };
 
 namespace {
@@ -1271,7 +1274,8 @@ int batch_upload(vlb_batch* b) {
     }
     VLB_HIP(hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(vlb::Item),
                            hipMemcpyHostToDevice, b->stream));
-    VLB_HIP(hipMemsetAsync(b->ws + b->off_queues, 0, 2 * vlb::kBatchQueues * sizeof(int), b->stream));
+    VLB_HIP(vlb::launch_fill_bytes(b->ws + b->off_queues, 2 * vlb::kBatchQueues * sizeof(int), 0,
+                                   b->stream));
     if (!b->fill_items.empty())
         VLB_HIP(hipMemcpyAsync(b->ws + b->off_fill_items, b->fill_items.data(),
                                b->fill_items.size() * sizeof(vlb::FillItem), hipMemcpyHostToDevice,
@@ -1383,6 +1387,44 @@ int batch_step(vlb_batch* b, int64_t n) {
 
 }  // namespace
 
+// Static scratch of vlb_batch_create_noalloc: the work lists, member descriptors and
+// persistent-form counters of one batch per device, in a file-scope device array that
+// each device holds for the life of the process.  Host code never uses the array's name
+// as an address (it is a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kBatchScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+namespace {
+
+struct ScratchSlot {
+    void* ptr = nullptr;  // device address of `scratch` on this device
+    bool busy = false;    // a live noalloc batch holds it
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchSlot> g_scratch;
+
+// Member checks shared by both batch constructors.
+int batch_check_members(const vlb_batch* b, vlb_sim* const* sims) {
+    for (vlb_sim* s : b->sims) {
+        int rc = check_ready(s);
+        if (rc) return rc;
+        if (s->stream != sims[0]->stream) return fail(VLB_E_INVALID_ARG, "batch members must share one stream");
+        if (s->step != sims[0]->step || s->parity != sims[0]->parity || s->first != sims[0]->first)
+            return fail(VLB_E_STATE, "batch members must be at the same step");
+    }
+    return VLB_OK;
+}
+
+void batch_release_scratch(vlb_batch* b) {
+    if (b->scratch_dev < 0) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    g_scratch[b->scratch_dev].busy = false;
+    b->scratch_dev = -1;
+}
+
+}  // namespace
+
 extern "C" {
 
 int vlb_batch_workspace_bytes(vlb_sim* const* sims, int n, int ty, size_t* bytes) {
@@ -1401,15 +1443,8 @@ int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* ws, size_t bytes
     if (!b) return fail(VLB_E_INVALID_ARG, "out of host memory");
     int rc = batch_lists(b, sims, n, ty);
     if (rc) { delete b; return rc; }
-    for (vlb_sim* s : b->sims) {
-        rc = check_ready(s);
-        if (rc) { delete b; return rc; }
-        if (s->stream != sims[0]->stream) { delete b; return fail(VLB_E_INVALID_ARG, "batch members must share one stream"); }
-        if (s->step != sims[0]->step || s->parity != sims[0]->parity || s->first != sims[0]->first) {
-            delete b;
-            return fail(VLB_E_STATE, "batch members must be at the same step");
-        }
-    }
+    rc = batch_check_members(b, sims);
+    if (rc) { delete b; return rc; }
     if (!ws || ((uintptr_t)ws & 255u) || bytes < b->total) {
         delete b;
         return fail(VLB_E_WORKSPACE, "batch workspace missing, misaligned or smaller than " +
@@ -1421,6 +1456,55 @@ int vlb_batch_create(vlb_sim* const* sims, int n, int ty, void* ws, size_t bytes
     b->step = sims[0]->step;
     rc = b->prec == VLB_FP32 ? batch_upload<float>(b) : batch_upload<double>(b);
     if (rc) { delete b; return rc; }
+    *out = b;
+    return VLB_OK;
+}
+
+int vlb_batch_create_noalloc(vlb_sim* const* sims, int n, int ty, vlb_batch** out) {
+    if (!out) return fail(VLB_E_INVALID_ARG, "null output");
+    *out = nullptr;
+    vlb_batch* b = new (std::nothrow) vlb_batch();
+    if (!b) return fail(VLB_E_INVALID_ARG, "out of host memory");
+    int rc = batch_lists(b, sims, n, ty);
+    if (rc) { delete b; return rc; }
+    if (b->total > kBatchScratchBytes) {
+        const size_t need = b->total;
+        delete b;
+        return fail(VLB_E_WORKSPACE, "batch lists need " + std::to_string(need) +
+                                         " bytes; the static scratch holds " +
+                                         std::to_string(kBatchScratchBytes));
+    }
+    rc = batch_check_members(b, sims);
+    if (rc) { delete b; return rc; }
+    int dev = 0;
+    {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) { delete b; return fail(VLB_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ScratchSlot& slot = g_scratch[dev];
+        if (!slot.ptr) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) {
+                delete b;
+                return fail(VLB_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            }
+            slot.ptr = ptr;
+        }
+        if (slot.busy) {
+            delete b;
+            return fail(VLB_E_STATE, "the static batch scratch of this device is held by another "
+                                     "batch (destroy it first)");
+        }
+        slot.busy = true;
+        b->ws = static_cast<char*>(slot.ptr);
+        b->scratch_dev = dev;
+    }
+    b->bytes = kBatchScratchBytes;
+    b->stream = sims[0]->stream;
+    b->step = sims[0]->step;
+    rc = b->prec == VLB_FP32 ? batch_upload<float>(b) : batch_upload<double>(b);
+    if (rc) { batch_release_scratch(b); delete b; return rc; }
     *out = b;
     return VLB_OK;
 }
@@ -1464,6 +1548,7 @@ int vlb_batch_set_graph_chunk(vlb_batch* b, int chunk) {
 void vlb_batch_destroy(vlb_batch* b) {
     if (!b) return;
     batch_drop_graphs(b);
+    batch_release_scratch(b);
     delete b;
 }
 

@@ -312,7 +312,11 @@ class Batch:
     :class:`Simulation` methods.
     """
 
-    def __init__(self, sims, tile: int = 4, graph_chunk: int = 0, persistent: bool = False):
+    def __init__(self, sims, tile: int = 4, graph_chunk: int = 0, persistent: bool = False,
+                 noalloc: bool = False):
+        """``noalloc``: build the batch with vlb_batch_create_noalloc (lists in the
+        library's static per-device scratch, no workspace tensor; one such batch per
+        device at a time)."""
         self.lib = L.load()
         self.sims = list(sims)
         if not self.sims:
@@ -320,16 +324,26 @@ class Batch:
         self.stream = self.sims[0].stream
         self.device = self.sims[0].device
         arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
-        nbytes = C.c_size_t()
-        L.check(self.lib.vlb_batch_workspace_bytes(arr, len(self.sims), int(tile),
-                                                   C.byref(nbytes)), "vlb_batch_workspace_bytes")
-        self.workspace_bytes = int(nbytes.value)
-        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
-        ptr = (self._ws.data_ptr() + 255) // 256 * 256
         h = C.c_void_p()
-        self.sims[0]._order_after_torch()
-        L.check(self.lib.vlb_batch_create(arr, len(self.sims), int(tile), C.c_void_p(ptr),
-                                          self.workspace_bytes, C.byref(h)), "vlb_batch_create")
+        if noalloc:
+            self.workspace_bytes, self._ws = 0, None
+            self.sims[0]._order_after_torch()
+            with torch.cuda.device(self.device):
+                L.check(self.lib.vlb_batch_create_noalloc(arr, len(self.sims), int(tile),
+                                                          C.byref(h)), "vlb_batch_create_noalloc")
+        else:
+            nbytes = C.c_size_t()
+            L.check(self.lib.vlb_batch_workspace_bytes(arr, len(self.sims), int(tile),
+                                                       C.byref(nbytes)),
+                    "vlb_batch_workspace_bytes")
+            self.workspace_bytes = int(nbytes.value)
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                   device=self.device)
+            ptr = (self._ws.data_ptr() + 255) // 256 * 256
+            self.sims[0]._order_after_torch()
+            L.check(self.lib.vlb_batch_create(arr, len(self.sims), int(tile), C.c_void_p(ptr),
+                                              self.workspace_bytes, C.byref(h)),
+                    "vlb_batch_create")
         self._h = h
         if graph_chunk:
             L.check(self.lib.vlb_batch_set_graph_chunk(h, int(graph_chunk)),

@@ -225,3 +225,23 @@ def test_batch_rejects_a_member_listed_twice(vlb):
         lib.vlb_destroy(h)
         lib.vlb_destroy(h2)
 
+
+def test_noalloc_batch_refuses_lists_beyond_its_scratch(vlb):
+    """vlb_batch_create_noalloc checks the size of the work lists against its static
+    scratch (16 MiB) before any device work: three of the largest grids at 64 x 1 tiles
+    need about 25 MB of lists and are refused with VLB_E_WORKSPACE."""
+    made = []
+    try:
+        for _ in range(3):
+            lib, L, st, h = _lib_and_sim(vlb, nx=8064, ny=4093)
+            assert st == L.VLB_OK
+            made.append(h)
+        arr = (C.c_void_p * 3)(*made)
+        out = C.c_void_p()
+        assert lib.vlb_batch_create_noalloc(arr, 3, 1, C.byref(out)) == L.VLB_E_WORKSPACE
+        assert b"static scratch" in lib.vlb_last_error_detail()
+        assert not out.value
+        assert lib.vlb_batch_create_noalloc(arr, 3, 4, None) == L.VLB_E_INVALID_ARG
+    finally:
+        for h in made:
+            lib.vlb_destroy(h)
