@@ -108,14 +108,20 @@ def workload(name):
     return pr, desc
 
 
-def bytes_per_node(pr, esz):
-    """Algorithmic HBM bytes of one coupled node update (one read + one write each)."""
-    b = 2 * 36 * esz + 2 * 5 * esz  # populations and S/u history
-    if not pr.uniform_force():
-        b += 2 * esz  # per-node body force (read only)
-    if pr.ymode in ("wall", "wet") or pr.xmode == "wall" or pr.circles or pr.solid is not None:
-        b += 2  # geometry word (read only)
-    return b
+def bytes_per_node(esz):
+    """Algorithmic HBM bytes of one coupled node update: one read and one write of the 36
+    populations and of the 5 history values (S and u of the previous step), 328 B in
+    FP32 storage and 656 B in FP64."""
+    return 2 * 36 * esz + 2 * 5 * esz
+
+
+def extra_bytes_per_node(pr, esz):
+    """Bytes a node update also reads on some workloads, kept out of the roofline figure:
+    the per-node body force (four-roll mill) and the 2-byte geometry word of walled or
+    obstructed grids."""
+    return {"force": 0 if pr.uniform_force() else 2 * esz,
+            "geometry": 2 if (pr.ymode in ("wall", "wet") or pr.xmode == "wall" or pr.circles
+                              or pr.solid is not None) else 0}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=20):
@@ -139,7 +145,7 @@ def copy_bandwidth(nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / s / 1e9
 
 
-def cylinder_leg(steps, warmup, tile, chunk):
+def cylinder_leg(steps, warmup, tile, chunk, cpu_steps=0):
     """Channel flow past a cylinder, 4096 x 1024, FP32 storage: a working set (1.4 GB)
     far beyond the last-level cache, so its rate is an HBM rate."""
     import torch
@@ -164,16 +170,23 @@ def cylinder_leg(steps, warmup, tile, chunk):
     step_s = ev0.elapsed_time(ev1) / 1e3 / steps
     bad = sim.monitors(raise_on_nonfinite=False)["nonfinite"]
     sim.close()
-    bpn = bytes_per_node(pr, 4)
+    bpn = bytes_per_node(4)
     achieved = bpn * nodes / step_s / 1e9
-    return {"workload": "channel flow past a cylinder 4096x1024, R=128, FP32 storage, Wi=1",
-            "fluid_nodes": nodes, "steps": steps, "MLUPS": round(nodes * steps / wall / 1e6, 2),
-            "us_per_step": round(step_s * 1e6, 3), "bytes_per_node": bpn,
-            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "tile": f"64x{tile}", "nonfinite": int(bad)}
+    out = {"workload": "channel flow past a cylinder 4096x1024, R=128, FP32 storage, Wi=1",
+           "fluid_nodes": nodes, "steps": steps, "MLUPS": round(nodes * steps / wall / 1e6, 2),
+           "us_per_step": round(step_s * 1e6, 3), "bytes_per_node": bpn,
+           "extra_bytes_per_node": extra_bytes_per_node(pr, 4),
+           "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "frac_basis": "328 B per fluid node over the whole step (k_step + k_fill, HIP "
+                         "events on the launch stream); the working set (1.4 GB) is HBM "
+                         "resident, so this is the gating HBM fraction",
+           "tile": f"64x{tile}", "nonfinite": int(bad)}
+    if cpu_steps:
+        out["cpu_baseline"] = cpu_baseline_steps([pr], cpu_steps, "the same 4096x1024 workload")
+    return out
 
 
-def batched_leg(steps, warmup, tile, chunk, forms=(False, True)):
+def batched_leg(steps, warmup, tile, chunk, forms=(False, True), cpu_steps=0):
     """Batched workload (256 uneven runs advanced together) vs the same runs one by one.
 
     The batch is timed in both forms (one step launch and one fill launch per step under
@@ -222,10 +235,10 @@ def batched_leg(steps, warmup, tile, chunk, forms=(False, True)):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     bad = sum(s.monitors(raise_on_nonfinite=False)["nonfinite"] > 0 for s in sims)
-    step_bytes = sum(bytes_per_node(r, 4) * int(r.fluid_mask().sum()) for r in runs)
+    step_bytes = bytes_per_node(4) * nodes
     for s in sims:
         s.close()
-    return {"runs": len(runs), "nodes": nodes, "steps": steps,
+    out = {"runs": len(runs), "nodes": nodes, "steps": steps,
             "batched_MLUPS": round(nodes * steps / t_batch / 1e6, 2),
             "sequential_MLUPS": round(nodes * steps / t_seq / 1e6, 2),
             "batched_vs_sequential": round(t_seq / t_batch, 3),
@@ -236,6 +249,14 @@ def batched_leg(steps, warmup, tile, chunk, forms=(False, True)):
                 "form": "persistent" if other[1] else "per-step launches",
                 "tile": f"64x{other[0]}", "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
             "runs_nonfinite": int(bad)}
+    if cpu_steps:
+        import numpy as np
+
+        pick = sorted(np.random.default_rng(7).choice(len(runs), size=8, replace=False).tolist())
+        out["cpu_baseline"] = cpu_baseline_steps(
+            [runs[i] for i in pick], cpu_steps,
+            f"8 runs of the batched set (indices {pick}, drawn with default_rng(7))")
+    return out
 
 
 def adjoint_leg(steps, stride, tile, chunk):
@@ -312,6 +333,30 @@ def _oracle_rate(pr, seconds, threads):
     return nodes * n / dt / 1e6, n, dt, oracle.max_threads()
 
 
+def cpu_baseline_steps(problems, steps, what):
+    """The FP64 oracle on all host cores (up to 16) for a fixed number of steps of each
+    problem, one after another: the coupled MLUPS of that sample."""
+    import oracle
+
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    oracle.set_threads(max(1, min(cores, 16)))
+    node_steps, dt = 0, 0.0
+    for pr in problems:
+        o = oracle.OracleSim(pr)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt += time.perf_counter() - t0
+        node_steps += int(pr.fluid_mask().sum()) * steps
+        del o
+    return {"value": node_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} coupled FP64 steps of {what}, {dt:.1f} s"}
+
+
 def cpu_baseline(pr, seconds):
     """The FP64 oracle as it stands, on all host cores (up to 16) and on one core."""
     import oracle
@@ -346,6 +391,10 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cylinder-steps", type=int, default=50,
+                    help="oracle steps of the cylinder for its CPU baseline (0: none)")
+    ap.add_argument("--cpu-batched-steps", type=int, default=500,
+                    help="oracle steps of each of 8 sampled batched runs (0: none)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-sequential leg (256 uneven runs)")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -409,10 +458,12 @@ def main():
     copy_gbs = copy_bandwidth()
 
     mlups = nodes * args.steps / wall / 1e6
-    bpn = bytes_per_node(pr, esz)
+    bpn = bytes_per_node(esz)
+    extra = extra_bytes_per_node(pr, esz)
     launch_s = gpu_ms / 1e3 / args.steps
     bytes_launch = bpn * nodes
     achieved = bytes_launch / launch_s / 1e9
+    achieved_all = (bpn + sum(extra.values())) * nodes / launch_s / 1e9
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -429,7 +480,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "storage": "f32" if prec == "fp32" else "f64",
                    "nx": pr.nx, "ny": pr.ny, "fluid_nodes": nodes,
-                   "bytes_per_node": bpn, "tile": f"64x{tile}",
+                   "bytes_per_node": bpn, "extra_bytes_per_node": extra, "tile": f"64x{tile}",
                    "store_mode": store_mode,
                    "tile_choice": "fixed" if args.tile else "autotuned",
                    "graph_chunk_steps": 2 * args.graph_chunk},
@@ -439,16 +490,19 @@ def main():
                      "kernel": "k_step",
                      "avg_launch_us": round(launch_s * 1e6, 3),
                      "bytes_per_launch": bytes_launch,
+                     "achieved_with_extra_reads": round(achieved_all, 1),
                      "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     sim.close()
     if not args.no_cylinder:
-        out["cylinder"] = cylinder_leg(1000, 100, args.tile, args.graph_chunk)
+        out["cylinder"] = cylinder_leg(1000, 100, args.tile, args.graph_chunk,
+                                       0 if args.no_cpu_baseline else args.cpu_cylinder_steps)
     if not args.no_batched:
         forms = {"both": (False, True), "per-step": (False,), "persistent": (True,)}
         out["batched"] = batched_leg(args.batched_steps, 2 * args.graph_chunk + 1, args.tile,
-                                     args.graph_chunk, forms[args.batched_form])
+                                     args.graph_chunk, forms[args.batched_form],
+                                     0 if args.no_cpu_baseline else args.cpu_batched_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_stride, tile,
                                      args.graph_chunk)
