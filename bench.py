@@ -80,6 +80,8 @@ def autotuned_tile(sim):
     with tempfile.TemporaryDirectory() as d:
         rec = tune(sim, cache=os.path.join(d, "autotune.json"), force=True)
     sim.store_mode_name = "cached" if rec["store_mode"] == 1 else "streaming"
+    sim.schedule_desc = {"tile_order": "xcd bands" if rec["tile_order"] == 1 else "row-major",
+                         "waves_per_simd": rec["waves"] or 3}
     return int(rec["tile"])
 
 
@@ -180,7 +182,7 @@ def cylinder_leg(steps, warmup, tile, chunk, cpu_steps=0):
            "frac_basis": "328 B per fluid node over the whole step (k_step + k_fill, HIP "
                          "events on the launch stream); the working set (1.4 GB) is HBM "
                          "resident, so this is the gating HBM fraction",
-           "tile": f"64x{tile}", "nonfinite": int(bad)}
+           "tile": f"64x{tile}", **getattr(sim, "schedule_desc", {}), "nonfinite": int(bad)}
     if cpu_steps:
         out["cpu_baseline"] = cpu_baseline_steps([pr], cpu_steps, "the same 4096x1024 workload")
     return out
@@ -208,11 +210,13 @@ def batched_leg(steps, warmup, tile, chunk, forms=(False, True), cpu_steps=0):
 
     # both batched forms, each at its fastest tile (or the tile given); the faster one
     # is the batched figure, the other is reported beside it
-    (tile, pers), tuned = tune_batch(sims, tiles=(tile,) if tile else (2, 4, 8),
-                                     graph_chunk=chunk, forms=tuple(forms))
+    best, tuned = tune_batch(sims, tiles=(tile,) if tile else (2, 4, 8), graph_chunk=chunk,
+                             forms=tuple(forms))
+    tile, pers = best[0], best[1]
 
-    def timed_batch(ty, persistent):
-        b = Batch(sims, tile=ty, graph_chunk=0 if persistent else chunk, persistent=persistent)
+    def timed_batch(ty, persistent, order, waves):
+        b = Batch(sims, tile=ty, graph_chunk=0 if persistent else chunk, persistent=persistent,
+                  schedule=(order, waves))
         b.step(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -222,7 +226,7 @@ def batched_leg(steps, warmup, tile, chunk, forms=(False, True), cpu_steps=0):
         b.close()
         return t
 
-    t_batch = timed_batch(tile, pers)
+    t_batch = timed_batch(*best)
     others = [k for k in tuned if k[1] != pers]
     other = min(others, key=tuned.get) if others else None
     t_other = timed_batch(*other) if other else None
@@ -245,9 +249,12 @@ def batched_leg(steps, warmup, tile, chunk, forms=(False, True), cpu_steps=0):
             "batched_GBs": round(step_bytes * steps / t_batch / 1e9, 1),
             "batched_frac": round(step_bytes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
             "tile": f"64x{tile}", "form": "persistent" if pers else "per-step launches",
+            "tile_order": "xcd bands" if best[2] == 1 else "row-major",
+            "waves_per_simd": best[3] or 3,
             "other_form": None if other is None else {
                 "form": "persistent" if other[1] else "per-step launches",
-                "tile": f"64x{other[0]}", "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
+                "tile": f"64x{other[0]}", "tile_order": "xcd bands" if other[2] == 1 else "row-major",
+                "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
             "runs_nonfinite": int(bad)}
     if cpu_steps:
         import numpy as np
@@ -483,6 +490,7 @@ def main():
                    "bytes_per_node": bpn, "extra_bytes_per_node": extra, "tile": f"64x{tile}",
                    "store_mode": store_mode,
                    "tile_choice": "fixed" if args.tile else "autotuned",
+                   **getattr(sim, "schedule_desc", {}),
                    "graph_chunk_steps": 2 * args.graph_chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -255,6 +255,16 @@ int vlb_set_tile(vlb_sim* sim, int ty);
 int vlb_set_store_mode(vlb_sim* sim, int mode);
 /* Use hipGraph replay for runs of nsteps >= 2 * chunk (chunk 0 disables graphs). */
 int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
+/* Launch schedule of the step kernel; results are bit-identical for every choice.
+ * tile_order: 1 = XCD bands (consecutive workgroups go round-robin to the 8 XCDs and each
+ * XCD sweeps one contiguous band of tiles, sharing its halo rows in that XCD's L2),
+ * 2 = row-major (the whole chip sweeps the grid together), 0 = automatic (bands while
+ * the two population buffers fit the last-level cache, row-major beyond).
+ * waves: register budget of the single-precision step kernel, 3 or 4 waves per SIMD
+ * (4 spills a few values to scratch), 0 = automatic (4 for a cache-resident state, 3
+ * beyond); double precision always runs at its natural allocation.
+ * Errors: VLB_E_INVALID_ARG for other values. */
+int vlb_set_schedule(vlb_sim* sim, int tile_order, int waves);
 
 /* ---- adjoint ------------------------------------------------------------------------ */
 
@@ -332,6 +342,10 @@ int vlb_batch_read_fields(vlb_batch* batch, int run, void* rho, void* ux, void* 
                           void* axy, void* ayy);
 /* hipGraph replay in chunks of 2 * chunk steps (0 disables). */
 int vlb_batch_set_graph_chunk(vlb_batch* batch, int chunk);
+/* vlb_set_schedule for the batch's launches (the members' own settings are not used;
+ * automatic by the size of all members' state together).  The persistent form follows
+ * the tile order and always runs three waves per SIMD.  Synchronizes the stream. */
+int vlb_batch_set_schedule(vlb_batch* batch, int tile_order, int waves);
 /* on = 1: persistent form -- one cooperative launch advances every member up to 256
  * steps (all tiles of a step, a grid-wide barrier, all boundary fills, a barrier, next
  * step).  The grid is as many workgroups as stay resident together; they draw tiles

@@ -31,10 +31,10 @@ EXPORTS = [
     "vlb_step", "vlb_get_step", "vlb_read_fields", "vlb_read_history", "vlb_monitors",
     "vlb_drag",
     "vlb_state_bytes", "vlb_save_state", "vlb_load_state", "vlb_set_tile",
-    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_adjoint_workspace_bytes",
+    "vlb_set_store_mode", "vlb_set_graph_chunk", "vlb_set_schedule", "vlb_adjoint_workspace_bytes",
     "vlb_adjoint_forward", "vlb_adjoint_backward", "vlb_adjoint", "vlb_batch_workspace_bytes",
     "vlb_batch_create", "vlb_batch_create_noalloc", "vlb_batch_step", "vlb_batch_read_fields", "vlb_batch_set_graph_chunk",
-    "vlb_batch_set_persistent",
+    "vlb_batch_set_persistent", "vlb_batch_set_schedule",
     "vlb_batch_destroy", "vlb_params_from_groups",
     "vlb_error_string", "vlb_last_error_detail",
 ]
@@ -103,6 +103,7 @@ def load():
     lib.vlb_set_tile.argtypes = [P, I]
     lib.vlb_set_graph_chunk.argtypes = [P, I]
     lib.vlb_set_store_mode.argtypes = [P, I]
+    lib.vlb_set_schedule.argtypes = [P, I, I]
     lib.vlb_drag.argtypes = [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     D = C.POINTER(C.c_double)
     lib.vlb_adjoint_workspace_bytes.argtypes = [P, C.c_int64, I, C.POINTER(C.c_size_t)]
@@ -115,6 +116,7 @@ def load():
     lib.vlb_batch_step.argtypes = [P, C.c_int64]
     lib.vlb_batch_set_graph_chunk.argtypes = [P, I]
     lib.vlb_batch_set_persistent.argtypes = [P, I]
+    lib.vlb_batch_set_schedule.argtypes = [P, I, I]
     lib.vlb_batch_read_fields.argtypes = [P, I, P, P, P, P, P, P]
     Dd = C.c_double
     lib.vlb_params_from_groups.argtypes = [Dd, Dd, Dd, Dd, Dd, Dd, Dd, Dd,

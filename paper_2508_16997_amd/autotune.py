@@ -1,11 +1,13 @@
 """Launch-shape autotuner for the step kernel.
 
-For a simulation it times every tile height (64 x TY threads, TY in 1, 2, 4, 8) and both
-store modes (cached, non-temporal) with HIP events on the simulation's stream, keeps the
-fastest, and caches the choice per size class in a JSON file (``VLB_AUTOTUNE_CACHE`` or
+For a simulation it times every tile height (64 x TY threads, TY in 1, 2, 4, 8), both
+store modes (cached, non-temporal), both tile orders (XCD bands, row-major) and, for
+single-precision storage, both register budgets of the step kernel (three or four
+waves per SIMD) with HIP events on the simulation's stream, keeps the fastest, and
+caches the choice per size class in a JSON file (``VLB_AUTOTUNE_CACHE`` or
 ``~/.cache/paper_2508_16997_amd/autotune.json``).  The simulation's state is saved
-before and restored after the sweep, so tuning does not advance it.  The register
-budget (waves per SIMD) is a compile-time choice of the library and is not swept here.
+before and restored after the sweep, so tuning does not advance it.  Results do not
+depend on any of these choices (bit-identical by test).
 """
 from __future__ import annotations
 
@@ -17,6 +19,13 @@ import torch
 
 TILES = (1, 2, 4, 8)
 STORE_MODES = {1: "cached", 2: "streaming"}
+ORDERS = {1: "xcd", 2: "rows"}
+CACHE_VERSION = "v2"  # records of an earlier search space are not reused
+
+
+def waves_for(precision) -> tuple:
+    """Register budgets worth sweeping: FP32 storage has two, FP64 one."""
+    return (3, 4) if precision == "fp32" else (0,)
 
 
 def cache_path() -> str:
@@ -29,7 +38,7 @@ def cache_path() -> str:
 def size_class(sim) -> str:
     """Key of the cache: precision, grid, boundary kinds, solids."""
     solid = "solid" if (sim._mask is not None and sim._mask.any()) or sim._circ.size else "open"
-    return f"{sim.precision}:{sim.nx}x{sim.ny}:{sim.xmode}/{sim.ymode}:{solid}"
+    return f"{CACHE_VERSION}:{sim.precision}:{sim.nx}x{sim.ny}:{sim.xmode}/{sim.ymode}:{solid}"
 
 
 def _load(path):
@@ -61,7 +70,8 @@ def time_step(sim, steps: int) -> float:
 
 def tune(sim, steps: int = 60, warmup: int = 10, cache: Optional[str] = None,
          force: bool = False) -> dict:
-    """Pick and apply the fastest (tile, store mode) for ``sim``; returns the record."""
+    """Pick and apply the fastest (tile, store mode, tile order, waves) for ``sim``;
+    returns the record."""
     path = cache or cache_path()
     data = _load(path)
     key = size_class(sim)
@@ -69,22 +79,29 @@ def tune(sim, steps: int = 60, warmup: int = 10, cache: Optional[str] = None,
         rec = data[key]
         sim.set_tile(rec["tile"])
         sim.set_store_mode(rec["store_mode"])
+        sim.set_schedule(rec["tile_order"], rec["waves"])
         return rec
     state = sim.save_state()
     timings = {}
     for ty in TILES:
         for mode in STORE_MODES:
-            sim.load_state(state)
-            sim.set_tile(ty)
-            sim.set_store_mode(mode)
-            sim.step(warmup)
-            timings[(ty, mode)] = time_step(sim, steps)
-    (ty, mode), best = min(timings.items(), key=lambda kv: kv[1])
+            for order in ORDERS:
+                for waves in waves_for(sim.precision):
+                    sim.load_state(state)
+                    sim.set_tile(ty)
+                    sim.set_store_mode(mode)
+                    sim.set_schedule(order, waves)
+                    sim.step(warmup)
+                    timings[(ty, mode, order, waves)] = time_step(sim, steps)
+    (ty, mode, order, waves), best = min(timings.items(), key=lambda kv: kv[1])
     sim.load_state(state)
     sim.set_tile(ty)
     sim.set_store_mode(mode)
-    rec = {"tile": ty, "store_mode": mode, "us_per_step": round(best * 1e6, 3),
-           "sweep_us": {f"{t}/{STORE_MODES[m]}": round(v * 1e6, 3) for (t, m), v in timings.items()}}
+    sim.set_schedule(order, waves)
+    rec = {"tile": ty, "store_mode": mode, "tile_order": order, "waves": waves,
+           "us_per_step": round(best * 1e6, 3),
+           "sweep_us": {f"{t}/{STORE_MODES[m]}/{ORDERS[o]}/w{w}": round(v * 1e6, 3)
+                        for (t, m, o, w), v in timings.items()}}
     data[key] = rec
     _store(path, data)
     return rec
@@ -92,26 +109,29 @@ def tune(sim, steps: int = 60, warmup: int = 10, cache: Optional[str] = None,
 
 def tune_batch(sims, tiles=TILES, steps: int = 20, warmup: int = 5, graph_chunk: int = 0,
                forms=(False,)):
-    """Time one batch per (tile height, form) over the same members and return
-    (fastest (tile, persistent), {(tile, persistent): seconds per step}).  ``forms``
-    lists the forms to try: False = one step launch and one fill launch per step
-    (hipGraph replay when graph_chunk > 0), True = the persistent cooperative launch.
-    The members advance by len(tiles) * len(forms) * (warmup + steps) steps; results do
-    not depend on the choice."""
+    """Time one batch per (tile height, form, tile order, waves) over the same members and
+    return (fastest (tile, persistent, order, waves), {that key: seconds per step}).
+    ``forms`` lists the forms to try: False = one step launch and one fill launch per step
+    (hipGraph replay when graph_chunk > 0), True = the persistent cooperative launch
+    (its register budget is fixed, so waves is not swept for it).  The members advance by
+    warmup + steps steps per configuration; results do not depend on the choice."""
     from .sim import Batch
 
     timings = {}
     for ty in tiles:
         for pers in forms:
-            b = Batch(sims, tile=ty, graph_chunk=0 if pers else graph_chunk, persistent=pers)
-            b.step(warmup)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(b.stream)
-            b.step(steps)
-            e1.record(b.stream)
-            e1.synchronize()
-            timings[(ty, bool(pers))] = e0.elapsed_time(e1) / 1e3 / steps
-            b.close()
+            for order in ORDERS:
+                for waves in ((0,) if pers else waves_for(sims[0].precision)):
+                    b = Batch(sims, tile=ty, graph_chunk=0 if pers else graph_chunk,
+                              persistent=pers, schedule=(order, waves))
+                    b.step(warmup)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(b.stream)
+                    b.step(steps)
+                    e1.record(b.stream)
+                    e1.synchronize()
+                    timings[(ty, bool(pers), order, waves)] = e0.elapsed_time(e1) / 1e3 / steps
+                    b.close()
     best = min(timings, key=timings.get)
     return best, timings

@@ -208,16 +208,9 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
     S f[9], g[3][9];
     T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
     if (in_dom) {
-        pull9(R, src, 0, p, pull, f);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pull9(R, src, 1 + k, p, pull, g[k]);
+        pull36(R, src, p, pull, f, g);
         node_force(R, p, Fx, Fy);
-        if (pull) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) hS[k] = ldu(R.hist + k * plane, (unsigned)p);
-            hux = ldu(R.hist + 3 * plane, (unsigned)p);
-            huy = ldu(R.hist + 4 * plane, (unsigned)p);
-        }
+        if (pull) hist_ld(R.hist, plane, (unsigned)p, hS, hux, huy);
     }
     for (int r = tid; r < 128 + 2 * TY; r += 64 * TY) {
         int cx, cy, lcx, lcy;

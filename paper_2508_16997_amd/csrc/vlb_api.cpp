@@ -116,6 +116,8 @@ struct vlb_sim {
     } adj;
     int graph_chunk = 0;
     int store_mode = 0;  // 0 auto (by working-set size), 1 cached stores, 2 streaming stores
+    int sched_order = 0;  // tile order: 0 auto, 1 XCD bands, 2 row-major
+    int sched_waves = 0;  // register budget of the FP32 step kernel: 0 auto, 3 or 4 waves
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 
     template <class T>
@@ -127,6 +129,9 @@ struct vlb_sim {
 struct vlb_batch {
     std::vector<vlb_sim*> sims;
     int prec = 0, ty = 4, streaming = 0;
+    int sched_order = 0, sched_waves = 0;  // as for a simulation
+    bool resident = true;                  // the members' state fits the last-level cache
+    std::vector<vlb::Item> tiles;          // the members' tiles, member by member
     char* ws = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
@@ -335,17 +340,39 @@ void build_fill(vlb_sim* s) {
 // Work items in an XCD-aware order: consecutive workgroups go round-robin to the 8
 // XCDs, so block b is given tile (start of XCD b % 8) + b / 8 and every XCD sweeps a
 // contiguous band of tiles (shared halo rows stay in one L2).
+// Launch order of a tile list.  XCD bands: consecutive workgroups go round-robin to
+// the 8 XCDs, so block b is given tile (start of XCD b % 8) + b / 8 and every XCD sweeps
+// one contiguous band, whose shared halo rows meet in that XCD's L2 -- the better order
+// while the state is cache resident.  Row-major: the tiles in list order, so the whole
+// chip sweeps the grid together and the open DRAM pages are shared by all XCDs -- the
+// better order once the state streams from HBM.
+void order_tiles(const std::vector<vlb::Item>& tiles, bool rowmajor, std::vector<vlb::Item>& out) {
+    const int n = (int)tiles.size(), nxcd = 8;
+    out.resize(n);
+    if (rowmajor) {
+        out = tiles;
+        return;
+    }
+    std::vector<int> start(nxcd + 1, 0);
+    for (int k = 0; k < nxcd; ++k) start[k + 1] = start[k] + n / nxcd + (k < n % nxcd ? 1 : 0);
+    for (int b = 0; b < n; ++b) out[b] = tiles[start[b % nxcd] + b / nxcd];
+}
+
+// The state of both population buffers fits the 256 MB last-level cache.
+bool resident_state(const vlb_sim* s) {
+    return 2.0 * 36.0 * (double)s->nx * (double)s->ny * (double)s->esz <= 192.0 * 1024 * 1024;
+}
+// Schedule in effect: explicit choices, else XCD bands and four waves per SIMD for a
+// cache-resident state, row-major tiles and three waves once it streams from HBM.
+bool rowmajor_tiles(int order, bool resident) { return order == 2 || (order == 0 && !resident); }
+int step_waves(int waves, bool resident) { return waves ? waves : (resident ? 4 : 3); }
+
 void build_items(vlb_sim* s) {
     const int ntx = (s->nx + 63) / 64, nty = (s->ny + s->ty - 1) / s->ty;
     const int n = ntx * nty;
-    s->items.assign(n, vlb::Item{0, 0, 0, 0});
-    const int nxcd = 8;
-    std::vector<int> start(nxcd + 1, 0);
-    for (int k = 0; k < nxcd; ++k) start[k + 1] = start[k] + n / nxcd + (k < n % nxcd ? 1 : 0);
-    for (int b = 0; b < n; ++b) {
-        const int t = start[b % nxcd] + b / nxcd;
-        s->items[b] = vlb::Item{0, t % ntx, t / ntx, 0};
-    }
+    std::vector<vlb::Item> tiles(n);
+    for (int t = 0; t < n; ++t) tiles[t] = vlb::Item{0, t % ntx, t / ntx, 0};
+    order_tiles(tiles, rowmajor_tiles(s->sched_order, resident_state(s)), s->items);
     s->nitems = n;
 }
 
@@ -482,7 +509,7 @@ int launch_steps(vlb_sim* s, int64_t n) {
     const vlb::FillItem* fi = s->dptr<vlb::FillItem>(s->off_fill_items);
     for (int64_t k = 0; k < n; ++k) {
         VLB_HIP(vlb::launch_step<T>(rd, it, s->nitems, s->ty, s->parity, s->first, streaming(s),
-                                    s->stream));
+                                    step_waves(s->sched_waves, resident_state(s)), s->stream));
         s->parity ^= 1;
         s->first = 0;
         ++s->step;
@@ -503,7 +530,8 @@ int graph_for(vlb_sim* s, int par, hipGraphExec_t* out) {
     const vlb::FillItem* fi = s->dptr<vlb::FillItem>(s->off_fill_items);
     int p = par;
     for (int k = 0; k < 2 * s->graph_chunk && err == hipSuccess; ++k) {
-        err = vlb::launch_step<T>(rd, it, s->nitems, s->ty, p, 0, streaming(s), s->stream);
+        err = vlb::launch_step<T>(rd, it, s->nitems, s->ty, p, 0, streaming(s),
+                                  step_waves(s->sched_waves, resident_state(s)), s->stream);
         p ^= 1;
         if (err == hipSuccess) err = vlb::launch_fill<T>(rd, fi, (int)s->fill_items.size(), p, s->stream);
     }
@@ -819,14 +847,14 @@ int vlb_read_fields(vlb_sim* s, void* rho, void* ux, void* uy, void* axx, void* 
 int vlb_read_history(vlb_sim* s, void* sxx, void* sxy, void* syy, void* uxp, void* uyp) {
     int rc = check_ready(s);
     if (rc) return rc;
-    void* out[5] = {sxx, sxy, syy, uxp, uyp};
-    const size_t row = (size_t)s->nx * s->esz, dp = (size_t)s->pitch * s->esz;
-    for (int c = 0; c < 5; ++c) {
-        if (!out[c]) continue;
-        VLB_HIP(hipMemcpy2DAsync(out[c], row,
-                                 s->ws + s->off_hist + ((size_t)c * s->plane + s->off0) * s->esz,
-                                 dp, row, s->ny, hipMemcpyDeviceToDevice, s->stream));
-    }
+    if (s->prec == VLB_FP32)
+        VLB_HIP(vlb::launch_read_history<float>(make_run<float>(s), s->dptr<Run<float>>(s->off_run),
+                                                (float*)sxx, (float*)sxy, (float*)syy,
+                                                (float*)uxp, (float*)uyp, s->stream));
+    else
+        VLB_HIP(vlb::launch_read_history<double>(make_run<double>(s), s->dptr<Run<double>>(s->off_run),
+                                                 (double*)sxx, (double*)sxy, (double*)syy,
+                                                 (double*)uxp, (double*)uyp, s->stream));
     return VLB_OK;
 }
 
@@ -961,6 +989,17 @@ int vlb_set_tile(vlb_sim* s, int ty) {
     return VLB_OK;
 }
 
+int vlb_set_schedule(vlb_sim* s, int tile_order, int waves) {
+    if (!s) return fail(VLB_E_INVALID_ARG, "null simulation");
+    if (tile_order < 0 || tile_order > 2) return fail(VLB_E_INVALID_ARG, "tile order must be 0, 1 or 2");
+    if (waves != 0 && waves != 3 && waves != 4) return fail(VLB_E_INVALID_ARG, "waves must be 0, 3 or 4");
+    s->sched_order = tile_order;
+    s->sched_waves = waves;
+    drop_graphs(s);
+    if (s->bound) return upload_items(s);
+    return VLB_OK;
+}
+
 }  // extern "C"
 
 // ---- adjoint (periodic domains) ------------------------------------------------------
@@ -1090,7 +1129,8 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
                                hipMemcpyDeviceToDevice, s->stream));
         for (int64_t k = 0; k + 1 < len; ++k) {
             const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
-            VLB_HIP(vlb::launch_step<T>(desc + k, items, s->nitems, s->ty, 0, first, 0, s->stream));
+            VLB_HIP(vlb::launch_step<T>(desc + k, items, s->nitems, s->ty, 0, first, 0,
+                                        step_waves(s->sched_waves, resident_state(s)), s->stream));
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
@@ -1229,7 +1269,8 @@ int batch_lists(vlb_batch* b, vlb_sim* const* sims, int n, int ty) {
     b->ty = ty;
     b->prec = sims[0]->prec;
     double state_bytes = 0;
-    std::vector<vlb::Item> tiles;
+    std::vector<vlb::Item>& tiles = b->tiles;
+    tiles.clear();
     for (int r = 0; r < n; ++r) {
         const vlb_sim* s = sims[r];
         if (!s) return fail(VLB_E_INVALID_ARG, "null simulation in batch");
@@ -1244,13 +1285,10 @@ int batch_lists(vlb_batch* b, vlb_sim* const* sims, int n, int ty) {
             b->fill_items.push_back(vlb::FillItem{r, fi.first, fi.count, 0});
         state_bytes += 2.0 * 36.0 * (double)s->nx * (double)s->ny * (double)s->esz;
     }
-    // XCD-aware order over the concatenated tiles (as for a single run)
-    const int nt = (int)tiles.size(), nxcd = 8;
-    std::vector<int> start(nxcd + 1, 0);
-    for (int k = 0; k < nxcd; ++k) start[k + 1] = start[k] + nt / nxcd + (k < nt % nxcd ? 1 : 0);
-    b->items.resize(nt);
-    for (int i = 0; i < nt; ++i) b->items[i] = tiles[start[i % nxcd] + i / nxcd];
-    b->streaming = state_bytes > 192.0 * 1024 * 1024 ? 1 : 0;
+    // the concatenated tiles in the order of the schedule (as for a single run)
+    b->resident = state_bytes <= 192.0 * 1024 * 1024;
+    b->streaming = b->resident ? 0 : 1;
+    order_tiles(tiles, rowmajor_tiles(b->sched_order, b->resident), b->items);
     batch_layout(b);
     return VLB_OK;
 }
@@ -1310,7 +1348,8 @@ int batch_launch(vlb_batch* b, int par, int first) {
     const Run<T>* rd = reinterpret_cast<const Run<T>*>(b->ws + b->off_runs);
     const vlb::Item* it = reinterpret_cast<const vlb::Item*>(b->ws + b->off_items);
     const vlb::FillItem* fi = reinterpret_cast<const vlb::FillItem*>(b->ws + b->off_fill_items);
-    VLB_HIP(vlb::launch_step<T>(rd, it, (int)b->items.size(), b->ty, par, first, b->streaming, b->stream));
+    VLB_HIP(vlb::launch_step<T>(rd, it, (int)b->items.size(), b->ty, par, first, b->streaming,
+                                step_waves(b->sched_waves, b->resident), b->stream));
     VLB_HIP(vlb::launch_fill<T>(rd, fi, (int)b->fill_items.size(), par ^ 1, b->stream));
     return VLB_OK;
 }
@@ -1542,6 +1581,20 @@ int vlb_batch_set_graph_chunk(vlb_batch* b, int chunk) {
     if (!b || chunk < 0 || chunk > 4096) return fail(VLB_E_INVALID_ARG, "chunk out of range");
     batch_drop_graphs(b);
     b->graph_chunk = chunk;
+    return VLB_OK;
+}
+
+int vlb_batch_set_schedule(vlb_batch* b, int tile_order, int waves) {
+    if (!b) return fail(VLB_E_INVALID_ARG, "null batch");
+    if (tile_order < 0 || tile_order > 2) return fail(VLB_E_INVALID_ARG, "tile order must be 0, 1 or 2");
+    if (waves != 0 && waves != 3 && waves != 4) return fail(VLB_E_INVALID_ARG, "waves must be 0, 3 or 4");
+    b->sched_order = tile_order;
+    b->sched_waves = waves;
+    batch_drop_graphs(b);
+    order_tiles(b->tiles, rowmajor_tiles(b->sched_order, b->resident), b->items);
+    VLB_HIP(hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(vlb::Item),
+                           hipMemcpyHostToDevice, b->stream));
+    VLB_HIP(hipStreamSynchronize(b->stream));
     return VLB_OK;
 }
 

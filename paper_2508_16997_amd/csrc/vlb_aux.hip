@@ -23,18 +23,22 @@ __global__ void k_init(const RunDev<S>* __restrict__ run, const S* rho0, const S
     const T r = rho0 ? (T)rho0[q] : 1.0;
     const T vx = ux0 ? (T)ux0[q] : 0.0, vy = uy0 ? (T)uy0[q] : 0.0;
     const S* a[3] = {a0, a1, a2};
+    T phi[3];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) stu(dst + i * plane, (unsigned)p, solid ? 0.0 : dfeq(i, r - 1.0, r, vx, vy));
+    for (int k = 0; k < 3; ++k) phi[k] = a[k] ? (T)a[k][q] : phi0(k);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const T phi = a[k] ? (T)a[k][q] : phi0(k);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            stu(dst + (9 + 9 * k + i) * plane, (unsigned)p,
-                solid ? 0.0 : dgeq(i, phi - phi0(k), phi, vx, vy));
+    for (int i = 0; i < 9; ++i) {
+        if (solid) {
+            st4<false>(dst, plane, i, (unsigned)p, make4<S>(0.0, 0.0, 0.0, 0.0));
+        } else {
+            st4<false>(dst, plane, i, (unsigned)p,
+                       make4<S>(dfeq(i, r - 1.0, r, vx, vy), dgeq(i, phi[0] - phi0(0), phi[0], vx, vy),
+                                dgeq(i, phi[1] - phi0(1), phi[1], vx, vy),
+                                dgeq(i, phi[2] - phi0(2), phi[2], vx, vy)));
+        }
     }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) stu(R.hist + c * plane, (unsigned)p, 0.0);
+    const T zero[3] = {0.0, 0.0, 0.0};
+    hist_st<false>(R.hist, plane, (unsigned)p, zero, 0.0, 0.0);
 }
 
 // Macroscopic fields of node (x, y) at the current time; false for solid nodes.  At a
@@ -44,8 +48,8 @@ __device__ __forceinline__ bool node_fields(const RunDev<S>& R, const S* src, in
                                             bool pull, T& rho, T& ux, T& uy, T a[3]) {
     const int p = node_index(R, x, y);
     if (node_bits(R, p) & BIT_SELF_SOLID) return false;
-    S f[9];
-    pull9(R, src, 0, p, pull, f);
+    S f[9], g[3][9];
+    pull36(R, src, p, pull, f, g);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     const bool wet = wet_row(R, y);
@@ -54,11 +58,9 @@ __device__ __forceinline__ bool node_fields(const RunDev<S>& R, const S* src, in
     if (wet) ux = uy = 0.0;  // wall node: the wall velocity
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        S g[9];
-        pull9(R, src, 1 + k, p, pull, g);
         T acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) acc += T(g[i]);
+        for (int i = 0; i < 9; ++i) acc += T(g[k][i]);
         a[k] = phi0(k) + acc;
     }
     return true;
@@ -80,6 +82,24 @@ __global__ void k_read(const RunDev<S>* __restrict__ run, int parity, int first,
     if (axx_o) axx_o[q] = (S)a[0];
     if (axy_o) axy_o[q] = (S)a[1];
     if (ayy_o) ayy_o[q] = (S)a[2];
+}
+
+// History the next step uses (S(t-1) and u(t-1)), unpadded [ny][nx] arrays.
+template <class S>
+__global__ void k_read_history(const RunDev<S>* __restrict__ run, S* sxx, S* sxy, S* syy, S* uxp,
+                               S* uyp) {
+    const RunDev<S>& R = *run;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= R.nx || y >= R.ny) return;
+    const int q = y * R.nx + x;
+    T hS[3], hux, huy;
+    hist_ld(R.hist, R.plane, (unsigned)node_index(R, x, y), hS, hux, huy);
+    if (sxx) sxx[q] = (S)hS[0];
+    if (sxy) sxy[q] = (S)hS[1];
+    if (syy) syy[q] = (S)hS[2];
+    if (uxp) uxp[q] = (S)hux;
+    if (uyp) uyp[q] = (S)huy;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -186,8 +206,8 @@ __global__ __launch_bounds__(256) void k_drag(const RunDev<S>* __restrict__ run,
             const S* buf = R.pop[parity];
             const long long plane = R.plane;
             const int o = opp(d);
-            const T v = ldu(buf + d * plane, (unsigned)p) + ldu(buf + o * plane, (unsigned)(p + ex(d) + ey(d) * R.pitch)) +
-                        2.0 * wgt(d);
+            const T v = ld1(buf, plane, 0, d, (unsigned)p) +
+                        ld1(buf, plane, 0, o, (unsigned)(p + ex(d) + ey(d) * R.pitch)) + 2.0 * wgt(d);
             fx = T(ex(d)) * v;
             fy = T(ey(d)) * v;
         }
@@ -241,6 +261,14 @@ hipError_t launch_read(const RunDev<S>& h, const RunDev<S>* d, int parity, int f
 }
 
 template <class S>
+hipError_t launch_read_history(const RunDev<S>& h, const RunDev<S>* d, S* sxx, S* sxy, S* syy,
+                               S* uxp, S* uyp, hipStream_t s) {
+    dim3 blk(64, 4), grd((h.nx + 63) / 64, (h.ny + 3) / 4);
+    hipLaunchKernelGGL((k_read_history<S>), grd, blk, 0, s, d, sxx, sxy, syy, uxp, uyp);
+    return hipGetLastError();
+}
+
+template <class S>
 hipError_t launch_monitor(const RunDev<S>& h, const RunDev<S>* d, int parity, int first,
                           S* usnap, double* part, MonitorAcc* acc, hipStream_t s) {
     dim3 blk(256), grd((h.nx + 63) / 64, (h.ny + 3) / 4);
@@ -280,6 +308,8 @@ hipError_t launch_drag(const RunDev<S>* run_dev, const int* links, int nlinks, i
                                        hipStream_t);                                       \
     template hipError_t launch_read<S>(const RunDev<S>&, const RunDev<S>*, int, int, S*,   \
                                        S*, S*, S*, S*, S*, hipStream_t);                   \
+    template hipError_t launch_read_history<S>(const RunDev<S>&, const RunDev<S>*, S*, S*, \
+                                               S*, S*, S*, hipStream_t);                   \
     template hipError_t launch_monitor<S>(const RunDev<S>&, const RunDev<S>*, int, int,    \
                                           S*, double*, MonitorAcc*, hipStream_t);          \
     template hipError_t launch_drag<S>(const RunDev<S>*, const int*, int, int, int, double*, \

@@ -26,7 +26,7 @@ namespace {
 // during the fills of step n, when nobody draws from it, and the last one after the
 // final barrier, so both are zero between launches.
 template <class S, int TY, bool NT>
-__global__ __launch_bounds__((StepBounds<S, TY>::threads), (StepBounds<S, TY>::batch_waves_per_eu)) void k_batch(
+__global__ __launch_bounds__((StepBounds<S, TY, 3>::threads), (StepBounds<S, TY, 3>::batch_waves_per_eu)) void k_batch(
     const RunDev<S>* __restrict__ runs, const Item* __restrict__ items, int nitems,
     const FillItem* __restrict__ fitems, int nfitems, int nsteps, int parity, int first,
     int* __restrict__ queues) {

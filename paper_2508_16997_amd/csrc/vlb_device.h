@@ -30,6 +30,65 @@ __device__ __forceinline__ void st_stream(S* base, unsigned off, T v) {
     else ((VLB_GLOBAL S*)base)[off] = (S)v;
 }
 
+// ---- state layout ----
+// Population buffer: direction-major with the four lattices of a direction interleaved,
+// (f_i, g^xx_i, g^xy_i, g^yy_i) as one 16-byte (FP32) or 32-byte (FP64) vector per slot:
+// element (lattice L, direction i, slot) at (i * plane + slot) * 4 + L.  A pull of all
+// four lattices in direction i is one vector load from one address stream, so a node
+// reads 9 streams instead of 36.
+// History buffer: (S_xx, S_xy, S_yy, u_x) of the previous step as one vector per slot
+// (the first 4 planes' worth), then u_y as a scalar plane at 4 * plane.
+template <class S> struct Vec4Of;
+template <> struct Vec4Of<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4Of<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <class S> using V4 = typename Vec4Of<S>::type;
+
+template <class S>
+__device__ __forceinline__ V4<S> ld4(const S* buf, long long plane, int i, unsigned slot) {
+    return ((const VLB_GLOBAL V4<S>*)(buf + 4 * (long long)i * plane))[slot];
+}
+template <bool NT, class S>
+__device__ __forceinline__ void st4(S* buf, long long plane, int i, unsigned slot, V4<S> v) {
+    VLB_GLOBAL V4<S>* a = (VLB_GLOBAL V4<S>*)(buf + 4 * (long long)i * plane) + slot;
+    if (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
+}
+// one lattice's population (scalar access: ring cells, boundary ops, read-out)
+template <class S>
+__device__ __forceinline__ T ld1(const S* buf, long long plane, int L, int i, unsigned slot) {
+    return (T)((const VLB_GLOBAL S*)(buf + 4 * (long long)i * plane))[4 * slot + (unsigned)L];
+}
+template <class S>
+__device__ __forceinline__ V4<S> make4(T a, T b, T c, T d) {
+    V4<S> v;
+    v.x = (S)a;
+    v.y = (S)b;
+    v.z = (S)c;
+    v.w = (S)d;
+    return v;
+}
+// history of the previous step at a slot: S_xx, S_xy, S_yy, u_x, u_y (V = S keeps them
+// in storage precision until used, V = T converts)
+template <class S, class V>
+__device__ __forceinline__ void hist_ld(const S* h, long long plane, unsigned slot, V hS[3], V& hux,
+                                        V& huy) {
+    const V4<S> v = ((const VLB_GLOBAL V4<S>*)h)[slot];
+    hS[0] = (V)v.x;
+    hS[1] = (V)v.y;
+    hS[2] = (V)v.z;
+    hux = (V)v.w;
+    huy = (V)((const VLB_GLOBAL S*)(h + 4 * plane))[slot];
+}
+template <bool NT, class S>
+__device__ __forceinline__ void hist_st(S* h, long long plane, unsigned slot, const T Sk[3], T ux,
+                                        T uy) {
+    const V4<S> v = make4<S>(Sk[0], Sk[1], Sk[2], ux);
+    VLB_GLOBAL V4<S>* a = (VLB_GLOBAL V4<S>*)h + slot;
+    if (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
+    st_stream<NT>(h + 4 * plane, slot, uy);
+}
+
 // D2Q9 velocities in the paper's order (Sec. 3.1), their opposites and weights.
 __host__ __device__ constexpr int ex(int i) {
     return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
@@ -98,12 +157,24 @@ __device__ __forceinline__ void node_force(const RunDev<S>& R, int p, T& Fx, T& 
 template <class S>
 __device__ __forceinline__ void pull9(const RunDev<S>& R, const S* src, int L, int p, bool pull,
                                       S v[9]) {
-    const long long plane = R.plane;
-    const S* base = src + (long long)(9 * L) * plane;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int off = pull ? p - ex(i) - ey(i) * R.pitch : p;
-        v[i] = ((const VLB_GLOBAL S*)(base + i * plane))[(unsigned)off];
+        v[i] = (S)ld1(src, R.plane, L, i, (unsigned)off);
+    }
+}
+// All 36 populations arriving at slot p: one vector load per direction.
+template <class S>
+__device__ __forceinline__ void pull36(const RunDev<S>& R, const S* src, int p, bool pull, S f[9],
+                                       S g[3][9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int off = pull ? p - ex(i) - ey(i) * R.pitch : p;
+        const V4<S> v = ld4(src, R.plane, i, (unsigned)off);
+        f[i] = v.x;
+        g[0][i] = v.y;
+        g[1][i] = v.z;
+        g[2][i] = v.w;
     }
 }
 
@@ -274,31 +345,27 @@ __device__ __forceinline__ void apply_fill_op(const RunDev<S>& R, const FillOp& 
         // itself.
         const bool in = kind == FILL_INLET;
         const T uin = in ? T(R.inlet[op.far]) : 0.0;
-        stu(buf + dir * plane, (unsigned)op.dst, in ? dfeq(dir, 0.0, 1.0, uin, 0.0) : 0.0);
+        T a[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const T a = in ? T(R.inlet[(1 + k) * R.ny + op.far]) : phi0(k);
-            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
-                in ? dgeq(dir, a - phi0(k), a, uin, 0.0) : 0.0);
+            const T ak = in ? T(R.inlet[(1 + k) * R.ny + op.far]) : phi0(k);
+            a[k] = in ? dgeq(dir, ak - phi0(k), ak, uin, 0.0) : 0.0;
         }
+        st4<false>(buf, plane, dir, (unsigned)op.dst,
+                   make4<S>(in ? dfeq(dir, 0.0, 1.0, uin, 0.0) : 0.0, a[0], a[1], a[2]));
     } else {
-        // conformation lattices: the population that left toward the wall (CNEBB input)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            stu(buf + (9 + 9 * k + dir) * plane, (unsigned)op.dst,
-                ldu(buf + (9 + 9 * k + o) * plane, (unsigned)op.src));
+        // conformation lattices: the populations that left toward the wall (CNEBB input);
         // hydrodynamic lattice: half-way or linear interpolated bounce-back
-        const T fo = ldu(buf + o * plane, (unsigned)op.src);
-        T v = fo;
+        V4<S> v = ld4(buf, plane, o, (unsigned)op.src);
         if (kind == FILL_CURVED) {
-            const T q = op.q;
+            const T q = op.q, fo = T(v.x);
             if (q < 0.5) {
-                if (op.far >= 0) v = 2.0 * q * fo + (1.0 - 2.0 * q) * ldu(buf + o * plane, (unsigned)op.far);
+                if (op.far >= 0) v.x = S(2.0 * q * fo + (1.0 - 2.0 * q) * ld1(buf, plane, 0, o, (unsigned)op.far));
             } else {
-                v = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * ldu(buf + dir * plane, (unsigned)op.src);
+                v.x = S(fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * ld1(buf, plane, 0, dir, (unsigned)op.src));
             }
         }
-        stu(buf + dir * plane, (unsigned)op.dst, v);
+        st4<false>(buf, plane, dir, (unsigned)op.dst, v);
     }
 }
 

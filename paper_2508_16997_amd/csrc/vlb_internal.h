@@ -55,8 +55,11 @@ struct RunDev {
     int model;          // constitutive closure (VLB_OLDROYD_B ... VLB_FENE_P)
     int wet_y;          // 1: rows 0 and ny - 1 are wet-node wall nodes (u = 0 there)
     long long plane;    // elements per plane ((ny + 2) * pitch)
-    S* pop[2];          // two population buffers of 36 planes: f (9), g_xx, g_xy, g_yy (9 each)
-    S* hist;            // 5 planes: S_xx, S_xy, S_yy, u_x, u_y of the previous step
+    S* pop[2];          // two population buffers of 36 planes' worth: per direction i a
+                        // plane of 4-vectors (f_i, g_xx,i, g_xy,i, g_yy,i), element
+                        // (i * plane + slot) * 4 + lattice
+    S* hist;            // 5 planes' worth: (S_xx, S_xy, S_yy, u_x) of the previous step as
+                        // 4-vectors, then a plane of u_y
     S* hist_out;        // where the step writes this step's S and u (hist, except when an
                         // adjoint segment is recomputed into separate state slots)
     const S* force;     // 2 planes (F_x, F_y) when !uniform_force
@@ -111,10 +114,11 @@ struct MonitorAcc {
 };
 
 // Kernel launchers (vlb_kernels.hip).  Return hipSuccess or the launch error.
-// streaming != 0 selects non-temporal stores of the post-collision state.
+// streaming != 0 selects non-temporal stores of the post-collision state; waves (3 or 4)
+// the register budget of the single-precision step kernel.
 template <class S>
 hipError_t launch_step(const RunDev<S>* runs_dev, const Item* items_dev, int nitems, int ty,
-                       int parity, int first, int streaming, hipStream_t s);
+                       int parity, int first, int streaming, int waves, hipStream_t s);
 // Persistent batch form (vlb_batch.hip): one cooperative launch runs nsteps steps (step,
 // grid barrier, fills, grid barrier) over the same work and fill lists.  queues: device
 // array of 2 * kBatchQueues ints, zero before the first launch and left zero by each.
@@ -133,6 +137,9 @@ hipError_t launch_init(const RunDev<S>& run_host, const RunDev<S>* run_dev, cons
 template <class S>
 hipError_t launch_read(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,
                        int first, S* rho, S* ux, S* uy, S* axx, S* axy, S* ayy, hipStream_t s);
+template <class S>
+hipError_t launch_read_history(const RunDev<S>& run_host, const RunDev<S>* run_dev, S* sxx, S* sxy,
+                               S* syy, S* uxp, S* uyp, hipStream_t s);
 // Deterministic two-pass reduction; part holds 8 doubles per 64 x 4 block of nodes.
 template <class S>
 hipError_t launch_monitor(const RunDev<S>& run_host, const RunDev<S>* run_dev, int parity,

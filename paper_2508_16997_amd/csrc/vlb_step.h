@@ -22,16 +22,17 @@
 
 #include "vlb_device.h"
 
-// Register budget of the step kernel: single-precision storage fits four waves per
-// SIMD without spilling; double precision keeps its natural allocation.
-template <class S, int TY>
+// Register budget of the step kernel, W waves per SIMD for single-precision storage
+// (W = 3: 170 VGPRs, no spills; W = 4: 128 VGPRs with a few spilled, the better choice
+// when the state is cache resident and the launch runs as one wave per SIMD slot);
+// double precision keeps its natural allocation (three waves).
+template <class S, int TY, int W>
 struct StepBounds {
     static constexpr int threads = 64 * TY;
-    static constexpr int min_waves_per_eu = sizeof(S) == 4 ? 4 : 1;
+    static constexpr int min_waves_per_eu = sizeof(S) == 4 ? W : 1;
     // the persistent batch kernel loops over tiles and keeps a few more values live:
-    // four waves per SIMD (FP32 storage) spill about 40 bytes per lane, touched once
-    // per tile, and ran faster than three without spills; FP64 at three spills 12
-    static constexpr int batch_waves_per_eu = sizeof(S) == 4 ? 4 : 3;
+    // three waves per SIMD, without spills in either precision
+    static constexpr int batch_waves_per_eu = 3;
 };
 
 namespace vlb {
@@ -97,27 +98,21 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
         s_w2[w][2][lx] = r2 * uy2 * uy2 * uy2;
     }
     S f[9], g[3][9];
-    T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
+    T Fx = 0.0, Fy = 0.0;
+    // history S(t-1), u(t-1), in storage precision until the collisions use it
+    S hS[3] = {S(0), S(0), S(0)}, hux = S(0), huy = S(0);
     // conformation deviations A - I: the zeroth moments of the pulled g lattices (CNEBB
     // keeps them, so they are final before the wall reconstruction)
     T dk[3] = {0.0, 0.0, 0.0};
     if (active) {
-        pull9(R, src, 0, p, pull, f);
+        pull36(R, src, p, pull, f, g);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            pull9(R, src, 1 + k, p, pull, g[k]);
-            dk[k] = zeroth(g[k]);
-        }
+        for (int k = 0; k < 3; ++k) dk[k] = zeroth(g[k]);
         node_force(R, p, Fx, Fy);
         // wet-node wall: the populations from beyond the wall by non-equilibrium
         // bounce-back (the pulled ghost values are discarded)
         if (pull && wet_row(R, y)) zou_he(f, y == 0, Fx, Fy);
-        if (pull) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) hS[k] = ldu(R.hist + k * plane, (unsigned)p);
-            hux = ldu(R.hist + 3 * plane, (unsigned)p);
-            huy = ldu(R.hist + 4 * plane, (unsigned)p);
-        }
+        if (pull) hist_ld(R.hist, plane, (unsigned)p, hS, hux, huy);
     }
     // ring cells: rows above/below the tile, columns left/right of it
     for (int r = tid; r < 128 + 2 * TY; r += 64 * TY) {
@@ -208,62 +203,37 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
         Sc[1] = -R.inv_lam * rf[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
         Sc[2] = -R.inv_lam * rf[2] + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
     }
-    if (!pull) {  // first step: F~(t - 1) := F~(t)
-        hS[0] = Sc[0]; hS[1] = Sc[1]; hS[2] = Sc[2];
-        hux = ux; huy = uy;
-    }
 
-    // Periodic images: an edge node also writes the populations that leave the domain
-    // into the ghost slots its periodic neighbours pull from (no fill op needed).
-    const bool px_per = R.xmode == XM_PERIODIC, py_per = R.ymode == XM_PERIODIC;
-    const int gxo = (px_per && x == R.nx - 1) ? -R.nx : ((px_per && x == 0) ? R.nx : 0);
-    const int gyo = (py_per && y == R.ny - 1) ? -R.ny : ((py_per && y == 0) ? R.ny : 0);
-    const bool edge = (gxo | gyo) != 0;
-    // ghost slot of direction i for this node, or -1: a population moving in direction
-    // i leaves through the edge it points at
-    auto ghost = [&](int i) -> int {
-        const int sx = (gxo != 0 && ex(i) == (gxo < 0 ? 1 : -1)) ? gxo : 0;
-        const int sy = (gyo != 0 && ey(i) == (gyo < 0 ? 1 : -1)) ? gyo : 0;
-        if (sx == 0 && sy == 0) return -1;
-        return p + sx + sy * R.pitch;
+    // Post-collision populations of the four lattices, in storage precision, stored
+    // together at the end (one vector store per direction).  Until then f, g^xx and g^xy
+    // wait in LDS, one column per lane (single-precision storage: registers are what
+    // limits the step to four waves per SIMD), or in registers (double precision);
+    // g^yy, computed last, stays in registers.
+    constexpr bool kStage = sizeof(S) == 4;
+    __shared__ S s_post[kStage ? 27 : 1][kStage ? 64 * TY : 1];
+    S rpost[kStage ? 1 : 27];
+    auto put = [&](int j, T v) {
+        if constexpr (kStage) s_post[j][tid] = S(v);
+        else rpost[j] = S(v);
     };
-
-    T out[9];
-    collide_hydro(R, moments(f), rho, ux, uy, Fx, Fy, txx, txy, tyy, Dx, Dy, out);
+    auto get = [&](int j) -> S {
+        if constexpr (kStage) return s_post[j][tid];
+        else return rpost[j];
+    };
+    S g2[9];
+    {
+        T out[9];
+        collide_hydro(R, moments(f), rho, ux, uy, Fx, Fy, txx, txy, tyy, Dx, Dy, out);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_stream<NT>(dst + i * plane, (unsigned)p, out[i]);
-    // Open ends (Sec. 4.3): the first (last) column node writes the ghosts its row's
-    // inlet (outlet) links pull next step by non-equilibrium extrapolation from its own
-    // post-collision populations (as stored): f_i = f_i^eq(rho_b, u_b) + f_i -
-    // f_i^eq(rho, u) with rho, u their moments; inlet rho_b = rho, u_b = profile;
-    // outlet rho_b = 1, u_b = u.  The conformation ghosts follow below.
-    const bool oend = R.xmode == XM_OPEN && (x == 0 || x == R.nx - 1);
-    const bool oin = x == 0;
-    T oux = 0.0, ouy = 0.0;
-    if (oend) {
-        S so[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) so[i] = S(out[i]);
-        T odr, orho;
-        hydro_macros(so, 0.0, 0.0, odr, orho, oux, ouy);
-        const T uin = oin ? T(R.inlet[y]) : 0.0;
-        open_end_slots(R, y, oin, [&](int i, unsigned gs) {
-            const T fneq = T(so[i]) - dfeq(i, odr, orho, oux, ouy);
-            stu(dst + i * plane, gs, (oin ? dfeq(i, odr, orho, uin, 0.0) : dfeq(i, 0.0, 1.0, oux, ouy)) + fneq);
-        });
-    }
-    if (edge) {
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const int gs = ghost(i);
-            if (gs >= 0) stu(dst + i * plane, (unsigned)gs, out[i]);
-        }
+        for (int i = 0; i < 9; ++i) put(i, out[i]);
     }
     // conformation lattices one at a time after the hydrodynamic one (keeps the
     // register budget of four waves per SIMD): CNEBB at wall-adjacent nodes, moments,
-    // collision, stores
+    // collision
     const unsigned solid = pull ? (b & 0x1FEu) : 0u;
     const T inv_rho = 1.0 / rho;
+    // F~(t - 1) of the collisions: from the history, or on the first step F~(t - 1) := F~(t)
+    const T uxp = pull ? T(hux) : ux, uyp = pull ? T(huy) : uy;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         Mom gm;
@@ -278,37 +248,79 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
         }
         gm.m0 = dk[k];
         const T phi = phi0(k) + dk[k];
-        collide_cde(R, gm, phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], hS[k], hux, huy, out);
+        T out[9];
+        collide_cde(R, gm, phi, ux, uy, phi * inv_rho, Fx, Fy, Sc[k], pull ? T(hS[k]) : Sc[k], uxp,
+                    uyp, out);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st_stream<NT>(dst + (9 + 9 * k + i) * plane, (unsigned)p, out[i]);
-        if (oend) {  // inlet: extrapolation around A_in, u_in; outlet: copy
-            S so[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) so[i] = S(out[i]);
-            T dphi = 0.0;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) dphi += T(so[i]);
-            const T uin = oin ? T(R.inlet[y]) : 0.0;
-            const T a = oin ? T(R.inlet[(1 + k) * R.ny + y]) : 0.0;
-            open_end_slots(R, y, oin, [&](int i, unsigned gs) {
-                stu(dst + (9 + 9 * k + i) * plane, gs,
-                    oin ? dgeq(i, a - phi0(k), a, uin, 0.0) + T(so[i]) -
-                              dgeq(i, dphi, phi0(k) + dphi, oux, ouy)
-                        : T(so[i]));
-            });
-        }
-        if (edge) {
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const int gs = ghost(i);
-                if (gs >= 0) stu(dst + (9 + 9 * k + i) * plane, (unsigned)gs, out[i]);
-            }
+        for (int i = 0; i < 9; ++i) {
+            if (k < 2) put(9 + 9 * k + i, out[i]);
+            else g2[i] = S(out[i]);
         }
     }
+    auto post4 = [&](int i) -> V4<S> {
+        V4<S> v;
+        v.x = get(i);
+        v.y = get(9 + i);
+        v.z = get(18 + i);
+        v.w = g2[i];
+        return v;
+    };
 #pragma unroll
-    for (int k = 0; k < 3; ++k) st_stream<NT>(R.hist_out + k * plane, (unsigned)p, Sc[k]);
-    st_stream<NT>(R.hist_out + 3 * plane, (unsigned)p, ux);
-    st_stream<NT>(R.hist_out + 4 * plane, (unsigned)p, uy);
+    for (int i = 0; i < 9; ++i) st4<NT>(dst, plane, i, (unsigned)p, post4(i));
+    hist_st<NT>(R.hist_out, plane, (unsigned)p, Sc, ux, uy);
+    // Open ends (Sec. 4.3): the first (last) column node writes the ghosts its row's
+    // inlet (outlet) links pull next step by non-equilibrium extrapolation from its own
+    // post-collision populations (as stored): f_i = f_i^eq(rho_b, u_b) + f_i -
+    // f_i^eq(rho, u) with rho, u their moments; inlet rho_b = rho, u_b = profile;
+    // outlet rho_b = 1, u_b = u.  Conformation: inlet g_i = g_i^eq(A_in, u_in) + g_i -
+    // g_i^eq(phi, u) with phi the moment of the stored g; outlet a copy (zero gradient).
+    if (R.xmode == XM_OPEN && (x == 0 || x == R.nx - 1)) {
+        const bool oin = x == 0;
+        S fo[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fo[i] = get(i);
+        T odr, orho, oux, ouy;
+        hydro_macros(fo, 0.0, 0.0, odr, orho, oux, ouy);
+        const T uin = oin ? T(R.inlet[y]) : 0.0;
+        T dphi[3], ain[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            T acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) acc += T(k < 2 ? get(9 + 9 * k + i) : g2[i]);
+            dphi[k] = acc;
+            ain[k] = oin ? T(R.inlet[(1 + k) * R.ny + y]) : 0.0;
+        }
+        open_end_slots(R, y, oin, [&](int i, unsigned gs) {
+            const V4<S> v = post4(i);
+            const T fneq = T(v.x) - dfeq(i, odr, orho, oux, ouy);
+            const T gk[3] = {T(v.y), T(v.z), T(v.w)};
+            T gv[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                gv[k] = oin ? dgeq(i, ain[k] - phi0(k), ain[k], uin, 0.0) + gk[k] -
+                                  dgeq(i, dphi[k], phi0(k) + dphi[k], oux, ouy)
+                            : gk[k];
+            st4<false>(dst, plane, i, gs,
+                       make4<S>((oin ? dfeq(i, odr, orho, uin, 0.0) : dfeq(i, 0.0, 1.0, oux, ouy)) + fneq,
+                                gv[0], gv[1], gv[2]));
+        });
+    }
+    // Periodic images: an edge node also writes the populations that leave the domain
+    // into the ghost slots its periodic neighbours pull from (no fill op needed).
+    const bool px_per = R.xmode == XM_PERIODIC, py_per = R.ymode == XM_PERIODIC;
+    const int gxo = (px_per && x == R.nx - 1) ? -R.nx : ((px_per && x == 0) ? R.nx : 0);
+    const int gyo = (py_per && y == R.ny - 1) ? -R.ny : ((py_per && y == 0) ? R.ny : 0);
+    if ((gxo | gyo) != 0) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            // a population moving in direction i leaves through the edge it points at
+            const int sx = (gxo != 0 && ex(i) == (gxo < 0 ? 1 : -1)) ? gxo : 0;
+            const int sy = (gyo != 0 && ey(i) == (gyo < 0 ? 1 : -1)) ? gyo : 0;
+            if (sx == 0 && sy == 0) continue;
+            st4<false>(dst, plane, i, (unsigned)(p + sx + sy * R.pitch), post4(i));
+        }
+    }
 }
 
 }  // namespace

@@ -222,6 +222,12 @@ class Simulation:
         """0 automatic, 1 cached, 2 non-temporal stores of the post-collision state."""
         L.check(self.lib.vlb_set_store_mode(self._h, int(mode)), "vlb_set_store_mode")
 
+    def set_schedule(self, tile_order: int = 0, waves: int = 0):
+        """Tile order (0 auto, 1 XCD bands, 2 row-major) and register budget of the
+        single-precision step kernel (0 auto, 3 or 4 waves per SIMD)."""
+        L.check(self.lib.vlb_set_schedule(self._h, int(tile_order), int(waves)),
+                "vlb_set_schedule")
+
     def set_graph_chunk(self, chunk: int):
         L.check(self.lib.vlb_set_graph_chunk(self._h, int(chunk)), "vlb_set_graph_chunk")
 
@@ -313,7 +319,7 @@ class Batch:
     """
 
     def __init__(self, sims, tile: int = 4, graph_chunk: int = 0, persistent: bool = False,
-                 noalloc: bool = False):
+                 noalloc: bool = False, schedule=None):
         """``noalloc``: build the batch with vlb_batch_create_noalloc (lists in the
         library's static per-device scratch, no workspace tensor; one such batch per
         device at a time)."""
@@ -350,6 +356,14 @@ class Batch:
                     "vlb_batch_set_graph_chunk")
         if persistent:
             L.check(self.lib.vlb_batch_set_persistent(h, 1), "vlb_batch_set_persistent")
+        if schedule:
+            self.set_schedule(*schedule)
+
+    def set_schedule(self, tile_order: int = 0, waves: int = 0):
+        """As :meth:`Simulation.set_schedule`, for the batch's launches."""
+        self.sims[0]._order_after_torch()
+        L.check(self.lib.vlb_batch_set_schedule(self._h, int(tile_order), int(waves)),
+                "vlb_batch_set_schedule")
 
     def step(self, n: int = 1):
         self.sims[0]._order_after_torch()

@@ -1,4 +1,5 @@
-"""Autotuner: sweeps tile height and store mode, leaves the state untouched, caches."""
+"""Autotuner: sweeps tile height, store mode, tile order and register budget, leaves the
+state untouched, caches."""
 import json
 
 import numpy as np
@@ -40,7 +41,8 @@ def test_autotune_sweeps_restores_and_caches(tmp_path):
     cache = str(tmp_path / "tune.json")
     rec = tune(sim, steps=20, warmup=3, cache=cache)
     assert rec["tile"] in (1, 2, 4, 8) and rec["store_mode"] in (1, 2)
-    assert len(rec["sweep_us"]) == 8 and min(rec["sweep_us"].values()) == rec["us_per_step"]
+    assert rec["tile_order"] in (1, 2) and rec["waves"] in (3, 4)
+    assert len(rec["sweep_us"]) == 32 and min(rec["sweep_us"].values()) == rec["us_per_step"]
     after = _exact(sim)
     for k in FIELDS:
         assert np.array_equal(before[k], after[k]), k
@@ -76,11 +78,13 @@ def test_tune_batch_picks_a_tile_and_members_stay_exact():
     alone = [Simulation.from_problem(r, stream=stream) for r in runs]
     best, timings = tune_batch(members, tiles=(2, 4, 8), steps=6, warmup=2, graph_chunk=2,
                                forms=(False, True))
-    ty, pers = best
-    assert set(timings) == {(t, f) for t in (2, 4, 8) for f in (False, True)}
+    ty, pers, order, waves = best
+    expect = {(t, False, o, w) for t in (2, 4, 8) for o in (1, 2) for w in (3, 4)}
+    expect |= {(t, True, o, 0) for t in (2, 4, 8) for o in (1, 2)}
+    assert set(timings) == expect
     assert timings[best] == min(timings.values())
-    done = 6 * (2 + 6)
-    b = Batch(members, tile=ty, graph_chunk=2, persistent=pers)
+    done = len(expect) * (2 + 6)
+    b = Batch(members, tile=ty, graph_chunk=2, persistent=pers, schedule=(order, waves))
     b.step(11)
     for s in alone:
         s.step(done + 11)

@@ -59,17 +59,18 @@ def _read_exact(sim):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("ty,chunk", [(4, 20), (2, 0)])
-def test_batch_bit_identical_to_single(precision, ty, chunk):
+@pytest.mark.parametrize("ty,chunk,schedule", [(4, 20, (0, 0)), (2, 0, (2, 3)), (8, 20, (1, 4))])
+def test_batch_bit_identical_to_single(precision, ty, chunk, schedule):
     import torch
     from paper_2508_16997_amd import Batch
 
     runs = _mixed_set(precision)
     stream = torch.cuda.Stream()
-    say("batch bit-identity", precision, "ty", ty, "chunk", chunk, "runs", len(runs))
+    say("batch bit-identity", precision, "ty", ty, "chunk", chunk, "schedule", schedule,
+        "runs", len(runs))
     batched = _make(runs, stream)
     single = _make(runs, stream)
-    b = Batch(batched, tile=ty, graph_chunk=chunk)
+    b = Batch(batched, tile=ty, graph_chunk=chunk, schedule=schedule)
     for n in (1, 129):  # first step, then graph replays and an eager tail
         b.step(n)
         for s in single:
@@ -88,8 +89,8 @@ def test_batch_bit_identical_to_single(precision, ty, chunk):
         s.close()
 
 
-@pytest.mark.parametrize("precision,ty", [("fp32", 4), ("fp32", 8), ("fp64", 2)])
-def test_persistent_batch_bit_identical(precision, ty):
+@pytest.mark.parametrize("precision,ty,order", [("fp32", 4, 0), ("fp32", 8, 2), ("fp64", 2, 1)])
+def test_persistent_batch_bit_identical(precision, ty, order):
     """One cooperative launch per chunk of at most 256 steps, grid-wide barriers between
     the tiles and the fills: same bits as the runs stepped alone, across the first step
     and a chunk boundary (1 + 300 steps = launches of 1, 256 and 44 steps)."""
@@ -101,7 +102,7 @@ def test_persistent_batch_bit_identical(precision, ty):
     say("persistent batch", precision, "ty", ty, "runs", len(runs))
     batched = _make(runs, stream)
     single = _make(runs, stream)
-    b = Batch(batched, tile=ty, persistent=True)
+    b = Batch(batched, tile=ty, persistent=True, schedule=(order, 0))
     for n in (1, 300):
         b.step(n)
         for s in single:

@@ -175,14 +175,17 @@ def test_cylinder_fp32_full_size_1000_steps_golden():
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_results_independent_of_tiling_and_graphs(prec):
-    """Bit-identical fields for every tile height, with and without hipGraph replay."""
+    """Bit-identical fields for every tile height, tile order and register budget, with
+    and without hipGraph replay."""
     from paper_2508_16997_amd import Simulation
 
     pr = synth.random_periodic(100, 45, seed=3, ymode="wall", circles=[(50.0, 20.0, 8.5)])
     say("tiling", prec)
     ref = None
-    for ty, chunk in ((4, 0), (1, 0), (2, 0), (8, 0), (4, 3)):
+    for ty, chunk, order, waves in ((4, 0, 0, 0), (1, 0, 1, 3), (2, 0, 2, 4), (8, 0, 1, 4),
+                                    (4, 3, 2, 3), (8, 3, 2, 4)):
         sim = Simulation.from_problem(pr, precision=prec, tile=ty, graph_chunk=chunk)
+        sim.set_schedule(order, waves)
         sim.step(15)
         g = gpu_fields(sim)
         sim.close()
@@ -190,7 +193,7 @@ def test_results_independent_of_tiling_and_graphs(prec):
             ref = g
         else:
             for k in FIELDS:
-                assert np.array_equal(g[k], ref[k]), (ty, chunk, k)
+                assert np.array_equal(g[k], ref[k]), (ty, chunk, order, waves, k)
 
 
 def test_checkpoint_resume_bit_exact():
