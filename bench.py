@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 METRIC = "coupled MLUPS (FP32) & % HBM roofline; batched vs single; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
+ORDER_NAMES = {0: "automatic", 1: "xcd bands", 2: "row-major", 3: "column strips"}
 
 # HBM bytes per k_step launch on a workload, from rocprofv3 counters (per dispatch, KiB):
 # FETCH_SIZE counts half of the bytes a plain 1 GiB copy reads and WRITE_SIZE all it
@@ -80,7 +81,7 @@ def autotuned_tile(sim):
     with tempfile.TemporaryDirectory() as d:
         rec = tune(sim, cache=os.path.join(d, "autotune.json"), force=True)
     sim.store_mode_name = "cached" if rec["store_mode"] == 1 else "streaming"
-    sim.schedule_desc = {"tile_order": "xcd bands" if rec["tile_order"] == 1 else "row-major",
+    sim.schedule_desc = {"tile_order": ORDER_NAMES[rec["tile_order"]],
                          "waves_per_simd": rec["waves"] or 3}
     return int(rec["tile"])
 
@@ -249,11 +250,11 @@ def batched_leg(steps, warmup, tile, chunk, forms=(False, True), cpu_steps=0):
             "batched_GBs": round(step_bytes * steps / t_batch / 1e9, 1),
             "batched_frac": round(step_bytes * steps / t_batch / 1e9 / HBM_PEAK_GBS, 4),
             "tile": f"64x{tile}", "form": "persistent" if pers else "per-step launches",
-            "tile_order": "xcd bands" if best[2] == 1 else "row-major",
+            "tile_order": ORDER_NAMES[best[2]],
             "waves_per_simd": best[3] or 3,
             "other_form": None if other is None else {
                 "form": "persistent" if other[1] else "per-step launches",
-                "tile": f"64x{other[0]}", "tile_order": "xcd bands" if other[2] == 1 else "row-major",
+                "tile": f"64x{other[0]}", "tile_order": ORDER_NAMES[other[2]],
                 "MLUPS": round(nodes * steps / t_other / 1e6, 2)},
             "runs_nonfinite": int(bad)}
     if cpu_steps:
@@ -395,6 +396,10 @@ def main():
     ap.add_argument("--store-mode", choices=["auto", "cached", "streaming"], default="auto",
                     help="stores of the step kernel when --tile is fixed (the autotuner picks "
                          "its own)")
+    ap.add_argument("--schedule", default="",
+                    help="ORDER,WAVES of the step kernel when --tile is fixed (tile order 1 = "
+                         "XCD bands, 2 = row-major, 3 = column strips; 3 or 4 waves per SIMD); "
+                         "default automatic")
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -442,6 +447,11 @@ def main():
     if args.tile and args.store_mode != "auto":
         sim.set_store_mode(1 if args.store_mode == "cached" else 2)
         sim.store_mode_name = args.store_mode
+    if args.tile and args.schedule:
+        order, waves = (int(v) for v in args.schedule.split(","))
+        sim.set_schedule(order, waves)
+        sim.schedule_desc = {"tile_order": ORDER_NAMES[order],
+                             "waves_per_simd": waves}
     store_mode = getattr(sim, "store_mode_name", None) or auto_store_mode(pr, esz)
     nodes = int(pr.fluid_mask().sum())
     sim.step(args.warmup)

@@ -257,12 +257,14 @@ int vlb_set_store_mode(vlb_sim* sim, int mode);
 int vlb_set_graph_chunk(vlb_sim* sim, int chunk);
 /* Launch schedule of the step kernel; results are bit-identical for every choice.
  * tile_order: 1 = XCD bands (consecutive workgroups go round-robin to the 8 XCDs and each
- * XCD sweeps one contiguous band of tiles, sharing its halo rows in that XCD's L2),
- * 2 = row-major (the whole chip sweeps the grid together), 0 = automatic (bands while
- * the two population buffers fit the last-level cache, row-major beyond).
+ * XCD sweeps one contiguous band of tile rows, sharing its halo rows in that XCD's L2),
+ * 2 = row-major (the whole chip sweeps the grid together), 3 = column strips (each XCD
+ * owns one eighth of the tile columns and all XCDs move down the rows together),
+ * 0 = automatic (bands while the two population buffers fit the last-level cache,
+ * row-major beyond).
  * waves: register budget of the single-precision step kernel, 3 or 4 waves per SIMD
- * (4 spills a few values to scratch), 0 = automatic (4 for a cache-resident state, 3
- * beyond); double precision always runs at its natural allocation.
+ * (the kernel fits 4 without spilling; 3 leaves the compiler more registers), 0 =
+ * automatic (4); double precision always runs at its natural allocation.
  * Errors: VLB_E_INVALID_ARG for other values. */
 int vlb_set_schedule(vlb_sim* sim, int tile_order, int waves);
 

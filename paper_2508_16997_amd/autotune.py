@@ -1,7 +1,8 @@
 """Launch-shape autotuner for the step kernel.
 
 For a simulation it times every tile height (64 x TY threads, TY in 1, 2, 4, 8), both
-store modes (cached, non-temporal), both tile orders (XCD bands, row-major) and, for
+store modes (cached, non-temporal), the three tile orders (XCD bands, row-major, column
+strips) and, for
 single-precision storage, both register budgets of the step kernel (three or four
 waves per SIMD) with HIP events on the simulation's stream, keeps the fastest, and
 caches the choice per size class in a JSON file (``VLB_AUTOTUNE_CACHE`` or
@@ -19,7 +20,7 @@ import torch
 
 TILES = (1, 2, 4, 8)
 STORE_MODES = {1: "cached", 2: "streaming"}
-ORDERS = {1: "xcd", 2: "rows"}
+ORDERS = {1: "xcd", 2: "rows", 3: "strips"}
 CACHE_VERSION = "v2"  # records of an earlier search space are not reused
 
 

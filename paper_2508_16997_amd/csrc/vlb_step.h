@@ -22,17 +22,16 @@
 
 #include "vlb_device.h"
 
-// Register budget of the step kernel, W waves per SIMD for single-precision storage
-// (W = 3: 170 VGPRs, no spills; W = 4: 128 VGPRs with a few spilled, the better choice
-// when the state is cache resident and the launch runs as one wave per SIMD slot);
-// double precision keeps its natural allocation (three waves).
+// Register budget of the step kernel: W waves per SIMD for single-precision storage
+// (124-126 VGPRs, no spills, at either W); double precision at its natural allocation
+// (170 VGPRs, two waves, no spills; a budget of three waves spills 20 bytes per lane).
 template <class S, int TY, int W>
 struct StepBounds {
     static constexpr int threads = 64 * TY;
     static constexpr int min_waves_per_eu = sizeof(S) == 4 ? W : 1;
     // the persistent batch kernel loops over tiles and keeps a few more values live:
-    // three waves per SIMD, without spills in either precision
-    static constexpr int batch_waves_per_eu = 3;
+    // three waves per SIMD for single precision, two for double, without spills
+    static constexpr int batch_waves_per_eu = sizeof(S) == 4 ? 3 : 2;
 };
 
 namespace vlb {
@@ -148,60 +147,60 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     if (!active) return;
 
     // ---- phase 2 ----
-    // neighbour values for the differences: LDS for fluid neighbours, the wall formula
-    // at walls, inlet/outlet ghost values at open ends.
+    // Neighbour values for the differences: LDS for fluid neighbours, the wall formula
+    // at walls, inlet/outlet ghost values at open ends.  d(rho u^3) is taken before the
+    // hydrodynamic collision (which uses it) and the velocity gradient after it (for the
+    // conformation source), so that neither set of values is held across the other work.
     const bool wxl = (b >> 1) & 1u, wxh = (b >> 3) & 1u, wyl = (b >> 2) & 1u, wyh = (b >> 4) & 1u;
-    T qxl = 0.5, qxh = 0.5, qyl = 0.5, qyh = 0.5;
-    if (R.has_curved && (b & 0x1Eu)) {
-        const int bi = R.bidx[p];
-        qxl = link_q(R, bi, 1); qxh = link_q(R, bi, 3);
-        qyl = link_q(R, bi, 2); qyh = link_q(R, bi, 4);
-    }
     const bool open_l = R.xmode == XM_OPEN && x == 0;
     const bool open_h = R.xmode == XM_OPEN && x == R.nx - 1;
-    T rl = 0.0, uxl = 0.0, uyl = 0.0, rh = 0.0, uxh = 0.0, uyh = 0.0;
-    if (open_l) { rl = 1.0; uxl = R.inlet[y]; }
-    else if (!wxl) { rl = s_rho[ly + 1][lx]; uxl = s_ux[ly + 1][lx]; uyl = s_uy[ly + 1][lx]; }
-    if (open_h) { rh = rho; uxh = ux; uyh = uy; }
-    else if (!wxh) { rh = s_rho[ly + 1][lx + 2]; uxh = s_ux[ly + 1][lx + 2]; uyh = s_uy[ly + 1][lx + 2]; }
-    T rd = 0.0, uxd = 0.0, uyd = 0.0, ru = 0.0, uxu = 0.0, uyu = 0.0;
-    if (!wyl) { rd = s_rho[ly][lx + 1]; uxd = s_ux[ly][lx + 1]; uyd = s_uy[ly][lx + 1]; }
-    if (!wyh) { ru = s_rho[ly + 2][lx + 1]; uxu = s_ux[ly + 2][lx + 1]; uyu = s_uy[ly + 2][lx + 1]; }
-    const T Lxx = dgrad(wxl, qxl, uxl, ux, wxh, qxh, uxh);
-    const T Lxy = dgrad(wxl, qxl, uyl, uy, wxh, qxh, uyh);
-    T Lyx = dgrad(wyl, qyl, uxd, ux, wyh, qyh, uxu);
-    T Lyy = dgrad(wyl, qyl, uyd, uy, wyh, qyh, uyu);
-    const T Dx = dgrad(wxl, qxl, rl * uxl * uxl * uxl, rho * ux * ux * ux, wxh, qxh,
-                       rh * uxh * uxh * uxh);
-    T Dy = dgrad(wyl, qyl, rd * uyd * uyd * uyd, rho * uy * uy * uy, wyh, qyh,
-                 ru * uyu * uyu * uyu);
-    if (wet_row(R, y)) {
-        // wall node of a wet-node wall: wall-normal derivatives by the one-sided
-        // second-order difference through the node and the next two rows (the nearer
-        // from the tile's LDS, the farther from s_w2)
-        const bool bot = y == 0;
-        const int w = bot ? 0 : 1;
-        const T s1 = bot ? 1.0 : -1.0;
-        const T r1 = bot ? ru : rd, ux1 = bot ? uxu : uxd, uy1 = bot ? uyu : uyd;
-        Lyx = s1 * (-1.5 * ux + 2.0 * ux1 - 0.5 * s_w2[w][0][lx]);
-        Lyy = s1 * (-1.5 * uy + 2.0 * uy1 - 0.5 * s_w2[w][1][lx]);
-        Dy = s1 * (-1.5 * (rho * uy * uy * uy) + 2.0 * (r1 * uy1 * uy1 * uy1) -
-                   0.5 * s_w2[w][2][lx]);
+    // wall fractions of the four axis links (1/2 on flat walls): low x, high x, low y, high y
+    auto wall_q = [&](T q[4]) {
+        q[0] = q[1] = q[2] = q[3] = 0.5;
+        if (R.has_curved && (b & 0x1Eu)) {
+            const int bi = R.bidx[p];
+            q[0] = link_q(R, bi, 1); q[1] = link_q(R, bi, 3);
+            q[2] = link_q(R, bi, 2); q[3] = link_q(R, bi, 4);
+        }
+    };
+    // the four axis neighbours of rho (v = 0), u_x (1) or u_y (2)
+    auto nbs = [&](int v, T& xl, T& xh, T& yl, T& yh) {
+        auto fld = [&](int yy, int xx) -> T {
+            return v == 0 ? s_rho[yy][xx] : (v == 1 ? s_ux[yy][xx] : s_uy[yy][xx]);
+        };
+        const T own = v == 0 ? rho : (v == 1 ? ux : uy);
+        xl = open_l ? (v == 0 ? T(1.0) : (v == 1 ? T(R.inlet[y]) : T(0.0))) : (wxl ? 0.0 : fld(ly + 1, lx));
+        xh = open_h ? own : (wxh ? 0.0 : fld(ly + 1, lx + 2));
+        yl = wyl ? 0.0 : fld(ly, lx + 1);
+        yh = wyh ? 0.0 : fld(ly + 2, lx + 1);
+    };
+    // wet-node wall row: wall-normal derivatives by the one-sided second-order
+    // difference through the node and the next two rows (the nearer from the tile's LDS,
+    // the farther from s_w2)
+    const bool wet = wet_row(R, y);
+    const int wsd = y == 0 ? 0 : 1;
+    const T s1 = y == 0 ? 1.0 : -1.0;
+    T Dx, Dy;
+    {
+        T q[4], rxl, rxh, ryl, ryh, axl, axh, ayl, ayh, bxl, bxh, byl, byh;
+        wall_q(q);
+        nbs(0, rxl, rxh, ryl, ryh);
+        nbs(1, axl, axh, ayl, ayh);
+        nbs(2, bxl, bxh, byl, byh);
+        Dx = dgrad(wxl, q[0], rxl * axl * axl * axl, rho * ux * ux * ux, wxh, q[1], rxh * axh * axh * axh);
+        Dy = dgrad(wyl, q[2], ryl * byl * byl * byl, rho * uy * uy * uy, wyh, q[3], ryh * byh * byh * byh);
+        if (wet) {
+            const T r1 = y == 0 ? ryh : ryl, uy1 = y == 0 ? byh : byl;
+            Dy = s1 * (-1.5 * (rho * uy * uy * uy) + 2.0 * (r1 * uy1 * uy1 * uy1) -
+                       0.5 * s_w2[wsd][2][lx]);
+        }
     }
-
     const T d0 = dk[0], d1 = dk[1], d2 = dk[2];
-    const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
-    T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
-    if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
-    const T txx = R.eta_over_lam * sf[0], txy = R.eta_over_lam * sf[1], tyy = R.eta_over_lam * sf[2];
-    T Sc[3];
-    if (R.no_source) {
-        Sc[0] = Sc[1] = Sc[2] = 0.0;
-    } else {
-        const T d = Lxx + Lyy;
-        Sc[0] = -R.inv_lam * rf[0] + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
-        Sc[1] = -R.inv_lam * rf[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
-        Sc[2] = -R.inv_lam * rf[2] + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
+    T txx, txy, tyy;
+    {
+        T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
+        if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
+        txx = R.eta_over_lam * sf[0], txy = R.eta_over_lam * sf[1], tyy = R.eta_over_lam * sf[2];
     }
 
     // Post-collision populations of the four lattices, in storage precision, stored
@@ -227,6 +226,35 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
 #pragma unroll
         for (int i = 0; i < 9; ++i) put(i, out[i]);
     }
+    // velocity gradient, constitutive source S(t) and the history the next step needs
+    T Sc[3];
+    {
+        T q[4], axl, axh, ayl, ayh, bxl, bxh, byl, byh;
+        wall_q(q);
+        nbs(1, axl, axh, ayl, ayh);
+        nbs(2, bxl, bxh, byl, byh);
+        const T Lxx = dgrad(wxl, q[0], axl, ux, wxh, q[1], axh);
+        const T Lxy = dgrad(wxl, q[0], bxl, uy, wxh, q[1], bxh);
+        T Lyx = dgrad(wyl, q[2], ayl, ux, wyh, q[3], ayh);
+        T Lyy = dgrad(wyl, q[2], byl, uy, wyh, q[3], byh);
+        if (wet) {
+            const T ux1 = y == 0 ? ayh : ayl, uy1 = y == 0 ? byh : byl;
+            Lyx = s1 * (-1.5 * ux + 2.0 * ux1 - 0.5 * s_w2[wsd][0][lx]);
+            Lyy = s1 * (-1.5 * uy + 2.0 * uy1 - 0.5 * s_w2[wsd][1][lx]);
+        }
+        const T axx = 1.0 + d0, axy = d1, ayy = 1.0 + d2;
+        T rf[3] = {d0, d1, d2}, sf[3] = {d0, d1, d2};
+        if (R.model != MODEL_OLDROYD_B) closure(R.model, R.mpar, d0, d1, d2, rf, sf);
+        if (R.no_source) {
+            Sc[0] = Sc[1] = Sc[2] = 0.0;
+        } else {
+            const T d = Lxx + Lyy;
+            Sc[0] = -R.inv_lam * rf[0] + 2.0 * (axx * Lxx + axy * Lyx) + axx * d;
+            Sc[1] = -R.inv_lam * rf[1] + axx * Lxy + axy * Lyy + axy * Lxx + ayy * Lyx + axy * d;
+            Sc[2] = -R.inv_lam * rf[2] + 2.0 * (axy * Lxy + ayy * Lyy) + ayy * d;
+        }
+    }
+    hist_st<NT>(R.hist_out, plane, (unsigned)p, Sc, ux, uy);
     // conformation lattices one at a time after the hydrodynamic one (keeps the
     // register budget of four waves per SIMD): CNEBB at wall-adjacent nodes, moments,
     // collision
@@ -267,7 +295,6 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     };
 #pragma unroll
     for (int i = 0; i < 9; ++i) st4<NT>(dst, plane, i, (unsigned)p, post4(i));
-    hist_st<NT>(R.hist_out, plane, (unsigned)p, Sc, ux, uy);
     // Open ends (Sec. 4.3): the first (last) column node writes the ghosts its row's
     // inlet (outlet) links pull next step by non-equilibrium extrapolation from its own
     // post-collision populations (as stored): f_i = f_i^eq(rho_b, u_b) + f_i -

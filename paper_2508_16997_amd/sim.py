@@ -6,6 +6,7 @@ step of the method runs in the library's kernels.  Nothing here computes physics
 from __future__ import annotations
 
 import ctypes as C
+import sys
 from typing import Optional
 
 import numpy as np
@@ -223,7 +224,7 @@ class Simulation:
         L.check(self.lib.vlb_set_store_mode(self._h, int(mode)), "vlb_set_store_mode")
 
     def set_schedule(self, tile_order: int = 0, waves: int = 0):
-        """Tile order (0 auto, 1 XCD bands, 2 row-major) and register budget of the
+        """Tile order (0 auto, 1 XCD bands, 2 row-major, 3 column strips) and register budget of the
         single-precision step kernel (0 auto, 3 or 4 waves per SIMD)."""
         L.check(self.lib.vlb_set_schedule(self._h, int(tile_order), int(waves)),
                 "vlb_set_schedule")
@@ -303,6 +304,10 @@ class Simulation:
             self._h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime (and a profiler's hooks) may already
+        # be torn down: leave the handle to process exit instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -389,6 +394,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime (and a profiler's hooks) may already
+        # be torn down: leave the handle to process exit instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

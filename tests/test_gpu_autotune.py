@@ -41,8 +41,8 @@ def test_autotune_sweeps_restores_and_caches(tmp_path):
     cache = str(tmp_path / "tune.json")
     rec = tune(sim, steps=20, warmup=3, cache=cache)
     assert rec["tile"] in (1, 2, 4, 8) and rec["store_mode"] in (1, 2)
-    assert rec["tile_order"] in (1, 2) and rec["waves"] in (3, 4)
-    assert len(rec["sweep_us"]) == 32 and min(rec["sweep_us"].values()) == rec["us_per_step"]
+    assert rec["tile_order"] in (1, 2, 3) and rec["waves"] in (3, 4)
+    assert len(rec["sweep_us"]) == 48 and min(rec["sweep_us"].values()) == rec["us_per_step"]
     after = _exact(sim)
     for k in FIELDS:
         assert np.array_equal(before[k], after[k]), k
@@ -79,8 +79,8 @@ def test_tune_batch_picks_a_tile_and_members_stay_exact():
     best, timings = tune_batch(members, tiles=(2, 4, 8), steps=6, warmup=2, graph_chunk=2,
                                forms=(False, True))
     ty, pers, order, waves = best
-    expect = {(t, False, o, w) for t in (2, 4, 8) for o in (1, 2) for w in (3, 4)}
-    expect |= {(t, True, o, 0) for t in (2, 4, 8) for o in (1, 2)}
+    expect = {(t, False, o, w) for t in (2, 4, 8) for o in (1, 2, 3) for w in (3, 4)}
+    expect |= {(t, True, o, 0) for t in (2, 4, 8) for o in (1, 2, 3)}
     assert set(timings) == expect
     assert timings[best] == min(timings.values())
     done = len(expect) * (2 + 6)

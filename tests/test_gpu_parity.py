@@ -182,8 +182,8 @@ def test_results_independent_of_tiling_and_graphs(prec):
     pr = synth.random_periodic(100, 45, seed=3, ymode="wall", circles=[(50.0, 20.0, 8.5)])
     say("tiling", prec)
     ref = None
-    for ty, chunk, order, waves in ((4, 0, 0, 0), (1, 0, 1, 3), (2, 0, 2, 4), (8, 0, 1, 4),
-                                    (4, 3, 2, 3), (8, 3, 2, 4)):
+    for ty, chunk, order, waves in ((4, 0, 0, 0), (1, 0, 1, 3), (2, 0, 2, 4), (8, 0, 3, 4),
+                                    (4, 3, 2, 3), (8, 3, 3, 3)):
         sim = Simulation.from_problem(pr, precision=prec, tile=ty, graph_chunk=chunk)
         sim.set_schedule(order, waves)
         sim.step(15)
