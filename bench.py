@@ -34,21 +34,14 @@ ORDER_NAMES = {0: "automatic", 1: "xcd bands", 2: "row-major", 3: "column strips
 # times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
     "four_roll_512": [
-        {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "streaming",
-         "fetch_KiB": 24953.2, "write_KiB": 42417.8,
-         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write.md"},
-        {"sources": "6c52ea7c87ecb45a", "tile": 8, "store_mode": "cached",
-         "fetch_KiB": 25170.2, "write_KiB": 42416.0,
-         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
-        {"sources": "6c52ea7c87ecb45a", "tile": 4, "store_mode": "streaming",
-         "fetch_KiB": 25549.2, "write_KiB": 42416.2,
-         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
-        {"sources": "6c52ea7c87ecb45a", "tile": 4, "store_mode": "cached",
-         "fetch_KiB": 25537.6, "write_KiB": 42416.0,
-         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
-        {"sources": "6c52ea7c87ecb45a", "tile": 2, "store_mode": "streaming",
-         "fetch_KiB": 26260.7, "write_KiB": 42418.2,
-         "profile": "profiles/k_step_four_roll_512_fp32_fetch_write_by_tile.md"},
+        {"sources": "dc75f4b57e0c0b7c", "tile": 8, "store_mode": "streaming",
+         "tile_order": "xcd bands", "fetch_KiB": 25093.4, "write_KiB": 42150.6,
+         "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
+    ],
+    "cylinder_4096x1024": [
+        {"sources": "dc75f4b57e0c0b7c", "tile": 4, "store_mode": "streaming",
+         "tile_order": "row-major", "fetch_KiB": 441844.4, "write_KiB": 663802.0,
+         "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
     ],
 }
 KERNEL_SOURCES = ("vlb_device.h", "vlb_internal.h", "vlb_step.h", "vlb_kernels.hip")
@@ -86,10 +79,10 @@ def autotuned_tile(sim):
     return int(rec["tile"])
 
 
-def measured_traffic(workload_name, tile, store_mode):
+def measured_traffic(workload_name, tile, store_mode, tile_order):
     for rec in MEASURED_TRAFFIC.get(workload_name, []):
         if (rec["sources"] == kernel_sources_hash() and rec["tile"] == tile
-                and rec["store_mode"] == store_mode):
+                and rec["store_mode"] == store_mode and rec["tile_order"] == tile_order):
             return int(round((2.0 * rec["fetch_KiB"] + rec["write_KiB"]) * 1024))
     return None
 
@@ -183,7 +176,11 @@ def cylinder_leg(steps, warmup, tile, chunk, cpu_steps=0):
            "frac_basis": "328 B per fluid node over the whole step (k_step + k_fill, HIP "
                          "events on the launch stream); the working set (1.4 GB) is HBM "
                          "resident, so this is the gating HBM fraction",
-           "tile": f"64x{tile}", **getattr(sim, "schedule_desc", {}), "nonfinite": int(bad)}
+           "tile": f"64x{tile}", **getattr(sim, "schedule_desc", {}),
+           "traffic": measured_traffic("cylinder_4096x1024", tile,
+                                       getattr(sim, "store_mode_name", None) or auto_store_mode(pr, 4),
+                                       getattr(sim, "schedule_desc", {}).get("tile_order")),
+           "nonfinite": int(bad)}
     if cpu_steps:
         out["cpu_baseline"] = cpu_baseline_steps([pr], cpu_steps, "the same 4096x1024 workload")
     return out
@@ -504,7 +501,8 @@ def main():
                    "graph_chunk_steps": 2 * args.graph_chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, tile, store_mode),
+                     "traffic": measured_traffic(args.workload, tile, store_mode,
+                                                 getattr(sim, "schedule_desc", {}).get("tile_order")),
                      "kernel": "k_step",
                      "avg_launch_us": round(launch_s * 1e6, 3),
                      "bytes_per_launch": bytes_launch,
