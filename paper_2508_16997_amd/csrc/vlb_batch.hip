@@ -14,10 +14,10 @@ namespace vlb {
 namespace {
 
 // Persistent form for batches: one cooperative launch advances every run nsteps steps.
-// The XCD-ordered item list is split into nq queues (item w belongs to queue w % nq;
-// nq = 8 when the grid has at least 8 workgroups), one per band of tiles.  A workgroup
-// first draws items of the queue of the XCD it runs on from that queue's atomic
-// counter, so each XCD sweeps its band in order (neighbouring tiles, whose rows the
+// The ordered item list is split into nq queues (item w belongs to queue w % nq;
+// nq = 8 when the grid has at least 8 workgroups).  A workgroup first draws items --
+// kBatchChunk consecutive entries per atomic -- of the queue of the XCD it runs on from
+// that queue's atomic counter, so each XCD sweeps its band in order (neighbouring tiles, whose rows the
 // pulls share, run at about the same time and meet in that XCD's L2) and faster
 // workgroups take more tiles; then it helps drain the other queues, so every item is
 // taken whatever the placement of the workgroups.  A grid-wide barrier separates the
@@ -25,6 +25,9 @@ namespace {
 // step.  Two counter sets alternate between steps; the set of step n + 1 is cleared
 // during the fills of step n, when nobody draws from it, and the last one after the
 // final barrier, so both are zero between launches.
+// Consecutive queue entries a workgroup takes per atomic draw.
+constexpr int kBatchChunk = 4;
+
 template <class S, int TY, bool NT>
 __global__ __launch_bounds__((StepBounds<S, TY, 3>::threads), (StepBounds<S, TY, 3>::batch_waves_per_eu)) void k_batch(
     const RunDev<S>* __restrict__ runs, const Item* __restrict__ items, int nitems,
@@ -43,17 +46,20 @@ __global__ __launch_bounds__((StepBounds<S, TY, 3>::threads), (StepBounds<S, TY,
             const int qlen = (nitems - q + nq - 1) / nq;  // items q, q + nq, ...
             int* ctr = queues + (n & 1) * kBatchQueues + q;
             __syncthreads();  // every read of s_next is done
-            if (tid == 0) s_next = atomicAdd(ctr, 1);
+            if (tid == 0) s_next = atomicAdd(ctr, kBatchChunk);
             __syncthreads();
             int k = s_next;
             while (k < qlen) {
-                // draw the following item now: the atomic's round trip overlaps this tile
+                // draw the following chunk now: the atomic's round trip overlaps this one
                 int k_next = 0;
-                if (tid == 0) k_next = atomicAdd(ctr, 1);
-                int lane0;
-                asm volatile("v_mov_b32 %0, 0" : "=v"(lane0));
-                step_tile<S, TY, NT>(runs, items[q + k * nq], parity, first, lane0);
-                __syncthreads();  // this tile's LDS reads and every read of s_next are done
+                if (tid == 0) k_next = atomicAdd(ctr, kBatchChunk);
+                const int kend = min(k + kBatchChunk, qlen);
+                for (int kk = k; kk < kend; ++kk) {
+                    int lane0;
+                    asm volatile("v_mov_b32 %0, 0" : "=v"(lane0));
+                    step_tile<S, TY, NT>(runs, items[q + kk * nq], parity, first, lane0);
+                    __syncthreads();  // this tile's LDS reads are done (and every read of s_next)
+                }
                 if (tid == 0) s_next = k_next;
                 __syncthreads();
                 k = s_next;
