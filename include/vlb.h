@@ -271,8 +271,10 @@ int vlb_set_schedule(vlb_sim* sim, int tile_order, int waves);
 /* ---- adjoint ------------------------------------------------------------------------ */
 
 /* Discrete adjoint of nsteps coupled steps (Sec. 3, Eqs. 31-51, differentiated step by
- * step in reverse order) for fully periodic domains without solid nodes, with any of
- * the constitutive closures above.  The
+ * step in reverse order) for domains whose axes are periodic or VLB_WALL, with solid
+ * masks and circles (the transposes of half-way and interpolated bounce-back, Sec. 3.3
+ * and 4.3, of CNEBB, Sec. 3.3, and of the wall-aware velocity-gradient differences),
+ * with any of the constitutive closures above.  The
  * differentiated quantities are the relaxation time lambda, the polymer viscosity
  * eta_p and the per-node body force F(x) (held fixed over the steps; with a uniform
  * force the gradient is still returned per node).  Memory: sqrt(N) checkpointing --
@@ -287,9 +289,11 @@ int vlb_set_schedule(vlb_sim* sim, int tile_order, int waves);
  *   or re-parameterised since), given dL/du of the velocity read out at the last step
  *   (device, [ny][nx], simulation precision), returns dL/dlambda and dL/deta_p (host)
  *   and dL/dF_x, dL/dF_y (device, [ny][nx], double; NULL to skip).  Synchronizes.
+ *   Solid nodes get zero force gradients; their entries of dL/du are ignored.
  * vlb_adjoint: both, for the loss L = (1 / 2N) sum_x |u(x, T) - u*(x)|^2 over the N
- *   nodes, with the target u* (device, [ny][nx], simulation precision); *loss gets L.
- * Errors: VLB_E_UNSUPPORTED (walls, open ends or solids), VLB_E_INVALID_ARG,
+ *   fluid nodes, with the target u* (device, [ny][nx], simulation precision; values at
+ *   solid nodes are ignored); *loss gets L.
+ * Errors: VLB_E_UNSUPPORTED (VLB_OPEN x or VLB_WET y), VLB_E_INVALID_ARG,
  * VLB_E_WORKSPACE, VLB_E_STATE (backward without a matching forward), VLB_E_HIP. */
 int vlb_adjoint_workspace_bytes(const vlb_sim* sim, int64_t nsteps, int stride, size_t* bytes);
 int vlb_adjoint_forward(vlb_sim* sim, int64_t nsteps, int stride, void* workspace_dev,

@@ -4,8 +4,8 @@
 ``nsteps`` coupled steps from a simulation's current state.  Its forward pass runs the
 steps with checkpoints and its backward pass runs the hand-written adjoint kernels
 (reverse sweep with segment recompute).  Both passes are HIP work; this module only
-moves arguments.  Fully periodic domains only (the library reports others as
-unsupported).
+moves arguments.  Periodic axes, half-way walls, solid masks and circles; the library
+reports open ends and wet-node walls as unsupported.
 """
 from __future__ import annotations
 

@@ -1,23 +1,30 @@
-// vlb_adjoint.hip -- discrete adjoint of the coupled step on periodic domains.
+// vlb_adjoint.hip -- discrete adjoint of the coupled step on domains with periodic axes,
+// half-way walls, solid nodes and curved (circle) walls.
 //
 // The reverse sweep of time step n maps the adjoint of the state after the step
 // (post-streaming populations of all four lattices and the S/u history) to the adjoint
 // of the state before it, and accumulates the parameter gradients.  Two launches:
 //   k_adj_local   per node: recomputes the forward quantities of step n from the
 //                 stored state exactly as the step kernel does (pulls, rho/u of a
-//                 one-node ring in LDS, central differences, constitutive source),
+//                 one-node ring in LDS, wall-aware differences, constitutive source),
 //                 pulls the adjoint of its post-collision populations from x + e_i
-//                 (transpose of the pull), and applies the transposed moment-form
-//                 collisions, constitutive source and polymer stress.  It writes the
+//                 (transpose of the pull) or, on wall links, from the boundary rule's
+//                 transpose (half-way or interpolated bounce-back for f, the copy into
+//                 the CNEBB input for g), applies the transposed moment-form collisions,
+//                 constitutive source and polymer stress, then the transpose of CNEBB
+//                 at wall-adjacent nodes.  It writes the
 //                 final conformation-lattice adjoints, the adjoint of the history
 //                 input, per-node intermediates for the second pass, and adds its
 //                 block's share of dL/dlambda and dL/deta_p.
-//   k_adj_gather  per node: transpose of the central differences (the velocity
-//                 gradient and d(rho u^3) of the four axis neighbours), then of the
+//   k_adj_gather  per node: transpose of the finite differences (the velocity gradient
+//                 and d(rho u^3) of the node and its four axis neighbours, each with the
+//                 coefficients its own wall configuration gives them), then of the
 //                 macroscopic moments (rho, u with the half-force shift): the final
 //                 hydrodynamic adjoint populations; accumulates dL/dF in double.
 // A seed kernel turns dL/du at the last step (or a target velocity, for the mean
-// squared error) into the adjoint of the last state.
+// squared error over the fluid nodes) into the adjoint of the last state.
+// Solid nodes carry zero adjoints: fluid nodes read the adjoints of the values their
+// pulls took from solid slots at their own slot (the fill's transpose), never there.
 // Arithmetic is double; adjoint planes use the storage type S of the forward state.
 #include "vlb_device.h"
 
@@ -166,6 +173,84 @@ __device__ __forceinline__ void collide_cde_adj(const RunDev<S>& R, T phi, T ux,
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Transpose of cnebb() (conservative non-equilibrium bounce-back, Sec. 3.3) at a node with
+// unknown set `solid` (bits 1..8): gr_i = E_i(s, u) + [opp(i) known] (g_opp(i) - E_opp(i)(s, u))
+// for unknown i, gr_i = g_i for known i >= 1, gr_0 = s - sum_{i >= 1} gr_i, with
+// s = sum_i g_i and E_i(s, u) = w_i [s + (phi0 + s) P_i(u)],
+// P_i(u) = 3 e_i.u + 4.5 (e_i.u)^2 - 1.5 u.u.  Given the adjoints ga of gr, returns in ga
+// the adjoints of the pulled g and adds the velocity adjoints to aux, auy.
+__device__ __forceinline__ void cnebb_adj(unsigned solid, int k, T s, T ux, T uy, T ga[9], T& aux,
+                                          T& auy) {
+    const T phi = phi0(k) + s;
+    T b[9], ag[9], as = ga[0];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ag[i] = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) b[i] = ga[i] - ga[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        if (!((solid >> i) & 1u)) {
+            ag[i] += b[i];
+            continue;
+        }
+        auto dE = [&](int j, T& ds, T& dx, T& dy) {
+            const T cx = T(ex(j)), cy = T(ey(j));
+            const T eu = cx * ux + cy * uy;
+            ds = wgt(j) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
+            dx = wgt(j) * phi * (3.0 * cx + 9.0 * eu * cx - 3.0 * ux);
+            dy = wgt(j) * phi * (3.0 * cy + 9.0 * eu * cy - 3.0 * uy);
+        };
+        T ds, dx, dy;
+        dE(i, ds, dx, dy);
+        const int o = opp(i);
+        if (!((solid >> o) & 1u)) {
+            T ds2, dx2, dy2;
+            dE(o, ds2, dx2, dy2);
+            ds -= ds2;
+            dx -= dx2;
+            dy -= dy2;
+            ag[o] += b[i];
+        }
+        as += b[i] * ds;
+        aux += b[i] * dx;
+        auy += b[i] * dy;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ga[i] = ag[i] + as;
+}
+
+// Coefficients of dgrad() along one axis of a node: the derivative is
+// c[0] psi(low neighbour) + c[1] psi(node) + c[2] psi(high neighbour).
+__device__ __forceinline__ void fd_coefs(bool lo_wall, T qlo, bool hi_wall, T qhi, T c[3]) {
+    if (!lo_wall && !hi_wall) { c[0] = -0.5; c[1] = 0.0; c[2] = 0.5; }
+    else if (lo_wall && !hi_wall) { c[0] = 0.0; c[1] = (1.0 - qlo) / qlo; c[2] = qlo / (1.0 + qlo); }
+    else if (!lo_wall) { c[0] = -(qhi / (1.0 + qhi)); c[1] = -((1.0 - qhi) / qhi); c[2] = 0.0; }
+    else { c[0] = 0.0; c[1] = (qhi - qlo) / (qlo * qhi); c[2] = 0.0; }
+}
+// Both axes of node slot p (x: low/high = directions 1/3, y: 2/4 as in the step kernel).
+template <class S>
+__device__ __forceinline__ void node_fd_coefs(const RunDev<S>& R, int p, unsigned b, T cx[3],
+                                              T cy[3]) {
+    T q1 = 0.5, q2 = 0.5, q3 = 0.5, q4 = 0.5;
+    if (R.has_curved && (b & 0x1Eu)) {
+        const int bi = R.bidx[p];
+        q1 = link_q(R, bi, 1); q3 = link_q(R, bi, 3);
+        q2 = link_q(R, bi, 2); q4 = link_q(R, bi, 4);
+    }
+    fd_coefs((b >> 1) & 1u, q1, (b >> 3) & 1u, q3, cx);
+    fd_coefs((b >> 2) & 1u, q2, (b >> 4) & 1u, q4, cy);
+}
+
+// Slot of the neighbour x + e_i across periodic axes (unwrapped across walls, where
+// the caller's geometry bits say it is not a fluid node).
+template <class S>
+__device__ __forceinline__ int nb_slot(const RunDev<S>& R, int x, int y, int dx, int dy) {
+    int xx = x + dx, yy = y + dy;
+    if (R.xmode == XM_PERIODIC) xx = wrapm(xx, R.nx);
+    if (R.ymode == XM_PERIODIC) yy = wrapm(yy, R.ny);
+    return node_index(R, xx, yy);
+}
+
 // Sum of one double over the block into slot[0] (+= when add, = otherwise).
 template <int TY>
 __device__ __forceinline__ void block_sum(T v, T* s_red, double* slot, bool add) {
@@ -203,11 +288,13 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
     const int x = x0 + lx, y = y0 + ly;
     const bool in_dom = x < R.nx && y < R.ny;
     const int p = node_index(R, x, y);
+    const unsigned b = in_dom ? node_bits(R, p) : 0u;
+    const bool active = in_dom && !(b & BIT_SELF_SOLID);
 
-    // ---- forward front end of step n (as in the step kernel; periodic domain) ----
+    // ---- forward front end of step n (as in the step kernel) ----
     S f[9], g[3][9];
     T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
-    if (in_dom) {
+    if (active) {
         pull36(R, src, p, pull, f, g);
         node_force(R, p, Fx, Fy);
         if (pull) hist_ld(R.hist, plane, (unsigned)p, hS, hux, huy);
@@ -226,12 +313,12 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
         }
     }
     T drho = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
-    if (in_dom) {
+    if (active) {
         hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
         s_rho[ly + 1][lx + 1] = rho;
         s_ux[ly + 1][lx + 1] = ux;
         s_uy[ly + 1][lx + 1] = uy;
-    } else {
+    } else if (!in_dom) {
         T rr, vx, vy;
         if (cell_macros(R, src, x, y, pull, rr, vx, vy)) {
             s_rho[ly + 1][lx + 1] = rr;
@@ -242,14 +329,27 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
     __syncthreads();
 
     T glam = 0.0, geta = 0.0;
-    if (in_dom) {
-        const T rl = s_rho[ly + 1][lx], uxl = s_ux[ly + 1][lx], uyl = s_uy[ly + 1][lx];
-        const T rh = s_rho[ly + 1][lx + 2], uxh = s_ux[ly + 1][lx + 2], uyh = s_uy[ly + 1][lx + 2];
-        const T rd = s_rho[ly][lx + 1], uxd = s_ux[ly][lx + 1], uyd = s_uy[ly][lx + 1];
-        const T ru = s_rho[ly + 2][lx + 1], uxu = s_ux[ly + 2][lx + 1], uyu = s_uy[ly + 2][lx + 1];
-        const T Lxx = 0.5 * (uxh - uxl), Lxy = 0.5 * (uyh - uyl);
-        const T Lyx = 0.5 * (uxu - uxd), Lyy = 0.5 * (uyu - uyd);
-        (void)rl; (void)rh; (void)rd; (void)ru;
+    if (in_dom && !active) {
+        // solid node: nothing flows through it
+        for (int c = 0; c < 41; ++c) stu(aout + c * plane, (unsigned)p, 0.0);
+        for (int c = 0; c < SC_NPLANES; ++c) stu(A.scr + c * plane, (unsigned)p, 0.0);
+    }
+    if (active) {
+        // velocity gradient by the step kernel's differences (wall-aware at fraction q)
+        const bool wxl = (b >> 1) & 1u, wxh = (b >> 3) & 1u, wyl = (b >> 2) & 1u, wyh = (b >> 4) & 1u;
+        const T uxl = wxl ? 0.0 : s_ux[ly + 1][lx], uyl = wxl ? 0.0 : s_uy[ly + 1][lx];
+        const T uxh = wxh ? 0.0 : s_ux[ly + 1][lx + 2], uyh = wxh ? 0.0 : s_uy[ly + 1][lx + 2];
+        const T uxd = wyl ? 0.0 : s_ux[ly][lx + 1], uyd = wyl ? 0.0 : s_uy[ly][lx + 1];
+        const T uxu = wyh ? 0.0 : s_ux[ly + 2][lx + 1], uyu = wyh ? 0.0 : s_uy[ly + 2][lx + 1];
+        T qq[5] = {0.5, 0.5, 0.5, 0.5, 0.5};
+        if (R.has_curved && (b & 0x1Eu)) {
+            const int bi = R.bidx[p];
+            for (int i = 1; i <= 4; ++i) qq[i] = link_q(R, bi, i);
+        }
+        const T Lxx = dgrad(wxl, qq[1], uxl, ux, wxh, qq[3], uxh);
+        const T Lxy = dgrad(wxl, qq[1], uyl, uy, wxh, qq[3], uyh);
+        const T Lyx = dgrad(wyl, qq[2], uxd, ux, wyh, qq[4], uxu);
+        const T Lyy = dgrad(wyl, qq[2], uyd, uy, wyh, qq[4], uyu);
 
         Mom gm[3];
 #pragma unroll
@@ -270,16 +370,53 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
             hux = ux; huy = uy;
         }
 
-        // neighbour x + e_i (periodic) from which the adjoint of direction i is pulled
-        const int xl = wrapm(x - 1, R.nx), xh = wrapm(x + 1, R.nx);
-        const int yl = wrapm(y - 1, R.ny), yh = wrapm(y + 1, R.ny);
-        const int row[3] = {R.off0 + yl * R.pitch, R.off0 + y * R.pitch, R.off0 + yh * R.pitch};
-        const int col[3] = {xl, x, xh};
-        auto nb = [&](int i) -> unsigned { return (unsigned)(row[1 + ey(i)] + col[1 + ex(i)]); };
+        // Adjoint of the post-collision population of direction i: where it streams --
+        // the neighbour x + e_i (across periodic axes) -- or, when that neighbour is
+        // solid, the boundary rule of this node's pull in direction opp(i) that used it
+        // (the transpose of k_fill).  Interpolated bounce-back on a curved link of
+        // fraction q (pull direction d, o = opp(d), far = x + e_d):
+        //   q < 1/2: f_d(x) = 2q f_o(x) + (1 - 2q) f_o(far)   (half-way if far is solid)
+        //   q >= 1/2: f_d(x) = f_o(x) / 2q + (2q - 1) / 2q f_d(x)
+        // so f_i(x) also feeds the pull of x in direction i (second branch) and, as
+        // f_o(far), the pull of the neighbour x + e_i in direction opp(i) (first branch).
+        // The conformation lattices copy f_o(x) into the CNEBB input of direction d.
+        auto nb = [&](int i) -> unsigned { return (unsigned)nb_slot(R, x, y, ex(i), ey(i)); };
+        auto lq = [&](unsigned bits, int slot, int i) -> T {
+            return (R.has_curved && ((bits >> i) & 1u)) ? link_q(R, R.bidx[slot], i) : 0.5;
+        };
+        auto solid_nb = [&](int i) -> bool { return (b >> opp(i)) & 1u; };
 
         T o[9];
+        o[0] = ldu(ain, (unsigned)p);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) o[i] = ldu(ain + i * plane, nb(i));
+        for (int i = 1; i < 9; ++i) {
+            const int d = opp(i);
+            T v;
+            if (!solid_nb(i)) {
+                const unsigned q_ = nb(i);
+                v = ldu(ain + i * plane, q_);
+                if (R.has_curved) {
+                    // (first branch at the neighbour) x + e_i pulls d from x + 2 e_i
+                    const unsigned bn = node_bits(R, (int)q_);
+                    if ((bn >> d) & 1u) {
+                        const T qn = lq(bn, (int)q_, d);
+                        if (qn < 0.5) v += (1.0 - 2.0 * qn) * ldu(ain + d * plane, q_);
+                    }
+                }
+            } else {
+                const T q = lq(b, p, d);
+                T alpha;
+                if (q < 0.5) alpha = ((b >> i) & 1u) ? 1.0 : 2.0 * q;  // far = x - e_i
+                else alpha = 1.0 / (2.0 * q);
+                v = alpha * ldu(ain + d * plane, (unsigned)p);
+            }
+            if ((b >> i) & 1u) {
+                // (second branch) this node pulls i from x - e_i solid with q > 1/2
+                const T q = lq(b, p, i);
+                if (q > 0.5) v += (2.0 * q - 1.0) / (2.0 * q) * ldu(ain + i * plane, (unsigned)p);
+            }
+            o[i] = v;
+        }
         HydroAdj ha;
         collide_hydro_adj(R, rho, ux, uy, o, ha);
         T a_rho = ha.rho, a_ux = ha.ux, a_uy = ha.uy, a_Fx = ha.Fx, a_Fy = ha.Fy;
@@ -295,8 +432,11 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
         Mom a_mg[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
+            o[0] = ldu(ain + (9 + 9 * k) * plane, (unsigned)p);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) o[i] = ldu(ain + (9 + 9 * k + i) * plane, nb(i));
+            for (int i = 1; i < 9; ++i)
+                o[i] = solid_nb(i) ? ldu(ain + (9 + 9 * k + opp(i)) * plane, (unsigned)p)
+                                   : ldu(ain + (9 + 9 * k + i) * plane, nb(i));
             const T phi = phi0(k) + gm[k].m0;
             const T fr = phi * inv_rho;
             CdeAdj ca;
@@ -348,12 +488,27 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
         geta += R.inv_lam * td;
         glam -= R.eta_over_lam * R.inv_lam * td;
 
-        // final adjoints of the conformation populations and of the history input
+        // final adjoints of the conformation populations and of the history input; at a
+        // wall-adjacent node the moments other than the zeroth were taken of the CNEBB
+        // reconstruction, the zeroth of the pulled populations (CNEBB keeps it)
+        const unsigned solid = pull ? (b & 0x1FEu) : 0u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            a_mg[k].m0 += a_d[k];
             T v[9];
-            expand(a_mg[k], v);
+            if (solid) {
+                const T a0 = a_mg[k].m0 + a_d[k];
+                a_mg[k].m0 = 0.0;
+                expand(a_mg[k], v);
+                T au_x = 0.0, au_y = 0.0;
+                cnebb_adj(solid, k, gm[k].m0, ux, uy, v, au_x, au_y);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) v[i] += a0;
+                a_ux += au_x;
+                a_uy += au_y;
+            } else {
+                a_mg[k].m0 += a_d[k];
+                expand(a_mg[k], v);
+            }
 #pragma unroll
             for (int i = 0; i < 9; ++i) stu(aout + (9 + 9 * k + i) * plane, (unsigned)p, v[i]);
             stu(aout + (ADJ_HIST + k) * plane, (unsigned)p, a_Sp[k]);
@@ -386,30 +541,54 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
 }
 
 template <class S, int TY>
-__global__ __launch_bounds__(64 * TY) void k_adj_gather(const AdjDev<S>* __restrict__ adj,
+__global__ __launch_bounds__(64 * TY) void k_adj_gather(const RunDev<S>* __restrict__ run,
+                                                        const AdjDev<S>* __restrict__ adj,
                                                         const Item* __restrict__ items,
                                                         S* __restrict__ aout) {
     const Item it = items[blockIdx.x];
+    const RunDev<S>& R = *run;
     const AdjDev<S>& A = *adj;
     const int x = it.tx * 64 + (int)threadIdx.x, y = it.ty * TY + (int)threadIdx.y;
     if (x >= A.nx || y >= A.ny) return;
     const long long plane = A.plane;
-    const int rowc = A.off0 + y * A.pitch;
-    const unsigned p = (unsigned)(rowc + x);
-    const unsigned pl = (unsigned)(rowc + wrapm(x - 1, A.nx));
-    const unsigned ph = (unsigned)(rowc + wrapm(x + 1, A.nx));
-    const unsigned pd = (unsigned)(A.off0 + wrapm(y - 1, A.ny) * A.pitch + x);
-    const unsigned pu = (unsigned)(A.off0 + wrapm(y + 1, A.ny) * A.pitch + x);
+    const unsigned p = (unsigned)node_index(R, x, y);
+    const unsigned b = node_bits(R, (int)p);
+    if (b & BIT_SELF_SOLID) return;
     const S* sc = A.scr;
     auto rd = [&](int c, unsigned q) -> T { return ldu(sc + c * plane, q); };
+    // The derivative along an axis at node n is c0(n) psi(n - e) + c1(n) psi(n) +
+    // c2(n) psi(n + e) with coefficients set by n's own walls.  Node x enters its own
+    // derivatives with c1(x), those of its fluid low neighbour with c2(low) and those of
+    // its fluid high neighbour with c0(high).
+    T cx[3], cy[3];
+    node_fd_coefs(R, (int)p, b, cx, cy);
+    T wLx[3] = {0.0, 0.0, 0.0}, wLy[3] = {0.0, 0.0, 0.0};  // a_Lxx/a_Lxy/a_Dx, a_Lyx/a_Lyy/a_Dy
+    const int cxs[3] = {SC_LXX, SC_LXY, SC_DX}, cys[3] = {SC_LYX, SC_LYY, SC_DY};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        wLx[c] = cx[1] * rd(cxs[c], p);
+        wLy[c] = cy[1] * rd(cys[c], p);
+    }
+    auto neighbour = [&](int bitdir, int dx, int dy, int slot_c, T* w, const int* chans) {
+        if ((b >> bitdir) & 1u) return;  // not a fluid node
+        const unsigned q = (unsigned)nb_slot(R, x, y, dx, dy);
+        T c[3], cdum[3];
+        const unsigned bn = node_bits(R, (int)q);
+        if (dx != 0) node_fd_coefs(R, (int)q, bn, c, cdum);
+        else node_fd_coefs(R, (int)q, bn, cdum, c);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] += c[slot_c] * rd(chans[k], q);
+    };
+    neighbour(1, -1, 0, 2, wLx, cxs);  // low x neighbour: x is its high neighbour
+    neighbour(3, 1, 0, 0, wLx, cxs);
+    neighbour(2, 0, -1, 2, wLy, cys);
+    neighbour(4, 0, 1, 0, wLy, cys);
 
     const T rho = rd(SC_R, p), ux = rd(SC_VX, p), uy = rd(SC_VY, p);
     T a_rho = rd(SC_RHO, p), a_ux = rd(SC_UX, p), a_uy = rd(SC_UY, p);
-    // central differences: node x enters the differences of x -/+ 1 with weight +/- 1/2
-    a_ux += 0.5 * (rd(SC_LXX, pl) - rd(SC_LXX, ph)) + 0.5 * (rd(SC_LYX, pd) - rd(SC_LYX, pu));
-    a_uy += 0.5 * (rd(SC_LXY, pl) - rd(SC_LXY, ph)) + 0.5 * (rd(SC_LYY, pd) - rd(SC_LYY, pu));
-    const T a_px = 0.5 * (rd(SC_DX, pl) - rd(SC_DX, ph));
-    const T a_py = 0.5 * (rd(SC_DY, pd) - rd(SC_DY, pu));
+    a_ux += wLx[0] + wLy[0];
+    a_uy += wLx[1] + wLy[1];
+    const T a_px = wLx[2], a_py = wLy[2];  // adjoints of rho ux^3, rho uy^3
     a_rho += a_px * ux * ux * ux + a_py * uy * uy * uy;
     a_ux += 3.0 * a_px * rho * ux * ux;
     a_uy += 3.0 * a_py * rho * uy * uy;
@@ -448,7 +627,12 @@ __global__ __launch_bounds__(64 * TY) void k_adj_seed(const RunDev<S>* __restric
     const long long plane = R.plane;
     const int x = it.tx * 64 + (int)threadIdx.x, y = it.ty * TY + (int)threadIdx.y;
     T loss = 0.0;
-    if (x < R.nx && y < R.ny) {
+    if (x < R.nx && y < R.ny && (node_bits(R, node_index(R, x, y)) & BIT_SELF_SOLID)) {
+        const int p = node_index(R, x, y);
+        for (int c = 0; c < 41; ++c) stu(aout + c * plane, (unsigned)p, 0.0);
+        A.gF[p] = 0.0;
+        A.gF[plane + p] = 0.0;
+    } else if (x < R.nx && y < R.ny) {
         const int p = node_index(R, x, y);
         S f[9];
         pull9(R, src, 0, p, pull != 0, f);
@@ -506,19 +690,19 @@ hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, c
     switch (ty) {
         case 1:
             hipLaunchKernelGGL((k_adj_local<S, 1>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 1>), dim3(nitems), dim3(64, 1), 0, s, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 1>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, aout);
             break;
         case 2:
             hipLaunchKernelGGL((k_adj_local<S, 2>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 2>), dim3(nitems), dim3(64, 2), 0, s, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 2>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, aout);
             break;
         case 4:
             hipLaunchKernelGGL((k_adj_local<S, 4>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 4>), dim3(nitems), dim3(64, 4), 0, s, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 4>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, aout);
             break;
         case 8:
             hipLaunchKernelGGL((k_adj_local<S, 8>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 8>), dim3(nitems), dim3(64, 8), 0, s, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 8>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, aout);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -1073,8 +1073,10 @@ AdjLayout adj_layout(const vlb_sim* s, int64_t nsteps, int stride) {
 int adj_check(const vlb_sim* s, int64_t nsteps, int stride) {
     int rc = check_ready(s);
     if (rc) return rc;
-    if (s->xmode != VLB_PERIODIC || s->ymode != VLB_PERIODIC || s->has_bits)
-        return fail(VLB_E_UNSUPPORTED, "the adjoint covers fully periodic domains without solids");
+    if (s->xmode == VLB_OPEN || s->ymode == VLB_WET)
+        return fail(VLB_E_UNSUPPORTED,
+                    "the adjoint covers periodic axes, half-way walls and solid masks, not open "
+                    "ends or wet-node walls");
     if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
     return VLB_OK;
 }
@@ -1140,11 +1142,14 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
     a.seed_x = static_cast<const T*>(gx);
     a.seed_y = static_cast<const T*>(gy);
     a.seed_is_target = is_target;
-    a.inv_nfluid = 1.0 / ((double)s->nx * (double)s->ny);
+    size_t nfluid = (size_t)s->nx * s->ny;
+    if (!s->solid.empty()) nfluid -= (size_t)std::count(s->solid.begin(), s->solid.end(), 1);
+    a.inv_nfluid = 1.0 / (double)std::max<size_t>(nfluid, 1);
     vlb::AdjDev<T>* ad = reinterpret_cast<vlb::AdjDev<T>*>(ws + L.off_adjdev);
     hipLaunchKernelGGL((k_store_value<vlb::AdjDev<T>>), dim3(1), dim3(64), 0, s->stream, a, ad);
     VLB_HIP(hipGetLastError());
     const vlb::Item* items = s->dptr<vlb::Item>(s->off_items);
+    const vlb::FillItem* fill = s->dptr<vlb::FillItem>(s->off_fill_items);
     T* abuf[2] = {reinterpret_cast<T*>(ws + L.off_a[0]), reinterpret_cast<T*>(ws + L.off_a[1])};
     const Run<T>* rs = s->dptr<Run<T>>(s->off_run);
     VLB_HIP(vlb::launch_adj_seed<T>(rs, ad, items, s->nitems, s->ty, s->dptr<T>(s->off_pop[s->parity]),
@@ -1159,6 +1164,7 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
             const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
             VLB_HIP(vlb::launch_step<T>(desc + k, items, s->nitems, s->ty, 0, first, 0,
                                         step_waves(s->sched_waves, resident_state(s)), s->stream));
+            VLB_HIP(vlb::launch_fill<T>(desc + k, fill, (int)s->fill_items.size(), 1, s->stream));
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;

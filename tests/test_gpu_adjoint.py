@@ -2,6 +2,12 @@
 
 * 8 x 8 periodic, FP64: the full gradient (lambda, eta_p and all 128 force components)
   against central differences of the FP64 oracle, for Oldroyd-B and the other closures.
+* Walled domains, FP64: the full gradient on an 8 x 8 channel (half-way walls, CNEBB),
+  a 12 x 12 channel with a circle (interpolated bounce-back on both sides of q = 1/2,
+  solid nodes, CNEBB on curved links, wall-aware differences at fraction q) and a
+  doubly periodic 10 x 10 grid with a solid block, against oracle central differences.
+* The force-driven channel (64 x 32, Wi = 1, beta = 0.5, 10,000 steps, FP64 and FP32
+  adjoints) against central differences of the FP64 HIP forward path.
 * 128 x 128, 200 steps: directional derivatives along lambda, eta_p and a random smooth
   force direction against the oracle's forward-mode (dual-number) derivatives.
 * The adjoint workload at full size (512 x 512, FP32, 2000 steps, checkpoint stride 45,
@@ -31,8 +37,10 @@ def _gpu():
     oracle.set_threads(min(16, oracle.max_threads()))
 
 
-def _loss(u, t, n):
-    return 0.5 * float(((u[0] - t[0]) ** 2 + (u[1] - t[1]) ** 2).sum()) / n
+def _loss(u, t, fluid):
+    """Mean squared velocity error over the fluid nodes (the library's loss)."""
+    e = (u[0] - t[0]) ** 2 + (u[1] - t[1]) ** 2
+    return 0.5 * float(e[fluid].sum()) / int(fluid.sum())
 
 
 def _oracle_loss(pr, steps, target):
@@ -41,7 +49,7 @@ def _oracle_loss(pr, steps, target):
     o = oracle.OracleSim(pr)
     o.step(steps)
     r = o.read()
-    return _loss((r["ux"], r["uy"]), target, pr.nx * pr.ny)
+    return _loss((r["ux"], r["uy"]), target, pr.fluid_mask())
 
 
 def _gpu_adjoint(pr, steps, target, precision, stride=None):
@@ -69,34 +77,42 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("model,mp", [("oldroyd_b", 0.0), ("giesekus", 0.3), ("lptt", 0.25),
-                                      ("eptt", 0.25), ("fene_p", 20.0)])
-def test_adjoint_bruteforce_8x8_fp64(model, mp):
-    """All 130 gradient components against oracle central differences, for every
-    constitutive closure (the transpose of each closure's Jacobian)."""
-    pr = synth.random_periodic(8, 8, seed=3, precision="fp64").with_(model=model,
-                                                                     model_param=mp)
-    steps, stride = 12, 5  # three segments, the last one partial
-    tgt = _target(pr, 11)
-    say("adjoint 8x8 brute force", model, steps, stride)
+def _bruteforce(pr, steps, stride, tgt):
+    """GPU FP64 adjoint against oracle central differences in every component."""
+    import oracle
+
     g = _gpu_adjoint(pr, steps, tgt, "fp64", stride)
     assert abs(g["loss"] - _oracle_loss(pr, steps, tgt)) < 1e-12 * abs(g["loss"]) + 1e-18
 
     def fd(make, h):
         return (_oracle_loss(make(+h), steps, tgt) - _oracle_loss(make(-h), steps, tgt)) / (2 * h)
 
-    hl = 1e-6 * pr.lam
+    # relative steps of 1e-4: truncation ~1e-8, rounding (eps L / h) far below the
+    # tolerance even where the derivative is small against L / lambda
+    hl = 1e-4 * pr.lam
     dl = fd(lambda d: pr.with_(lam=pr.lam + d), hl)
-    he = 1e-6 * pr.eta_p
+    he = 1e-4 * pr.eta_p
     de = fd(lambda d: pr.with_(eta_p=pr.eta_p + d), he)
     assert abs(g["dlambda"] - dl) < 1e-6 * abs(dl), (g["dlambda"], dl)
     assert abs(g["deta_p"] - de) < 1e-6 * abs(de), (g["deta_p"], de)
+    # and the oracle's forward-mode derivatives, exact up to rounding
+    fluid = pr.fluid_mask()
+    for key, kw in (("dlambda", dict(dlam=1.0)), ("deta_p", dict(deta=1.0))):
+        od = oracle.OracleSim(pr, dual=True)
+        od.set_tangent(**kw)
+        od.step(steps)
+        u, t = od.read(), od.read_tangent()
+        e = (u["ux"] - tgt[0]) * t["ux"] + (u["uy"] - tgt[1]) * t["uy"]
+        dd = float(e[fluid].sum()) / int(fluid.sum())
+        assert abs(g[key] - dd) < 1e-9 * abs(dd), (key, g[key], dd)
     # the force enters almost linearly: a larger step keeps rounding (eps L / h) small
     hF = 1e-3 * float(np.abs(pr.Fx).max())
-    dFx = np.zeros((8, 8))
-    dFy = np.zeros((8, 8))
-    for y in range(8):
-        for x in range(8):
+    dFx = np.zeros((pr.ny, pr.nx))
+    dFy = np.zeros((pr.ny, pr.nx))
+    for y in range(pr.ny):
+        for x in range(pr.nx):
+            if not fluid[y, x]:
+                continue  # the force at a solid node acts on nothing
             def mkx(d, x=x, y=y):
                 F = np.array(pr.Fx, dtype=float)
                 F[y, x] += d
@@ -111,6 +127,150 @@ def test_adjoint_bruteforce_8x8_fp64(model, mp):
             dFy[y, x] = fd(mky, hF)
     assert _rel(g["dFx"], dFx) < 1e-6, _rel(g["dFx"], dFx)
     assert _rel(g["dFy"], dFy) < 1e-6, _rel(g["dFy"], dFy)
+    assert not g["dFx"][~fluid].any() and not g["dFy"][~fluid].any()
+
+
+@pytest.mark.parametrize("model,mp", [("oldroyd_b", 0.0), ("giesekus", 0.3), ("lptt", 0.25),
+                                      ("eptt", 0.25), ("fene_p", 20.0)])
+def test_adjoint_bruteforce_8x8_fp64(model, mp):
+    """All 130 gradient components against oracle central differences, for every
+    constitutive closure (the transpose of each closure's Jacobian)."""
+    pr = synth.random_periodic(8, 8, seed=3, precision="fp64").with_(model=model,
+                                                                     model_param=mp)
+    steps, stride = 12, 5  # three segments, the last one partial
+    say("adjoint 8x8 brute force", model, steps, stride)
+    _bruteforce(pr, steps, stride, _target(pr, 11))
+
+
+def _block_mask(n):
+    m = np.zeros((n, n), np.uint8)
+    m[3:6, 4:7] = 1
+    m[8, 1] = 1
+    return m
+
+
+@pytest.mark.parametrize("case", ["channel_8x8", "circle_12x12", "block_10x10",
+                                  "circle_12x12_giesekus"])
+def test_adjoint_bruteforce_walls_fp64(case):
+    """Every gradient component on walled domains against oracle central differences:
+    the transposes of half-way and interpolated bounce-back (q below and above 1/2),
+    of CNEBB on flat and curved links, of the wall-aware differences at fraction q,
+    and of solid nodes across a periodic edge."""
+    if case == "channel_8x8":
+        pr = synth.random_periodic(8, 8, seed=3, ymode="wall", precision="fp64")
+    elif case.startswith("circle"):
+        pr = synth.random_periodic(12, 12, seed=5, ymode="wall", circles=[(5.6, 6.3, 2.7)],
+                                   precision="fp64")
+        if case.endswith("giesekus"):
+            pr = pr.with_(model="giesekus", model_param=0.3)
+    else:
+        pr = synth.random_periodic(10, 10, seed=6, solid=_block_mask(10), precision="fp64")
+    steps, stride = 12, 5
+    say("adjoint walls brute force", case, steps, stride)
+    _bruteforce(pr, steps, stride, _target(pr, 11))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-4)])
+def test_adjoint_cylinder_channel_vs_oracle_forward_mode(precision, tol):
+    """Force-driven channel past a circle (160 x 64, R = 10.7, from rest, 300 steps):
+    directional derivatives along lambda, eta_p and a smooth force field against the
+    oracle's forward-mode (dual-number) derivatives; spans several tiles with curved
+    links, solid nodes and flat walls."""
+    import oracle
+
+    base = synth.poiseuille(nx=160, ny=64, Wi=1.0, beta=0.59, precision="fp64")
+    pr = base.with_(circles=[(52.3, 31.4, 10.7)], Fx=np.full((64, 160), float(base.Fx)),
+                    Fy=np.zeros((64, 160)))
+    steps = 300
+    fluid = pr.fluid_mask()
+    o = oracle.OracleSim(pr.with_(lam=pr.lam * 1.1, eta_p=pr.eta_p * 0.9))
+    o.step(steps)
+    r = o.read()
+    tgt = (np.where(fluid, r["ux"], 0.0), np.where(fluid, r["uy"], 0.0))
+    vx, vy = _channel_dir(160, 64)
+    vx, vy = vx * float(base.Fx), vy * float(base.Fx)
+    say("adjoint cylinder channel forward-mode", precision)
+    g = _gpu_adjoint(pr.with_(precision=precision), steps, tgt, precision)
+    checks = []
+    nf = int(fluid.sum())
+    for name, kw in (("lambda", dict(dlam=1.0)), ("eta_p", dict(deta=1.0)),
+                     ("force", dict(dFx=vx, dFy=vy))):
+        od = oracle.OracleSim(pr, dual=True)
+        od.set_tangent(**kw)
+        od.step(steps)
+        u = od.read()
+        t = od.read_tangent()
+        e = (u["ux"] - tgt[0]) * t["ux"] + (u["uy"] - tgt[1]) * t["uy"]
+        dd = float(e[fluid].sum()) / nf
+        if name == "lambda":
+            ad = g["dlambda"]
+        elif name == "eta_p":
+            ad = g["deta_p"]
+        else:
+            ad = float((g["dFx"] * vx + g["dFy"] * vy).sum())
+        checks.append((name, ad, dd))
+    for name, ad, dd in checks:
+        assert abs(ad - dd) <= tol * abs(dd), (name, ad, dd, checks)
+
+
+def _channel_dir(nx, ny):
+    """A smooth force direction on the channel (zero mean in neither component)."""
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    return (np.sin(2 * np.pi * X) * Y * (1 - Y) * 4 + 0.3,
+            np.cos(2 * np.pi * X) * np.sin(np.pi * Y) * 0.5)
+
+
+@pytest.mark.parametrize("precision,steps,tol", [("fp64", 10000, 1e-6), ("fp32", 1500, 1e-3)])
+def test_adjoint_channel_vs_fp64_central_differences(precision, steps, tol):
+    """Force-driven Oldroyd-B channel (64 x 32, walls at y, Wi = 1, beta = 0.5, from
+    rest): dL/dlambda, dL/deta_p and a smooth force direction against central
+    differences of the FP64 HIP forward path, for a target made with hidden lambda,
+    eta_p and force.  FP64 over the full 10,000 steps; FP32 over the start-up (about
+    three relaxation times), since at steady state the velocity no longer depends on
+    lambda and dL/dlambda is a difference of rounding-sized terms."""
+    import torch
+    from paper_2508_16997_amd import Simulation
+
+    pr = synth.poiseuille(precision="fp64")
+    Fx0 = np.full((pr.ny, pr.nx), float(pr.Fx))
+    Fy0 = np.zeros((pr.ny, pr.nx))
+    pr = pr.with_(Fx=Fx0, Fy=Fy0)
+    vx, vy = _channel_dir(pr.nx, pr.ny)
+    fluid = pr.fluid_mask()
+
+    def run64(p):
+        sim = Simulation.from_problem(p, precision="fp64", graph_chunk=100)
+        sim.step(steps)
+        r = sim.read()
+        torch.cuda.synchronize()
+        out = (r["ux"].cpu().numpy(), r["uy"].cpu().numpy())
+        sim.close()
+        return out
+
+    say("adjoint channel: target", precision)
+    F0 = float(Fx0[0, 0])
+    tgt = run64(pr.with_(lam=pr.lam * 1.2, eta_p=pr.eta_p * 0.85, Fx=Fx0 + 0.1 * F0 * vx,
+                         Fy=Fy0 + 0.1 * F0 * vy))
+    say("adjoint channel: adjoint", precision)
+    g = _gpu_adjoint(pr.with_(precision=precision), steps, tgt, precision)
+    assert g["dFx"].shape == (pr.ny, pr.nx)
+
+    def L(p):
+        return _loss(run64(p), tgt, fluid)
+
+    say("adjoint channel: central differences")
+    res = {}
+    h = 1e-5 * pr.lam
+    res["lambda"] = (g["dlambda"], (L(pr.with_(lam=pr.lam + h)) - L(pr.with_(lam=pr.lam - h))) / (2 * h))
+    h = 1e-5 * pr.eta_p
+    res["eta_p"] = (g["deta_p"], (L(pr.with_(eta_p=pr.eta_p + h)) - L(pr.with_(eta_p=pr.eta_p - h))) / (2 * h))
+    s = 1e-5 * F0
+    fd = (L(pr.with_(Fx=Fx0 + s * vx, Fy=Fy0 + s * vy)) - L(pr.with_(Fx=Fx0 - s * vx, Fy=Fy0 - s * vy))) / (2 * s)
+    res["force"] = (float((g["dFx"] * vx + g["dFy"] * vy).sum()), fd)
+    for name, (ad, dd) in res.items():
+        assert abs(ad - dd) <= tol * abs(dd), (name, ad, dd, res)
 
 
 def _smooth_dir(n, seed):
@@ -162,7 +322,6 @@ def test_adjoint_full_size_vs_fp64_central_differences():
 
     pr, hidden = synth.adjoint_c5()
     steps, stride = pr.steps, 45
-    n = pr.nx * pr.ny
     say("adjoint full size: target run", pr.nx, steps)
 
     def run64(p):
@@ -184,7 +343,7 @@ def test_adjoint_full_size_vs_fp64_central_differences():
     say("adjoint full size: FP64 central differences")
 
     def L(p):
-        return _loss(run64(p), tgt, n)
+        return _loss(run64(p), tgt, np.ones((pr.ny, pr.nx), bool))
 
     res = {}
     h = 1e-6 * pr.lam
@@ -243,12 +402,13 @@ def test_adjoint_rejects_misuse():
     from paper_2508_16997_amd import Simulation, VlbError
 
     say("adjoint errors")
-    wall = synth.random_periodic(40, 24, seed=1, ymode="wall", precision="fp32")
-    sim = Simulation.from_problem(wall)
     z = torch.zeros((24, 40), device="cuda")
-    with pytest.raises(VlbError):
-        sim.adjoint(5, z, z)  # walls: unsupported
-    sim.close()
+    for kw in (dict(xmode="open"), dict(ymode="wet")):
+        other = synth.random_periodic(40, 24, seed=1, precision="fp32", **kw)
+        sim = Simulation.from_problem(other)
+        with pytest.raises(VlbError):
+            sim.adjoint(5, z, z)  # open ends, wet-node walls: unsupported
+        sim.close()
     per = synth.random_periodic(40, 24, seed=1, precision="fp32")
     sim = Simulation.from_problem(per)
     with pytest.raises(RuntimeError):
