@@ -31,6 +31,9 @@ FLAG_NO_GTILDE = 2  # planted mistake for sensitivity checks: drop G~_i
 # alternative readings of the CNEBB scheme (Sec. 3.3), for sensitivity measurements only:
 FLAG_CNEBB_UB_ZERO = 4  # zero wall velocity in the CNEBB equilibrium (reading A11's alternative)
 FLAG_CNEBB_PAIR_NEQ = 8  # both-unknown pairs keep a non-equilibrium part (A12's alternative)
+# the curved-wall scheme of the paper's cylinder for f (Sec. 4.3, reading A30); set from
+# Problem.curved == "ylw"
+FLAG_CURVED_YLW = 16
 
 
 def build(force: bool = True) -> str:
@@ -127,6 +130,8 @@ class OracleSim:
                                 1 if dual else 0)
         if not self.h:
             raise ValueError("oracle: invalid grid")
+        if getattr(prob, "curved", "bouzidi") == "ylw":
+            flags |= FLAG_CURVED_YLW
         rc = lib.orc_set_params(self.h, prob.nu_s, prob.eta_p, prob.lam, prob.kappa,
                                 prob.Lambda_s, prob.Lambda_p, flags)
         if rc != 0:

@@ -20,7 +20,8 @@
  *   5. hydrodynamic TRT regularized collision with G_i, F_i, T_i         (Sec. 3.1)
  *   6. three convection-diffusion TRT regularized collisions with
  *      the auxiliary source, the source term and its time derivative   (Sec. 3.2)
- *   7. streaming; half-way / linearly interpolated bounce-back for f;
+ *   7. streaming; half-way / linearly interpolated bounce-back for f, or the
+ *      unified interpolation with the rest-population mass restore      (reading A30);
  *      non-equilibrium extrapolation at the inlet and outlet ghosts    (readings A13, A21)
  *      or, for wet-node walls, non-equilibrium bounce-back of f at the wall nodes
  *      themselves (Sec. 4.2-4.3, reading A29)
@@ -336,7 +337,13 @@ enum { SRC_FLUID = 0, SRC_SOLID = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
 // instead of the boundary node's (reading A11), and an unknown population whose opposite
 // is unknown too rebuilt with the non-equilibrium part of the population that left in
 // its own direction instead of the equilibrium alone (reading A12).
-enum { FLAG_NO_SOURCE = 1, FLAG_NO_GTILDE = 2, FLAG_CNEBB_UB_ZERO = 4, FLAG_CNEBB_PAIR_NEQ = 8 };
+// FLAG_CURVED_YLW selects the paper's curved-wall scheme for the hydrodynamic lattice on
+// the cylinder (Sec. 4.3, "YLW", reading A30) instead of linear interpolated bounce-back:
+// the unified interpolation of Yu, Mei, Luo and Shyy (2003) on links with q != 1/2, and
+// the rest population restoring the local mass (known populations plus those that left
+// toward the wall), the conservation strategy CNEBB shares with it (Sec. 3.3).
+enum { FLAG_NO_SOURCE = 1, FLAG_NO_GTILDE = 2, FLAG_CNEBB_UB_ZERO = 4, FLAG_CNEBB_PAIR_NEQ = 8,
+       FLAG_CURVED_YLW = 16 };
 
 struct Src {
     int kind;
@@ -614,10 +621,28 @@ struct Sim {
                     }
                 } else {
                     // Hydrodynamic wall: half-way bounce-back for q = 1/2 (reading A13),
-                    // linear interpolated bounce-back otherwise (reading A21).
+                    // linear interpolated bounce-back otherwise (reading A21), or the
+                    // unified scheme (reading A30).
                     const double q = s.q;
                     if (q == 0.5) {
                         f[i][n] = fp[o][n];
+                    } else if (flags & FLAG_CURVED_YLW) {
+                        // The population that left x toward the wall in direction o meets
+                        // it at distance q.  Linear interpolation along the link between
+                        // where the direction-o populations sit after streaming -- x (from
+                        // the far node x + e_i) and the solid node (from x) -- gives the
+                        // value at the wall point; bounced there, it is interpolated back
+                        // to x with the direction-i population streamed from x to x + e_i
+                        // (one spacing on the other side):
+                        //   f_o(wall) = (1 - q) fp_o(x + e_i) + q fp_o(x)
+                        //   f_i(x) = [f_o(wall) + q fp_i(x)] / (1 + q).
+                        // Without a fluid far node: half-way bounce-back.
+                        const Src far = geo.source(x, y, o);  // x - e_o = x + e_i
+                        if (far.kind == SRC_FLUID)
+                            f[i][n] = (R(1.0 - q) * fp[o][far.node] + R(q) * fp[o][n] +
+                                       R(q) * fp[i][n]) / R(1.0 + q);
+                        else
+                            f[i][n] = fp[o][n];
                     } else if (q < 0.5) {
                         const Src far = geo.source(x, y, o);  // x - e_o = x + e_i
                         if (far.kind == SRC_FLUID)
@@ -632,6 +657,20 @@ struct Sim {
                     // used for phi at the boundary node; replaced by CNEBB below.
                     for (int k = 0; k < 3; ++k) g[k][i][n] = gp[k][o][n];
                 }
+            }
+        }
+        // Stage 7a (reading A30): the rest population of a wall-adjacent node takes the
+        // mass the interpolation did not return -- the node's density after streaming is
+        // its known populations plus the post-collision populations that left toward
+        // the wall.
+        if (flags & FLAG_CURVED_YLW) {
+#pragma omp parallel for schedule(static)
+            for (long long nn = 0; nn < (long long)N; ++nn) {
+                const size_t n = (size_t)nn;
+                if (!fluid(n)) continue;
+                const int x = (int)(n % nx), y = (int)(n / nx);
+                for (int i = 1; i < Q; ++i)
+                    if (geo.source(x, y, i).kind == SRC_SOLID) f[0][n] += fp[OPP[i]][n] - f[i][n];
             }
         }
         // Stage 7b: wet-node walls -- the populations the wall nodes would receive from

@@ -51,6 +51,9 @@ class Problem:
     # 'fene_p' (model_param = L^2)
     model: str = "oldroyd_b"
     model_param: float = 0.0
+    # hydrodynamic scheme on curved (circle) links: 'bouzidi' (linear interpolated
+    # bounce-back) or 'ylw' (the curved-wall scheme of the paper's cylinder)
+    curved: str = "bouzidi"
 
     @property
     def nodes(self) -> int:
