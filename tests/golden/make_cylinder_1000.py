@@ -1,12 +1,13 @@
-"""Writes cylinder_1000.npz: oracle fields of the 4096 x 1024 cylinder after 1,000 steps.
+"""Writes cylinder_1000.npz (Wi = 1) or cylinder_1000_wi<Wi>.npz: oracle fields of the
+4096 x 1024 cylinder after 1,000 steps.
 
 Calls only the FP64 oracle (oracle/) on the seeded workload of synth.cylinder (R = 128 at
-(2048, 512), Wi = 1, beta = 0.59, Sc = 1e6; the FP32 configuration of the benchmark, run
-in FP64 by the oracle).  Stores the fields at a sample of nodes: every 32nd node in x and
+(2048, 512), Wi in {0.5, 1, 2}, beta = 0.59, Sc = 1e6; the FP32 configuration of the
+benchmark, run in FP64 by the oracle).  Stores the fields at a sample of nodes: every 32nd node in x and
 y, every fluid node within two lattice units of the cylinder surface (curved links and
 CNEBB), every 8th node of the first and last fluid rows (channel walls) and of the first
 and last columns (inlet and outlet).
-Run from the repository root: python tests/golden/make_cylinder_1000.py [threads]
+Run from the repository root: python tests/golden/make_cylinder_1000.py [threads] [Wi]
 """
 import os
 import sys
@@ -21,7 +22,6 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 STEPS = 1000
-WI = 1.0
 
 
 def sample_nodes(pr):
@@ -41,6 +41,7 @@ def sample_nodes(pr):
 
 def main():
     threads = int(sys.argv[1]) if len(sys.argv) > 1 else os.cpu_count()
+    WI = float(sys.argv[2]) if len(sys.argv) > 2 else 1.0
     oracle.build(force=False)
     oracle.set_threads(threads)
     pr = synth.cylinder(Wi=WI)
@@ -55,7 +56,8 @@ def main():
         print(f"{done} steps, {time.time() - t0:.0f} s", flush=True)
     r = o.read()
     out = {k: v[ys, xs].copy() for k, v in r.items()}
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cylinder_1000.npz")
+    name = "cylinder_1000.npz" if WI == 1.0 else f"cylinder_1000_wi{WI:g}.npz"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     np.savez_compressed(path, steps=STEPS, wi=WI, ys=ys, xs=xs, **out)
     print("wrote", path, len(ys), "nodes")
 
