@@ -67,7 +67,18 @@ enum { VLB_PERIODIC = 0, VLB_WALL = 1, VLB_OPEN = 2, VLB_WET = 3 };
 /* Node classes returned by vlb_geometry. */
 enum { VLB_NODE_FLUID = 0, VLB_NODE_SOLID = 1, VLB_NODE_BOUNDARY = 2 };
 /* Parameter flags. */
-enum { VLB_FLAG_NO_SOURCE = 1 /* constitutive source S forced to 0 (conservation checks) */ };
+enum {
+    VLB_FLAG_NO_SOURCE = 1,   /* constitutive source S forced to 0 (conservation checks)     */
+    VLB_FLAG_CURVED_YLW = 2   /* curved (circle) links of f: the paper's cylinder scheme YLW
+                                 (Sec. 4.3) instead of linear interpolated bounce-back -- the
+                                 unified interpolation of Yu, Mei, Luo and Shyy (2003),
+                                 [(1 - q) f_o(x + e_i) + q f_o(x) + q f_i(x)] / (1 + q) for the
+                                 unknown f_i(x) with o opposite to i (half-way without a fluid
+                                 x + e_i), and the rest population restoring the node's mass
+                                 (known populations plus those that left toward the wall), the
+                                 conservation CNEBB shares with it (Sec. 3.3).  Flat walls
+                                 (q = 1/2) stay half-way.  Not differentiable by the adjoint. */
+};
 
 typedef struct vlb_sim vlb_sim;
 

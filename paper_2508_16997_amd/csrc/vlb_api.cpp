@@ -291,14 +291,13 @@ void build_fill(vlb_sim* s) {
                 if (b & (1u << i)) {
                     const double q = bi >= 0 ? s->bq[(size_t)bi * 8 + (i - 1)] : 0.5;
                     int far = -1;
-                    if (q == 0.5) {
-                        op.dir_kind = i | (vlb::FILL_WALL << 8);
-                    } else if (q < 0.5 && !fluid_at(x + EXH[i], y + EYH[i], &far)) {
+                    const bool has_far = q != 0.5 && fluid_at(x + EXH[i], y + EYH[i], &far);
+                    if (q == 0.5 || (q < 0.5 && !has_far)) {
                         op.dir_kind = i | (vlb::FILL_WALL << 8);
                     } else {
                         op.dir_kind = i | (vlb::FILL_CURVED << 8);
                         op.q = q;
-                        op.far = q < 0.5 ? far : -1;
+                        op.far = has_far ? far : -1;
                     }
                     s->fill.push_back(op);
                     continue;
@@ -440,6 +439,7 @@ Run<T> make_run(const vlb_sim* s) {
     r.has_curved = s->has_curved ? 1 : 0;
     r.uniform_force = s->force_field ? 0 : 1;
     r.no_source = (s->params.flags & VLB_FLAG_NO_SOURCE) ? 1 : 0;
+    r.ylw = (s->params.flags & VLB_FLAG_CURVED_YLW) ? 1 : 0;
     r.plane = s->plane;
     r.pop[0] = s->dptr<T>(s->off_pop[0]);
     r.pop[1] = s->dptr<T>(s->off_pop[1]);
@@ -764,7 +764,8 @@ int vlb_set_params(vlb_sim* s, const vlb_params* p) {
     if (!(p->eta_p >= 0)) return fail(VLB_E_INVALID_ARG, "eta_p must be >= 0");
     if (!(p->Lambda_s > 0) || !(p->Lambda_p > 0))
         return fail(VLB_E_INVALID_ARG, "magic parameters must be > 0");
-    if (p->flags & ~VLB_FLAG_NO_SOURCE) return fail(VLB_E_INVALID_ARG, "unknown flag");
+    if (p->flags & ~(VLB_FLAG_NO_SOURCE | VLB_FLAG_CURVED_YLW))
+        return fail(VLB_E_INVALID_ARG, "unknown flag");
     if (p->model < VLB_OLDROYD_B || p->model > VLB_FENE_P)
         return fail(VLB_E_INVALID_ARG, "unknown constitutive model");
     if (p->model != VLB_OLDROYD_B && !std::isfinite(p->model_param))
@@ -1077,6 +1078,9 @@ int adj_check(const vlb_sim* s, int64_t nsteps, int stride) {
         return fail(VLB_E_UNSUPPORTED,
                     "the adjoint covers periodic axes, half-way walls and solid masks, not open "
                     "ends or wet-node walls");
+    if (s->has_curved && (s->params.flags & VLB_FLAG_CURVED_YLW))
+        return fail(VLB_E_UNSUPPORTED, "the adjoint covers linear interpolated bounce-back on "
+                                       "curved links, not VLB_FLAG_CURVED_YLW");
     if (nsteps < 0 || stride < 1) return fail(VLB_E_INVALID_ARG, "nsteps >= 0 and stride >= 1 required");
     return VLB_OK;
 }

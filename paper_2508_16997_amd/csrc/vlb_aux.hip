@@ -47,9 +47,11 @@ template <class S>
 __device__ __forceinline__ bool node_fields(const RunDev<S>& R, const S* src, int x, int y,
                                             bool pull, T& rho, T& ux, T& uy, T a[3]) {
     const int p = node_index(R, x, y);
-    if (node_bits(R, p) & BIT_SELF_SOLID) return false;
+    const unsigned b = node_bits(R, p);
+    if (b & BIT_SELF_SOLID) return false;
     S f[9], g[3][9];
     pull36(R, src, p, pull, f, g);
+    if (pull && R.ylw && (b & 0x1FEu)) ylw_restore(R, src, p, b, f);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     const bool wet = wet_row(R, y);

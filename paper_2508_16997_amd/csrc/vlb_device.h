@@ -357,7 +357,19 @@ __device__ __forceinline__ void apply_fill_op(const RunDev<S>& R, const FillOp& 
         // conformation lattices: the populations that left toward the wall (CNEBB input);
         // hydrodynamic lattice: half-way or linear interpolated bounce-back
         V4<S> v = ld4(buf, plane, o, (unsigned)op.src);
-        if (kind == FILL_CURVED) {
+        if (kind == FILL_CURVED && R.ylw) {
+            // YLW (Sec. 4.3): the population that left toward the wall, interpolated to the
+            // wall point between where direction o sits after streaming (the node, from
+            // the far node x + e_dir; the solid, from the node), bounced, and
+            // interpolated back to the node with the direction-dir population streamed
+            // one spacing away from the wall: [(1 - q) f_o(far) + q f_o(x) + q f_dir(x)]
+            // / (1 + q).  Half-way without a fluid far node.
+            if (op.far >= 0) {
+                const T q = op.q;
+                v.x = S(((1.0 - q) * T(ld1(buf, plane, 0, o, (unsigned)op.far)) + q * T(v.x) +
+                         q * T(ld1(buf, plane, 0, dir, (unsigned)op.src))) / (1.0 + q));
+            }
+        } else if (kind == FILL_CURVED) {
             const T q = op.q, fo = T(v.x);
             if (q < 0.5) {
                 if (op.far >= 0) v.x = S(2.0 * q * fo + (1.0 - 2.0 * q) * ld1(buf, plane, 0, o, (unsigned)op.far));
@@ -483,15 +495,33 @@ __device__ __forceinline__ bool wrap_cell(const RunDev<S>& R, int& xx, int& yy) 
     return true;
 }
 
+// Mass restore of the curved-wall scheme YLW (Sec. 4.3, with the conservation strategy
+// CNEBB shares with it, Sec. 3.3): the rest population of a node with wall links takes
+// what the wall fill did not return, so that the node holds its known populations plus
+// those that left toward the wall -- its own post-collision values, still in its slot of
+// src.  Stored values are deviations from w_i rho0 and opposite directions share a
+// weight, so the difference is the same in either form.  Half-way links add exactly 0.
+template <class S>
+__device__ __forceinline__ void ylw_restore(const RunDev<S>& R, const S* src, int p, unsigned b,
+                                            S f[9]) {
+    T acc = T(f[0]);
+#pragma unroll
+    for (int d = 1; d < 9; ++d)
+        if ((b >> d) & 1u) acc += T(ld1(src, R.plane, 0, opp(d), (unsigned)p)) - T(f[d]);
+    f[0] = S(acc);
+}
+
 // rho and u of one tile/ring cell (hydrodynamic pull + moments); false if not fluid.
 template <class S>
 __device__ __forceinline__ bool cell_macros(const RunDev<S>& R, const S* src, int cx, int cy,
                                             bool pull, T& rho, T& ux, T& uy) {
     if (!wrap_cell(R, cx, cy)) return false;
     const int p = node_index(R, cx, cy);
-    if (node_bits(R, p) & BIT_SELF_SOLID) return false;
+    const unsigned b = node_bits(R, p);
+    if (b & BIT_SELF_SOLID) return false;
     S f[9];
     pull9(R, src, 0, p, pull, f);
+    if (pull && R.ylw && (b & 0x1FEu)) ylw_restore(R, src, p, b, f);
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     const bool wet = wet_row(R, cy);

@@ -69,7 +69,7 @@ struct RunDev {
     const double* inlet;  // 4 rows of ny: u_x, A_xx, A_xy, A_yy
     const FillOp* fill;   // fill operations of this run
     int nfill;
-    int pad1;
+    int ylw;              // 1: the curved-wall scheme YLW for f (else linear interpolation)
     // coefficients, computed in double on the host
     double c1, c2, h1, inv_ts1;  // 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
     double p1, p2, h2;           // 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)

@@ -105,6 +105,7 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
     T dk[3] = {0.0, 0.0, 0.0};
     if (active) {
         pull36(R, src, p, pull, f, g);
+        if (pull && R.ylw && (b & 0x1FEu)) ylw_restore(R, src, p, b, f);
 #pragma unroll
         for (int k = 0; k < 3; ++k) dk[k] = zeroth(g[k]);
         node_force(R, p, Fx, Fy);

@@ -70,8 +70,12 @@ class Simulation:
         """Build, parameterise and initialise from a problem description (synth.Problem)."""
         sim = cls(prob.nx, prob.ny, prob.xmode, prob.ymode, precision or prob.precision,
                   solid=prob.solid, circles=prob.circles, **kw)
+        curved = getattr(prob, "curved", "bouzidi")
+        if curved not in ("bouzidi", "ylw"):
+            raise ValueError(f"unknown curved-wall scheme {curved!r}")
         sim.set_params(prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s, prob.Lambda_p,
                        *(((float(prob.Fx), float(prob.Fy)) if prob.uniform_force() else (0.0, 0.0))),
+                       flags=L.VLB_FLAG_CURVED_YLW if curved == "ylw" else 0,
                        model=getattr(prob, "model", "oldroyd_b"),
                        model_param=getattr(prob, "model_param", 0.0))
         if not prob.uniform_force():

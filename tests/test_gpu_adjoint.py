@@ -409,6 +409,12 @@ def test_adjoint_rejects_misuse():
         with pytest.raises(VlbError):
             sim.adjoint(5, z, z)  # open ends, wet-node walls: unsupported
         sim.close()
+    ylw = synth.random_periodic(40, 24, seed=1, ymode="wall", circles=[(20.3, 11.6, 4.4)],
+                                precision="fp32").with_(curved="ylw")
+    sim = Simulation.from_problem(ylw)
+    with pytest.raises(VlbError):
+        sim.adjoint(5, z, z)  # the YLW curved-wall scheme: not differentiated
+    sim.close()
     per = synth.random_periodic(40, 24, seed=1, precision="fp32")
     sim = Simulation.from_problem(per)
     with pytest.raises(RuntimeError):

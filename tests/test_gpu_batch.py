@@ -38,6 +38,8 @@ def _mixed_set(precision):
         synth.random_periodic(70, 37, seed=2, ymode="wall", solid=mask, precision=precision),
         synth.random_periodic(90, 30, seed=3, xmode="wall", circles=[(45.0, 15.0, 6.7)],
                               precision=precision),
+        synth.random_periodic(75, 33, seed=4, ymode="wall", circles=[(30.2, 16.3, 5.9)],
+                              precision=precision).with_(curved="ylw"),
         synth.random_periodic(130, 33, seed=4, xmode="open", ymode="wall",
                               circles=[(50.0, 16.0, 7.2)], precision=precision),
     ]
@@ -168,6 +170,39 @@ def test_batch_oracle_sample():
         o.step(steps)
         err = parity(gpu_fields(s), o.read(), r.fluid_mask())
         assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, (i, r.name, err)
+    b.close()
+    for s in sims:
+        s.close()
+
+
+def test_batch_full_set_5000_steps_golden():
+    """The whole 256-run batched workload for its 5,000 steps in the launch
+    configuration the benchmark times (per-step graphs, 64 x 8 tiles), then eight runs
+    (Wi <= 10, the draw of the 500-step sample) at a sample of nodes against oracle
+    values written by tests/golden/make_batch_5000.py (oracle only)."""
+    import os
+
+    import torch
+    from paper_2508_16997_amd import Batch
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch_5000.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    ref = np.load(path)
+    steps = int(ref["steps"])
+    runs = synth.batch_c4()
+    stream = torch.cuda.Stream()
+    say("batch 5000-step golden", len(runs), "runs", steps, "steps")
+    sims = _make(runs, stream)
+    b = Batch(sims, tile=8, graph_chunk=50)
+    b.step(steps)
+    stream.synchronize()
+    for i in ref["runs"].tolist():
+        ys, xs = ref[f"r{i}_ys"], ref[f"r{i}_xs"]
+        g = {k: v[ys, xs] for k, v in gpu_fields(sims[i]).items()}
+        o = {k: ref[f"r{i}_{k}"] for k in FIELDS}
+        err = parity(g, o, np.ones(len(ys), dtype=bool))
+        assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, (i, runs[i].name, err)
     b.close()
     for s in sims:
         s.close()

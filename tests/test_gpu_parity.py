@@ -45,13 +45,24 @@ def _cases():
         "open_periodic_y": dict(nx=100, ny=26, xmode="open", ymode="periodic",
                                 circles=[(40.0, 13.0, 5.2)]),
         "open_solid_ends": dict(nx=90, ny=37, xmode="open", ymode="wall", solid=end_mask),
+        # the cylinder's curved-wall scheme for f (YLW): both sides of q = 1/2, the mass
+        # restore, next to half-way walls and open ends
+        "x_walls_circle_ylw": dict(nx=90, ny=30, xmode="wall", circles=[(45.0, 15.0, 6.7)],
+                                   curved="ylw"),
+        "open_circle_ylw": dict(nx=130, ny=33, xmode="open", ymode="wall",
+                                circles=[(50.0, 16.0, 7.2), (100.0, 10.0, 3.1)], curved="ylw"),
     }
+
+
+def _case_problem(name, seed):
+    kw = _cases()[name]
+    curved = kw.pop("curved", "bouzidi")
+    return synth.random_periodic(kw.pop("nx"), kw.pop("ny"), seed=seed, **kw).with_(curved=curved)
 
 
 @pytest.mark.parametrize("name", list(_cases()))
 def test_random_state_fp64(name):
-    kw = _cases()[name]
-    pr = synth.random_periodic(kw.pop("nx"), kw.pop("ny"), seed=17, **kw)
+    pr = _case_problem(name, 17)
     say("fp64", name, pr.nx, pr.ny)
     g, o = run_pair(pr, 40, precision="fp64", dual_chunks=[1, 39])
     err = parity(g, o, pr.fluid_mask())
@@ -60,8 +71,7 @@ def test_random_state_fp64(name):
 
 @pytest.mark.parametrize("name", list(_cases()))
 def test_random_state_fp32(name):
-    kw = _cases()[name]
-    pr = synth.random_periodic(kw.pop("nx"), kw.pop("ny"), seed=23, **kw)
+    pr = _case_problem(name, 23)
     say("fp32", name, pr.nx, pr.ny)
     g, o = run_pair(pr, 40, precision="fp32")
     err = parity(g, o, pr.fluid_mask())
@@ -141,8 +151,11 @@ def test_four_roll_fp32_512_20k_steps_golden():
     assert max(err["u"], err["axx"], err["axy"], err["ayy"]) < 1e-5, err
 
 
-def test_cylinder_fp32_full_size_1000_steps_golden():
-    """Full cylinder workload (4096 x 1024, R = 128, FP32 storage) after 1,000 steps.
+@pytest.mark.parametrize("name", ["cylinder_1000.npz", "cylinder_1000_wi0.5.npz",
+                                  "cylinder_1000_wi2.npz"])
+def test_cylinder_fp32_full_size_1000_steps_golden(name):
+    """Full cylinder workload (4096 x 1024, R = 128, FP32 storage) after 1,000 steps at
+    Wi = 1, 0.5 and 2.
 
     Compared against oracle values written by tests/golden/make_cylinder_1000.py (oracle
     only) at a stride-32 sample, every fluid node within two units of the cylinder (curved
@@ -151,7 +164,7 @@ def test_cylinder_fp32_full_size_1000_steps_golden():
     """
     import os
 
-    path = os.path.join(os.path.dirname(__file__), "golden", "cylinder_1000.npz")
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
     if not os.path.exists(path):
         pytest.skip("golden file not generated")
     ref = np.load(path)
@@ -173,14 +186,16 @@ def test_cylinder_fp32_full_size_1000_steps_golden():
     assert max(err_near["u"], err_near["axx"], err_near["axy"], err_near["ayy"]) < 1e-5, err_near
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_results_independent_of_tiling_and_graphs(prec):
+@pytest.mark.parametrize("prec,curved", [("fp32", "bouzidi"), ("fp64", "bouzidi"),
+                                         ("fp32", "ylw")])
+def test_results_independent_of_tiling_and_graphs(prec, curved):
     """Bit-identical fields for every tile height, tile order and register budget, with
     and without hipGraph replay."""
     from paper_2508_16997_amd import Simulation
 
     pr = synth.random_periodic(100, 45, seed=3, ymode="wall", circles=[(50.0, 20.0, 8.5)])
-    say("tiling", prec)
+    pr = pr.with_(curved=curved)
+    say("tiling", prec, curved)
     ref = None
     for ty, chunk, order, waves in ((4, 0, 0, 0), (1, 0, 1, 3), (2, 0, 2, 4), (8, 0, 3, 4),
                                     (4, 3, 2, 3), (8, 3, 3, 3)):
@@ -250,17 +265,19 @@ def test_load_state_refuses_another_precision_or_boundary_kind():
     assert a32.time == 2
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_shifted_wall_channel_parity(precision, tol):
+@pytest.mark.parametrize("precision,tol,curved", [("fp64", 1e-10, "bouzidi"),
+                                                  ("fp32", 1e-5, "bouzidi"),
+                                                  ("fp64", 1e-10, "ylw"), ("fp32", 1e-5, "ylw")])
+def test_shifted_wall_channel_parity(precision, tol, curved):
     """Channel between two circles of radius 1e6 (flat walls at fractions 0.3 and 0.7,
     both interpolation branches, curved-link CNEBB and wall-aware differences on every
-    wall node): GPU equals the oracle after 400 steps."""
+    wall node): GPU equals the oracle after 400 steps, for both curved-wall schemes of f."""
     H, R = 32, 1e6
     yb, yt = 1.0 - 0.3, H + 0.7
     base = synth.poiseuille(nx=64, ny=H, precision=precision)
     pr = base.with_(ny=H + 2, ymode="periodic", name="shifted_walls",
-                    circles=[(32.0, yb - R, R), (32.0, yt + R, R)])
-    say("shifted-wall channel", precision)
+                    circles=[(32.0, yb - R, R), (32.0, yt + R, R)], curved=curved)
+    say("shifted-wall channel", precision, curved)
     g, o = run_pair(pr, 400, dual_chunks=[1, 399])
     e = parity(g, o, pr.fluid_mask())
     assert max(e["u"], e["axx"], e["axy"], e["ayy"]) < tol, e
