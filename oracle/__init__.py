@@ -34,6 +34,8 @@ FLAG_CNEBB_PAIR_NEQ = 8  # both-unknown pairs keep a non-equilibrium part (A12's
 # the curved-wall scheme of the paper's cylinder for f (Sec. 4.3, reading A30); set from
 # Problem.curved == "ylw"
 FLAG_CURVED_YLW = 16
+# wet-node NEBB open ends for f (Sec. 4.3, reading A31); set from Problem.open_ends == "nebb"
+FLAG_OPEN_NEBB = 32
 
 
 def build(force: bool = True) -> str:
@@ -132,6 +134,8 @@ class OracleSim:
             raise ValueError("oracle: invalid grid")
         if getattr(prob, "curved", "bouzidi") == "ylw":
             flags |= FLAG_CURVED_YLW
+        if getattr(prob, "open_ends", "neqe") == "nebb":
+            flags |= FLAG_OPEN_NEBB
         rc = lib.orc_set_params(self.h, prob.nu_s, prob.eta_p, prob.lam, prob.kappa,
                                 prob.Lambda_s, prob.Lambda_p, flags)
         if rc != 0:

@@ -342,8 +342,13 @@ enum { SRC_FLUID = 0, SRC_SOLID = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
 // the unified interpolation of Yu, Mei, Luo and Shyy (2003) on links with q != 1/2, and
 // the rest population restoring the local mass (known populations plus those that left
 // toward the wall), the conservation strategy CNEBB shares with it (Sec. 3.3).
+// FLAG_OPEN_NEBB selects the paper's hydrodynamic open ends of the cylinder (Sec. 4.3,
+// reading A31): the first and last columns are wet boundary nodes whose populations from
+// beyond the inlet / outlet are rebuilt by non-equilibrium bounce-back (Zou-He) for the
+// inlet velocity (u_in(y), 0) and for the reference density 1 with u_y = 0 at the outlet;
+// the conformation lattices keep the non-equilibrium extrapolation ghosts.
 enum { FLAG_NO_SOURCE = 1, FLAG_NO_GTILDE = 2, FLAG_CNEBB_UB_ZERO = 4, FLAG_CNEBB_PAIR_NEQ = 8,
-       FLAG_CURVED_YLW = 16 };
+       FLAG_CURVED_YLW = 16, FLAG_OPEN_NEBB = 32 };
 
 struct Src {
     int kind;
@@ -671,6 +676,59 @@ struct Sim {
                 const int x = (int)(n % nx), y = (int)(n / nx);
                 for (int i = 1; i < Q; ++i)
                     if (geo.source(x, y, i).kind == SRC_SOLID) f[0][n] += fp[OPP[i]][n] - f[i][n];
+            }
+        }
+        // Stage 7c (reading A31): wet-node open ends.  At the inlet column the three
+        // populations arriving from x < 0 (e_x = +1) are unknown.  The density follows
+        // from the known ones and the prescribed velocity: with K the sum of the rest,
+        // tangential and twice the outgoing populations, the streamed momentum
+        // j_x = rho u_in - F_x/2 (half-force shift) gives rho = (K - F_x/2) / (1 - u_in).
+        // The normal unknown keeps the non-equilibrium part of its opposite; the two
+        // diagonal ones then follow from the x and y momentum balances
+        // (j_y = -F_y/2, no transverse velocity).  At the outlet column the same with the
+        // roles of +x and -x exchanged and the density prescribed (1): j_x = K - 1.
+        if (geo.xmode == MODE_OPEN && (flags & FLAG_OPEN_NEBB)) {
+#pragma omp parallel for schedule(static)
+            for (long long yy = 0; yy < (long long)ny; ++yy) {
+                for (int side = 0; side < 2; ++side) {
+                    const int x = side == 0 ? 0 : nx - 1;
+                    const size_t n = (size_t)yy * nx + (size_t)x;
+                    if (!fluid(n)) continue;
+                    const int sx = side == 0 ? 1 : -1;  // unknown directions have e_x = sx
+                    R K = R(0.0);
+                    for (int i = 0; i < Q; ++i) {
+                        if (EX[i] == 0) K += f[i][n];
+                        else if (EX[i] == -sx) K += R(2.0) * f[i][n];
+                    }
+                    R r, jx;
+                    if (side == 0) {
+                        r = (K - R(0.5) * Fx[n]) / (R(1.0) - uin[yy]);
+                        jx = r * uin[yy] - R(0.5) * Fx[n];
+                    } else {
+                        r = R(1.0);
+                        jx = K - r;
+                    }
+                    const R jy = R(-0.5) * Fy[n];
+                    // normal: f_n - f_opp(n) = 2 w_n 3 e_n.j (the equilibrium difference)
+                    const int in = sx > 0 ? 1 : 3;
+                    f[in][n] = f[OPP[in]][n] + R(2.0 * W[in] * 3.0 * sx) * jx;
+                    // diagonals (a: e_y = +1, b: e_y = -1): solve
+                    //   sx (f_a + f_b) = jx - [sum_{e_x != 0, known} e_x f] - sx f_n
+                    //   f_a - f_b = jy - [sum_{e_y != 0, not a, b} e_y f]
+                    int ia = -1, ib = -1;
+                    for (int i = 0; i < Q; ++i)
+                        if (EX[i] == sx && EY[i] == 1) ia = i;
+                        else if (EX[i] == sx && EY[i] == -1) ib = i;
+                    R mx = R(0.0), my = R(0.0);
+                    for (int i = 0; i < Q; ++i) {
+                        if (i == ia || i == ib) continue;
+                        mx += R((double)EX[i]) * f[i][n];
+                        my += R((double)EY[i]) * f[i][n];
+                    }
+                    const R sum_ab = R((double)sx) * (jx - mx), diff_ab = jy - my;
+                    f[ia][n] = R(0.5) * (sum_ab + diff_ab);
+                    f[ib][n] = R(0.5) * (sum_ab - diff_ab);
+                }
             }
         }
         // Stage 7b: wet-node walls -- the populations the wall nodes would receive from

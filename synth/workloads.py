@@ -54,6 +54,9 @@ class Problem:
     # hydrodynamic scheme on curved (circle) links: 'bouzidi' (linear interpolated
     # bounce-back) or 'ylw' (the curved-wall scheme of the paper's cylinder)
     curved: str = "bouzidi"
+    # hydrodynamic open ends (xmode 'open'): 'neqe' (non-equilibrium extrapolation ghosts)
+    # or 'nebb' (the first and last columns as wet nodes, the paper's cylinder set-up)
+    open_ends: str = "neqe"
 
     @property
     def nodes(self) -> int:

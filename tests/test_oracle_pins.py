@@ -415,7 +415,7 @@ def test_open_channel_poiseuille_second_order(oracle_lib):
     assert err[32] < 6e-3 and err[16] / err[32] > 3.5, err
 
 
-def _open_channel_oldroyd_b(oracle_lib, ny, steps):
+def _open_channel_oldroyd_b(oracle_lib, ny, steps, open_ends="neqe"):
     """Oldroyd-B channel 3*ny x ny between half-way walls at Wi = 1, beta = 0.5, Ma = 0.01
     (the Sec. 4.2 groups), driven only through its open ends: the inlet carries the
     parabolic velocity and the conformation of the steady channel solution, the outlet
@@ -426,7 +426,7 @@ def _open_channel_oldroyd_b(oracle_lib, ny, steps):
     ux = 4 * Uc * yp * (ny - yp) / ny ** 2
     du = 4 * Uc * (ny - 2 * yp) / ny ** 2
     axy, axx = lam * du, 1 + 2 * (lam * du) ** 2
-    pr = base.with_(xmode="open", Fx=0.0, name="open_oldroyd_b",
+    pr = base.with_(xmode="open", Fx=0.0, name="open_oldroyd_b", open_ends=open_ends,
                     inlet=dict(ux=ux, axx=axx, axy=axy, ayy=np.ones(ny)))
     full = lambda v: np.ascontiguousarray(np.broadcast_to(v[:, None], (ny, pr.nx)))
     pr.init = dict(ux=full(ux), axx=full(axx), axy=full(axy))
@@ -468,6 +468,92 @@ def test_open_channel_oldroyd_b_conformation_at_every_column(oracle_lib):
     assert e_xy.max() < 1.25 * bud_xy and e_xx.max() < 1.25 * bud_xx
     assert e_u.max() < 1e-2, e_u.max()
     assert np.abs(r["ayy"] - 1).max() < 1e-3 * np.abs(ex["axx"] - 1).max()
+
+
+def test_nebb_open_ends_hold_their_boundary_state(oracle_lib):
+    """Wet-node NEBB open ends (Sec. 4.3, reading A31): from a random state with a
+    per-node body force, after every step the first column carries exactly the inlet
+    velocity (u_in(y), 0) and the last column the reference density 1 with u_y = 0 (read
+    out with the half-force shift).  A wrong density closure, a dropped half-force term
+    or a wrong diagonal weight breaks one of the four at 1e-6 or more."""
+    pr = synth.random_periodic(40, 18, seed=5, xmode="open", ymode="wall",
+                               circles=[(20.3, 9.1, 3.3)]).with_(open_ends="nebb")
+    o = oracle_lib.OracleSim(pr)
+    for n in (1, 1, 5):
+        o.step(n)
+        r = o.read()
+        assert np.abs(r["ux"][:, 0] - pr.inlet["ux"]).max() < 1e-15
+        assert np.abs(r["uy"][:, 0]).max() < 1e-15
+        assert np.abs(r["rho"][:, -1] - 1.0).max() < 1e-14
+        assert np.abs(r["uy"][:, -1]).max() < 1e-15
+    # the conformation open ends are still the extrapolation ghosts: A is not pinned there
+    assert np.abs(r["axx"][:, 0] - pr.inlet["axx"]).max() > 1e-6
+
+
+def _nebb_channel(oracle_lib, ny, nu=0.5, umax=2e-4):
+    nx = 3 * ny
+    pr = synth.random_periodic(nx, ny, seed=0, amp_u=0, amp_rho=0, amp_a=0, xmode="open",
+                               ymode="wall", nu_s=nu, eta_p=0.0,
+                               force_amp=0.0).with_(open_ends="nebb")
+    yp = np.arange(ny) + 0.5
+    exact = umax * 4 * yp * (ny - yp) / ny ** 2
+    pr.inlet["ux"] = exact
+    o = oracle_lib.OracleSim(pr)
+    prev = None
+    for _ in range(80):
+        o.step(1000)
+        r = o.read()
+        if prev is not None and np.abs(r["ux"] - prev).max() < 1e-9 * umax:
+            return pr, r, exact
+        prev = r["ux"].copy()
+    raise AssertionError("open channel not steady")
+
+
+def test_nebb_open_channel_poiseuille_second_order(oracle_lib):
+    """Newtonian channel with wet-node NEBB open ends (reading A31): the mass flux of the
+    inlet passes unchanged, the pressure falls at dp/dx = -8 mu U_max / H^2 to the
+    reference density at the outlet column, and mid-channel the profile is the inlet's
+    parabola scaled by the density ratio (the flux is rho u), with an error falling at
+    second order from H = 16 (0.11 % of U_max) to H = 32 (0.03 %)."""
+    oracle_lib.set_threads(min(8, oracle_lib.max_threads()))
+    nu, umax = 0.5, 2e-4
+    err = {}
+    for ny in (16, 32):
+        pr, r, exact = _nebb_channel(oracle_lib, ny, nu, umax)
+        nx = pr.nx
+        flux = (r["rho"] * r["ux"]).sum(axis=0)
+        assert np.abs(flux / flux[0] - 1).max() < 1e-8
+        rho = r["rho"].mean(0)
+        x = np.arange(nx)
+        slope, icpt = np.polyfit(x[nx // 4: 3 * nx // 4], rho[nx // 4: 3 * nx // 4], 1)
+        ref = -8 * nu * umax / ny ** 2 / CS2
+        assert abs(slope / ref - 1) < (3e-3 if ny == 16 else 1e-3), (ny, slope, ref)
+        assert abs(slope * (nx - 1) + icpt - 1.0) < 1e-6, (ny, slope * (nx - 1) + icpt)
+        scaled = exact * r["rho"][:, 0].mean() / r["rho"][:, nx // 2].mean()
+        err[ny] = np.abs(r["ux"][:, nx // 2] - scaled).max() / umax
+    assert err[16] < 1.3e-3 and err[32] < 3.5e-4 and err[16] / err[32] > 3.3, err
+
+
+def test_nebb_open_channel_oldroyd_b_conformation_at_every_column(oracle_lib):
+    """The Oldroyd-B channel driven only through its open ends, with the hydrodynamic
+    ends as wet NEBB nodes (reading A31) and the conformation ends as the extrapolation
+    ghosts: every column holds the steady closed form A_xy = lambda u',
+    A_xx = 1 + 2 (lambda u')^2 within 1.25 times the error of the periodic channel."""
+    oracle_lib.set_threads(min(8, oracle_lib.max_threads()))
+    ny = 16
+    pr, r, ex = _open_channel_oldroyd_b(oracle_lib, ny, 30000, open_ends="nebb")
+    per = synth.poiseuille(nx=2, ny=ny, Wi=1.0, Ma=0.01)
+    op = oracle_lib.OracleSim(per)
+    op.step(int(round(18 * per.meta["Tc"])))
+    rp = op.read()
+    bud_xy = np.abs(rp["axy"][:, 0] - ex["axy"]).max() / np.abs(ex["axy"]).max()
+    bud_xx = np.abs(rp["axx"][:, 0] - ex["axx"]).max() / np.abs(ex["axx"] - 1).max()
+    e_xy = np.abs(r["axy"] - ex["axy"][:, None]).max(axis=0) / np.abs(ex["axy"]).max()
+    e_xx = np.abs(r["axx"] - ex["axx"][:, None]).max(axis=0) / np.abs(ex["axx"] - 1).max()
+    e_u = np.abs(r["ux"] - ex["ux"][:, None]).max(axis=0) / pr.meta["Uc"]
+    assert e_xy.max() < 1.25 * bud_xy and e_xx.max() < 1.25 * bud_xx, (e_xy.max(), e_xx.max(),
+                                                                        bud_xy, bud_xx)
+    assert e_u[0] < 1e-14 and e_u.max() < 1e-2, e_u
 
 
 @pytest.mark.parametrize("walls", ["y", "x"])
