@@ -69,7 +69,7 @@ enum { VLB_NODE_FLUID = 0, VLB_NODE_SOLID = 1, VLB_NODE_BOUNDARY = 2 };
 /* Parameter flags. */
 enum {
     VLB_FLAG_NO_SOURCE = 1,   /* constitutive source S forced to 0 (conservation checks)     */
-    VLB_FLAG_CURVED_YLW = 2   /* curved (circle) links of f: the paper's cylinder scheme YLW
+    VLB_FLAG_CURVED_YLW = 2,  /* curved (circle) links of f: the paper's cylinder scheme YLW
                                  (Sec. 4.3) instead of linear interpolated bounce-back -- the
                                  unified interpolation of Yu, Mei, Luo and Shyy (2003),
                                  [(1 - q) f_o(x + e_i) + q f_o(x) + q f_i(x)] / (1 + q) for the
@@ -78,6 +78,13 @@ enum {
                                  (known populations plus those that left toward the wall), the
                                  conservation CNEBB shares with it (Sec. 3.3).  Flat walls
                                  (q = 1/2) stay half-way.  Not differentiable by the adjoint. */
+    VLB_FLAG_OPEN_NEBB = 4    /* VLB_OPEN x only, y not VLB_WET: the hydrodynamic open ends of
+                                 the paper's cylinder (Sec. 4.3) as wet boundary nodes -- the
+                                 first and last columns rebuild the populations from beyond the
+                                 inlet / outlet by non-equilibrium bounce-back (Zou-He) for the
+                                 inlet velocity (u_in(y), 0) and for density 1 with u_y = 0,
+                                 with the half-force shift; the conformation lattices keep the
+                                 extrapolation ghosts.  VLB_E_UNSUPPORTED otherwise. */
 };
 
 typedef struct vlb_sim vlb_sim;

@@ -23,6 +23,7 @@ VLB_FP32, VLB_FP64 = 0, 1
 VLB_PERIODIC, VLB_WALL, VLB_OPEN, VLB_WET = 0, 1, 2, 3
 VLB_FLAG_NO_SOURCE = 1
 VLB_FLAG_CURVED_YLW = 2
+VLB_FLAG_OPEN_NEBB = 4
 MODES = {"periodic": VLB_PERIODIC, "wall": VLB_WALL, "open": VLB_OPEN, "wet": VLB_WET}
 
 # Every symbol declared in include/vlb.h.

@@ -440,6 +440,7 @@ Run<T> make_run(const vlb_sim* s) {
     r.uniform_force = s->force_field ? 0 : 1;
     r.no_source = (s->params.flags & VLB_FLAG_NO_SOURCE) ? 1 : 0;
     r.ylw = (s->params.flags & VLB_FLAG_CURVED_YLW) ? 1 : 0;
+    r.open_nebb = (s->params.flags & VLB_FLAG_OPEN_NEBB) ? 1 : 0;
     r.plane = s->plane;
     r.pop[0] = s->dptr<T>(s->off_pop[0]);
     r.pop[1] = s->dptr<T>(s->off_pop[1]);
@@ -764,8 +765,11 @@ int vlb_set_params(vlb_sim* s, const vlb_params* p) {
     if (!(p->eta_p >= 0)) return fail(VLB_E_INVALID_ARG, "eta_p must be >= 0");
     if (!(p->Lambda_s > 0) || !(p->Lambda_p > 0))
         return fail(VLB_E_INVALID_ARG, "magic parameters must be > 0");
-    if (p->flags & ~(VLB_FLAG_NO_SOURCE | VLB_FLAG_CURVED_YLW))
+    if (p->flags & ~(VLB_FLAG_NO_SOURCE | VLB_FLAG_CURVED_YLW | VLB_FLAG_OPEN_NEBB))
         return fail(VLB_E_INVALID_ARG, "unknown flag");
+    if ((p->flags & VLB_FLAG_OPEN_NEBB) && (s->xmode != VLB_OPEN || s->ymode == VLB_WET))
+        return fail(VLB_E_UNSUPPORTED, "VLB_FLAG_OPEN_NEBB needs xmode = VLB_OPEN and ymode "
+                                       "VLB_PERIODIC or VLB_WALL");
     if (p->model < VLB_OLDROYD_B || p->model > VLB_FENE_P)
         return fail(VLB_E_INVALID_ARG, "unknown constitutive model");
     if (p->model != VLB_OLDROYD_B && !std::isfinite(p->model_param))

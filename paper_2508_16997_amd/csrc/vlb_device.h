@@ -228,6 +228,47 @@ __device__ __forceinline__ void zou_he(V f[9], bool bottom, T Fx, T Fy) {
     f[8] = bottom ? f[8] : t8;
 }
 
+// Wet-node NEBB open end (Sec. 4.3, the hydrodynamic inlet and outlet of the cylinder):
+// at the first column the three populations from beyond the inlet (e_x = +1) for the
+// prescribed velocity (uin, 0), at the last column those from beyond the outlet
+// (e_x = -1) for density 1 and u_y = 0, by the Zou-He closure: the normal unknown keeps
+// the non-equilibrium part of its opposite, the diagonals close the x and y momentum.
+// The streamed momentum is j = rho u - F/2 (half-force shift).  The inlet density comes
+// from the known populations, rho = (K - F_x/2) / (1 - uin) with K the rest, tangential
+// and twice the outgoing populations; the outlet momentum is j_x = K - 1.  On the stored
+// deviations f_i - w_i the weights of K sum to 1, and every other relation is a
+// difference of equally weighted populations.
+template <class V>
+__device__ __forceinline__ void zou_he_x(V f[9], bool inlet, T uin, T Fx, T Fy) {
+    const T jy = -0.5 * Fy;
+    const T d24 = T(f[2]) - T(f[4]);
+    const T c = T(f[0]) + T(f[2]) + T(f[4]);
+    // inlet, unknown e_x = +1
+    const T Ki = c + 2.0 * (T(f[3]) + T(f[6]) + T(f[7]));
+    const T rho = (1.0 + Ki - 0.5 * Fx) / (1.0 - uin);
+    const T jxi = rho * uin - 0.5 * Fx;
+    const V i1 = V(T(f[3]) + (2.0 / 3.0) * jxi);
+    const V i5 = V(T(f[7]) - 0.5 * d24 + (1.0 / 6.0) * jxi + 0.5 * jy);
+    const V i8 = V(T(f[6]) + 0.5 * d24 + (1.0 / 6.0) * jxi - 0.5 * jy);
+    // outlet, unknown e_x = -1
+    const T jxo = c + 2.0 * (T(f[1]) + T(f[5]) + T(f[8]));
+    const V o3 = V(T(f[1]) - (2.0 / 3.0) * jxo);
+    const V o7 = V(T(f[5]) + 0.5 * d24 - (1.0 / 6.0) * jxo - 0.5 * jy);
+    const V o6 = V(T(f[8]) - 0.5 * d24 - (1.0 / 6.0) * jxo + 0.5 * jy);
+    f[1] = inlet ? i1 : f[1];
+    f[5] = inlet ? i5 : f[5];
+    f[8] = inlet ? i8 : f[8];
+    f[3] = inlet ? f[3] : o3;
+    f[7] = inlet ? f[7] : o7;
+    f[6] = inlet ? f[6] : o6;
+}
+
+// The node is a wet NEBB open-end node.
+template <class S>
+__device__ __forceinline__ bool nebb_end(const RunDev<S>& R, int x) {
+    return R.open_nebb && (x == 0 || x == R.nx - 1);
+}
+
 // Conservative non-equilibrium bounce-back for one lattice at a boundary node
 // (Sec. 3.3).  On entry g holds the known post-streaming populations and, on wall
 // links, the post-collision populations that moved toward the wall; phi_b is their
@@ -526,6 +567,7 @@ __device__ __forceinline__ bool cell_macros(const RunDev<S>& R, const S* src, in
     node_force(R, p, Fx, Fy);
     const bool wet = wet_row(R, cy);
     if (wet && pull) zou_he(f, cy == 0, Fx, Fy);
+    if (pull && nebb_end(R, cx)) zou_he_x(f, cx == 0, T(R.inlet[cy]), Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
     if (wet) ux = uy = 0.0;  // wall node: the wall velocity
     return true;

@@ -70,6 +70,8 @@ struct RunDev {
     const FillOp* fill;   // fill operations of this run
     int nfill;
     int ylw;              // 1: the curved-wall scheme YLW for f (else linear interpolation)
+    int open_nebb;        // 1: wet-node NEBB open ends for f (first and last columns)
+    int pad2;
     // coefficients, computed in double on the host
     double c1, c2, h1, inv_ts1;  // 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
     double p1, p2, h2;           // 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)

@@ -112,6 +112,7 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
         // wet-node wall: the populations from beyond the wall by non-equilibrium
         // bounce-back (the pulled ghost values are discarded)
         if (pull && wet_row(R, y)) zou_he(f, y == 0, Fx, Fy);
+        if (pull && nebb_end(R, x)) zou_he_x(f, x == 0, T(R.inlet[y]), Fx, Fy);
         if (pull) hist_ld(R.hist, plane, (unsigned)p, hS, hux, huy);
     }
     // ring cells: rows above/below the tile, columns left/right of it

@@ -73,9 +73,14 @@ class Simulation:
         curved = getattr(prob, "curved", "bouzidi")
         if curved not in ("bouzidi", "ylw"):
             raise ValueError(f"unknown curved-wall scheme {curved!r}")
+        ends = getattr(prob, "open_ends", "neqe")
+        if ends not in ("neqe", "nebb"):
+            raise ValueError(f"unknown open-end scheme {ends!r}")
+        flags = (L.VLB_FLAG_CURVED_YLW if curved == "ylw" else 0) | \
+            (L.VLB_FLAG_OPEN_NEBB if ends == "nebb" else 0)
         sim.set_params(prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s, prob.Lambda_p,
                        *(((float(prob.Fx), float(prob.Fy)) if prob.uniform_force() else (0.0, 0.0))),
-                       flags=L.VLB_FLAG_CURVED_YLW if curved == "ylw" else 0,
+                       flags=flags,
                        model=getattr(prob, "model", "oldroyd_b"),
                        model_param=getattr(prob, "model_param", 0.0))
         if not prob.uniform_force():

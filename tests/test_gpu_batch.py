@@ -42,6 +42,9 @@ def _mixed_set(precision):
                               precision=precision).with_(curved="ylw"),
         synth.random_periodic(130, 33, seed=4, xmode="open", ymode="wall",
                               circles=[(50.0, 16.0, 7.2)], precision=precision),
+        synth.random_periodic(100, 29, seed=6, xmode="open", ymode="wall",
+                              circles=[(40.0, 14.2, 6.1)],
+                              precision=precision).with_(curved="ylw", open_ends="nebb"),
     ]
     return runs
 

@@ -51,13 +51,19 @@ def _cases():
                                    curved="ylw"),
         "open_circle_ylw": dict(nx=130, ny=33, xmode="open", ymode="wall",
                                 circles=[(50.0, 16.0, 7.2), (100.0, 10.0, 3.1)], curved="ylw"),
+        # the paper's cylinder set-up: wet-node NEBB open ends and YLW on the circle; and
+        # NEBB ends on a periodic y edge with solid nodes in the end columns
+        "cylinder_nebb_ylw": dict(nx=130, ny=33, xmode="open", ymode="wall",
+                                  circles=[(50.0, 16.0, 7.2)], curved="ylw", open_ends="nebb"),
+        "nebb_periodic_y_solid_ends": dict(nx=90, ny=37, xmode="open", ymode="periodic",
+                                           solid=end_mask, open_ends="nebb"),
     }
 
 
 def _case_problem(name, seed):
     kw = _cases()[name]
-    curved = kw.pop("curved", "bouzidi")
-    return synth.random_periodic(kw.pop("nx"), kw.pop("ny"), seed=seed, **kw).with_(curved=curved)
+    extra = dict(curved=kw.pop("curved", "bouzidi"), open_ends=kw.pop("open_ends", "neqe"))
+    return synth.random_periodic(kw.pop("nx"), kw.pop("ny"), seed=seed, **kw).with_(**extra)
 
 
 @pytest.mark.parametrize("name", list(_cases()))
@@ -186,16 +192,20 @@ def test_cylinder_fp32_full_size_1000_steps_golden(name):
     assert max(err_near["u"], err_near["axx"], err_near["axy"], err_near["ayy"]) < 1e-5, err_near
 
 
-@pytest.mark.parametrize("prec,curved", [("fp32", "bouzidi"), ("fp64", "bouzidi"),
-                                         ("fp32", "ylw")])
-def test_results_independent_of_tiling_and_graphs(prec, curved):
+@pytest.mark.parametrize("prec,variant", [("fp32", "bouzidi"), ("fp64", "bouzidi"),
+                                          ("fp32", "cylinder")])
+def test_results_independent_of_tiling_and_graphs(prec, variant):
     """Bit-identical fields for every tile height, tile order and register budget, with
-    and without hipGraph replay."""
+    and without hipGraph replay (also with the cylinder's YLW wall and NEBB open ends)."""
     from paper_2508_16997_amd import Simulation
 
-    pr = synth.random_periodic(100, 45, seed=3, ymode="wall", circles=[(50.0, 20.0, 8.5)])
-    pr = pr.with_(curved=curved)
-    say("tiling", prec, curved)
+    if variant == "cylinder":
+        pr = synth.random_periodic(130, 45, seed=3, xmode="open", ymode="wall",
+                                   circles=[(50.0, 20.0, 8.5)]).with_(curved="ylw",
+                                                                      open_ends="nebb")
+    else:
+        pr = synth.random_periodic(100, 45, seed=3, ymode="wall", circles=[(50.0, 20.0, 8.5)])
+    say("tiling", prec, variant)
     ref = None
     for ty, chunk, order, waves in ((4, 0, 0, 0), (1, 0, 1, 3), (2, 0, 2, 4), (8, 0, 3, 4),
                                     (4, 3, 2, 3), (8, 3, 3, 3)):
