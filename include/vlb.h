@@ -78,13 +78,15 @@ enum {
                                  (known populations plus those that left toward the wall), the
                                  conservation CNEBB shares with it (Sec. 3.3).  Flat walls
                                  (q = 1/2) stay half-way.  Not differentiable by the adjoint. */
-    VLB_FLAG_OPEN_NEBB = 4    /* VLB_OPEN x only, y not VLB_WET: the hydrodynamic open ends of
+    VLB_FLAG_OPEN_NEBB = 4    /* VLB_OPEN x only: the hydrodynamic open ends of
                                  the paper's cylinder (Sec. 4.3) as wet boundary nodes -- the
                                  first and last columns rebuild the populations from beyond the
                                  inlet / outlet by non-equilibrium bounce-back (Zou-He) for the
                                  inlet velocity (u_in(y), 0) and for density 1 with u_y = 0,
                                  with the half-force shift; the conformation lattices keep the
-                                 extrapolation ghosts.  VLB_E_UNSUPPORTED otherwise. */
+                                 extrapolation ghosts.  With VLB_WET y the corner nodes take
+                                 the open-end rule first, then the wall rule.
+                                 VLB_E_UNSUPPORTED off VLB_OPEN x. */
 };
 
 typedef struct vlb_sim vlb_sim;

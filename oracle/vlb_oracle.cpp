@@ -687,6 +687,8 @@ struct Sim {
         // diagonal ones then follow from the x and y momentum balances
         // (j_y = -F_y/2, no transverse velocity).  At the outlet column the same with the
         // roles of +x and -x exchanged and the density prescribed (1): j_x = K - 1.
+        // At a corner with a wet-node wall the wall rule (stage 7b) follows and has the
+        // last word.
         if (geo.xmode == MODE_OPEN && (flags & FLAG_OPEN_NEBB)) {
 #pragma omp parallel for schedule(static)
             for (long long yy = 0; yy < (long long)ny; ++yy) {

@@ -767,9 +767,8 @@ int vlb_set_params(vlb_sim* s, const vlb_params* p) {
         return fail(VLB_E_INVALID_ARG, "magic parameters must be > 0");
     if (p->flags & ~(VLB_FLAG_NO_SOURCE | VLB_FLAG_CURVED_YLW | VLB_FLAG_OPEN_NEBB))
         return fail(VLB_E_INVALID_ARG, "unknown flag");
-    if ((p->flags & VLB_FLAG_OPEN_NEBB) && (s->xmode != VLB_OPEN || s->ymode == VLB_WET))
-        return fail(VLB_E_UNSUPPORTED, "VLB_FLAG_OPEN_NEBB needs xmode = VLB_OPEN and ymode "
-                                       "VLB_PERIODIC or VLB_WALL");
+    if ((p->flags & VLB_FLAG_OPEN_NEBB) && s->xmode != VLB_OPEN)
+        return fail(VLB_E_UNSUPPORTED, "VLB_FLAG_OPEN_NEBB needs xmode = VLB_OPEN");
     if (p->model < VLB_OLDROYD_B || p->model > VLB_FENE_P)
         return fail(VLB_E_INVALID_ARG, "unknown constitutive model");
     if (p->model != VLB_OLDROYD_B && !std::isfinite(p->model_param))

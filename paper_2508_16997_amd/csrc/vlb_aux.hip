@@ -55,8 +55,8 @@ __device__ __forceinline__ bool node_fields(const RunDev<S>& R, const S* src, in
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     const bool wet = wet_row(R, y);
-    if (wet && pull) zou_he(f, y == 0, Fx, Fy);
     if (pull && nebb_end(R, x)) zou_he_x(f, x == 0, T(R.inlet[y]), Fx, Fy);
+    if (wet && pull) zou_he(f, y == 0, Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
     if (wet) ux = uy = 0.0;  // wall node: the wall velocity
 #pragma unroll

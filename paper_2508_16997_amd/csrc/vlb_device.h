@@ -566,8 +566,8 @@ __device__ __forceinline__ bool cell_macros(const RunDev<S>& R, const S* src, in
     T Fx, Fy, drho;
     node_force(R, p, Fx, Fy);
     const bool wet = wet_row(R, cy);
-    if (wet && pull) zou_he(f, cy == 0, Fx, Fy);
     if (pull && nebb_end(R, cx)) zou_he_x(f, cx == 0, T(R.inlet[cy]), Fx, Fy);
+    if (wet && pull) zou_he(f, cy == 0, Fx, Fy);
     hydro_macros(f, Fx, Fy, drho, rho, ux, uy);
     if (wet) ux = uy = 0.0;  // wall node: the wall velocity
     return true;

@@ -111,8 +111,9 @@ __device__ __forceinline__ void step_tile(const RunDev<S>* __restrict__ runs, co
         node_force(R, p, Fx, Fy);
         // wet-node wall: the populations from beyond the wall by non-equilibrium
         // bounce-back (the pulled ghost values are discarded)
-        if (pull && wet_row(R, y)) zou_he(f, y == 0, Fx, Fy);
+        // (open end first, then the wall row: at a corner the wall rule has the last word)
         if (pull && nebb_end(R, x)) zou_he_x(f, x == 0, T(R.inlet[y]), Fx, Fy);
+        if (pull && wet_row(R, y)) zou_he(f, y == 0, Fx, Fy);
         if (pull) hist_ld(R.hist, plane, (unsigned)p, hS, hux, huy);
     }
     // ring cells: rows above/below the tile, columns left/right of it

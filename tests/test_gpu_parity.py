@@ -57,6 +57,10 @@ def _cases():
                                   circles=[(50.0, 16.0, 7.2)], curved="ylw", open_ends="nebb"),
         "nebb_periodic_y_solid_ends": dict(nx=90, ny=37, xmode="open", ymode="periodic",
                                            solid=end_mask, open_ends="nebb"),
+        # the paper's full cylinder set-up: wet-node walls, NEBB ends (corner nodes), YLW
+        "cylinder_wet_nebb_ylw": dict(nx=120, ny=31, xmode="open", ymode="wet",
+                                      circles=[(45.0, 15.0, 6.3)], curved="ylw",
+                                      open_ends="nebb"),
     }
 
 
