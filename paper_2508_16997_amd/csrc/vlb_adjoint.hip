@@ -266,8 +266,10 @@ __device__ __forceinline__ void block_sum(T v, T* s_red, double* slot, bool add)
     __syncthreads();
 }
 
-template <class S, int TY>
-__global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restrict__ run,
+// WALLS = false compiles the periodic form (no geometry bits: every wall branch folds
+// away and the kernel keeps the register budget of three waves per SIMD).
+template <class S, int TY, bool WALLS>
+__global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __restrict__ run,
                                                        const AdjDev<S>* __restrict__ adj,
                                                        const Item* __restrict__ items, int first,
                                                        const S* __restrict__ ain,
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
     const int x = x0 + lx, y = y0 + ly;
     const bool in_dom = x < R.nx && y < R.ny;
     const int p = node_index(R, x, y);
-    const unsigned b = in_dom ? node_bits(R, p) : 0u;
+    const unsigned b = (WALLS && in_dom) ? node_bits(R, p) : 0u;
     const bool active = in_dom && !(b & BIT_SELF_SOLID);
 
     // ---- forward front end of step n (as in the step kernel) ----
@@ -380,9 +382,16 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
         // so f_i(x) also feeds the pull of x in direction i (second branch) and, as
         // f_o(far), the pull of the neighbour x + e_i in direction opp(i) (first branch).
         // The conformation lattices copy f_o(x) into the CNEBB input of direction d.
-        auto nb = [&](int i) -> unsigned { return (unsigned)nb_slot(R, x, y, ex(i), ey(i)); };
+        // (wrapped on every axis: a neighbour across a wall axis is never fluid, so its
+        // slot is never used)
+        const int xl = wrapm(x - 1, R.nx), xh = wrapm(x + 1, R.nx);
+        const int yl = wrapm(y - 1, R.ny), yh = wrapm(y + 1, R.ny);
+        const int row[3] = {R.off0 + yl * R.pitch, R.off0 + y * R.pitch, R.off0 + yh * R.pitch};
+        const int col[3] = {xl, x, xh};
+        auto nb = [&](int i) -> unsigned { return (unsigned)(row[1 + ey(i)] + col[1 + ex(i)]); };
         auto lq = [&](unsigned bits, int slot, int i) -> T {
-            return (R.has_curved && ((bits >> i) & 1u)) ? link_q(R, R.bidx[slot], i) : 0.5;
+            return (WALLS && R.has_curved && ((bits >> i) & 1u)) ? link_q(R, R.bidx[slot], i)
+                                                                 : 0.5;
         };
         auto solid_nb = [&](int i) -> bool { return (b >> opp(i)) & 1u; };
 
@@ -395,7 +404,7 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
             if (!solid_nb(i)) {
                 const unsigned q_ = nb(i);
                 v = ldu(ain + i * plane, q_);
-                if (R.has_curved) {
+                if (WALLS && R.has_curved) {
                     // (first branch at the neighbour) x + e_i pulls d from x + 2 e_i
                     const unsigned bn = node_bits(R, (int)q_);
                     if ((bn >> d) & 1u) {
@@ -540,7 +549,7 @@ __global__ __launch_bounds__(64 * TY) void k_adj_local(const RunDev<S>* __restri
     block_sum<TY>(geta, s_red, A.part + 2 * blockIdx.x + 1, true);
 }
 
-template <class S, int TY>
+template <class S, int TY, bool WALLS>
 __global__ __launch_bounds__(64 * TY) void k_adj_gather(const RunDev<S>* __restrict__ run,
                                                         const AdjDev<S>* __restrict__ adj,
                                                         const Item* __restrict__ items,
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(64 * TY) void k_adj_gather(const RunDev<S>* __restr
     if (x >= A.nx || y >= A.ny) return;
     const long long plane = A.plane;
     const unsigned p = (unsigned)node_index(R, x, y);
-    const unsigned b = node_bits(R, (int)p);
+    const unsigned b = WALLS ? node_bits(R, (int)p) : 0u;
     if (b & BIT_SELF_SOLID) return;
     const S* sc = A.scr;
     auto rd = [&](int c, unsigned q) -> T { return ldu(sc + c * plane, q); };
@@ -573,7 +582,7 @@ __global__ __launch_bounds__(64 * TY) void k_adj_gather(const RunDev<S>* __restr
         if ((b >> bitdir) & 1u) return;  // not a fluid node
         const unsigned q = (unsigned)nb_slot(R, x, y, dx, dy);
         T c[3], cdum[3];
-        const unsigned bn = node_bits(R, (int)q);
+        const unsigned bn = WALLS ? node_bits(R, (int)q) : 0u;
         if (dx != 0) node_fd_coefs(R, (int)q, bn, c, cdum);
         else node_fd_coefs(R, (int)q, bn, cdum, c);
 #pragma unroll
@@ -683,35 +692,43 @@ hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, c
     return hipGetLastError();
 }
 
-template <class S>
-hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
-                           int nitems, int ty, int first, const S* ain, S* aout, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
+template <class S, bool WALLS>
+hipError_t launch_adj_step_w(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                             int nitems, int ty, int first, const S* ain, S* aout, hipStream_t s) {
     switch (ty) {
         case 1:
-            hipLaunchKernelGGL((k_adj_local<S, 1>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 1>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_local<S, 1, WALLS>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, first, ain, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 1, WALLS>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, aout);
             break;
         case 2:
-            hipLaunchKernelGGL((k_adj_local<S, 2>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 2>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_local<S, 2, WALLS>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, first, ain, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 2, WALLS>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, aout);
             break;
         case 4:
-            hipLaunchKernelGGL((k_adj_local<S, 4>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 4>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_local<S, 4, WALLS>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, first, ain, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 4, WALLS>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, aout);
             break;
         case 8:
-            hipLaunchKernelGGL((k_adj_local<S, 8>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 8>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, aout);
+            hipLaunchKernelGGL((k_adj_local<S, 8, WALLS>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, first, ain, aout);
+            hipLaunchKernelGGL((k_adj_gather<S, 8, WALLS>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, aout);
             break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <class S>
+hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                           int nitems, int ty, int first, int walls, const S* ain, S* aout,
+                           hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    return walls ? launch_adj_step_w<S, true>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, s)
+                 : launch_adj_step_w<S, false>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, s);
+}
+
 template hipError_t launch_adj_seed<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, const float*, int, float*, hipStream_t);
 template hipError_t launch_adj_seed<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, const double*, int, double*, hipStream_t);
-template hipError_t launch_adj_step<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, int, const float*, float*, hipStream_t);
-template hipError_t launch_adj_step<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_adj_step<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, int, int, const float*, float*, hipStream_t);
+template hipError_t launch_adj_step<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, int, int, const double*, double*, hipStream_t);
 
 }  // namespace vlb

@@ -1175,7 +1175,8 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
-            VLB_HIP(vlb::launch_adj_step<T>(desc + k, ad, items, s->nitems, s->ty, first, abuf[cur],
+            VLB_HIP(vlb::launch_adj_step<T>(desc + k, ad, items, s->nitems, s->ty, first,
+                                            s->has_bits ? 1 : 0, abuf[cur],
                                             abuf[cur ^ 1], s->stream));
             cur ^= 1;
         }

@@ -149,9 +149,11 @@ hipError_t launch_monitor(const RunDev<S>& run_host, const RunDev<S>* run_dev, i
 template <class S>
 hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
                            int nitems, int ty, const S* src, int pull, S* aout, hipStream_t s);
+// walls: the run has geometry bits (walls, solids); 0 selects the periodic kernels.
 template <class S>
 hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
-                           int nitems, int ty, int first, const S* ain, S* aout, hipStream_t s);
+                           int nitems, int ty, int first, int walls, const S* ain, S* aout,
+                           hipStream_t s);
 // Momentum-exchange force: per block of 256 boundary links, 2 partial sums (F_x, F_y).
 template <class S>
 hipError_t launch_drag(const RunDev<S>* run_dev, const int* links, int nlinks, int circle,

@@ -179,6 +179,62 @@ def test_cylinder_drag_coefficient_vs_paper(Sc, wis):
         s.close()
 
 
+def _steady_cd(probs, cases, stream):
+    """Run a batch of cylinder channels to the steady criterion; C_d per case (None for a
+    run that is not steady by t* = 1000)."""
+    from paper_2508_16997_amd import Batch, Simulation
+
+    sims = [Simulation.from_problem(p, stream=stream) for p in probs]
+    b = Batch(sims, tile=4, graph_chunk=100)
+    tcs = [p.meta["Tc"] for p in probs]
+    ucs = [p.meta["Uc"] for p in probs]
+    b.step(1)
+    for s in sims:
+        s.monitors()
+    n, last, cd, done = 1, [1] * len(sims), [None] * len(sims), [False] * len(sims)
+    step = int(round(min(tcs)))
+    while not all(done):
+        b.step(step)
+        n += step
+        for i, s in enumerate(sims):
+            if not done[i] and n - last[i] >= tcs[i]:
+                m = s.monitors(raise_on_nonfinite=False)
+                last[i] = n
+                assert m["nonfinite"] == 0, ("breakdown", cases[i], n / tcs[i])
+                if m["residual"] / ucs[i] < 1e-8:
+                    fx, _ = s.drag(0)
+                    cd[i] = fx / (0.5 * ucs[i] ** 2 * 2 * cases[i][0])
+                    done[i] = True
+                elif n / tcs[i] > 1000:
+                    done[i] = True
+    b.close()
+    for s in sims:
+        s.close()
+    return cd
+
+
+def test_cylinder_drag_paper_boundary_set():
+    """The paper's boundary set for f on the cylinder (Sec. 4.3): wet-node NEBB inlet and
+    outlet and the curved-wall scheme YLW on the circle (readings A30, A31), half-way
+    channel walls; Sc = 1e6, R = 20, Wi = 0.1 and 0.5, FP64.  Both runs become steady,
+    within 1.5 % and 2 % of the paper's CNEBB values, with C_d falling from Wi = 0.1 to
+    0.5 as in the paper."""
+    import torch
+
+    paper = _paper_cd()
+    cases = [(20, 0.1), (20, 0.5)]
+    probs = [synth.cylinder_channel(R=R, Wi=wi, Sc=1e6).with_(open_ends="nebb", curved="ylw")
+             for R, wi in cases]
+    say("cylinder C_d, NEBB ends + YLW", cases)
+    cd = _steady_cd(probs, cases, torch.cuda.Stream())
+    say("C_d", dict(zip(cases, cd)))
+    assert all(c is not None for c in cd), cd
+    for (R, wi), c, tol in zip(cases, cd, (0.015, 0.02)):
+        ref = paper[(1e6, R)][wi]
+        assert abs(c / ref - 1) < tol, (R, wi, c, ref)
+    assert cd[1] < cd[0]
+
+
 @pytest.mark.skipif(not os.environ.get("VLB_LONG_TESTS"),
                     reason="2-13 minutes of GPU time per Schmidt number; set VLB_LONG_TESTS=1")
 @pytest.mark.parametrize("Sc", [1e4, 1e5, 1e6])
