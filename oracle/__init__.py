@@ -22,6 +22,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vlb_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
+# the three-dimensional (D3Q19) oracle: a separate library, vlb_oracle3d.cpp
+_SRC3 = os.path.join(_HERE, "vlb_oracle3d.cpp")
+_LIB3 = os.path.join(_HERE, "liboracle3d.so")
+_lib3 = None
 
 MODES = {"periodic": 0, "wall": 1, "open": 2, "wet": 3}
 # constitutive closures (model function F(A), Sec. 2.2) and the meaning of model_param
@@ -39,13 +43,15 @@ FLAG_OPEN_NEBB = 32
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/liboracle.so`` (g++, -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-shared", "-fPIC", "-o", tmp, _SRC]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracles into ``oracle/liboracle.so`` and ``oracle/liboracle3d.so``
+    (g++, -O2, no fast-math)."""
+    for src, lib in ((_SRC, _LIB), (_SRC3, _LIB3)):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            tmp = lib + ".tmp"
+            cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                   "-fopenmp", "-shared", "-fPIC", "-o", tmp, src]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -281,3 +287,75 @@ def node_source(A3, L4, lam, model=None, mpar=0.0):
 
 def node_fd(lo_solid, qlo, plo, p0, hi_solid, qhi, phi):
     return float(_load().orc_node_fd(int(lo_solid), qlo, plo, p0, int(hi_solid), qhi, phi))
+
+
+# ------------------------------------------------------------------------------------
+# Three-dimensional (D3Q19) oracle
+# ------------------------------------------------------------------------------------
+FIELDS3 = ("rho", "ux", "uy", "uz", "axx", "axy", "axz", "ayy", "ayz", "azz")
+
+
+def _load3():
+    global _lib3
+    if _lib3 is not None:
+        return _lib3
+    path = os.environ.get("ORACLE3D_LIBRARY")
+    if not path:
+        if not os.path.exists(_LIB3) or os.path.getmtime(_LIB3) < os.path.getmtime(_SRC3):
+            build(force=False)
+        path = _LIB3
+    lib = C.CDLL(path)
+    P, D, DP = C.c_void_p, C.c_double, C.POINTER(C.c_double)
+    lib.o3_create.restype = P
+    lib.o3_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.o3_destroy.argtypes = [P]
+    lib.o3_set_params.argtypes = [P, D, D, D, D, D, D, D, D, D, C.c_int]
+    lib.o3_init.argtypes = [P] + [DP] * 10
+    lib.o3_step.argtypes = [P, C.c_longlong]
+    lib.o3_read.argtypes = [P] + [DP] * 10
+    lib.o3_lattice.argtypes = [C.c_void_p, DP, C.c_void_p, DP]
+    _lib3 = lib
+    return lib
+
+
+class OracleSim3D:
+    """One three-dimensional oracle simulation built from a :class:`synth.Problem3D`."""
+
+    def __init__(self, prob, no_source: bool = False):
+        lib = _load3()
+        self.prob = prob
+        self.shape = (prob.nz, prob.ny, prob.nx)
+        self.h = lib.o3_create(prob.nx, prob.ny, prob.nz, 1 if prob.ymode == "wall" else 0)
+        if not self.h:
+            raise ValueError("oracle3d: invalid grid")
+        Fx, Fy, Fz = (float(v) for v in prob.F)
+        if lib.o3_set_params(self.h, prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s,
+                             prob.Lambda_p, Fx, Fy, Fz, 1 if no_source else 0) != 0:
+            raise ValueError("oracle3d: invalid parameters")
+        f = prob.init_arrays()
+        arrs = [_c64(f[k]) for k in FIELDS3]
+        lib.o3_init(self.h, *[_dp(a) for a in arrs])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _load3().o3_destroy(self.h)
+            self.h = None
+
+    def step(self, n: int = 1):
+        _load3().o3_step(self.h, int(n))
+
+    def read(self) -> dict:
+        out = {k: np.zeros(self.shape) for k in FIELDS3}
+        _load3().o3_read(self.h, *[_dp(out[k]) for k in FIELDS3])
+        return out
+
+
+def lattice3d():
+    """D3Q19 velocities (19, 3), weights, opposites and the third-order combinations
+    (h_{c,+}, h_{c,-}) for c = 0, 1, 2 at every velocity (19, 6)."""
+    e = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, np.int32)
+    h3 = np.zeros((19, 6))
+    _load3().o3_lattice(e.ctypes.data, _dp(w), opp.ctypes.data, _dp(h3))
+    return e, w, opp, h3

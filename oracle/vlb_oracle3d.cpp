@@ -1,0 +1,507 @@
+/*
+ * vlb_oracle3d.cpp -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, double-precision CPU implementation of the coupled viscoelastic
+ * lattice Boltzmann step of arXiv:2508.16997 extended to three dimensions on the D3Q19
+ * lattice (the paper works in two dimensions and calls the three-dimensional extension
+ * straightforward, Sec. 3.1; the readings of that extension are listed in the design
+ * notes under A32).  Only the tests and the CPU-baseline leg of the benchmark may load
+ * it; it shares no code with the HIP library nor with the two-dimensional oracle.
+ *
+ * Same stages and the same formulas as the two-dimensional method, with every tensor
+ * index running over x, y, z:
+ *   1. rho and u with the half-force shift                               (Sec. 3.1)
+ *   2. conformation A (six components, one convection-diffusion lattice each) and the
+ *      polymer stress (eta_p / lambda)(A - I) (Oldroyd-B)                  (Sec. 2.2-2.3)
+ *   3. velocity gradient L[g][b] = d_g u_b and D_a = d_a(rho u_a^3) by central
+ *      differences; next to a flat half-way wall the quadratic through the no-slip wall
+ *      value half a spacing away                                         (readings A6/A7)
+ *   4. constitutive source Phi = -(A - I)/lambda + A L + (A L)^T + A tr L  (Sec. 3.2)
+ *   5. hydrodynamic TRT regularized collision: Hermite moments of orders 0..3 of f - f^eq
+ *      (third order projected with the lattice's own norms), tau_s1 on orders 0..2,
+ *      tau_s2 on order 3, plus G_i (diagonal third-order defects D_a), F_i and T_i
+ *                                                                         (Sec. 3.1)
+ *   6. six convection-diffusion TRT regularized collisions with the auxiliary term
+ *      G~_i, the source term F~_i and half its backward time difference   (Sec. 3.2)
+ *   7. streaming (pull) with half-way bounce-back of f at flat walls normal to y; the
+ *      conformation populations that left toward the wall are the CNEBB input
+ *   8. conservative non-equilibrium bounce-back for every conformation lattice at
+ *      wall-adjacent nodes                                                (Sec. 3.3)
+ *   9. history of S and u for the time difference
+ *
+ * Axes x and z are periodic; y is periodic or bounded by half-way walls.  Uniform body
+ * force.  Index convention of fields: [z][y][x], x fastest.
+ *
+ * Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
+ */
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ----------------------------------------------------------------------------------
+// D3Q19: the rest velocity, the six axis velocities (weight 1/18) and the twelve
+// face diagonals (weight 1/36), enumerated from {-1, 0, 1}^3 with |e|^2 <= 2;
+// c_s^2 = 1/3.
+// ----------------------------------------------------------------------------------
+const int Q = 19;
+int E[Q][3], OPP[Q];
+double W[Q];
+const double CS2 = 1.0 / 3.0;
+
+struct LatticeInit {
+    LatticeInit() {
+        int n = 0;
+        for (int norm = 0; norm <= 2; ++norm)
+            for (int a = -1; a <= 1; ++a)
+                for (int b = -1; b <= 1; ++b)
+                    for (int c = -1; c <= 1; ++c)
+                        if (a * a + b * b + c * c == norm) {
+                            E[n][0] = a;
+                            E[n][1] = b;
+                            E[n][2] = c;
+                            W[n] = norm == 0 ? 1.0 / 3.0 : (norm == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+                            ++n;
+                        }
+        for (int i = 0; i < Q; ++i)
+            for (int j = 0; j < Q; ++j)
+                if (E[j][0] == -E[i][0] && E[j][1] == -E[i][1] && E[j][2] == -E[i][2]) OPP[i] = j;
+    }
+} lattice_init_instance;
+
+inline double ec(int i, int a) { return (double)E[i][a]; }
+inline double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+// Hermite polynomials of orders 1..3 (Sec. 3.1), indices over x, y, z.
+inline double H1(int i, int a) { return ec(i, a); }
+inline double H2(int i, int a, int b) { return ec(i, a) * ec(i, b) - CS2 * kd(a, b); }
+inline double H3(int i, int a, int b, int c) {
+    return ec(i, a) * ec(i, b) * ec(i, c) -
+           CS2 * (ec(i, a) * kd(b, c) + ec(i, b) * kd(a, c) + ec(i, c) * kd(a, b));
+}
+
+// Third-order content on D3Q19 (reading A32).  The xxx- and xyz-type Hermite
+// polynomials vanish at every D3Q19 velocity; the six xxy-type ones remain but are
+// neither orthogonal nor of their continuous norm 2 c_s^6 on this lattice.  They are
+// handled through the six combinations h_{c,s} = H_aab + s H_bcc (s = +1, -1) for
+// (a, b, c) = (x, y, z), (z, x, y), (y, z, x) -- H_xxy -+ H_yzz, H_zzx -+ H_xyy,
+// H_yyz -+ H_zxx -- which are mutually orthogonal on D3Q19 with lattice norms
+// sum_i w_i h^2 = 2 c_s^6 (s = +1) and 6 c_s^6 (s = -1) (checked by the tests).
+const int HC[3][3] = {{0, 1, 2}, {2, 0, 1}, {1, 2, 0}};
+inline double hc(int i, int c, int sgn) {
+    const int a = HC[c][0], b = HC[c][1], d = HC[c][2];
+    return H3(i, a, a, b) + sgn * H3(i, b, d, d);
+}
+inline double hnorm(int sgn) { return (sgn > 0 ? 2.0 : 6.0) * CS2 * CS2 * CS2; }
+// The matching continuous third-order moments of the equilibrium per unit density:
+// u_a^2 u_b -+ u_b u_c^2.
+inline double uc3(const double u[3], int c, int sgn) {
+    const int a = HC[c][0], b = HC[c][1], d = HC[c][2];
+    return u[a] * u[a] * u[b] + sgn * u[b] * u[d] * u[d];
+}
+
+// Hydrodynamic equilibrium, Hermite expansion to third order (Sec. 3.1); the third
+// order expanded in the h_{c,s} with their lattice norms, so that the lattice
+// equilibrium has the continuous third-order moments along every direction the
+// lattice resolves.
+double feq(int i, double rho, const double u[3]) {
+    double s = 1.0;
+    for (int a = 0; a < 3; ++a) s += H1(i, a) / CS2 * u[a];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) s += H2(i, a, b) / (2.0 * CS2 * CS2) * u[a] * u[b];
+    for (int c = 0; c < 3; ++c)
+        for (int sg = -1; sg <= 1; sg += 2) s += hc(i, c, sg) / hnorm(sg) * uc3(u, c, sg);
+    return W[i] * rho * s;
+}
+
+// Convection-diffusion equilibrium, second-order Hermite expansion (Sec. 3.2).
+double geq(int i, double phi, const double u[3]) {
+    double s = 1.0;
+    for (int a = 0; a < 3; ++a) s += H1(i, a) / CS2 * u[a];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) s += H2(i, a, b) / (2.0 * CS2 * CS2) * u[a] * u[b];
+    return W[i] * phi * s;
+}
+
+struct Params {
+    double tau_s1 = 1.0, tau_s2 = 1.0, tau_p1 = 1.0, tau_p2 = 1.0, lam = 1.0, eta_p = 0.0;
+    double F[3] = {0.0, 0.0, 0.0};
+    int no_source = 0;
+};
+
+// Hydrodynamic TRT regularized collision (Sec. 3.1, three-dimensional indices).
+void collide_hydro(const double f[Q], double rho, const double u[3], const double F[3],
+                   const double tau[3][3], const double D[3], const Params& p, double out[Q]) {
+    double fe[Q];
+    for (int i = 0; i < Q; ++i) fe[i] = feq(i, rho, u);
+    double A0 = 0.0, A1[3] = {0.0, 0.0, 0.0}, A2[3][3], A3[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) A2[a][b] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        const double d = f[i] - fe[i];
+        A0 += d;
+        for (int a = 0; a < 3; ++a) A1[a] += H1(i, a) * d;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A2[a][b] += H2(i, a, b) * d;
+        for (int c = 0; c < 3; ++c) {
+            A3[c][0] += hc(i, c, -1) * d;
+            A3[c][1] += hc(i, c, +1) * d;
+        }
+    }
+    const double c1 = 1.0 - 1.0 / p.tau_s1, c2 = 1.0 - 1.0 / p.tau_s2;
+    const double h1 = 1.0 - 1.0 / (2.0 * p.tau_s1);
+    for (int i = 0; i < Q; ++i) {
+        double reg1 = A0;
+        for (int a = 0; a < 3; ++a) reg1 += H1(i, a) / CS2 * A1[a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) reg1 += H2(i, a, b) / (2.0 * CS2 * CS2) * A2[a][b];
+        double reg2 = 0.0;  // projection on the h_{c,s} with their lattice norms
+        for (int c = 0; c < 3; ++c)
+            reg2 += hc(i, c, -1) / hnorm(-1) * A3[c][0] + hc(i, c, +1) / hnorm(+1) * A3[c][1];
+        // G_i: d_g Phi_abg restricted to the diagonal defects (a, a) <- d_a(rho u_a^3)
+        double sumG = 0.0, sumT = 0.0, sumF = 0.0;
+        for (int a = 0; a < 3; ++a) sumG += H2(i, a, a) / (6.0 * CS2 * CS2 * CS2) * D[a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) sumT += H2(i, a, b) / (2.0 * CS2 * CS2) * tau[a][b];
+        for (int a = 0; a < 3; ++a) sumF += H1(i, a) / CS2 * F[a];
+        const double Gi = -W[i] * h1 * sumG;
+        const double Ti = -W[i] * sumT / p.tau_s1;
+        const double Fi = h1 * W[i] * sumF;
+        out[i] = fe[i] + W[i] * c1 * reg1 + W[i] * c2 * reg2 + Gi + Fi + Ti;
+    }
+}
+
+// Convection-diffusion TRT regularized collision for one component (Sec. 3.2).
+void collide_cde(const double g[Q], double phi, double rho, const double u[3],
+                 const double F[3], double S, double Sp, const double up[3], const Params& p,
+                 double out[Q]) {
+    double ge[Q];
+    for (int i = 0; i < Q; ++i) ge[i] = geq(i, phi, u);
+    double B0 = 0.0, B1[3] = {0.0, 0.0, 0.0}, B2[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) B2[a][b] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        const double d = g[i] - ge[i];
+        B0 += d;
+        for (int a = 0; a < 3; ++a) B1[a] += H1(i, a) * d;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) B2[a][b] += H2(i, a, b) * d;
+    }
+    const double c1 = 1.0 - 1.0 / p.tau_p1, c2 = 1.0 - 1.0 / p.tau_p2;
+    const double h2 = 1.0 - 1.0 / (2.0 * p.tau_p1);
+    for (int i = 0; i < Q; ++i) {
+        double reg1 = B0;
+        for (int a = 0; a < 3; ++a) reg1 += H1(i, a) / CS2 * B1[a];
+        double reg2 = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) reg2 += H2(i, a, b) / (2.0 * CS2 * CS2) * B2[a][b];
+        double eF = 0.0, eu = 0.0, eup = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            eF += ec(i, a) / CS2 * F[a];
+            eu += ec(i, a) / CS2 * u[a];
+            eup += ec(i, a) / CS2 * up[a];
+        }
+        const double Gt = W[i] * h2 * eF * phi / rho;
+        const double Ft_now = W[i] * S + h2 * W[i] * eu * S;
+        const double Ft_prev = W[i] * Sp + h2 * W[i] * eup * Sp;
+        out[i] = ge[i] + W[i] * c1 * reg1 + W[i] * c2 * reg2 + Gt + Ft_now +
+                 0.5 * (Ft_now - Ft_prev);
+    }
+}
+
+// Components of the symmetric conformation tensor, one lattice each.
+const int KA[6] = {0, 0, 0, 1, 1, 2}, KB[6] = {0, 1, 2, 1, 2, 2};
+inline int comp(int a, int b) {
+    if (a > b) std::swap(a, b);
+    for (int k = 0; k < 6; ++k)
+        if (KA[k] == a && KB[k] == b) return k;
+    return -1;
+}
+
+// Central difference along one axis, or (flat half-way wall half a spacing away) the
+// quadratic through the no-slip wall value 0 (reading A6 with q = 1/2).
+double fd(bool lo_wall, double vlo, double v0, bool hi_wall, double vhi) {
+    const double q = 0.5;
+    if (!lo_wall && !hi_wall) return 0.5 * (vhi - vlo);
+    if (lo_wall && !hi_wall) return q / (1.0 + q) * vhi + (1.0 - q) / q * v0;
+    if (!lo_wall) return -(q / (1.0 + q) * vlo + (1.0 - q) / q * v0);
+    return 0.0;
+}
+
+struct Sim {
+    int nx, ny, nz, ywall;
+    size_t N;
+    Params p;
+    std::vector<double> f[Q], fp[Q], g[6][Q], gp[6][Q];
+    std::vector<double> rho, u[3], A[6], Sprev[6], uprev[3];
+    bool first = true;
+    long long step = 0;
+
+    Sim(int nx_, int ny_, int nz_, int ywall_) : nx(nx_), ny(ny_), nz(nz_), ywall(ywall_) {
+        N = (size_t)nx * ny * nz;
+        for (int i = 0; i < Q; ++i) {
+            f[i].assign(N, 0.0);
+            fp[i].assign(N, 0.0);
+            for (int k = 0; k < 6; ++k) {
+                g[k][i].assign(N, 0.0);
+                gp[k][i].assign(N, 0.0);
+            }
+        }
+        rho.assign(N, 1.0);
+        for (int a = 0; a < 3; ++a) {
+            u[a].assign(N, 0.0);
+            uprev[a].assign(N, 0.0);
+        }
+        for (int k = 0; k < 6; ++k) {
+            A[k].assign(N, 0.0);
+            Sprev[k].assign(N, 0.0);
+        }
+    }
+    size_t idx(int x, int y, int z) const { return ((size_t)z * ny + y) * nx + x; }
+    static int wrap(int v, int n) { return ((v % n) + n) % n; }
+    // Source node of the pull x - e_i: false when it lies beyond a wall.
+    bool source(int x, int y, int z, int i, size_t* s) const {
+        int xs = wrap(x - E[i][0], nx), ys = y - E[i][1], zs = wrap(z - E[i][2], nz);
+        if (ys < 0 || ys >= ny) {
+            if (ywall) return false;
+            ys = wrap(ys, ny);
+        }
+        *s = idx(xs, ys, zs);
+        return true;
+    }
+
+    void macros() {
+        for (size_t n = 0; n < N; ++n) {
+            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < Q; ++i) {
+                r += f[i][n];
+                for (int a = 0; a < 3; ++a) j[a] += ec(i, a) * f[i][n];
+            }
+            rho[n] = r;
+            for (int a = 0; a < 3; ++a) u[a][n] = (j[a] + 0.5 * p.F[a]) / r;
+            for (int k = 0; k < 6; ++k) {
+                double s = 0.0;
+                for (int i = 0; i < Q; ++i) s += g[k][i][n];
+                A[k][n] = s;
+            }
+        }
+    }
+
+    void init(const double* r0, const double* u0[3], const double* a0[6]) {
+        for (size_t n = 0; n < N; ++n) {
+            const double r = r0 ? r0[n] : 1.0;
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = u0[a] ? u0[a][n] : 0.0;
+            for (int i = 0; i < Q; ++i) f[i][n] = feq(i, r, v);
+            for (int k = 0; k < 6; ++k) {
+                const double phi = a0[k] ? a0[k][n] : (KA[k] == KB[k] ? 1.0 : 0.0);
+                for (int i = 0; i < Q; ++i) g[k][i][n] = geq(i, phi, v);
+            }
+        }
+        first = true;
+        step = 0;
+    }
+
+    void step_once() {
+        macros();
+        std::vector<double> Snew[6];
+        for (int k = 0; k < 6; ++k) Snew[k].assign(N, 0.0);
+#pragma omp parallel for schedule(static)
+        for (long long nn = 0; nn < (long long)N; ++nn) {
+            const size_t n = (size_t)nn;
+            const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
+            // neighbours along the axes
+            const size_t nxl = idx(wrap(x - 1, nx), y, z), nxh = idx(wrap(x + 1, nx), y, z);
+            const size_t nzl = idx(x, y, wrap(z - 1, nz)), nzh = idx(x, y, wrap(z + 1, nz));
+            const bool ylo_wall = ywall && y == 0, yhi_wall = ywall && y == ny - 1;
+            const size_t nyl = idx(x, wrap(y - 1, ny), z), nyh = idx(x, wrap(y + 1, ny), z);
+            auto dax = [&](int ax, auto val) {
+                if (ax == 0) return fd(false, val(nxl), val(n), false, val(nxh));
+                if (ax == 2) return fd(false, val(nzl), val(n), false, val(nzh));
+                return fd(ylo_wall, ylo_wall ? 0.0 : val(nyl), val(n), yhi_wall,
+                          yhi_wall ? 0.0 : val(nyh));
+            };
+            double L[3][3], D[3];
+            for (int gm = 0; gm < 3; ++gm)
+                for (int b = 0; b < 3; ++b) L[gm][b] = dax(gm, [&](size_t m) { return u[b][m]; });
+            for (int a = 0; a < 3; ++a)
+                D[a] = dax(a, [&](size_t m) { return rho[m] * u[a][m] * u[a][m] * u[a][m]; });
+            double Am[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Am[a][b] = A[comp(a, b)][n];
+            // constitutive source (Oldroyd-B)
+            double S[3][3];
+            const double trL = L[0][0] + L[1][1] + L[2][2];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double s = -(Am[a][b] - kd(a, b)) / p.lam;
+                    for (int gm = 0; gm < 3; ++gm) s += Am[a][gm] * L[gm][b] + Am[gm][b] * L[gm][a];
+                    s += Am[a][b] * trL;
+                    S[a][b] = p.no_source ? 0.0 : s;
+                }
+            double tau[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) tau[a][b] = p.eta_p / p.lam * (Am[a][b] - kd(a, b));
+            double fl[Q], out[Q];
+            for (int i = 0; i < Q; ++i) fl[i] = f[i][n];
+            const double uu[3] = {u[0][n], u[1][n], u[2][n]};
+            collide_hydro(fl, rho[n], uu, p.F, tau, D, p, out);
+            for (int i = 0; i < Q; ++i) fp[i][n] = out[i];
+            const double upv[3] = {first ? uu[0] : uprev[0][n], first ? uu[1] : uprev[1][n],
+                                   first ? uu[2] : uprev[2][n]};
+            for (int k = 0; k < 6; ++k) {
+                double gl[Q], go[Q];
+                for (int i = 0; i < Q; ++i) gl[i] = g[k][i][n];
+                const double Sk = S[KA[k]][KB[k]];
+                const double Spk = first ? Sk : Sprev[k][n];
+                collide_cde(gl, A[k][n], rho[n], uu, p.F, Sk, Spk, upv, p, go);
+                for (int i = 0; i < Q; ++i) gp[k][i][n] = go[i];
+                Snew[k][n] = Sk;
+            }
+        }
+        // streaming (pull), half-way bounce-back of f at the walls, wall-bound g kept
+#pragma omp parallel for schedule(static)
+        for (long long nn = 0; nn < (long long)N; ++nn) {
+            const size_t n = (size_t)nn;
+            const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
+            for (int i = 0; i < Q; ++i) {
+                size_t s;
+                if (source(x, y, z, i, &s)) {
+                    f[i][n] = fp[i][s];
+                    for (int k = 0; k < 6; ++k) g[k][i][n] = gp[k][i][s];
+                } else {
+                    f[i][n] = fp[OPP[i]][n];
+                    for (int k = 0; k < 6; ++k) g[k][i][n] = gp[k][OPP[i]][n];
+                }
+            }
+        }
+        // CNEBB at wall-adjacent nodes (Sec. 3.3): phi_b = sum of the pulled populations
+        // (known ones plus those that left toward the wall), unknowns rebuilt from the
+        // equilibrium at (phi_b, u_b) plus the non-equilibrium part of the known
+        // opposite, g_0 restores phi_b; u_b from the filled f with the half-force shift
+        // (reading A11).
+        if (ywall) {
+#pragma omp parallel for schedule(static)
+            for (long long nn = 0; nn < (long long)N; ++nn) {
+                const size_t n = (size_t)nn;
+                const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
+                if (y != 0 && y != ny - 1) continue;
+                bool unknown[Q];
+                for (int i = 0; i < Q; ++i) {
+                    size_t s;
+                    unknown[i] = !source(x, y, z, i, &s);
+                }
+                double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < Q; ++i) {
+                    r += f[i][n];
+                    for (int a = 0; a < 3; ++a) j[a] += ec(i, a) * f[i][n];
+                }
+                double ub[3];
+                for (int a = 0; a < 3; ++a) ub[a] = (j[a] + 0.5 * p.F[a]) / r;
+                for (int k = 0; k < 6; ++k) {
+                    double gabs[Q], phib = 0.0;
+                    for (int i = 0; i < Q; ++i) {
+                        gabs[i] = g[k][i][n];
+                        phib += gabs[i];
+                    }
+                    double known[Q];
+                    for (int i = 0; i < Q; ++i) known[i] = gabs[i];
+                    for (int i = 0; i < Q; ++i) {
+                        if (!unknown[i]) continue;
+                        const int o = OPP[i];
+                        gabs[i] = geq(i, phib, ub);
+                        if (!unknown[o]) gabs[i] += known[o] - geq(o, phib, ub);
+                    }
+                    double rest = phib;
+                    for (int i = 0; i < Q; ++i)
+                        if (E[i][0] != 0 || E[i][1] != 0 || E[i][2] != 0) rest -= gabs[i];
+                    for (int i = 0; i < Q; ++i)
+                        if (E[i][0] == 0 && E[i][1] == 0 && E[i][2] == 0) gabs[i] = rest;
+                    for (int i = 0; i < Q; ++i) g[k][i][n] = gabs[i];
+                }
+            }
+        }
+        for (size_t n = 0; n < N; ++n) {
+            for (int k = 0; k < 6; ++k) Sprev[k][n] = Snew[k][n];
+            for (int a = 0; a < 3; ++a) uprev[a][n] = u[a][n];
+        }
+        first = false;
+        ++step;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void* o3_create(int nx, int ny, int nz, int ywall) {
+    if (nx < 1 || ny < 1 || nz < 1 || (ywall && ny < 3)) return nullptr;
+    return new Sim(nx, ny, nz, ywall ? 1 : 0);
+}
+void o3_destroy(void* h) { delete static_cast<Sim*>(h); }
+
+// Relaxation times from the transport coefficients (Sec. 3.1-3.2), rho0 = 1.
+int o3_set_params(void* h, double nu_s, double eta_p, double lam, double kappa, double Lambda_s,
+                  double Lambda_p, double Fx, double Fy, double Fz, int no_source) {
+    if (!(nu_s > 0) || !(kappa > 0) || !(lam > 0) || !(eta_p >= 0)) return -1;
+    Sim* s = static_cast<Sim*>(h);
+    s->p.tau_s1 = nu_s / CS2 + 0.5;
+    s->p.tau_s2 = Lambda_s / (s->p.tau_s1 - 0.5) + 0.5;
+    s->p.tau_p1 = kappa / CS2 + 0.5;
+    s->p.tau_p2 = Lambda_p / (s->p.tau_p1 - 0.5) + 0.5;
+    s->p.lam = lam;
+    s->p.eta_p = eta_p;
+    s->p.F[0] = Fx;
+    s->p.F[1] = Fy;
+    s->p.F[2] = Fz;
+    s->p.no_source = no_source;
+    return 0;
+}
+
+void o3_init(void* h, const double* rho, const double* ux, const double* uy, const double* uz,
+             const double* a0, const double* a1, const double* a2, const double* a3,
+             const double* a4, const double* a5) {
+    const double* u[3] = {ux, uy, uz};
+    const double* a[6] = {a0, a1, a2, a3, a4, a5};
+    static_cast<Sim*>(h)->init(rho, u, a);
+}
+
+void o3_step(void* h, long long n) {
+    Sim* s = static_cast<Sim*>(h);
+    for (long long k = 0; k < n; ++k) s->step_once();
+}
+
+// rho, u (with the half-force shift) and the six conformation components.
+void o3_read(void* h, double* rho, double* ux, double* uy, double* uz, double* a0, double* a1,
+             double* a2, double* a3, double* a4, double* a5) {
+    Sim* s = static_cast<Sim*>(h);
+    s->macros();
+    double* u[3] = {ux, uy, uz};
+    double* a[6] = {a0, a1, a2, a3, a4, a5};
+    for (size_t n = 0; n < s->N; ++n) {
+        rho[n] = s->rho[n];
+        for (int k = 0; k < 3; ++k) u[k][n] = s->u[k][n];
+        for (int k = 0; k < 6; ++k) a[k][n] = s->A[k][n];
+    }
+}
+
+// Lattice tables and the third-order combinations h_{c,+}, h_{c,-} at every velocity
+// (19 x 6).
+void o3_lattice(int* e, double* w, int* opp, double* h3) {
+    for (int i = 0; i < Q; ++i) {
+        for (int a = 0; a < 3; ++a) e[3 * i + a] = E[i][a];
+        w[i] = W[i];
+        opp[i] = OPP[i];
+        for (int c = 0; c < 3; ++c) {
+            h3[6 * i + 2 * c] = hc(i, c, +1);
+            h3[6 * i + 2 * c + 1] = hc(i, c, -1);
+        }
+    }
+}
+
+}  // extern "C"

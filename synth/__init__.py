@@ -8,6 +8,9 @@ implemented separately by the library and by the oracle.
 """
 from .workloads import (  # noqa: F401
     Problem,
+    Problem3D,
+    random3d,
+    channel3d,
     lattice_units,
     poiseuille,
     four_roll_mill,

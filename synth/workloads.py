@@ -352,3 +352,88 @@ def waves(kind, n=64, amp=1e-3, nu_s=0.1, kappa=0.1, lam=1e12, eta_p=0.0, U=0.0,
                    nu_s=nu_s, eta_p=eta_p, lam=lam, kappa=kappa, Lambda_s=Lambda_s,
                    Lambda_p=Lambda_p, init={k2: np.ascontiguousarray(v) for k2, v in init.items()},
                    precision="fp64", meta=dict(k=k))
+
+
+# ------------------------------------------------------------------------------------
+# Three-dimensional (D3Q19) problems
+# ------------------------------------------------------------------------------------
+@dataclass
+class Problem3D:
+    """One three-dimensional simulation: x and z periodic, y periodic or bounded by
+    half-way walls; uniform body force; fields indexed [z][y][x]."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    ymode: str  # 'periodic' | 'wall'
+    nu_s: float
+    eta_p: float
+    lam: float
+    kappa: float
+    Lambda_s: float = 0.25
+    Lambda_p: float = 1e-6
+    F: tuple = (0.0, 0.0, 0.0)
+    init: Optional[dict] = None  # rho, ux, uy, uz, axx, axy, axz, ayy, ayz, azz
+    steps: int = 0
+    precision: str = "fp32"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def init_arrays(self):
+        shape = (self.nz, self.ny, self.nx)
+        d = dict(self.init or {})
+        out = {}
+        for key, default in (("rho", 1.0), ("ux", 0.0), ("uy", 0.0), ("uz", 0.0),
+                             ("axx", 1.0), ("axy", 0.0), ("axz", 0.0), ("ayy", 1.0),
+                             ("ayz", 0.0), ("azz", 1.0)):
+            v = d.get(key, default)
+            out[key] = np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), shape))
+        return out
+
+    def with_(self, **kw) -> "Problem3D":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Problem3D(**d)
+
+
+def random3d(nx, ny, nz, seed, ymode="periodic", amp_u=0.02, amp_rho=0.01, amp_a=0.2,
+             nu_s=0.1, eta_p=0.07, lam=40.0, kappa=0.02, Lambda_s=0.25, Lambda_p=0.05,
+             F=(1e-5, -2e-5, 1.5e-5), precision="fp64") -> Problem3D:
+    """Seeded random state: density, velocity and a symmetric positive-definite
+    conformation (A = R diag(l) R^T with a random rotation R and eigenvalues l drawn near
+    1) node by node from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    rho = 1.0 + amp_rho * rng.uniform(-1, 1, shape)
+    u = [amp_u * rng.uniform(-1, 1, shape) for _ in range(3)]
+    lam_e = 1.0 + amp_a * rng.uniform(-1, 1, shape + (3,))
+    M = rng.normal(size=shape + (3, 3))
+    Qm, _ = np.linalg.qr(M)
+    A = np.einsum("...ij,...j,...kj->...ik", Qm, lam_e, Qm)
+    init = dict(rho=rho, ux=u[0], uy=u[1], uz=u[2], axx=A[..., 0, 0], axy=A[..., 0, 1],
+                axz=A[..., 0, 2], ayy=A[..., 1, 1], ayz=A[..., 1, 2], azz=A[..., 2, 2])
+    init = {k: np.ascontiguousarray(v) for k, v in init.items()}
+    return Problem3D(name=f"random3d_{nx}x{ny}x{nz}_s{seed}", nx=nx, ny=ny, nz=nz, ymode=ymode,
+                     nu_s=nu_s, eta_p=eta_p, lam=lam, kappa=kappa, Lambda_s=Lambda_s,
+                     Lambda_p=Lambda_p, F=tuple(F), init=init, precision=precision)
+
+
+def channel3d(nx=4, ny=32, nz=4, Re=1.0, Wi=1.0, beta=0.5, Ma=0.1, Sc=1e6, Lambda_s=0.25,
+              Lambda_p=1e-6, axis="x", steps=10000, precision="fp64") -> Problem3D:
+    """Force-driven plane Poiseuille flow between half-way walls normal to y (the
+    channel of Sec. 4.2 with a third, periodic direction), driven along x or z:
+    H = L_c = ny, F = 8 (nu_s + nu_p) U_c / L_c^2, start from rest with A = I."""
+    Lc = float(ny)
+    p = lattice_units(Re, Wi, beta, Sc, Ma, Lc)
+    Fm = 8.0 * p["nu0"] * p["Uc"] / (Lc * Lc)
+    F = (Fm, 0.0, 0.0) if axis == "x" else (0.0, 0.0, Fm)
+    return Problem3D(name=f"channel3d_{nx}x{ny}x{nz}_{axis}_Wi{Wi:g}", nx=nx, ny=ny, nz=nz,
+                     ymode="wall", nu_s=p["nu_s"], eta_p=p["eta_p"], lam=p["lam"],
+                     kappa=p["kappa"], Lambda_s=Lambda_s, Lambda_p=Lambda_p, F=F, steps=steps,
+                     precision=precision,
+                     meta=dict(Re=Re, Wi=Wi, beta=beta, Sc=Sc, Ma=Ma, Uc=p["Uc"], Lc=Lc, H=Lc,
+                               Tc=Lc / p["Uc"]))

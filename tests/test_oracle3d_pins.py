@@ -1,0 +1,147 @@
+"""Pins of the three-dimensional (D3Q19) oracle (test infrastructure) against facts that
+do not come from the oracle itself: lattice quadrature identities, the moments its
+equilibria must carry, the closed-form steady channel of Sec. 4.2 driven along x and
+along z, the viscous decay of a shear wave along z, exact conservation and the rest
+state.  Readings of the three-dimensional extension: A32 in the design notes."""
+import numpy as np
+import pytest
+
+import synth
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def o3():
+    import oracle
+
+    oracle.build(force=False)
+    oracle.set_threads(min(8, oracle.max_threads()))
+    return oracle
+
+
+def test_d3q19_quadrature_and_third_order_basis(o3):
+    """Weights, isotropy to fourth order, opposites; the six third-order combinations
+    H_aab -+ H_bcc are orthogonal to each other and to orders 0-2 on the lattice, with
+    norms 2 c_s^6 and 6 c_s^6 (the continuous norm would be 4 c_s^6 for both)."""
+    e, w, opp, h3 = o3.lattice3d()
+    assert abs(w.sum() - 1) < 1e-15
+    assert sorted(np.round(w * 36).astype(int).tolist()) == [1] * 12 + [2] * 6 + [12]
+    d = np.eye(3)
+    m2 = np.einsum("i,ia,ib->ab", w, e, e)
+    assert np.allclose(m2, CS2 * d, atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    iso = CS2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                      + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(m4, iso, atol=1e-15)
+    assert np.array_equal(e[opp], -e)
+    # third-order combinations: explicit formula from the Hermite polynomials
+    def H3(a, b, c):
+        return (e[:, a] * e[:, b] * e[:, c]
+                - CS2 * (e[:, a] * d[b, c] + e[:, b] * d[a, c] + e[:, c] * d[a, b]))
+    X, Y, Z = 0, 1, 2
+    ref = np.stack([H3(X, X, Y) + H3(Y, Z, Z), H3(X, X, Y) - H3(Y, Z, Z),
+                    H3(Z, Z, X) + H3(X, Y, Y), H3(Z, Z, X) - H3(X, Y, Y),
+                    H3(Y, Y, Z) + H3(Z, X, X), H3(Y, Y, Z) - H3(Z, X, X)], axis=1)
+    assert np.allclose(h3, ref, atol=1e-15)
+    G = np.einsum("i,ip,iq->pq", w, h3, h3)
+    assert np.allclose(G, np.diag([2, 6, 2, 6, 2, 6]) * CS2 ** 3, atol=1e-15)
+    low = np.column_stack([np.ones(19), e, np.einsum("ia,ib->iab", e, e).reshape(19, 9)])
+    assert np.abs(np.einsum("i,ip,iq->pq", w, h3, low)).max() < 1e-15
+
+
+def _channel(o3, ny, axis):
+    pr = synth.channel3d(ny=ny, axis=axis, Ma=0.1)
+    o = o3.OracleSim3D(pr)
+    o.step(int(round(30 * pr.meta["Tc"])))
+    return pr, o.read()
+
+
+def _gre(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+def test_channel_closed_form_along_x_and_z(o3):
+    """Force-driven Oldroyd-B channel between half-way walls normal to y (Wi = 1,
+    beta = 0.5, Sc = 1e6; 30 T_c): the closed form u = 4 U y (H - y) / H^2,
+    A_xy = lambda u', A_xx = 1 + 2 (lambda u')^2, every other component at rest, at
+    second order in H for u; the same channel driven along z is the same solution with
+    x and z exchanged, to round-off."""
+    err = {}
+    for ny in (16, 32):
+        res = {}
+        for axis in ("x", "z"):
+            pr, r = _channel(o3, ny, axis)
+            res[axis] = r
+        rx, rz = res["x"], res["z"]
+        for a, b in (("ux", "uz"), ("uz", "ux"), ("uy", "uy"), ("axy", "ayz"), ("axx", "azz"),
+                     ("azz", "axx"), ("axz", "axz"), ("ayy", "ayy"), ("rho", "rho")):
+            assert np.abs(rx[a] - rz[b]).max() < 1e-11, (a, b)
+        y = np.arange(ny) + 0.5
+        lam, Uc = pr.lam, pr.meta["Uc"]
+        ex_u = 4 * Uc * y * (ny - y) / ny ** 2
+        du = 4 * Uc * (ny - 2 * y) / ny ** 2
+        err[ny] = (_gre(rx["ux"][0, :, 0], ex_u), _gre(rx["axy"][0, :, 0], lam * du),
+                   _gre(rx["axx"][0, :, 0] - 1, 2 * (lam * du) ** 2))
+        # x-invariant, z-invariant, no transverse flow, the untouched components at rest
+        assert np.ptp(rx["ux"], axis=(0, 2)).max() < 1e-12
+        assert np.abs(rx["uy"]).max() < 1e-12 and np.abs(rx["uz"]).max() < 1e-12
+        for c, one in (("axz", 0.0), ("ayz", 0.0), ("azz", 1.0)):
+            assert np.abs(rx[c] - one).max() < 1e-11, c
+    assert err[32][0] < 1e-3 and err[16][0] / err[32][0] > 3.5, err
+    assert err[32][1] < 6e-3 and err[32][2] < 1.5e-2, err
+    assert all(a / b > 2.3 for a, b in zip(err[16], err[32])), err
+
+
+def _wave(o3, eta, N=32, nu=0.05, lam=1.0, U=1e-4, steps=400):
+    pr = synth.Problem3D(name="wave_z", nx=4, ny=4, nz=N, ymode="periodic", nu_s=nu,
+                         eta_p=eta, lam=lam, kappa=0.05, Lambda_s=0.25, Lambda_p=0.25)
+    z = np.indices((N, 4, 4))[0].astype(float)
+    k = 2 * np.pi / N
+    s = np.sin(k * z)
+    pr.init = {"ux": U * s}
+    o = o3.OracleSim3D(pr)
+    amp = []
+    for _ in range(2):
+        o.step(steps)
+        amp.append((o.read()["ux"] * s).sum() / (s * s).sum())
+    return np.log(amp[0] / amp[1]) / steps / k ** 2
+
+
+def test_shear_wave_along_z_decays_viscously(o3):
+    """u_x = U sin(k z) decays at nu k^2: with the solvent alone nu = nu_s (0.3 % at
+    N = 32), and with a polymer that relaxes fast against the decay (lambda = 1 step,
+    decay time 260 steps) at nu_s + eta_p (0.7 %): the z components of the velocity
+    gradient, the source and the polymer stress all take part."""
+    nu0 = _wave(o3, 0.0)
+    assert abs(nu0 / 0.05 - 1) < 5e-3, nu0
+    nu1 = _wave(o3, 0.05)
+    assert abs(nu1 / 0.10 - 1) < 1.5e-2, nu1
+
+
+@pytest.mark.parametrize("ymode", ["periodic", "wall"])
+def test_mass_and_conformation_budget_exact(o3, ymode):
+    """Total mass exact (periodic streaming, half-way walls); with the constitutive source
+    off every conformation component's total is exact too (CNEBB at the walls, Sec. 3.3)."""
+    pr = synth.random3d(10, 8, 6, seed=4, ymode=ymode)
+    o = o3.OracleSim3D(pr, no_source=True)
+    r0 = o.read()
+    o.step(30)
+    r1 = o.read()
+    assert abs(r1["rho"].sum() / r0["rho"].sum() - 1) < 1e-13
+    for c in ("axx", "axy", "axz", "ayy", "ayz", "azz"):
+        assert abs(r1[c].sum() - r0[c].sum()) < 1e-12 * np.abs(r0[c]).sum(), c
+
+
+def test_rest_state_is_exact(o3):
+    """rho = 1, u = 0, A = I, no force: every step leaves it unchanged (walls included)."""
+    pr = synth.Problem3D(name="rest", nx=6, ny=7, nz=5, ymode="wall", nu_s=0.1, eta_p=0.1,
+                         lam=50.0, kappa=1e-3)
+    o = o3.OracleSim3D(pr)
+    o.step(40)
+    r = o.read()
+    assert np.abs(r["rho"] - 1).max() < 1e-14
+    for c in ("ux", "uy", "uz", "axy", "axz", "ayz"):
+        assert np.abs(r[c]).max() < 1e-14, c
+    for c in ("axx", "ayy", "azz"):
+        assert np.abs(r[c] - 1).max() < 1e-14, c
