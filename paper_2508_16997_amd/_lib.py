@@ -40,6 +40,11 @@ EXPORTS = [
     "vlb_batch_destroy", "vlb_params_from_groups",
     "vlb_error_string", "vlb_last_error_detail",
 ]
+# Every symbol declared in include/vlb3d.h (the three-dimensional D3Q19 form).
+EXPORTS3 = [
+    "vlb3_create", "vlb3_workspace_bytes", "vlb3_bind", "vlb3_set_params",
+    "vlb3_init_equilibrium", "vlb3_step", "vlb3_read_fields", "vlb3_get_step", "vlb3_destroy",
+]
 
 
 class VlbGrid(C.Structure):
@@ -129,10 +134,22 @@ def load():
     lib.vlb_error_string.restype = C.c_char_p
     lib.vlb_last_error_detail.argtypes = []
     lib.vlb_last_error_detail.restype = C.c_char_p
-    for name in EXPORTS:
+    for name in EXPORTS + EXPORTS3:
         if name not in ("vlb_destroy", "vlb_batch_destroy", "vlb_error_string",
-                        "vlb_last_error_detail"):
+                        "vlb_last_error_detail", "vlb3_destroy"):
             getattr(lib, name).restype = I
+    D = C.c_double
+    PA = C.POINTER(C.c_void_p)
+    lib.vlb3_create.argtypes = [I, I, I, I, I, C.POINTER(P)]
+    lib.vlb3_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+    lib.vlb3_bind.argtypes = [P, P, C.c_size_t, P]
+    lib.vlb3_set_params.argtypes = [P, D, D, D, D, D, D, D, D, D, I]
+    lib.vlb3_init_equilibrium.argtypes = [P, PA]
+    lib.vlb3_step.argtypes = [P, C.c_int64]
+    lib.vlb3_read_fields.argtypes = [P, PA]
+    lib.vlb3_get_step.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.vlb3_destroy.argtypes = [P]
+    lib.vlb3_destroy.restype = None
     _lib = lib
     return lib
 

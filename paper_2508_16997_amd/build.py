@@ -14,7 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvlb.so")
-SOURCES = ["vlb_kernels.hip", "vlb_batch.hip", "vlb_fill.hip", "vlb_aux.hip", "vlb_adjoint.hip", "vlb_api.cpp"]
+SOURCES = ["vlb_kernels.hip", "vlb_batch.hip", "vlb_fill.hip", "vlb_aux.hip", "vlb_adjoint.hip",
+           "vlb3d.hip", "vlb_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VLB_OFFLOAD_ARCH", "gfx950")
@@ -37,6 +38,7 @@ PER_FILE = {
     "vlb_batch.hip": ["-ffp-contract=on", "-mllvm", "-disable-machine-licm"],
     "vlb_fill.hip": ["-ffp-contract=on"],
     "vlb_adjoint.hip": ["-ffp-contract=on"],
+    "vlb3d.hip": ["-ffp-contract=on", "-mllvm", "-pragma-unroll-threshold=1000000"],
     "vlb_aux.hip": ["-ffp-contract=on"],
 }
 

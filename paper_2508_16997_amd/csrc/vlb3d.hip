@@ -1,0 +1,678 @@
+// vlb3d.hip -- the coupled step in three dimensions (D3Q19) for gfx950, and its C ABI
+// (include/vlb3d.h).
+//
+// State: two population buffers of 133 planes (7 lattices x 19 directions; plane
+// (L * 19 + i), node (z * ny + y) * nx + x), storing deviations from the rest state
+// (f_i - w_i, g_i - w_i phi0 with phi0 = 1 for A_xx, A_yy, A_zz and 0 otherwise); history
+// of S (6 planes) and u (3 planes); rho and u at time n (4 planes) for the neighbours'
+// differences.  Per step two launches:
+//   k3_macro  rho and u of every node from its pulled populations (mac planes)
+//   k3_step   per node: pulls, conformation, velocity gradient from the mac planes of
+//             the six axis neighbours, constitutive source, the hydrodynamic collision
+//             (stored at once), then lattice by lattice the conformation pulls, CNEBB at
+//             wall-adjacent nodes and the collision (stored at once); history in place.
+// Pull streaming: node x takes direction i from x - e_i (periodic wrap in x and z, and in
+// y unless walls); a source beyond a wall gives the node's own post-collision value of
+// the opposite direction (half-way bounce-back for f, the CNEBB input for g).
+// One node per lane, 64 x 4 lanes per block in x and y, one z slice per block row.
+// All arithmetic in double.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "vlb3d.h"
+#include "vlb_internal.h"
+
+namespace vlb3 {
+namespace {
+
+using T = double;
+constexpr int Q = 19;
+constexpr int NLAT = 7;  // hydrodynamic + six conformation lattices
+constexpr int TX = 64, TY = 4;
+constexpr T CS2 = 1.0 / 3.0;
+
+// D3Q19 velocities: rest; +-x, +-y, +-z; the twelve face diagonals in opposite pairs.
+__host__ __device__ constexpr int ec(int i, int a) {
+    return a == 0 ? ((i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+                     : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0)
+         : a == 1 ? ((i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+                     : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0)
+                  : ((i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+                     : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr T w3(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// conformation components: (a, b) of component k, rest value phi0
+__host__ __device__ constexpr int ka(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
+__host__ __device__ constexpr int kb(int k) { return k == 0 ? 0 : (k == 1 || k == 3) ? 1 : 2; }
+__host__ __device__ constexpr T phi0(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
+
+// Third-order Hermite combinations on D3Q19: h_{c,s} = H_aab + s H_bcc for
+// (a, b, c) = (x, y, z), (z, x, y), (y, z, x), with H_abc = e_a e_b e_c - c_s^2 (e_a d_bc +
+// e_b d_ac + e_c d_ab); lattice norms 2 c_s^6 (s = +1) and 6 c_s^6 (s = -1).
+__host__ __device__ constexpr int hca(int c) { return c == 0 ? 0 : (c == 1 ? 2 : 1); }
+__host__ __device__ constexpr int hcb(int c) { return c == 0 ? 1 : (c == 1 ? 0 : 2); }
+__host__ __device__ constexpr int hcc(int c) { return c == 0 ? 2 : (c == 1 ? 1 : 0); }
+__host__ __device__ constexpr T h3aab(int i, int a, int b) {
+    // H_aab with a != b: e_a^2 e_b - c_s^2 e_b
+    return (T)(ec(i, a) * ec(i, a) * ec(i, b)) - CS2 * (T)ec(i, b);
+}
+__host__ __device__ constexpr T hcomb(int i, int c, int s) {
+    return h3aab(i, hca(c), hcb(c)) + (T)s * h3aab(i, hcc(c), hcb(c));
+}
+__host__ __device__ constexpr T hinvnorm(int s) { return s > 0 ? 13.5 : 4.5; }  // 1/(2 cs^6), 1/(6 cs^6)
+
+template <class S>
+struct Run3 {
+    int nx, ny, nz, ywall, first;
+    int N;
+    const S* src;
+    S* dst;
+    S* hist;  // 9 planes: S_xx, S_xy, S_xz, S_yy, S_yz, S_zz, u_x, u_y, u_z (previous step)
+    S* mac;   // 4 planes: rho, u_x, u_y, u_z at time n
+    T c1, c2, h1, inv_ts1;  // hydrodynamic: 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
+    T p1, p2, h2;           // conformation: 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)
+    T inv_lam, eta_over_lam, F[3];
+    int no_source;
+};
+
+template <class S>
+__device__ __forceinline__ T ldg(const S* p, long long i) { return (T)p[i]; }
+
+// Slot that node (x, y, z) pulls direction i from, or -1 beyond a wall.
+template <class S>
+__device__ __forceinline__ int src_slot(const Run3<S>& R, int x, int y, int z, int i) {
+    int xs = x - ec(i, 0), ys = y - ec(i, 1), zs = z - ec(i, 2);
+    xs = xs < 0 ? xs + R.nx : (xs >= R.nx ? xs - R.nx : xs);
+    zs = zs < 0 ? zs + R.nz : (zs >= R.nz ? zs - R.nz : zs);
+    if (ys < 0 || ys >= R.ny) {
+        if (R.ywall) return -1;
+        ys = ys < 0 ? ys + R.ny : ys - R.ny;
+    }
+    return (zs * R.ny + ys) * R.nx + xs;
+}
+
+// The nine (or, lattice by lattice, 19) populations node n receives; `own` on the first
+// step (the initial state sits at the node's own slot).
+template <class S>
+__device__ __forceinline__ S pull1(const Run3<S>& R, int L, int i, int n, int x, int y, int z) {
+    const long long N = R.N;
+    if (R.first) return R.src[(L * Q + i) * N + n];
+    const int s = src_slot(R, x, y, z, i);
+    return s >= 0 ? R.src[(L * Q + i) * N + s] : R.src[(L * Q + opp3(i)) * N + n];
+}
+
+template <class S>
+__device__ __forceinline__ void hydro_pull(const Run3<S>& R, int n, int x, int y, int z, S f[Q],
+                                           T& rho, T u[3]) {
+    T dr = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        f[i] = pull1(R, 0, i, n, x, y, z);
+        const T v = (T)f[i];
+        dr += v;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (ec(i, a) != 0) j[a] += ec(i, a) > 0 ? v : -v;
+    }
+    rho = 1.0 + dr;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * R.F[a]) / rho;
+}
+
+template <class S>
+__global__ __launch_bounds__(TX * TY) void k3_macro(Run3<S> R) {
+    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
+    if (x >= R.nx || y >= R.ny) return;
+    const int n = (z * R.ny + y) * R.nx + x;
+    S f[Q];
+    T rho, u[3];
+    hydro_pull(R, n, x, y, z, f, rho, u);
+    R.mac[n] = (S)rho;
+    R.mac[(long long)R.N + n] = (S)u[0];
+    R.mac[2LL * R.N + n] = (S)u[1];
+    R.mac[3LL * R.N + n] = (S)u[2];
+}
+
+// Derivative along one axis: central difference, or next to a flat half-way wall the
+// quadratic through the no-slip value half a spacing away.
+__device__ __forceinline__ T fd(bool lo_wall, T vlo, T v0, bool hi_wall, T vhi) {
+    if (!lo_wall && !hi_wall) return 0.5 * (vhi - vlo);
+    if (lo_wall && !hi_wall) return (1.0 / 3.0) * vhi + v0;
+    if (!lo_wall) return -((1.0 / 3.0) * vlo + v0);
+    return 0.0;
+}
+
+// One conformation lattice K: pulls, CNEBB at a wall-adjacent node, collision, store.
+template <int k, class S>
+__device__ __forceinline__ void conf_lattice(const Run3<S>& R, int n, int x, int y, int z,
+                                             const T u[3], const T up[3], T rho, T uu, T dp,
+                                             T Sk, T Spk, bool wall_lo, bool wall_hi) {
+    const long long N = R.N;
+    T gv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gv[i] = (T)pull1(R, 1 + k, i, n, x, y, z);
+    const T phi = phi0(k) + dp;
+    if (wall_lo || wall_hi) {
+        // unknown: the directions arriving from beyond the wall; equilibrium deviation
+        // at (phi_b, u_b) plus the non-equilibrium part of the known opposite (at a flat
+        // wall the opposite of an unknown is always known, so the update is in place);
+        // g_0 the remainder of phi_b
+        T rest = dp;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const bool unk = wall_lo ? ec(i, 1) > 0 : ec(i, 1) < 0;
+            if (unk) {
+                const int o = opp3(i);
+                const T eui = ec(i, 0) * u[0] + ec(i, 1) * u[1] + ec(i, 2) * u[2];
+                const T eqi = w3(i) * (dp + phi * (3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
+                const T eqo = w3(o) * (dp + phi * (-3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
+                gv[i] = eqi + gv[o] - eqo;
+            }
+        }
+#pragma unroll
+        for (int i = 1; i < Q; ++i) rest -= gv[i];
+        gv[0] = rest;
+    }
+    T J[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T v = gv[i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (ec(i, a) != 0) J[a] += ec(i, a) > 0 ? v : -v;
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            if (ec(i, ka(m)) * ec(i, kb(m)) != 0) P[m] += (ec(i, ka(m)) * ec(i, kb(m)) > 0) ? v : -v;
+    }
+    // B1 = J - phi u; B2 = P - c_s^2 d (phi - phi0) - phi u u (deviations carry phi0)
+    T B1[3], B2[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) B1[a] = J[a] - phi * u[a];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int a = ka(m), b = kb(m);
+        B2[m] = P[m] - (a == b ? CS2 * dp : 0.0) - phi * u[a] * u[b];
+    }
+    const T trB2 = B2[0] + B2[3] + B2[5];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T e0 = ec(i, 0), e1 = ec(i, 1), e2 = ec(i, 2);
+        const T eu = e0 * u[0] + e1 * u[1] + e2 * u[2];
+        const T eup = e0 * up[0] + e1 * up[1] + e2 * up[2];
+        const T eF = e0 * R.F[0] + e1 * R.F[1] + e2 * R.F[2];
+        const T eB2e = e0 * e0 * B2[0] + e1 * e1 * B2[3] + e2 * e2 * B2[5] +
+                       2.0 * (e0 * e1 * B2[1] + e0 * e2 * B2[2] + e1 * e2 * B2[4]);
+        const T eq = dp + phi * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu));
+        const T r1 = 3.0 * (e0 * B1[0] + e1 * B1[1] + e2 * B1[2]);
+        const T r2 = 4.5 * (eB2e - CS2 * trB2);
+        const T Gt = R.h2 * 3.0 * eF * phi / rho;
+        const T Fn = Sk * (1.0 + R.h2 * 3.0 * eu);
+        const T Fp = Spk * (1.0 + R.h2 * 3.0 * eup);
+        R.dst[((long long)(1 + k) * Q + i) * N + n] =
+            (S)(w3(i) * (eq + R.p1 * r1 + R.p2 * r2 + Gt + Fn + 0.5 * (Fn - Fp)));
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
+    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
+    if (x >= R.nx || y >= R.ny) return;
+    const long long N = R.N;
+    const int n = (z * R.ny + y) * R.nx + x;
+
+    // ---- hydrodynamic pulls, rho, u ----
+    S f[Q];
+    T rho, u[3];
+    hydro_pull(R, n, x, y, z, f, rho, u);
+
+    // ---- conformation (zeroth moments of the pulled populations; CNEBB keeps them) ----
+    T dphi[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        T s = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += (T)pull1(R, 1 + k, i, n, x, y, z);
+        dphi[k] = s;
+    }
+
+    // ---- velocity gradient L[g][b] = d_g u_b and D_a = d_a(rho u_a^3) at time n ----
+    T L[3][3], D[3];
+    {
+        const int xl = x == 0 ? R.nx - 1 : x - 1, xh = x == R.nx - 1 ? 0 : x + 1;
+        const int zl = z == 0 ? R.nz - 1 : z - 1, zh = z == R.nz - 1 ? 0 : z + 1;
+        const bool wl = R.ywall && y == 0, wh = R.ywall && y == R.ny - 1;
+        const int yl = y == 0 ? R.ny - 1 : y - 1, yh = y == R.ny - 1 ? 0 : y + 1;
+        const int nb[3][2] = {{(z * R.ny + y) * R.nx + xl, (z * R.ny + y) * R.nx + xh},
+                              {(z * R.ny + yl) * R.nx + x, (z * R.ny + yh) * R.nx + x},
+                              {(zl * R.ny + y) * R.nx + x, (zh * R.ny + y) * R.nx + x}};
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const bool lw = g == 1 && wl, hw = g == 1 && wh;
+            T rl = 0.0, rh = 0.0, vl[3] = {0.0, 0.0, 0.0}, vh[3] = {0.0, 0.0, 0.0};
+            if (!lw) {
+                rl = ldg(R.mac, nb[g][0]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) vl[b] = ldg(R.mac, (1 + b) * N + nb[g][0]);
+            }
+            if (!hw) {
+                rh = ldg(R.mac, nb[g][1]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) vh[b] = ldg(R.mac, (1 + b) * N + nb[g][1]);
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b) L[g][b] = fd(lw, vl[b], u[b], hw, vh[b]);
+            D[g] = fd(lw, rl * vl[g] * vl[g] * vl[g], rho * u[g] * u[g] * u[g], hw,
+                      rh * vh[g] * vh[g] * vh[g]);
+        }
+    }
+
+    // ---- constitutive source (Oldroyd-B) and polymer stress ----
+    T Sc[6], tau[6];
+    {
+        T A[3][3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            A[ka(k)][kb(k)] = phi0(k) + dphi[k];
+            A[kb(k)][ka(k)] = phi0(k) + dphi[k];
+        }
+        const T trL = L[0][0] + L[1][1] + L[2][2];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int a = ka(k), b = kb(k);
+            T s = -R.inv_lam * (A[a][b] - (a == b ? 1.0 : 0.0));
+#pragma unroll
+            for (int g = 0; g < 3; ++g) s += A[a][g] * L[g][b] + A[g][b] * L[g][a];
+            s += A[a][b] * trL;
+            Sc[k] = R.no_source ? 0.0 : s;
+            tau[k] = R.eta_over_lam * dphi[k];
+        }
+    }
+    // history: S and u of the previous step (the first step takes this step's)
+    T Sp[6], up[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Sp[k] = R.first ? Sc[k] : ldg(R.hist, k * N + n);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) up[a] = R.first ? u[a] : ldg(R.hist, (6 + a) * N + n);
+
+    // ---- hydrodynamic collision (moment form) ----
+    {
+        // second moments and third-order combinations of the pulled deviations
+        T P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Qm[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const T v = (T)f[i];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (ec(i, ka(k)) * ec(i, kb(k)) != 0) P[k] += (ec(i, ka(k)) * ec(i, kb(k)) > 0) ? v : -v;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Qm[c][0] += hcomb(i, c, -1) * v;
+                Qm[c][1] += hcomb(i, c, +1) * v;
+            }
+        }
+        // off-equilibrium moments: A1 = -F/2 (literal), A2 = Pi - c_s^2 d (rho - 1) - rho u u
+        // (deviations carry the rest part), A3 along h_{c,s}: moment - rho (u_a^2 u_b +- u_b u_c^2)
+        const T dr = rho - 1.0;
+        T A2[6], A3[3][2], uc[3][2];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int a = ka(k), b = kb(k);
+            A2[k] = P[k] - (a == b ? CS2 * dr : 0.0) - rho * u[a] * u[b];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int a = hca(c), b = hcb(c), d = hcc(c);
+            const T t1 = u[a] * u[a] * u[b], t2 = u[b] * u[d] * u[d];
+            uc[c][0] = t1 - t2;
+            uc[c][1] = t1 + t2;
+            A3[c][0] = Qm[c][0] - rho * uc[c][0];
+            A3[c][1] = Qm[c][1] - rho * uc[c][1];
+        }
+        const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const T trA2 = A2[0] + A2[3] + A2[5], trt = tau[0] + tau[3] + tau[5];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const T e0 = ec(i, 0), e1 = ec(i, 1), e2 = ec(i, 2);
+            const T eu = e0 * u[0] + e1 * u[1] + e2 * u[2];
+            T third = 0.0, third_neq = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                third += hinvnorm(-1) * hcomb(i, c, -1) * uc[c][0] + hinvnorm(1) * hcomb(i, c, 1) * uc[c][1];
+                third_neq += hinvnorm(-1) * hcomb(i, c, -1) * A3[c][0] + hinvnorm(1) * hcomb(i, c, 1) * A3[c][1];
+            }
+            const T eA2e = e0 * e0 * A2[0] + e1 * e1 * A2[3] + e2 * e2 * A2[5] +
+                           2.0 * (e0 * e1 * A2[1] + e0 * e2 * A2[2] + e1 * e2 * A2[4]);
+            const T ete = e0 * e0 * tau[0] + e1 * e1 * tau[3] + e2 * e2 * tau[5] +
+                          2.0 * (e0 * e1 * tau[1] + e0 * e2 * tau[2] + e1 * e2 * tau[4]);
+            const T eq = dr + rho * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu) + third);
+            const T neq1 = 3.0 * (-0.5) * (e0 * R.F[0] + e1 * R.F[1] + e2 * R.F[2]) +
+                           4.5 * (eA2e - CS2 * trA2);
+            const T Gi = -R.h1 * 4.5 * ((e0 * e0 - CS2) * D[0] + (e1 * e1 - CS2) * D[1] + (e2 * e2 - CS2) * D[2]);
+            const T Ti = -4.5 * R.inv_ts1 * (ete - CS2 * trt);
+            const T Fi = R.h1 * 3.0 * (e0 * R.F[0] + e1 * R.F[1] + e2 * R.F[2]);
+            R.dst[(long long)i * N + n] = (S)(w3(i) * (eq + R.c1 * neq1 + R.c2 * third_neq + Gi + Ti + Fi));
+        }
+    }
+
+    // ---- conformation lattices: pulls, CNEBB at wall-adjacent nodes, collision ----
+    const bool wall_lo = R.ywall && y == 0 && !R.first, wall_hi = R.ywall && y == R.ny - 1 && !R.first;
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    conf_lattice<0>(R, n, x, y, z, u, up, rho, uu, dphi[0], Sc[0], Sp[0], wall_lo, wall_hi);
+    conf_lattice<1>(R, n, x, y, z, u, up, rho, uu, dphi[1], Sc[1], Sp[1], wall_lo, wall_hi);
+    conf_lattice<2>(R, n, x, y, z, u, up, rho, uu, dphi[2], Sc[2], Sp[2], wall_lo, wall_hi);
+    conf_lattice<3>(R, n, x, y, z, u, up, rho, uu, dphi[3], Sc[3], Sp[3], wall_lo, wall_hi);
+    conf_lattice<4>(R, n, x, y, z, u, up, rho, uu, dphi[4], Sc[4], Sp[4], wall_lo, wall_hi);
+    conf_lattice<5>(R, n, x, y, z, u, up, rho, uu, dphi[5], Sc[5], Sp[5], wall_lo, wall_hi);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) R.hist[k * N + n] = (S)Sc[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.hist[(6 + a) * N + n] = (S)u[a];
+}
+
+// Equilibrium state of the given fields at every node's own slot (read without a pull
+// by the first step); history cleared.
+template <class S>
+__global__ __launch_bounds__(TX * TY) void k3_init(Run3<S> R, S* pop, const S* const* fields) {
+    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
+    if (x >= R.nx || y >= R.ny) return;
+    const long long N = R.N;
+    const int n = (z * R.ny + y) * R.nx + x;
+    T v[10];
+    const T dflt[10] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 1.0};
+#pragma unroll
+    for (int c = 0; c < 10; ++c) v[c] = fields[c] ? (T)fields[c][n] : dflt[c];
+    const T rho = v[0], u[3] = {v[1], v[2], v[3]};
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    T uc[3][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = hca(c), b = hcb(c), d = hcc(c);
+        uc[c][0] = u[a] * u[a] * u[b] - u[b] * u[d] * u[d];
+        uc[c][1] = u[a] * u[a] * u[b] + u[b] * u[d] * u[d];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T eu = ec(i, 0) * u[0] + ec(i, 1) * u[1] + ec(i, 2) * u[2];
+        T third = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            third += hinvnorm(-1) * hcomb(i, c, -1) * uc[c][0] + hinvnorm(1) * hcomb(i, c, 1) * uc[c][1];
+        pop[(long long)i * N + n] = (S)(w3(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu) + third)));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const T phi = v[4 + k];
+            pop[((long long)(1 + k) * Q + i) * N + n] =
+                (S)(w3(i) * ((phi - phi0(k)) + phi * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu))));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) R.hist[c * N + n] = (S)0.0;
+}
+
+// rho, u (half-force shift) and A of the current state.
+template <class S>
+__global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
+    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
+    if (x >= R.nx || y >= R.ny) return;
+    const int n = (z * R.ny + y) * R.nx + x;
+    S f[Q];
+    T rho, u[3];
+    hydro_pull(R, n, x, y, z, f, rho, u);
+    T v[10] = {rho, u[0], u[1], u[2]};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        T s = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += (T)pull1(R, 1 + k, i, n, x, y, z);
+        v[4 + k] = phi0(k) + s;
+    }
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        if (out[c]) out[c][n] = (S)v[c];
+}
+
+}  // namespace
+}  // namespace vlb3
+
+// ---------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------
+struct vlb3_sim {
+    int nx, ny, nz, prec, ywall;
+    size_t esz;
+    long long N;
+    bool bound = false, params_set = false, inited = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    size_t off_pop[2] = {0, 0}, off_hist = 0, off_mac = 0, off_ptrs = 0, total = 0;
+    int parity = 0, first = 1;
+    int64_t step = 0;
+    double nu_s = 0, eta_p = 0, lam = 1, kappa = 0, Ls = 0.25, Lp = 1e-6, F[3] = {0, 0, 0};
+    int flags = 0;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void layout(vlb3_sim* s) {
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t r = o; o = align256(o + b); return r; };
+    const size_t plane = (size_t)s->N * s->esz;
+    s->off_pop[0] = take(vlb3::NLAT * vlb3::Q * plane);
+    s->off_pop[1] = take(vlb3::NLAT * vlb3::Q * plane);
+    s->off_hist = take(9 * plane);
+    s->off_mac = take(4 * plane);
+    s->off_ptrs = take(10 * sizeof(void*));
+    s->total = o;
+}
+
+template <class S>
+vlb3::Run3<S> make_run(const vlb3_sim* s) {
+    vlb3::Run3<S> r{};
+    r.nx = s->nx;
+    r.ny = s->ny;
+    r.nz = s->nz;
+    r.ywall = s->ywall;
+    r.first = s->first;
+    r.N = (int)s->N;
+    r.src = reinterpret_cast<const S*>(s->ws + s->off_pop[s->parity]);
+    r.dst = reinterpret_cast<S*>(s->ws + s->off_pop[s->parity ^ 1]);
+    r.hist = reinterpret_cast<S*>(s->ws + s->off_hist);
+    r.mac = reinterpret_cast<S*>(s->ws + s->off_mac);
+    // relaxation times from the transport coefficients (Sec. 3.1-3.2), c_s^2 = 1/3
+    const double ts1 = 3.0 * s->nu_s + 0.5, ts2 = s->Ls / (3.0 * s->nu_s) + 0.5;
+    const double tp1 = 3.0 * s->kappa + 0.5, tp2 = s->Lp / (3.0 * s->kappa) + 0.5;
+    r.c1 = 1.0 - 1.0 / ts1;
+    r.c2 = 1.0 - 1.0 / ts2;
+    r.h1 = 1.0 - 1.0 / (2.0 * ts1);
+    r.inv_ts1 = 1.0 / ts1;
+    r.p1 = 1.0 - 1.0 / tp1;
+    r.p2 = 1.0 - 1.0 / tp2;
+    r.h2 = 1.0 - 1.0 / (2.0 * tp1);
+    r.inv_lam = 1.0 / s->lam;
+    r.eta_over_lam = s->eta_p / s->lam;
+    for (int a = 0; a < 3; ++a) r.F[a] = s->F[a];
+    r.no_source = (s->flags & VLB_FLAG_NO_SOURCE) ? 1 : 0;
+    return r;
+}
+
+dim3 grid_of(const vlb3_sim* s) {
+    return dim3((unsigned)((s->nx + vlb3::TX - 1) / vlb3::TX),
+                (unsigned)((s->ny + vlb3::TY - 1) / vlb3::TY), (unsigned)s->nz);
+}
+
+int check_ready(const vlb3_sim* s) {
+    if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "null simulation");
+    if (!s->bound) return vlb::report_error(VLB_E_STATE, "workspace not bound (vlb3_bind)");
+    if (!s->params_set) return vlb::report_error(VLB_E_STATE, "parameters not set (vlb3_set_params)");
+    return VLB_OK;
+}
+
+#define VLB3_HIP(expr)                                                                           \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return vlb::report_error(VLB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class S>
+int do_steps(vlb3_sim* s, int64_t n) {
+    const dim3 blk(vlb3::TX, vlb3::TY), grd = grid_of(s);
+    for (int64_t k = 0; k < n; ++k) {
+        const vlb3::Run3<S> r = make_run<S>(s);
+        hipLaunchKernelGGL((vlb3::k3_macro<S>), grd, blk, 0, s->stream, r);
+        hipLaunchKernelGGL((vlb3::k3_step<S>), grd, blk, 0, s->stream, r);
+        VLB3_HIP(hipGetLastError());
+        s->parity ^= 1;
+        s->first = 0;
+        ++s->step;
+    }
+    return VLB_OK;
+}
+
+template <class S>
+int do_init(vlb3_sim* s, const void* const fields[10]) {
+    void* host_ptrs[10];
+    for (int c = 0; c < 10; ++c) host_ptrs[c] = const_cast<void*>(fields ? fields[c] : nullptr);
+    void** dev_ptrs = reinterpret_cast<void**>(s->ws + s->off_ptrs);
+    VLB3_HIP(hipMemcpyAsync(dev_ptrs, host_ptrs, sizeof(host_ptrs), hipMemcpyHostToDevice, s->stream));
+    s->parity = 0;
+    s->first = 1;
+    s->step = 0;
+    const vlb3::Run3<S> r = make_run<S>(s);
+    hipLaunchKernelGGL((vlb3::k3_init<S>), grid_of(s), dim3(vlb3::TX, vlb3::TY), 0, s->stream, r,
+                       reinterpret_cast<S*>(s->ws + s->off_pop[0]),
+                       reinterpret_cast<const S* const*>(dev_ptrs));
+    VLB3_HIP(hipGetLastError());
+    // the pointer table is read by the kernel: keep the host copy alive until it ran
+    VLB3_HIP(hipStreamSynchronize(s->stream));
+    s->inited = true;
+    return VLB_OK;
+}
+
+template <class S>
+int do_read(vlb3_sim* s, void* const out[10]) {
+    void* host_ptrs[10];
+    for (int c = 0; c < 10; ++c) host_ptrs[c] = out ? out[c] : nullptr;
+    void** dev_ptrs = reinterpret_cast<void**>(s->ws + s->off_ptrs);
+    VLB3_HIP(hipMemcpyAsync(dev_ptrs, host_ptrs, sizeof(host_ptrs), hipMemcpyHostToDevice, s->stream));
+    const vlb3::Run3<S> r = make_run<S>(s);
+    hipLaunchKernelGGL((vlb3::k3_read<S>), grid_of(s), dim3(vlb3::TX, vlb3::TY), 0, s->stream, r,
+                       reinterpret_cast<S* const*>(dev_ptrs));
+    VLB3_HIP(hipGetLastError());
+    VLB3_HIP(hipStreamSynchronize(s->stream));
+    return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out) {
+    if (!out) return vlb::report_error(VLB_E_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return vlb::report_error(VLB_E_INVALID_ARG, "grid sizes must be >= 1");
+    if (prec != VLB_FP32 && prec != VLB_FP64) return vlb::report_error(VLB_E_INVALID_ARG, "unknown precision");
+    if (ymode != VLB_PERIODIC && ymode != VLB_WALL)
+        return vlb::report_error(VLB_E_INVALID_ARG, "ymode must be VLB_PERIODIC or VLB_WALL");
+    if (ymode == VLB_WALL && ny < 3) return vlb::report_error(VLB_E_INVALID_ARG, "walls need ny >= 3");
+    if (nz > 65535 || (ny + vlb3::TY - 1) / vlb3::TY > 65535)
+        return vlb::report_error(VLB_E_INVALID_ARG, "nz and ny / 4 must stay within the launch grid (65535)");
+    const long long N = (long long)nx * ny * nz;
+    if (N >= (1LL << 31) / (vlb3::NLAT * vlb3::Q))
+        return vlb::report_error(VLB_E_INVALID_ARG, "grid too large for 32-bit plane offsets");
+    vlb3_sim* s = new (std::nothrow) vlb3_sim();
+    if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "out of host memory");
+    s->nx = nx;
+    s->ny = ny;
+    s->nz = nz;
+    s->prec = prec;
+    s->ywall = ymode == VLB_WALL ? 1 : 0;
+    s->esz = prec == VLB_FP32 ? 4 : 8;
+    s->N = N;
+    layout(s);
+    *out = s;
+    return VLB_OK;
+}
+
+int vlb3_workspace_bytes(const vlb3_sim* s, size_t* bytes) {
+    if (!s || !bytes) return vlb::report_error(VLB_E_INVALID_ARG, "null argument");
+    *bytes = s->total;
+    return VLB_OK;
+}
+
+int vlb3_bind(vlb3_sim* s, void* ws, size_t bytes, void* stream) {
+    if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "null simulation");
+    if (!ws || ((uintptr_t)ws & 255u) || bytes < s->total)
+        return vlb::report_error(VLB_E_WORKSPACE, "workspace missing, misaligned or smaller than " +
+                                                      std::to_string(s->total) + " bytes");
+    s->ws = static_cast<char*>(ws);
+    s->ws_bytes = bytes;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->bound = true;
+    s->inited = false;
+    return VLB_OK;
+}
+
+int vlb3_set_params(vlb3_sim* s, double nu_s, double eta_p, double lambda, double kappa,
+                    double Lambda_s, double Lambda_p, double Fx, double Fy, double Fz, int flags) {
+    if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "null simulation");
+    const double v[9] = {nu_s, eta_p, lambda, kappa, Lambda_s, Lambda_p, Fx, Fy, Fz};
+    for (double d : v)
+        if (!std::isfinite(d)) return vlb::report_error(VLB_E_INVALID_ARG, "non-finite parameter");
+    if (!(nu_s > 0) || !(kappa > 0) || !(lambda > 0) || !(eta_p >= 0) || !(Lambda_s > 0) ||
+        !(Lambda_p > 0))
+        return vlb::report_error(VLB_E_INVALID_ARG,
+                                 "need nu_s, kappa, lambda, magic parameters > 0 and eta_p >= 0");
+    if (flags & ~VLB_FLAG_NO_SOURCE) return vlb::report_error(VLB_E_INVALID_ARG, "unknown flag");
+    s->nu_s = nu_s;
+    s->eta_p = eta_p;
+    s->lam = lambda;
+    s->kappa = kappa;
+    s->Ls = Lambda_s;
+    s->Lp = Lambda_p;
+    s->F[0] = Fx;
+    s->F[1] = Fy;
+    s->F[2] = Fz;
+    s->flags = flags;
+    s->params_set = true;
+    return VLB_OK;
+}
+
+int vlb3_init_equilibrium(vlb3_sim* s, const void* const fields[10]) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    return s->prec == VLB_FP32 ? do_init<float>(s, fields) : do_init<double>(s, fields);
+}
+
+int vlb3_step(vlb3_sim* s, int64_t n) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!s->inited) return vlb::report_error(VLB_E_STATE, "state not initialised (vlb3_init_equilibrium)");
+    if (n < 0) return vlb::report_error(VLB_E_INVALID_ARG, "nsteps must be >= 0");
+    return s->prec == VLB_FP32 ? do_steps<float>(s, n) : do_steps<double>(s, n);
+}
+
+int vlb3_read_fields(vlb3_sim* s, void* const out[10]) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!s->inited) return vlb::report_error(VLB_E_STATE, "state not initialised (vlb3_init_equilibrium)");
+    return s->prec == VLB_FP32 ? do_read<float>(s, out) : do_read<double>(s, out);
+}
+
+int vlb3_get_step(const vlb3_sim* s, int64_t* step) {
+    if (!s || !step) return vlb::report_error(VLB_E_INVALID_ARG, "null argument");
+    *step = s->step;
+    return VLB_OK;
+}
+
+void vlb3_destroy(vlb3_sim* s) { delete s; }
+
+}  // extern "C"

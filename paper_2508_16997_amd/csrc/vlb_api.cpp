@@ -62,6 +62,8 @@ using Run = vlb::RunDev<T>;
 
 }  // namespace
 
+int vlb::report_error(int code, const std::string& msg) { return fail(code, msg); }
+
 static_assert(vlb::MODEL_GIESEKUS == VLB_GIESEKUS && vlb::MODEL_LPTT == VLB_LPTT &&
                   vlb::MODEL_EPTT == VLB_EPTT && vlb::MODEL_FENE_P == VLB_FENE_P,
               "closure codes of the ABI and the kernels differ");

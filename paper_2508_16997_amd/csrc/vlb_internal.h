@@ -5,8 +5,13 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace vlb {
+
+// Record the thread-local error detail returned by vlb_last_error_detail; returns code.
+int report_error(int code, const std::string& msg);
+
 
 // XM_WET (y only): the first and last rows are wall nodes (wet-node walls).
 enum { XM_PERIODIC = 0, XM_WALL = 1, XM_OPEN = 2, XM_WET = 3 };

@@ -40,6 +40,39 @@ def test_library_exports_every_declared_symbol(vlb):
     assert sorted(vlb.EXPORTS) == declared
 
 
+def test_library_exports_every_3d_symbol(vlb):
+    """Every entry point of include/vlb3d.h (the D3Q19 form) is exported."""
+    from paper_2508_16997_amd import _lib
+
+    text = open(os.path.join(ROOT, "include", "vlb3d.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(vlb3_[a-z_]+)\s*\(", text)))
+    lib = vlb.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS3) == declared
+
+
+def test_3d_create_validates_without_a_gpu(vlb):
+    """Host-side checks of vlb3_create / vlb3_set_params (no device call)."""
+    import ctypes as C
+    from paper_2508_16997_amd import _lib
+
+    lib = vlb.load()
+    h = C.c_void_p()
+    assert lib.vlb3_create(0, 4, 4, _lib.VLB_FP32, _lib.VLB_PERIODIC, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(4, 2, 4, _lib.VLB_FP32, _lib.VLB_WALL, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(4, 4, 4, _lib.VLB_FP32, _lib.VLB_OPEN, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(8, 6, 5, _lib.VLB_FP64, _lib.VLB_WALL, C.byref(h)) == _lib.VLB_OK
+    v = C.c_size_t()
+    assert lib.vlb3_workspace_bytes(h, C.byref(v)) == _lib.VLB_OK
+    assert v.value >= (2 * 133 + 13) * 240 * 8
+    assert lib.vlb3_set_params(h, 0.1, 0.1, 10.0, 0.01, 0.25, 0.25, 0.0, 0.0, 0.0, 0) == _lib.VLB_OK
+    assert lib.vlb3_set_params(h, -0.1, 0.1, 10.0, 0.01, 0.25, 0.25, 0.0, 0.0, 0.0, 0) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_step(h, 1) == _lib.VLB_E_STATE  # not bound
+    lib.vlb3_destroy(h)
+
+
 def _geom_cases():
     mask = np.zeros((23, 41), np.uint8)
     mask[5:9, 10:13] = 1
