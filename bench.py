@@ -383,6 +383,62 @@ def cpu_baseline(pr, seconds):
             "value_1_core": v1}
 
 
+def d3_leg(steps, warmup, cpu_steps=0):
+    """Three-dimensional (D3Q19) form: force-driven Oldroyd-B channel 256 x 64 x 256
+    (4.2 M nodes, half-way walls normal to y), FP32 storage.  Algorithmic bytes per node
+    and step: 133 populations read and written (7 lattices x 19 directions) and the
+    history of S (6) and u (3) read and written: 2 x 142 x 4 = 1,136 B; the rho/u planes
+    of the neighbour differences (16 B written, 16 B read) and the 76 B of hydrodynamic
+    pulls of the rho/u launch are reported beside it.  HIP events on the simulation's
+    stream bracket both launches of every step."""
+    import torch
+    import synth
+    from paper_2508_16997_amd.sim3d import Simulation3D
+
+    pr = synth.channel3d(nx=256, ny=64, nz=256, Ma=0.1, precision="fp32")
+    stream = torch.cuda.Stream()
+    sim = Simulation3D.from_problem(pr, stream=stream)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_s = ev0.elapsed_time(ev1) / 1e3 / steps
+    r = sim.read()
+    torch.cuda.synchronize()
+    finite = bool(torch.isfinite(r["ux"]).all())
+    sim.close()
+    nodes = pr.nx * pr.ny * pr.nz
+    bpn = 2 * (7 * 19 + 9) * 4
+    achieved = bpn * nodes / step_s / 1e9
+    out = {"workload": "D3Q19 Oldroyd-B channel 256x64x256, half-way walls in y, FP32 storage, "
+                       "Wi=1, beta=0.5",
+           "nodes": nodes, "steps": steps, "MLUPS": round(nodes * steps / wall / 1e6, 2),
+           "us_per_step": round(step_s * 1e6, 3), "bytes_per_node": bpn,
+           "extra_bytes_per_node": {"rho_u_planes": 32, "rho_u_launch_pulls": 76},
+           "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "kernels": "k3_macro + k3_step", "finite": finite}
+    if cpu_steps:
+        import oracle
+
+        oracle.build(force=False)
+        oracle.set_threads(os.cpu_count() or 1)
+        o = oracle.OracleSim3D(pr)
+        t = time.perf_counter()
+        o.step(cpu_steps)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(nodes * cpu_steps / dt / 1e6, 3), "unit": "MLUPS",
+                               "cores": os.cpu_count() or 1, "kind": "oracle",
+                               "sample": f"{cpu_steps} coupled FP64 steps of the same "
+                                         f"256x64x256 channel, {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,6 +474,11 @@ def main():
                     help="skip the adjoint leg (512x512, gradient of a velocity misfit)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-stride", type=int, default=45)
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the three-dimensional (D3Q19) leg")
+    ap.add_argument("--d3-steps", type=int, default=200)
+    ap.add_argument("--cpu-3d-steps", type=int, default=2,
+                    help="oracle steps of the 3-D channel for its CPU baseline (0: none)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -525,6 +586,8 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_stride, tile,
                                      args.graph_chunk)
+    if not args.no_3d:
+        out["d3q19"] = d3_leg(args.d3_steps, 20, 0 if args.no_cpu_baseline else args.cpu_3d_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

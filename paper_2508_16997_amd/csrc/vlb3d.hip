@@ -83,36 +83,72 @@ struct Run3 {
 template <class S>
 __device__ __forceinline__ T ldg(const S* p, long long i) { return (T)p[i]; }
 
-// Slot that node (x, y, z) pulls direction i from, or -1 beyond a wall.
-template <class S>
-__device__ __forceinline__ int src_slot(const Run3<S>& R, int x, int y, int z, int i) {
-    int xs = x - ec(i, 0), ys = y - ec(i, 1), zs = z - ec(i, 2);
-    xs = xs < 0 ? xs + R.nx : (xs >= R.nx ? xs - R.nx : xs);
-    zs = zs < 0 ? zs + R.nz : (zs >= R.nz ? zs - R.nz : zs);
-    if (ys < 0 || ys >= R.ny) {
-        if (R.ywall) return -1;
-        ys = ys < 0 ? ys + R.ny : ys - R.ny;
-    }
-    return (zs * R.ny + ys) * R.nx + xs;
+// c0 + e_i.c + e_i.M.e_i for the symmetric M stored as (xx, xy, xz, yy, yz, zz): with
+// components of e_i in {-1, 0, 1} this is a handful of additions per direction.
+__device__ __forceinline__ T quad_at(int i, T c0, const T c[3], const T M[6]) {
+    T v = c0;
+    const int e0 = ec(i, 0), e1 = ec(i, 1), e2 = ec(i, 2);
+    if (e0) v += e0 > 0 ? c[0] : -c[0];
+    if (e1) v += e1 > 0 ? c[1] : -c[1];
+    if (e2) v += e2 > 0 ? c[2] : -c[2];
+    if (e0) v += M[0];
+    if (e1) v += M[3];
+    if (e2) v += M[5];
+    if (e0 * e1) v += e0 * e1 > 0 ? 2.0 * M[1] : -2.0 * M[1];
+    if (e0 * e2) v += e0 * e2 > 0 ? 2.0 * M[2] : -2.0 * M[2];
+    if (e1 * e2) v += e1 * e2 > 0 ? 2.0 * M[4] : -2.0 * M[4];
+    return v;
 }
 
-// The nine (or, lattice by lattice, 19) populations node n receives; `own` on the first
-// step (the initial state sits at the node's own slot).
+// Where node (x, y, z) pulls from: its own slot n and, per axis, the slot offsets of
+// the source behind it for e = +1 ([0]) and e = -1 ([1]) with the periodic wrap; the wall
+// flags mark rows whose pulls from beyond y are the node's own opposite values.  On the
+// first step every pull is the node's own slot (the initial state sits there).
+struct Nbr {
+    int n;
+    int dx[2], dy[2], dz[2];
+    bool ylo_wall, yhi_wall, first;
+};
 template <class S>
-__device__ __forceinline__ S pull1(const Run3<S>& R, int L, int i, int n, int x, int y, int z) {
-    const long long N = R.N;
-    if (R.first) return R.src[(L * Q + i) * N + n];
-    const int s = src_slot(R, x, y, z, i);
-    return s >= 0 ? R.src[(L * Q + i) * N + s] : R.src[(L * Q + opp3(i)) * N + n];
+__device__ __forceinline__ Nbr make_nbr(const Run3<S>& R, int x, int y, int z) {
+    Nbr b;
+    const int nxy = R.nx * R.ny;
+    b.n = (z * R.ny + y) * R.nx + x;
+    b.dx[0] = x == 0 ? R.nx - 1 : -1;
+    b.dx[1] = x == R.nx - 1 ? -(R.nx - 1) : 1;
+    b.dy[0] = (y == 0 ? R.ny - 1 : -1) * R.nx;
+    b.dy[1] = (y == R.ny - 1 ? -(R.ny - 1) : 1) * R.nx;
+    b.dz[0] = (z == 0 ? R.nz - 1 : -1) * nxy;
+    b.dz[1] = (z == R.nz - 1 ? -(R.nz - 1) : 1) * nxy;
+    b.ylo_wall = R.ywall && y == 0;
+    b.yhi_wall = R.ywall && y == R.ny - 1;
+    b.first = R.first != 0;
+    return b;
+}
+// Population i of lattice L arriving at the node.
+// (The plane base is uniform -- a scalar pointer -- and the slot a per-lane offset, so
+// each load is one scalar-base, vector-offset instruction.)
+template <class S>
+__device__ __forceinline__ const S* plane_of(const Run3<S>& R, int L, int i) {
+    return R.src + (size_t)(L * Q + i) * (size_t)R.N;
+}
+template <class S>
+__device__ __forceinline__ S pullb(const Run3<S>& R, const Nbr& b, int L, int i) {
+    if (b.first) return plane_of(R, L, i)[b.n];
+    const int ex = ec(i, 0), ey = ec(i, 1), ez = ec(i, 2);
+    if ((ey > 0 && b.ylo_wall) || (ey < 0 && b.yhi_wall)) return plane_of(R, L, opp3(i))[b.n];
+    const int s = b.n + (ex > 0 ? b.dx[0] : (ex < 0 ? b.dx[1] : 0)) +
+                  (ey > 0 ? b.dy[0] : (ey < 0 ? b.dy[1] : 0)) +
+                  (ez > 0 ? b.dz[0] : (ez < 0 ? b.dz[1] : 0));
+    return plane_of(R, L, i)[s];
 }
 
 template <class S>
-__device__ __forceinline__ void hydro_pull(const Run3<S>& R, int n, int x, int y, int z, S f[Q],
-                                           T& rho, T u[3]) {
+__device__ __forceinline__ void hydro_pull(const Run3<S>& R, const Nbr& b, S f[Q], T& rho, T u[3]) {
     T dr = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = pull1(R, 0, i, n, x, y, z);
+        f[i] = pullb(R, b, 0, i);
         const T v = (T)f[i];
         dr += v;
 #pragma unroll
@@ -128,10 +164,11 @@ template <class S>
 __global__ __launch_bounds__(TX * TY) void k3_macro(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
-    const int n = (z * R.ny + y) * R.nx + x;
+    const Nbr b = make_nbr(R, x, y, z);
+    const int n = b.n;
     S f[Q];
     T rho, u[3];
-    hydro_pull(R, n, x, y, z, f, rho, u);
+    hydro_pull(R, b, f, rho, u);
     R.mac[n] = (S)rho;
     R.mac[(long long)R.N + n] = (S)u[0];
     R.mac[2LL * R.N + n] = (S)u[1];
@@ -147,16 +184,19 @@ __device__ __forceinline__ T fd(bool lo_wall, T vlo, T v0, bool hi_wall, T vhi) 
     return 0.0;
 }
 
-// One conformation lattice K: pulls, CNEBB at a wall-adjacent node, collision, store.
-template <int k, class S>
-__device__ __forceinline__ void conf_lattice(const Run3<S>& R, int n, int x, int y, int z,
-                                             const T u[3], const T up[3], T rho, T uu, T dp,
-                                             T Sk, T Spk, bool wall_lo, bool wall_hi) {
+// One conformation lattice k (a run-time index, so that the six lattices share one copy
+// of the code and its registers): pulls, CNEBB at a wall-adjacent node, collision, store.
+__device__ __forceinline__ T phi0_rt(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
+template <class S>
+__device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, int k, const T u[3],
+                                             const T up[3], T rho, T uu, T dp, T Sk, T Spk,
+                                             bool wall_lo, bool wall_hi) {
     const long long N = R.N;
+    const int n = nb.n;
     T gv[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gv[i] = (T)pull1(R, 1 + k, i, n, x, y, z);
-    const T phi = phi0(k) + dp;
+    for (int i = 0; i < Q; ++i) gv[i] = (T)pullb(R, nb, 1 + k, i);
+    const T phi = phi0_rt(k) + dp;
     if (wall_lo || wall_hi) {
         // unknown: the directions arriving from beyond the wall; equilibrium deviation
         // at (phi_b, u_b) plus the non-equilibrium part of the known opposite (at a flat
@@ -199,23 +239,22 @@ __device__ __forceinline__ void conf_lattice(const Run3<S>& R, int n, int x, int
         B2[m] = P[m] - (a == b ? CS2 * dp : 0.0) - phi * u[a] * u[b];
     }
     const T trB2 = B2[0] + B2[3] + B2[5];
+    // Post-collision deviation g_i - w_i phi0 = w_i (c0 + e_i.c + e_i.M.e_i), collecting
+    // the equilibrium phi (1 + 3 e.u + 4.5 ((e.u)^2 - c_s^2 u.u)), the regularized
+    // non-equilibrium p1 3 e.B1 + p2 4.5 (e.B2.e - c_s^2 tr B2), the auxiliary term
+    // 3 h2 (e.F) phi / rho and the source term 1.5 F~(t) - 0.5 F~(t-1) with
+    // F~ = S (1 + 3 h2 e.u):
+    T c0 = dp - 1.5 * phi * uu - 1.5 * R.p2 * trB2 + 1.5 * Sk - 0.5 * Spk;
+    T c[3], M[6];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T e0 = ec(i, 0), e1 = ec(i, 1), e2 = ec(i, 2);
-        const T eu = e0 * u[0] + e1 * u[1] + e2 * u[2];
-        const T eup = e0 * up[0] + e1 * up[1] + e2 * up[2];
-        const T eF = e0 * R.F[0] + e1 * R.F[1] + e2 * R.F[2];
-        const T eB2e = e0 * e0 * B2[0] + e1 * e1 * B2[3] + e2 * e2 * B2[5] +
-                       2.0 * (e0 * e1 * B2[1] + e0 * e2 * B2[2] + e1 * e2 * B2[4]);
-        const T eq = dp + phi * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu));
-        const T r1 = 3.0 * (e0 * B1[0] + e1 * B1[1] + e2 * B1[2]);
-        const T r2 = 4.5 * (eB2e - CS2 * trB2);
-        const T Gt = R.h2 * 3.0 * eF * phi / rho;
-        const T Fn = Sk * (1.0 + R.h2 * 3.0 * eu);
-        const T Fp = Spk * (1.0 + R.h2 * 3.0 * eup);
-        R.dst[((long long)(1 + k) * Q + i) * N + n] =
-            (S)(w3(i) * (eq + R.p1 * r1 + R.p2 * r2 + Gt + Fn + 0.5 * (Fn - Fp)));
-    }
+    for (int a = 0; a < 3; ++a)
+        c[a] = 3.0 * phi * u[a] + 3.0 * R.p1 * B1[a] + 3.0 * R.h2 * R.F[a] * phi / rho +
+               3.0 * R.h2 * (1.5 * Sk * u[a] - 0.5 * Spk * up[a]);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) M[m] = 4.5 * (phi * u[ka(m)] * u[kb(m)] + R.p2 * B2[m]);
+    S* out = R.dst + (size_t)(1 + k) * Q * (size_t)R.N;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[(size_t)i * R.N + n] = (S)(w3(i) * quad_at(i, c0, c, M));
 }
 
 template <class S>
@@ -223,33 +262,37 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
     const long long N = R.N;
-    const int n = (z * R.ny + y) * R.nx + x;
+    const Nbr nbr = make_nbr(R, x, y, z);
+    const int n = nbr.n;
 
     // ---- hydrodynamic pulls, rho, u ----
     S f[Q];
     T rho, u[3];
-    hydro_pull(R, n, x, y, z, f, rho, u);
+    hydro_pull(R, nbr, f, rho, u);
 
     // ---- conformation (zeroth moments of the pulled populations; CNEBB keeps them) ----
+    // Per-lattice values wait in LDS, one column per lane, so that the lattice loops run
+    // with a run-time index and one lattice's registers.
+    __shared__ T s_dphi[6][TX * TY], s_Sc[6][TX * TY], s_Sp[6][TX * TY];
+    const int tid = threadIdx.y * TX + threadIdx.x;
     T dphi[6];
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < 6; ++k) {
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)pull1(R, 1 + k, i, n, x, y, z);
-        dphi[k] = s;
+        for (int i = 0; i < Q; ++i) s += (T)pullb(R, nbr, 1 + k, i);
+        s_dphi[k][tid] = s;
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dphi[k] = s_dphi[k][tid];
 
     // ---- velocity gradient L[g][b] = d_g u_b and D_a = d_a(rho u_a^3) at time n ----
     T L[3][3], D[3];
     {
-        const int xl = x == 0 ? R.nx - 1 : x - 1, xh = x == R.nx - 1 ? 0 : x + 1;
-        const int zl = z == 0 ? R.nz - 1 : z - 1, zh = z == R.nz - 1 ? 0 : z + 1;
-        const bool wl = R.ywall && y == 0, wh = R.ywall && y == R.ny - 1;
-        const int yl = y == 0 ? R.ny - 1 : y - 1, yh = y == R.ny - 1 ? 0 : y + 1;
-        const int nb[3][2] = {{(z * R.ny + y) * R.nx + xl, (z * R.ny + y) * R.nx + xh},
-                              {(z * R.ny + yl) * R.nx + x, (z * R.ny + yh) * R.nx + x},
-                              {(zl * R.ny + y) * R.nx + x, (zh * R.ny + y) * R.nx + x}};
+        const bool wl = nbr.ylo_wall, wh = nbr.yhi_wall;
+        const int nb[3][2] = {{n + nbr.dx[0], n + nbr.dx[1]},
+                              {n + nbr.dy[0], n + nbr.dy[1]},
+                              {n + nbr.dz[0], n + nbr.dz[1]}};
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
             const bool lw = g == 1 && wl, hw = g == 1 && wh;
@@ -293,9 +336,12 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         }
     }
     // history: S and u of the previous step (the first step takes this step's)
-    T Sp[6], up[3];
+    T up[3];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Sp[k] = R.first ? Sc[k] : ldg(R.hist, k * N + n);
+    for (int k = 0; k < 6; ++k) {
+        s_Sc[k][tid] = Sc[k];
+        s_Sp[k][tid] = R.first ? Sc[k] : ldg(R.hist, k * N + n);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) up[a] = R.first ? u[a] : ldg(R.hist, (6 + a) * N + n);
 
@@ -335,41 +381,46 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         }
         const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const T trA2 = A2[0] + A2[3] + A2[5], trt = tau[0] + tau[3] + tau[5];
+        // Post-collision deviation f_i - w_i = w_i (c0 + e_i.c + e_i.M.e_i + sum h_{c,s}(e_i)
+        // d_{c,s}), collecting the equilibrium, c1 times the regularized orders 1-2 (A1 =
+        // -F/2), c2 times the projected third order, G_i, T_i and F_i:
+        const T c0 = dr - 1.5 * rho * uu - 1.5 * R.c1 * trA2 +
+                     1.5 * R.h1 * (D[0] + D[1] + D[2]) + 1.5 * R.inv_ts1 * trt;
+        T c[3], M[6], d[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] = 3.0 * rho * u[a] - 1.5 * R.c1 * R.F[a] + 3.0 * R.h1 * R.F[a];
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            M[m] = 4.5 * (rho * u[ka(m)] * u[kb(m)] + R.c1 * A2[m] - R.inv_ts1 * tau[m]);
+        M[0] -= 4.5 * R.h1 * D[0];
+        M[3] -= 4.5 * R.h1 * D[1];
+        M[5] -= 4.5 * R.h1 * D[2];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            d[cc][0] = hinvnorm(-1) * (rho * uc[cc][0] + R.c2 * A3[cc][0]);
+            d[cc][1] = hinvnorm(1) * (rho * uc[cc][1] + R.c2 * A3[cc][1]);
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const T e0 = ec(i, 0), e1 = ec(i, 1), e2 = ec(i, 2);
-            const T eu = e0 * u[0] + e1 * u[1] + e2 * u[2];
-            T third = 0.0, third_neq = 0.0;
+            T v = quad_at(i, c0, c, M);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                third += hinvnorm(-1) * hcomb(i, c, -1) * uc[c][0] + hinvnorm(1) * hcomb(i, c, 1) * uc[c][1];
-                third_neq += hinvnorm(-1) * hcomb(i, c, -1) * A3[c][0] + hinvnorm(1) * hcomb(i, c, 1) * A3[c][1];
+            for (int cc = 0; cc < 3; ++cc) {
+                if (hcomb(i, cc, -1) != 0.0) v += hcomb(i, cc, -1) * d[cc][0];
+                if (hcomb(i, cc, 1) != 0.0) v += hcomb(i, cc, 1) * d[cc][1];
             }
-            const T eA2e = e0 * e0 * A2[0] + e1 * e1 * A2[3] + e2 * e2 * A2[5] +
-                           2.0 * (e0 * e1 * A2[1] + e0 * e2 * A2[2] + e1 * e2 * A2[4]);
-            const T ete = e0 * e0 * tau[0] + e1 * e1 * tau[3] + e2 * e2 * tau[5] +
-                          2.0 * (e0 * e1 * tau[1] + e0 * e2 * tau[2] + e1 * e2 * tau[4]);
-            const T eq = dr + rho * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu) + third);
-            const T neq1 = 3.0 * (-0.5) * (e0 * R.F[0] + e1 * R.F[1] + e2 * R.F[2]) +
-                           4.5 * (eA2e - CS2 * trA2);
-            const T Gi = -R.h1 * 4.5 * ((e0 * e0 - CS2) * D[0] + (e1 * e1 - CS2) * D[1] + (e2 * e2 - CS2) * D[2]);
-            const T Ti = -4.5 * R.inv_ts1 * (ete - CS2 * trt);
-            const T Fi = R.h1 * 3.0 * (e0 * R.F[0] + e1 * R.F[1] + e2 * R.F[2]);
-            R.dst[(long long)i * N + n] = (S)(w3(i) * (eq + R.c1 * neq1 + R.c2 * third_neq + Gi + Ti + Fi));
+            R.dst[(long long)i * N + n] = (S)(w3(i) * v);
         }
     }
 
     // ---- conformation lattices: pulls, CNEBB at wall-adjacent nodes, collision ----
     const bool wall_lo = R.ywall && y == 0 && !R.first, wall_hi = R.ywall && y == R.ny - 1 && !R.first;
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    conf_lattice<0>(R, n, x, y, z, u, up, rho, uu, dphi[0], Sc[0], Sp[0], wall_lo, wall_hi);
-    conf_lattice<1>(R, n, x, y, z, u, up, rho, uu, dphi[1], Sc[1], Sp[1], wall_lo, wall_hi);
-    conf_lattice<2>(R, n, x, y, z, u, up, rho, uu, dphi[2], Sc[2], Sp[2], wall_lo, wall_hi);
-    conf_lattice<3>(R, n, x, y, z, u, up, rho, uu, dphi[3], Sc[3], Sp[3], wall_lo, wall_hi);
-    conf_lattice<4>(R, n, x, y, z, u, up, rho, uu, dphi[4], Sc[4], Sp[4], wall_lo, wall_hi);
-    conf_lattice<5>(R, n, x, y, z, u, up, rho, uu, dphi[5], Sc[5], Sp[5], wall_lo, wall_hi);
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k)
+        conf_lattice(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], wall_lo,
+                     wall_hi);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) R.hist[k * N + n] = (S)Sc[k];
+    for (int k = 0; k < 6; ++k) R.hist[k * N + n] = (S)s_Sc[k][tid];
 #pragma unroll
     for (int a = 0; a < 3; ++a) R.hist[(6 + a) * N + n] = (S)u[a];
 }
@@ -419,16 +470,17 @@ template <class S>
 __global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
-    const int n = (z * R.ny + y) * R.nx + x;
+    const Nbr nbr = make_nbr(R, x, y, z);
+    const int n = nbr.n;
     S f[Q];
     T rho, u[3];
-    hydro_pull(R, n, x, y, z, f, rho, u);
+    hydro_pull(R, nbr, f, rho, u);
     T v[10] = {rho, u[0], u[1], u[2]};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)pull1(R, 1 + k, i, n, x, y, z);
+        for (int i = 0; i < Q; ++i) s += (T)pullb(R, nbr, 1 + k, i);
         v[4 + k] = phi0(k) + s;
     }
 #pragma unroll
