@@ -80,9 +80,6 @@ struct Run3 {
     int no_source;
 };
 
-template <class S>
-__device__ __forceinline__ T ldg(const S* p, long long i) { return (T)p[i]; }
-
 // c0 + e_i.c + e_i.M.e_i for the symmetric M stored as (xx, xy, xz, yy, yz, zz): with
 // components of e_i in {-1, 0, 1} this is a handful of additions per direction.
 __device__ __forceinline__ T quad_at(int i, T c0, const T c[3], const T M[6]) {
@@ -125,30 +122,91 @@ __device__ __forceinline__ Nbr make_nbr(const Run3<S>& R, int x, int y, int z) {
     b.first = R.first != 0;
     return b;
 }
-// Population i of lattice L arriving at the node.
-// (The plane base is uniform -- a scalar pointer -- and the slot a per-lane offset, so
-// each load is one scalar-base, vector-offset instruction.)
+// Memory access by plane and slot through raw buffer instructions: a uniform resource
+// for a group of planes (scalar registers), the plane's byte offset as the scalar offset
+// and the slot's as the per-lane 32-bit offset, so that a pull holds one vector register
+// for its address.  Offsets stay below 2^32 by the size limits of vlb3_create (a group
+// is at most one lattice of 19 planes).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+using u32x2 = __attribute__((ext_vector_type(2))) unsigned;
 template <class S>
-__device__ __forceinline__ const S* plane_of(const Run3<S>& R, int L, int i) {
-    return R.src + (size_t)(L * Q + i) * (size_t)R.N;
+struct Planes {
+    rsrc_t r;
+    unsigned stride;  // bytes per plane
+};
+template <class S>
+__device__ __forceinline__ Planes<S> planes(const S* base, int N) {
+    // stride 0 (raw), no range limit, the data format the untyped loads expect on gfx9
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base), (short)0, -1, 0x00020000),
+            (unsigned)N * (unsigned)sizeof(S)};
+}
+__device__ __forceinline__ float bload(float*, rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
+}
+__device__ __forceinline__ double bload(double*, rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
+}
+__device__ __forceinline__ void bstore(float x, rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)v, (int)s, 0);
+}
+__device__ __forceinline__ void bstore(double x, rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)v, (int)s, 0);
 }
 template <class S>
-__device__ __forceinline__ S pullb(const Run3<S>& R, const Nbr& b, int L, int i) {
-    if (b.first) return plane_of(R, L, i)[b.n];
+__device__ __forceinline__ S at(const Planes<S>& P, int plane, int slot) {
+    return bload((S*)nullptr, P.r, (unsigned)slot * (unsigned)sizeof(S), (unsigned)plane * P.stride);
+}
+template <class S>
+__device__ __forceinline__ void put(const Planes<S>& P, int plane, int slot, T v) {
+    bstore((S)v, P.r, (unsigned)slot * (unsigned)sizeof(S), (unsigned)plane * P.stride);
+}
+// The 19 planes of lattice L of the source or destination buffer.
+template <class S>
+__device__ __forceinline__ Planes<S> src_lattice(const Run3<S>& R, int L) {
+    return planes(R.src + (size_t)L * Q * (size_t)R.N, R.N);
+}
+template <class S>
+__device__ __forceinline__ Planes<S> dst_lattice(const Run3<S>& R, int L) {
+    return planes((const S*)R.dst + (size_t)L * Q * (size_t)R.N, R.N);
+}
+// Population i of a lattice arriving at the node from x - e_i with the periodic wrap in
+// all three axes (the wall fix-up below replaces the pulls from beyond a y wall).
+template <class S>
+__device__ __forceinline__ S pullb(const Planes<S>& P, const Nbr& b, int i) {
+    if (b.first) return at(P, i, b.n);
     const int ex = ec(i, 0), ey = ec(i, 1), ez = ec(i, 2);
-    if ((ey > 0 && b.ylo_wall) || (ey < 0 && b.yhi_wall)) return plane_of(R, L, opp3(i))[b.n];
     const int s = b.n + (ex > 0 ? b.dx[0] : (ex < 0 ? b.dx[1] : 0)) +
                   (ey > 0 ? b.dy[0] : (ey < 0 ? b.dy[1] : 0)) +
                   (ez > 0 ? b.dz[0] : (ez < 0 ? b.dz[1] : 0));
-    return plane_of(R, L, i)[s];
+    return at(P, i, s);
+}
+// Pulls of lattice L with the directions arriving from beyond a y wall taken as the node's
+// own post-collision value of the opposite direction.  (A wave holds one row, so the wall
+// branches are uniform.)
+template <class S>
+__device__ __forceinline__ void pull_all(const Run3<S>& R, const Nbr& b, int L, S g[Q]) {
+    const Planes<S> P = src_lattice(R, L);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = pullb(P, b, i);
+    if (b.first) return;
+    if (b.ylo_wall) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (ec(i, 1) > 0) g[i] = at(P, opp3(i), b.n);
+    }
+    if (b.yhi_wall) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (ec(i, 1) < 0) g[i] = at(P, opp3(i), b.n);
+    }
 }
 
 template <class S>
 __device__ __forceinline__ void hydro_pull(const Run3<S>& R, const Nbr& b, S f[Q], T& rho, T u[3]) {
+    pull_all(R, b, 0, f);
     T dr = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = pullb(R, b, 0, i);
         const T v = (T)f[i];
         dr += v;
 #pragma unroll
@@ -169,10 +227,10 @@ __global__ __launch_bounds__(TX * TY) void k3_macro(Run3<S> R) {
     S f[Q];
     T rho, u[3];
     hydro_pull(R, b, f, rho, u);
-    R.mac[n] = (S)rho;
-    R.mac[(long long)R.N + n] = (S)u[0];
-    R.mac[2LL * R.N + n] = (S)u[1];
-    R.mac[3LL * R.N + n] = (S)u[2];
+    const Planes<S> M = planes((const S*)R.mac, R.N);
+    put(M, 0, n, rho);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) put(M, 1 + a, n, u[a]);
 }
 
 // Derivative along one axis: central difference, or next to a flat half-way wall the
@@ -191,18 +249,27 @@ template <class S>
 __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, int k, const T u[3],
                                              const T up[3], T rho, T uu, T dp, T Sk, T Spk,
                                              bool wall_lo, bool wall_hi) {
-    const long long N = R.N;
     const int n = nb.n;
-    T gv[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) gv[i] = (T)pullb(R, nb, 1 + k, i);
+    S gs[Q];
+    pull_all(R, nb, 1 + k, gs);
     const T phi = phi0_rt(k) + dp;
+    // first and second moments of the pulled deviations
+    T J[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T v = (T)gs[i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (ec(i, a) != 0) J[a] += ec(i, a) > 0 ? v : -v;
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            if (ec(i, ka(m)) * ec(i, kb(m)) != 0) P[m] += (ec(i, ka(m)) * ec(i, kb(m)) > 0) ? v : -v;
+    }
     if (wall_lo || wall_hi) {
-        // unknown: the directions arriving from beyond the wall; equilibrium deviation
-        // at (phi_b, u_b) plus the non-equilibrium part of the known opposite (at a flat
-        // wall the opposite of an unknown is always known, so the update is in place);
-        // g_0 the remainder of phi_b
-        T rest = dp;
+        // CNEBB: each unknown (a direction arriving from beyond the wall) becomes the
+        // equilibrium deviation at (phi_b, u_b) plus the non-equilibrium part of its known
+        // opposite; g_0 takes the remainder of phi_b, so the zeroth moment is unchanged
+        // and the first and second moments change by the unknowns' corrections only.
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const bool unk = wall_lo ? ec(i, 1) > 0 : ec(i, 1) < 0;
@@ -211,23 +278,16 @@ __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, in
                 const T eui = ec(i, 0) * u[0] + ec(i, 1) * u[1] + ec(i, 2) * u[2];
                 const T eqi = w3(i) * (dp + phi * (3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
                 const T eqo = w3(o) * (dp + phi * (-3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
-                gv[i] = eqi + gv[o] - eqo;
+                const T delta = eqi + (T)gs[o] - eqo - (T)gs[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (ec(i, a) != 0) J[a] += ec(i, a) > 0 ? delta : -delta;
+#pragma unroll
+                for (int m = 0; m < 6; ++m)
+                    if (ec(i, ka(m)) * ec(i, kb(m)) != 0)
+                        P[m] += (ec(i, ka(m)) * ec(i, kb(m)) > 0) ? delta : -delta;
             }
         }
-#pragma unroll
-        for (int i = 1; i < Q; ++i) rest -= gv[i];
-        gv[0] = rest;
-    }
-    T J[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T v = gv[i];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            if (ec(i, a) != 0) J[a] += ec(i, a) > 0 ? v : -v;
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-            if (ec(i, ka(m)) * ec(i, kb(m)) != 0) P[m] += (ec(i, ka(m)) * ec(i, kb(m)) > 0) ? v : -v;
     }
     // B1 = J - phi u; B2 = P - c_s^2 d (phi - phi0) - phi u u (deviations carry phi0)
     T B1[3], B2[6];
@@ -252,9 +312,9 @@ __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, in
                3.0 * R.h2 * (1.5 * Sk * u[a] - 0.5 * Spk * up[a]);
 #pragma unroll
     for (int m = 0; m < 6; ++m) M[m] = 4.5 * (phi * u[ka(m)] * u[kb(m)] + R.p2 * B2[m]);
-    S* out = R.dst + (size_t)(1 + k) * Q * (size_t)R.N;
+    const Planes<S> out = dst_lattice(R, 1 + k);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[(size_t)i * R.N + n] = (S)(w3(i) * quad_at(i, c0, c, M));
+    for (int i = 0; i < Q; ++i) put(out, i, n, w3(i) * quad_at(i, c0, c, M));
 }
 
 template <class S>
@@ -278,9 +338,11 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     T dphi[6];
 #pragma unroll 1
     for (int k = 0; k < 6; ++k) {
+        S g[Q];
+        pull_all(R, nbr, 1 + k, g);
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)pullb(R, nbr, 1 + k, i);
+        for (int i = 0; i < Q; ++i) s += (T)g[i];
         s_dphi[k][tid] = s;
     }
 #pragma unroll
@@ -289,6 +351,7 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     // ---- velocity gradient L[g][b] = d_g u_b and D_a = d_a(rho u_a^3) at time n ----
     T L[3][3], D[3];
     {
+        const Planes<S> mac = planes((const S*)R.mac, R.N);
         const bool wl = nbr.ylo_wall, wh = nbr.yhi_wall;
         const int nb[3][2] = {{n + nbr.dx[0], n + nbr.dx[1]},
                               {n + nbr.dy[0], n + nbr.dy[1]},
@@ -298,14 +361,14 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
             const bool lw = g == 1 && wl, hw = g == 1 && wh;
             T rl = 0.0, rh = 0.0, vl[3] = {0.0, 0.0, 0.0}, vh[3] = {0.0, 0.0, 0.0};
             if (!lw) {
-                rl = ldg(R.mac, nb[g][0]);
+                rl = at(mac, 0, nb[g][0]);
 #pragma unroll
-                for (int b = 0; b < 3; ++b) vl[b] = ldg(R.mac, (1 + b) * N + nb[g][0]);
+                for (int b = 0; b < 3; ++b) vl[b] = at(mac, 1 + b, nb[g][0]);
             }
             if (!hw) {
-                rh = ldg(R.mac, nb[g][1]);
+                rh = at(mac, 0, nb[g][1]);
 #pragma unroll
-                for (int b = 0; b < 3; ++b) vh[b] = ldg(R.mac, (1 + b) * N + nb[g][1]);
+                for (int b = 0; b < 3; ++b) vh[b] = at(mac, 1 + b, nb[g][1]);
             }
 #pragma unroll
             for (int b = 0; b < 3; ++b) L[g][b] = fd(lw, vl[b], u[b], hw, vh[b]);
@@ -336,17 +399,19 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         }
     }
     // history: S and u of the previous step (the first step takes this step's)
+    const Planes<S> hist = planes((const S*)R.hist, R.N);
     T up[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         s_Sc[k][tid] = Sc[k];
-        s_Sp[k][tid] = R.first ? Sc[k] : ldg(R.hist, k * N + n);
+        s_Sp[k][tid] = R.first ? Sc[k] : (T)at(hist, k, n);
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) up[a] = R.first ? u[a] : ldg(R.hist, (6 + a) * N + n);
+    for (int a = 0; a < 3; ++a) up[a] = R.first ? u[a] : (T)at(hist, 6 + a, n);
 
     // ---- hydrodynamic collision (moment form) ----
     {
+        const Planes<S> out = dst_lattice(R, 0);
         // second moments and third-order combinations of the pulled deviations
         T P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Qm[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
@@ -408,7 +473,7 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
                 if (hcomb(i, cc, -1) != 0.0) v += hcomb(i, cc, -1) * d[cc][0];
                 if (hcomb(i, cc, 1) != 0.0) v += hcomb(i, cc, 1) * d[cc][1];
             }
-            R.dst[(long long)i * N + n] = (S)(w3(i) * v);
+            put(out, i, n, w3(i) * v);
         }
     }
 
@@ -420,9 +485,9 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         conf_lattice(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], wall_lo,
                      wall_hi);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) R.hist[k * N + n] = (S)s_Sc[k][tid];
+    for (int k = 0; k < 6; ++k) put(hist, k, n, s_Sc[k][tid]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) R.hist[(6 + a) * N + n] = (S)u[a];
+    for (int a = 0; a < 3; ++a) put(hist, 6 + a, n, u[a]);
 }
 
 // Equilibrium state of the given fields at every node's own slot (read without a pull
@@ -478,9 +543,11 @@ __global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
     T v[10] = {rho, u[0], u[1], u[2]};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
+        S g[Q];
+        pull_all(R, nbr, 1 + k, g);
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)pullb(R, nbr, 1 + k, i);
+        for (int i = 0; i < Q; ++i) s += (T)g[i];
         v[4 + k] = phi0(k) + s;
     }
 #pragma unroll
