@@ -7,10 +7,12 @@
 // of S (6 planes) and u (3 planes); rho and u at time n (4 planes) for the neighbours'
 // differences.  Per step two launches:
 //   k3_macro  rho and u of every node from its pulled populations (mac planes)
-//   k3_step   per node: pulls, conformation, velocity gradient from the mac planes of
-//             the six axis neighbours, constitutive source, the hydrodynamic collision
-//             (stored at once), then lattice by lattice the conformation pulls, CNEBB at
-//             wall-adjacent nodes and the collision (stored at once); history in place.
+//   k3_step   per node: pulls of all seven lattices (the conformation populations held in
+//             registers in FP32 storage, pulled again for the collision in FP64), the
+//             conformation's zeroth moments, the velocity gradient from the mac planes of
+//             the six axis neighbours, the constitutive source, the hydrodynamic collision
+//             (stored at once), then lattice by lattice CNEBB at wall-adjacent nodes and
+//             the conformation collision (stored at once); history in place.
 // Pull streaming: node x takes direction i from x - e_i (periodic wrap in x and z, and in
 // y unless walls); a source beyond a wall gives the node's own post-collision value of
 // the opposite direction (half-way bounce-back for f, the CNEBB input for g).
@@ -33,6 +35,12 @@ using T = double;
 constexpr int Q = 19;
 constexpr int NLAT = 7;  // hydrodynamic + six conformation lattices
 constexpr int TX = 64, TY = 4;
+// Conformation lattices whose pulled populations k3_step holds in registers from the
+// zeroth-moment pass to the collision (the others are pulled twice): all six in FP32
+// storage (two waves per SIMD, no second read), none in FP64, where holding them would
+// leave one wave per SIMD.
+template <class S>
+constexpr int kHold = sizeof(S) == 4 ? 6 : 0;
 constexpr T CS2 = 1.0 / 3.0;
 
 // D3Q19 velocities: rest; +-x, +-y, +-z; the twelve face diagonals in opposite pairs.
@@ -180,6 +188,15 @@ __device__ __forceinline__ S pullb(const Planes<S>& P, const Nbr& b, int i) {
                   (ez > 0 ? b.dz[0] : (ez < 0 ? b.dz[1] : 0));
     return at(P, i, s);
 }
+// A copy of the pull offsets that the compiler cannot hoist out of a lattice loop (the
+// empty asm redefines them), so that each iteration recomputes the 19 slots instead of
+// holding them in registers across the loop.
+__device__ __forceinline__ Nbr fresh(const Nbr& b) {
+    Nbr c = b;
+    asm volatile("" : "+v"(c.n), "+v"(c.dx[0]), "+v"(c.dx[1]), "+v"(c.dy[0]), "+v"(c.dy[1]),
+                 "+v"(c.dz[0]), "+v"(c.dz[1]));
+    return c;
+}
 // Pulls of lattice L with the directions arriving from beyond a y wall taken as the node's
 // own post-collision value of the opposite direction.  (A wave holds one row, so the wall
 // branches are uniform.)
@@ -242,16 +259,14 @@ __device__ __forceinline__ T fd(bool lo_wall, T vlo, T v0, bool hi_wall, T vhi) 
     return 0.0;
 }
 
-// One conformation lattice k (a run-time index, so that the six lattices share one copy
-// of the code and its registers): pulls, CNEBB at a wall-adjacent node, collision, store.
+// Collision of conformation lattice k (a run-time index, so that the six lattices share
+// one copy of the code and its registers) from its pulled populations: CNEBB at a
+// wall-adjacent node, moments, collision, store.
 __device__ __forceinline__ T phi0_rt(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
 template <class S>
-__device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, int k, const T u[3],
+__device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, const S gs[Q], const T u[3],
                                              const T up[3], T rho, T uu, T dp, T Sk, T Spk,
                                              bool wall_lo, bool wall_hi) {
-    const int n = nb.n;
-    S gs[Q];
-    pull_all(R, nb, 1 + k, gs);
     const T phi = phi0_rt(k) + dp;
     // first and second moments of the pulled deviations
     T J[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -317,12 +332,26 @@ __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, in
     for (int i = 0; i < Q; ++i) put(out, i, n, w3(i) * quad_at(i, c0, c, M));
 }
 
+// Pulls and collision of conformation lattice k.
 template <class S>
+__device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, int k, const T u[3],
+                                             const T up[3], T rho, T uu, T dp, T Sk, T Spk,
+                                             bool wall_lo, bool wall_hi) {
+    const Nbr b = fresh(nb);
+    S gs[Q];
+    pull_all(R, b, 1 + k, gs);
+    conf_collide(R, b.n, k, gs, u, up, rho, uu, dp, Sk, Spk, wall_lo, wall_hi);
+}
+
+// WALLS: the y walls' fix-ups, one-sided differences and CNEBB compiled in (a wave holds
+// one row, so they are uniform branches); without walls they are compiled out.
+template <class S, bool WALLS, int HOLD>
 __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
     const long long N = R.N;
-    const Nbr nbr = make_nbr(R, x, y, z);
+    Nbr nbr = make_nbr(R, x, y, z);
+    if (!WALLS) nbr.ylo_wall = nbr.yhi_wall = false;
     const int n = nbr.n;
 
     // ---- hydrodynamic pulls, rho, u ----
@@ -336,13 +365,23 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     __shared__ T s_dphi[6][TX * TY], s_Sc[6][TX * TY], s_Sp[6][TX * TY];
     const int tid = threadIdx.y * TX + threadIdx.x;
     T dphi[6];
+    S G[HOLD > 0 ? HOLD : 1][Q];  // the held lattices 6 - HOLD .. 5
 #pragma unroll 1
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 6 - HOLD; ++k) {
         S g[Q];
-        pull_all(R, nbr, 1 + k, g);
+        pull_all(R, fresh(nbr), 1 + k, g);
         T s = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) s += (T)g[i];
+        s_dphi[k][tid] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < HOLD; ++j) {
+        const int k = 6 - HOLD + j;
+        pull_all(R, nbr, 1 + k, G[j]);
+        T s = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += (T)G[j][i];
         s_dphi[k][tid] = s;
     }
 #pragma unroll
@@ -478,10 +517,22 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     }
 
     // ---- conformation lattices: pulls, CNEBB at wall-adjacent nodes, collision ----
-    const bool wall_lo = R.ywall && y == 0 && !R.first, wall_hi = R.ywall && y == R.ny - 1 && !R.first;
+    const bool wall_lo = WALLS && nbr.ylo_wall && !R.first, wall_hi = WALLS && nbr.yhi_wall && !R.first;
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    // The held lattices (the last HOLD of the zeroth-moment pass) from their registers,
+    // then the others pulled again, most recently read first.
+#pragma unroll
+    for (int j = HOLD - 1; j >= 0; --j) {
+        const int k = 6 - HOLD + j;
+        // (held in storage precision: the empty asm keeps the widened copies of the
+        // zeroth-moment sum from being kept instead)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(G[j][i]));
+        conf_collide(R, n, k, G[j], u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid],
+                     wall_lo, wall_hi);
+    }
 #pragma unroll 1
-    for (int k = 0; k < 6; ++k)
+    for (int k = 5 - HOLD; k >= 0; --k)
         conf_lattice(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], wall_lo,
                      wall_hi);
 #pragma unroll
@@ -647,7 +698,10 @@ int do_steps(vlb3_sim* s, int64_t n) {
     for (int64_t k = 0; k < n; ++k) {
         const vlb3::Run3<S> r = make_run<S>(s);
         hipLaunchKernelGGL((vlb3::k3_macro<S>), grd, blk, 0, s->stream, r);
-        hipLaunchKernelGGL((vlb3::k3_step<S>), grd, blk, 0, s->stream, r);
+        if (s->ywall)
+            hipLaunchKernelGGL((vlb3::k3_step<S, true, vlb3::kHold<S>>), grd, blk, 0, s->stream, r);
+        else
+            hipLaunchKernelGGL((vlb3::k3_step<S, false, vlb3::kHold<S>>), grd, blk, 0, s->stream, r);
         VLB3_HIP(hipGetLastError());
         s->parity ^= 1;
         s->first = 0;
