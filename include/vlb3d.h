@@ -36,12 +36,14 @@ extern "C" {
 typedef struct vlb3_sim vlb3_sim;
 
 /* Host object for an nx x ny x nz grid (each >= 1; ny >= 3 with VLB_WALL; nz <= 65535,
- * ny <= 262140; 133 nx * ny * nz below 2^31).  prec: VLB_FP32 or VLB_FP64; ymode: VLB_PERIODIC or VLB_WALL.
+ * ny <= 262140; 133 (nx * ny * nz + 4224) below 2^31).  prec: VLB_FP32 or VLB_FP64;
+ * ymode: VLB_PERIODIC or VLB_WALL.
  * Errors: VLB_E_INVALID_ARG. */
 int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out);
 /* Device workspace the simulation needs: two buffers of 133 population planes, 9
  * history planes (S of the six components and u), 4 planes of rho and u (256-byte
- * aligned sections). */
+ * aligned sections; each plane nx * ny * nz rounded up to 64 elements plus 4160 of
+ * padding). */
 int vlb3_workspace_bytes(const vlb3_sim* sim, size_t* bytes);
 /* Attach the caller's 256-byte aligned device workspace of at least
  * vlb3_workspace_bytes and the HIP stream (NULL: the null stream) all work goes to.

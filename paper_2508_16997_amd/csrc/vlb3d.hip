@@ -77,7 +77,7 @@ __host__ __device__ constexpr T hinvnorm(int s) { return s > 0 ? 13.5 : 4.5; }  
 template <class S>
 struct Run3 {
     int nx, ny, nz, ywall, first;
-    int N;
+    int N;  // plane stride in elements (the node count rounded up, plus a pad)
     const S* src;
     S* dst;
     S* hist;  // 9 planes: S_xx, S_xy, S_xz, S_yy, S_yz, S_zz, u_x, u_y, u_z (previous step)
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
 struct vlb3_sim {
     int nx, ny, nz, prec, ywall;
     size_t esz;
-    long long N;
+    long long N, P;  // nodes; plane stride in elements
     bool bound = false, params_set = false, inited = false;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -630,11 +630,15 @@ struct vlb3_sim {
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+// Plane stride: the node count rounded up to 64 elements plus 4160 (4096 + 64), so that
+// the 133 planes a node touches do not all start at the same offset modulo a large power
+// of two (worth about 4% on a 2^22-node grid).
+long long plane_stride(long long N) { return ((N + 63) & ~63LL) + 4160; }
 
 void layout(vlb3_sim* s) {
     size_t o = 0;
     auto take = [&](size_t b) { const size_t r = o; o = align256(o + b); return r; };
-    const size_t plane = (size_t)s->N * s->esz;
+    const size_t plane = (size_t)s->P * s->esz;
     s->off_pop[0] = take(vlb3::NLAT * vlb3::Q * plane);
     s->off_pop[1] = take(vlb3::NLAT * vlb3::Q * plane);
     s->off_hist = take(9 * plane);
@@ -651,7 +655,7 @@ vlb3::Run3<S> make_run(const vlb3_sim* s) {
     r.nz = s->nz;
     r.ywall = s->ywall;
     r.first = s->first;
-    r.N = (int)s->N;
+    r.N = (int)s->P;
     r.src = reinterpret_cast<const S*>(s->ws + s->off_pop[s->parity]);
     r.dst = reinterpret_cast<S*>(s->ws + s->off_pop[s->parity ^ 1]);
     r.hist = reinterpret_cast<S*>(s->ws + s->off_hist);
@@ -759,7 +763,7 @@ int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out) {
     if (nz > 65535 || (ny + vlb3::TY - 1) / vlb3::TY > 65535)
         return vlb::report_error(VLB_E_INVALID_ARG, "nz and ny / 4 must stay within the launch grid (65535)");
     const long long N = (long long)nx * ny * nz;
-    if (N >= (1LL << 31) / (vlb3::NLAT * vlb3::Q))
+    if (plane_stride(N) >= (1LL << 31) / (vlb3::NLAT * vlb3::Q))
         return vlb::report_error(VLB_E_INVALID_ARG, "grid too large for 32-bit plane offsets");
     vlb3_sim* s = new (std::nothrow) vlb3_sim();
     if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "out of host memory");
@@ -770,6 +774,7 @@ int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out) {
     s->ywall = ymode == VLB_WALL ? 1 : 0;
     s->esz = prec == VLB_FP32 ? 4 : 8;
     s->N = N;
+    s->P = plane_stride(N);
     layout(s);
     *out = s;
     return VLB_OK;
