@@ -290,7 +290,7 @@ def node_fd(lo_solid, qlo, plo, p0, hi_solid, qhi, phi):
 
 
 # ------------------------------------------------------------------------------------
-# Three-dimensional (D3Q19) oracle
+# Three-dimensional (D3Q19 / D3Q27) oracle
 # ------------------------------------------------------------------------------------
 FIELDS3 = ("rho", "ux", "uy", "uz", "axx", "axy", "axz", "ayy", "ayz", "azz")
 
@@ -307,13 +307,14 @@ def _load3():
     lib = C.CDLL(path)
     P, D, DP = C.c_void_p, C.c_double, C.POINTER(C.c_double)
     lib.o3_create.restype = P
-    lib.o3_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.o3_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.o3_destroy.argtypes = [P]
     lib.o3_set_params.argtypes = [P, D, D, D, D, D, D, D, D, D, C.c_int]
     lib.o3_init.argtypes = [P] + [DP] * 10
     lib.o3_step.argtypes = [P, C.c_longlong]
     lib.o3_read.argtypes = [P] + [DP] * 10
-    lib.o3_lattice.argtypes = [C.c_void_p, DP, C.c_void_p, DP]
+    lib.o3_lattice.restype = C.c_int
+    lib.o3_lattice.argtypes = [C.c_int, C.c_void_p, DP, C.c_void_p, DP]
     _lib3 = lib
     return lib
 
@@ -325,7 +326,8 @@ class OracleSim3D:
         lib = _load3()
         self.prob = prob
         self.shape = (prob.nz, prob.ny, prob.nx)
-        self.h = lib.o3_create(prob.nx, prob.ny, prob.nz, 1 if prob.ymode == "wall" else 0)
+        self.h = lib.o3_create(prob.nx, prob.ny, prob.nz, 1 if prob.ymode == "wall" else 0,
+                               int(prob.q))
         if not self.h:
             raise ValueError("oracle3d: invalid grid")
         Fx, Fy, Fz = (float(v) for v in prob.F)
@@ -350,12 +352,15 @@ class OracleSim3D:
         return out
 
 
-def lattice3d():
-    """D3Q19 velocities (19, 3), weights, opposites and the third-order combinations
-    (h_{c,+}, h_{c,-}) for c = 0, 1, 2 at every velocity (19, 6)."""
-    e = np.zeros((19, 3), np.int32)
-    w = np.zeros(19)
-    opp = np.zeros(19, np.int32)
-    h3 = np.zeros((19, 6))
-    _load3().o3_lattice(e.ctypes.data, _dp(w), opp.ctypes.data, _dp(h3))
-    return e, w, opp, h3
+def lattice3d(q: int = 19):
+    """Velocities (q, 3), weights, opposites and the third-order basis at every velocity
+    (q, nb3) of D3Q19 (q = 19: the combinations h_{c,+}, h_{c,-} for c = 0, 1, 2) or
+    D3Q27 (q = 27: H_xxy, H_xxz, H_yyx, H_yyz, H_zzx, H_zzy, H_xyz)."""
+    e = np.zeros((27, 3), np.int32)
+    w = np.zeros(27)
+    opp = np.zeros(27, np.int32)
+    h3 = np.zeros(27 * 7)
+    nb3 = _load3().o3_lattice(int(q), e.ctypes.data, _dp(w), opp.ctypes.data, _dp(h3))
+    if nb3 < 0:
+        raise ValueError("oracle3d: q must be 19 or 27")
+    return e[:q], w[:q], opp[:q], h3[:q * nb3].reshape(q, nb3)

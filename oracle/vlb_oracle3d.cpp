@@ -3,9 +3,9 @@
  *
  * A plain, slow, double-precision CPU implementation of the coupled viscoelastic
  * lattice Boltzmann step of arXiv:2508.16997 extended to three dimensions on the D3Q19
- * lattice (the paper works in two dimensions and calls the three-dimensional extension
- * straightforward, Sec. 3.1; the readings of that extension are listed in the design
- * notes under A32).  Only the tests and the CPU-baseline leg of the benchmark may load
+ * or the D3Q27 lattice (the paper works in two dimensions and calls the
+ * three-dimensional extension straightforward, Sec. 3.1; the readings of that extension
+ * are listed in the design notes under A32).  Only the tests and the CPU-baseline leg of the benchmark may load
  * it; it shares no code with the HIP library nor with the two-dimensional oracle.
  *
  * Same stages and the same formulas as the two-dimensional method, with every tensor
@@ -18,7 +18,7 @@
  *      value half a spacing away                                         (readings A6/A7)
  *   4. constitutive source Phi = -(A - I)/lambda + A L + (A L)^T + A tr L  (Sec. 3.2)
  *   5. hydrodynamic TRT regularized collision: Hermite moments of orders 0..3 of f - f^eq
- *      (third order projected with the lattice's own norms), tau_s1 on orders 0..2,
+ *      (third order on the lattice's own orthogonal basis and norms), tau_s1 on orders 0..2,
  *      tau_s2 on order 3, plus G_i (diagonal third-order defects D_a), F_i and T_i
  *                                                                         (Sec. 3.1)
  *   6. six convection-diffusion TRT regularized collisions with the auxiliary term
@@ -45,19 +45,59 @@
 namespace {
 
 // ----------------------------------------------------------------------------------
-// D3Q19: the rest velocity, the six axis velocities (weight 1/18) and the twelve
-// face diagonals (weight 1/36), enumerated from {-1, 0, 1}^3 with |e|^2 <= 2;
-// c_s^2 = 1/3.
+// D3Q19: the rest velocity, the six axis velocities (weight 1/18) and the twelve face
+// diagonals (weight 1/36), enumerated from {-1, 0, 1}^3 with |e|^2 <= 2.
+// D3Q27: all of {-1, 0, 1}^3, the tensor product of D1Q3 (weights 2/3, 1/6, 1/6): rest
+// 8/27, axis 2/27, face diagonals 1/54, corners 1/216.  c_s^2 = 1/3 on both.
 // ----------------------------------------------------------------------------------
-const int Q = 19;
-int E[Q][3], OPP[Q];
-double W[Q];
+const int QMAX = 27;
+const int NB3MAX = 7;
 const double CS2 = 1.0 / 3.0;
 
-struct LatticeInit {
-    LatticeInit() {
+inline double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+// A third-order basis function: a sum of coef * H_abc terms.
+struct Term {
+    double coef;
+    int a, b, c;
+};
+struct Basis3 {
+    int nterms;
+    Term t[2];
+};
+
+struct Lattice {
+    int Q;
+    int E[QMAX][3], OPP[QMAX];
+    double W[QMAX];
+    int nb3;
+    Basis3 b3[NB3MAX];
+    double norm3[NB3MAX];  // lattice norms sum_i w_i h_m(e_i)^2
+
+    double ec(int i, int a) const { return (double)E[i][a]; }
+    // Hermite polynomials of orders 1..3 (Sec. 3.1), indices over x, y, z.
+    double H1(int i, int a) const { return ec(i, a); }
+    double H2(int i, int a, int b) const { return ec(i, a) * ec(i, b) - CS2 * kd(a, b); }
+    double H3(int i, int a, int b, int c) const {
+        return ec(i, a) * ec(i, b) * ec(i, c) -
+               CS2 * (ec(i, a) * kd(b, c) + ec(i, b) * kd(a, c) + ec(i, c) * kd(a, b));
+    }
+    double h3(int i, int m) const {
+        double v = 0.0;
+        for (int k = 0; k < b3[m].nterms; ++k) v += b3[m].t[k].coef * H3(i, b3[m].t[k].a, b3[m].t[k].b, b3[m].t[k].c);
+        return v;
+    }
+    // the matching third-order moment of the continuous equilibrium per unit density
+    double u3(const double u[3], int m) const {
+        double v = 0.0;
+        for (int k = 0; k < b3[m].nterms; ++k) v += b3[m].t[k].coef * u[b3[m].t[k].a] * u[b3[m].t[k].b] * u[b3[m].t[k].c];
+        return v;
+    }
+    bool rest(int i) const { return E[i][0] == 0 && E[i][1] == 0 && E[i][2] == 0; }
+
+    explicit Lattice(int q) : Q(q) {
         int n = 0;
-        for (int norm = 0; norm <= 2; ++norm)
+        for (int norm = 0; norm <= (q == 27 ? 3 : 2); ++norm)
             for (int a = -1; a <= 1; ++a)
                 for (int b = -1; b <= 1; ++b)
                     for (int c = -1; c <= 1; ++c)
@@ -65,67 +105,77 @@ struct LatticeInit {
                             E[n][0] = a;
                             E[n][1] = b;
                             E[n][2] = c;
-                            W[n] = norm == 0 ? 1.0 / 3.0 : (norm == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+                            if (q == 27) {
+                                const double w1[2] = {2.0 / 3.0, 1.0 / 6.0};
+                                W[n] = w1[a * a] * w1[b * b] * w1[c * c];
+                            } else {
+                                W[n] = norm == 0 ? 1.0 / 3.0 : (norm == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+                            }
                             ++n;
                         }
         for (int i = 0; i < Q; ++i)
             for (int j = 0; j < Q; ++j)
                 if (E[j][0] == -E[i][0] && E[j][1] == -E[i][1] && E[j][2] == -E[i][2]) OPP[i] = j;
+        // Third-order content (reading A32).  No H_aaa survives on either lattice.
+        // D3Q19: H_xyz vanishes at every velocity; the six xxy-type polynomials remain but
+        // are neither orthogonal nor of their continuous norm 2 c_s^6, so the basis is the
+        // six combinations h_{c,s} = H_aab + s H_bcc (s = +1, -1) for (a, b, c) = (x, y, z),
+        // (z, x, y), (y, z, x) -- H_xxy -+ H_yzz, H_zzx -+ H_xyy, H_yyz -+ H_zxx -- mutually
+        // orthogonal on D3Q19 with lattice norms 2 c_s^6 (s = +1) and 6 c_s^6 (s = -1).
+        // D3Q27: the six H_aab and H_xyz themselves, orthogonal with their continuous norms
+        // 2 c_s^6 and c_s^6 (products of one-dimensional Hermite polynomials).
+        const int HC[3][3] = {{0, 1, 2}, {2, 0, 1}, {1, 2, 0}};
+        nb3 = 0;
+        if (q == 19) {
+            for (int c = 0; c < 3; ++c)
+                for (int sg = 1; sg >= -1; sg -= 2) {
+                    const int a = HC[c][0], b = HC[c][1], d = HC[c][2];
+                    b3[nb3].nterms = 2;
+                    b3[nb3].t[0] = {1.0, a, a, b};
+                    b3[nb3].t[1] = {(double)sg, b, d, d};
+                    ++nb3;
+                }
+        } else {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    if (a != b) {
+                        b3[nb3].nterms = 1;
+                        b3[nb3].t[0] = {1.0, a, a, b};
+                        ++nb3;
+                    }
+            b3[nb3].nterms = 1;
+            b3[nb3].t[0] = {1.0, 0, 1, 2};
+            ++nb3;
+        }
+        for (int m = 0; m < nb3; ++m) {
+            double s = 0.0;
+            for (int i = 0; i < Q; ++i) s += W[i] * h3(i, m) * h3(i, m);
+            norm3[m] = s;
+        }
     }
-} lattice_init_instance;
-
-inline double ec(int i, int a) { return (double)E[i][a]; }
-inline double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
-
-// Hermite polynomials of orders 1..3 (Sec. 3.1), indices over x, y, z.
-inline double H1(int i, int a) { return ec(i, a); }
-inline double H2(int i, int a, int b) { return ec(i, a) * ec(i, b) - CS2 * kd(a, b); }
-inline double H3(int i, int a, int b, int c) {
-    return ec(i, a) * ec(i, b) * ec(i, c) -
-           CS2 * (ec(i, a) * kd(b, c) + ec(i, b) * kd(a, c) + ec(i, c) * kd(a, b));
-}
-
-// Third-order content on D3Q19 (reading A32).  The xxx- and xyz-type Hermite
-// polynomials vanish at every D3Q19 velocity; the six xxy-type ones remain but are
-// neither orthogonal nor of their continuous norm 2 c_s^6 on this lattice.  They are
-// handled through the six combinations h_{c,s} = H_aab + s H_bcc (s = +1, -1) for
-// (a, b, c) = (x, y, z), (z, x, y), (y, z, x) -- H_xxy -+ H_yzz, H_zzx -+ H_xyy,
-// H_yyz -+ H_zxx -- which are mutually orthogonal on D3Q19 with lattice norms
-// sum_i w_i h^2 = 2 c_s^6 (s = +1) and 6 c_s^6 (s = -1) (checked by the tests).
-const int HC[3][3] = {{0, 1, 2}, {2, 0, 1}, {1, 2, 0}};
-inline double hc(int i, int c, int sgn) {
-    const int a = HC[c][0], b = HC[c][1], d = HC[c][2];
-    return H3(i, a, a, b) + sgn * H3(i, b, d, d);
-}
-inline double hnorm(int sgn) { return (sgn > 0 ? 2.0 : 6.0) * CS2 * CS2 * CS2; }
-// The matching continuous third-order moments of the equilibrium per unit density:
-// u_a^2 u_b -+ u_b u_c^2.
-inline double uc3(const double u[3], int c, int sgn) {
-    const int a = HC[c][0], b = HC[c][1], d = HC[c][2];
-    return u[a] * u[a] * u[b] + sgn * u[b] * u[d] * u[d];
-}
+};
+const Lattice LAT19(19), LAT27(27);
 
 // Hydrodynamic equilibrium, Hermite expansion to third order (Sec. 3.1); the third
-// order expanded in the h_{c,s} with their lattice norms, so that the lattice
-// equilibrium has the continuous third-order moments along every direction the
+// order expanded in the lattice's third-order basis with its lattice norms, so that the
+// lattice equilibrium has the continuous third-order moments along every direction the
 // lattice resolves.
-double feq(int i, double rho, const double u[3]) {
+double feq(const Lattice& L, int i, double rho, const double u[3]) {
     double s = 1.0;
-    for (int a = 0; a < 3; ++a) s += H1(i, a) / CS2 * u[a];
+    for (int a = 0; a < 3; ++a) s += L.H1(i, a) / CS2 * u[a];
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) s += H2(i, a, b) / (2.0 * CS2 * CS2) * u[a] * u[b];
-    for (int c = 0; c < 3; ++c)
-        for (int sg = -1; sg <= 1; sg += 2) s += hc(i, c, sg) / hnorm(sg) * uc3(u, c, sg);
-    return W[i] * rho * s;
+        for (int b = 0; b < 3; ++b) s += L.H2(i, a, b) / (2.0 * CS2 * CS2) * u[a] * u[b];
+    for (int m = 0; m < L.nb3; ++m) s += L.h3(i, m) / L.norm3[m] * L.u3(u, m);
+    return L.W[i] * rho * s;
 }
 
 // Convection-diffusion equilibrium, second-order Hermite expansion (Sec. 3.2).
-double geq(int i, double phi, const double u[3]) {
+double geq(const Lattice& L, int i, double phi, const double u[3]) {
     double s = 1.0;
-    for (int a = 0; a < 3; ++a) s += H1(i, a) / CS2 * u[a];
+    for (int a = 0; a < 3; ++a) s += L.H1(i, a) / CS2 * u[a];
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) s += H2(i, a, b) / (2.0 * CS2 * CS2) * u[a] * u[b];
-    return W[i] * phi * s;
+        for (int b = 0; b < 3; ++b) s += L.H2(i, a, b) / (2.0 * CS2 * CS2) * u[a] * u[b];
+    return L.W[i] * phi * s;
 }
 
 struct Params {
@@ -135,81 +185,82 @@ struct Params {
 };
 
 // Hydrodynamic TRT regularized collision (Sec. 3.1, three-dimensional indices).
-void collide_hydro(const double f[Q], double rho, const double u[3], const double F[3],
-                   const double tau[3][3], const double D[3], const Params& p, double out[Q]) {
-    double fe[Q];
-    for (int i = 0; i < Q; ++i) fe[i] = feq(i, rho, u);
-    double A0 = 0.0, A1[3] = {0.0, 0.0, 0.0}, A2[3][3], A3[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+void collide_hydro(const Lattice& L, const double* f, double rho, const double u[3],
+                   const double F[3], const double tau[3][3], const double D[3], const Params& p,
+                   double* out) {
+    const int Q = L.Q;
+    double fe[QMAX];
+    for (int i = 0; i < Q; ++i) fe[i] = feq(L, i, rho, u);
+    double A0 = 0.0, A1[3] = {0.0, 0.0, 0.0}, A2[3][3], A3[NB3MAX];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) A2[a][b] = 0.0;
+    for (int m = 0; m < L.nb3; ++m) A3[m] = 0.0;
     for (int i = 0; i < Q; ++i) {
         const double d = f[i] - fe[i];
         A0 += d;
-        for (int a = 0; a < 3; ++a) A1[a] += H1(i, a) * d;
+        for (int a = 0; a < 3; ++a) A1[a] += L.H1(i, a) * d;
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) A2[a][b] += H2(i, a, b) * d;
-        for (int c = 0; c < 3; ++c) {
-            A3[c][0] += hc(i, c, -1) * d;
-            A3[c][1] += hc(i, c, +1) * d;
-        }
+            for (int b = 0; b < 3; ++b) A2[a][b] += L.H2(i, a, b) * d;
+        for (int m = 0; m < L.nb3; ++m) A3[m] += L.h3(i, m) * d;
     }
     const double c1 = 1.0 - 1.0 / p.tau_s1, c2 = 1.0 - 1.0 / p.tau_s2;
     const double h1 = 1.0 - 1.0 / (2.0 * p.tau_s1);
     for (int i = 0; i < Q; ++i) {
         double reg1 = A0;
-        for (int a = 0; a < 3; ++a) reg1 += H1(i, a) / CS2 * A1[a];
+        for (int a = 0; a < 3; ++a) reg1 += L.H1(i, a) / CS2 * A1[a];
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) reg1 += H2(i, a, b) / (2.0 * CS2 * CS2) * A2[a][b];
-        double reg2 = 0.0;  // projection on the h_{c,s} with their lattice norms
-        for (int c = 0; c < 3; ++c)
-            reg2 += hc(i, c, -1) / hnorm(-1) * A3[c][0] + hc(i, c, +1) / hnorm(+1) * A3[c][1];
+            for (int b = 0; b < 3; ++b) reg1 += L.H2(i, a, b) / (2.0 * CS2 * CS2) * A2[a][b];
+        double reg2 = 0.0;  // projection on the third-order basis with its lattice norms
+        for (int m = 0; m < L.nb3; ++m) reg2 += L.h3(i, m) / L.norm3[m] * A3[m];
         // G_i: d_g Phi_abg restricted to the diagonal defects (a, a) <- d_a(rho u_a^3)
         double sumG = 0.0, sumT = 0.0, sumF = 0.0;
-        for (int a = 0; a < 3; ++a) sumG += H2(i, a, a) / (6.0 * CS2 * CS2 * CS2) * D[a];
+        for (int a = 0; a < 3; ++a) sumG += L.H2(i, a, a) / (6.0 * CS2 * CS2 * CS2) * D[a];
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) sumT += H2(i, a, b) / (2.0 * CS2 * CS2) * tau[a][b];
-        for (int a = 0; a < 3; ++a) sumF += H1(i, a) / CS2 * F[a];
-        const double Gi = -W[i] * h1 * sumG;
-        const double Ti = -W[i] * sumT / p.tau_s1;
-        const double Fi = h1 * W[i] * sumF;
-        out[i] = fe[i] + W[i] * c1 * reg1 + W[i] * c2 * reg2 + Gi + Fi + Ti;
+            for (int b = 0; b < 3; ++b) sumT += L.H2(i, a, b) / (2.0 * CS2 * CS2) * tau[a][b];
+        for (int a = 0; a < 3; ++a) sumF += L.H1(i, a) / CS2 * F[a];
+        const double Gi = -L.W[i] * h1 * sumG;
+        const double Ti = -L.W[i] * sumT / p.tau_s1;
+        const double Fi = h1 * L.W[i] * sumF;
+        out[i] = fe[i] + L.W[i] * c1 * reg1 + L.W[i] * c2 * reg2 + Gi + Fi + Ti;
     }
 }
 
 // Convection-diffusion TRT regularized collision for one component (Sec. 3.2).
-void collide_cde(const double g[Q], double phi, double rho, const double u[3],
+void collide_cde(const Lattice& L, const double* g, double phi, double rho, const double u[3],
                  const double F[3], double S, double Sp, const double up[3], const Params& p,
-                 double out[Q]) {
-    double ge[Q];
-    for (int i = 0; i < Q; ++i) ge[i] = geq(i, phi, u);
+                 double* out) {
+    const int Q = L.Q;
+    double ge[QMAX];
+    for (int i = 0; i < Q; ++i) ge[i] = geq(L, i, phi, u);
     double B0 = 0.0, B1[3] = {0.0, 0.0, 0.0}, B2[3][3];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) B2[a][b] = 0.0;
     for (int i = 0; i < Q; ++i) {
         const double d = g[i] - ge[i];
         B0 += d;
-        for (int a = 0; a < 3; ++a) B1[a] += H1(i, a) * d;
+        for (int a = 0; a < 3; ++a) B1[a] += L.H1(i, a) * d;
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) B2[a][b] += H2(i, a, b) * d;
+            for (int b = 0; b < 3; ++b) B2[a][b] += L.H2(i, a, b) * d;
     }
     const double c1 = 1.0 - 1.0 / p.tau_p1, c2 = 1.0 - 1.0 / p.tau_p2;
     const double h2 = 1.0 - 1.0 / (2.0 * p.tau_p1);
     for (int i = 0; i < Q; ++i) {
         double reg1 = B0;
-        for (int a = 0; a < 3; ++a) reg1 += H1(i, a) / CS2 * B1[a];
+        for (int a = 0; a < 3; ++a) reg1 += L.H1(i, a) / CS2 * B1[a];
         double reg2 = 0.0;
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) reg2 += H2(i, a, b) / (2.0 * CS2 * CS2) * B2[a][b];
+            for (int b = 0; b < 3; ++b) reg2 += L.H2(i, a, b) / (2.0 * CS2 * CS2) * B2[a][b];
         double eF = 0.0, eu = 0.0, eup = 0.0;
         for (int a = 0; a < 3; ++a) {
-            eF += ec(i, a) / CS2 * F[a];
-            eu += ec(i, a) / CS2 * u[a];
-            eup += ec(i, a) / CS2 * up[a];
+            eF += L.ec(i, a) / CS2 * F[a];
+            eu += L.ec(i, a) / CS2 * u[a];
+            eup += L.ec(i, a) / CS2 * up[a];
         }
-        const double Gt = W[i] * h2 * eF * phi / rho;
-        const double Ft_now = W[i] * S + h2 * W[i] * eu * S;
-        const double Ft_prev = W[i] * Sp + h2 * W[i] * eup * Sp;
-        out[i] = ge[i] + W[i] * c1 * reg1 + W[i] * c2 * reg2 + Gt + Ft_now +
+        const double W = L.W[i];
+        const double Gt = W * h2 * eF * phi / rho;
+        const double Ft_now = W * S + h2 * W * eu * S;
+        const double Ft_prev = W * Sp + h2 * W * eup * Sp;
+        out[i] = ge[i] + W * c1 * reg1 + W * c2 * reg2 + Gt + Ft_now +
                  0.5 * (Ft_now - Ft_prev);
     }
 }
@@ -234,15 +285,18 @@ double fd(bool lo_wall, double vlo, double v0, bool hi_wall, double vhi) {
 }
 
 struct Sim {
+    const Lattice& lat;
+    int Q;
     int nx, ny, nz, ywall;
     size_t N;
     Params p;
-    std::vector<double> f[Q], fp[Q], g[6][Q], gp[6][Q];
+    std::vector<double> f[QMAX], fp[QMAX], g[6][QMAX], gp[6][QMAX];
     std::vector<double> rho, u[3], A[6], Sprev[6], uprev[3];
     bool first = true;
     long long step = 0;
 
-    Sim(int nx_, int ny_, int nz_, int ywall_) : nx(nx_), ny(ny_), nz(nz_), ywall(ywall_) {
+    Sim(const Lattice& lat_, int nx_, int ny_, int nz_, int ywall_)
+        : lat(lat_), Q(lat_.Q), nx(nx_), ny(ny_), nz(nz_), ywall(ywall_) {
         N = (size_t)nx * ny * nz;
         for (int i = 0; i < Q; ++i) {
             f[i].assign(N, 0.0);
@@ -266,7 +320,7 @@ struct Sim {
     static int wrap(int v, int n) { return ((v % n) + n) % n; }
     // Source node of the pull x - e_i: false when it lies beyond a wall.
     bool source(int x, int y, int z, int i, size_t* s) const {
-        int xs = wrap(x - E[i][0], nx), ys = y - E[i][1], zs = wrap(z - E[i][2], nz);
+        int xs = wrap(x - lat.E[i][0], nx), ys = y - lat.E[i][1], zs = wrap(z - lat.E[i][2], nz);
         if (ys < 0 || ys >= ny) {
             if (ywall) return false;
             ys = wrap(ys, ny);
@@ -280,7 +334,7 @@ struct Sim {
             double r = 0.0, j[3] = {0.0, 0.0, 0.0};
             for (int i = 0; i < Q; ++i) {
                 r += f[i][n];
-                for (int a = 0; a < 3; ++a) j[a] += ec(i, a) * f[i][n];
+                for (int a = 0; a < 3; ++a) j[a] += lat.ec(i, a) * f[i][n];
             }
             rho[n] = r;
             for (int a = 0; a < 3; ++a) u[a][n] = (j[a] + 0.5 * p.F[a]) / r;
@@ -297,10 +351,10 @@ struct Sim {
             const double r = r0 ? r0[n] : 1.0;
             double v[3];
             for (int a = 0; a < 3; ++a) v[a] = u0[a] ? u0[a][n] : 0.0;
-            for (int i = 0; i < Q; ++i) f[i][n] = feq(i, r, v);
+            for (int i = 0; i < Q; ++i) f[i][n] = feq(lat, i, r, v);
             for (int k = 0; k < 6; ++k) {
                 const double phi = a0[k] ? a0[k][n] : (KA[k] == KB[k] ? 1.0 : 0.0);
-                for (int i = 0; i < Q; ++i) g[k][i][n] = geq(i, phi, v);
+                for (int i = 0; i < Q; ++i) g[k][i][n] = geq(lat, i, phi, v);
             }
         }
         first = true;
@@ -347,19 +401,19 @@ struct Sim {
             double tau[3][3];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) tau[a][b] = p.eta_p / p.lam * (Am[a][b] - kd(a, b));
-            double fl[Q], out[Q];
+            double fl[QMAX], out[QMAX];
             for (int i = 0; i < Q; ++i) fl[i] = f[i][n];
             const double uu[3] = {u[0][n], u[1][n], u[2][n]};
-            collide_hydro(fl, rho[n], uu, p.F, tau, D, p, out);
+            collide_hydro(lat, fl, rho[n], uu, p.F, tau, D, p, out);
             for (int i = 0; i < Q; ++i) fp[i][n] = out[i];
             const double upv[3] = {first ? uu[0] : uprev[0][n], first ? uu[1] : uprev[1][n],
                                    first ? uu[2] : uprev[2][n]};
             for (int k = 0; k < 6; ++k) {
-                double gl[Q], go[Q];
+                double gl[QMAX], go[QMAX];
                 for (int i = 0; i < Q; ++i) gl[i] = g[k][i][n];
                 const double Sk = S[KA[k]][KB[k]];
                 const double Spk = first ? Sk : Sprev[k][n];
-                collide_cde(gl, A[k][n], rho[n], uu, p.F, Sk, Spk, upv, p, go);
+                collide_cde(lat, gl, A[k][n], rho[n], uu, p.F, Sk, Spk, upv, p, go);
                 for (int i = 0; i < Q; ++i) gp[k][i][n] = go[i];
                 Snew[k][n] = Sk;
             }
@@ -375,8 +429,8 @@ struct Sim {
                     f[i][n] = fp[i][s];
                     for (int k = 0; k < 6; ++k) g[k][i][n] = gp[k][i][s];
                 } else {
-                    f[i][n] = fp[OPP[i]][n];
-                    for (int k = 0; k < 6; ++k) g[k][i][n] = gp[k][OPP[i]][n];
+                    f[i][n] = fp[lat.OPP[i]][n];
+                    for (int k = 0; k < 6; ++k) g[k][i][n] = gp[k][lat.OPP[i]][n];
                 }
             }
         }
@@ -391,7 +445,7 @@ struct Sim {
                 const size_t n = (size_t)nn;
                 const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
                 if (y != 0 && y != ny - 1) continue;
-                bool unknown[Q];
+                bool unknown[QMAX];
                 for (int i = 0; i < Q; ++i) {
                     size_t s;
                     unknown[i] = !source(x, y, z, i, &s);
@@ -399,29 +453,29 @@ struct Sim {
                 double r = 0.0, j[3] = {0.0, 0.0, 0.0};
                 for (int i = 0; i < Q; ++i) {
                     r += f[i][n];
-                    for (int a = 0; a < 3; ++a) j[a] += ec(i, a) * f[i][n];
+                    for (int a = 0; a < 3; ++a) j[a] += lat.ec(i, a) * f[i][n];
                 }
                 double ub[3];
                 for (int a = 0; a < 3; ++a) ub[a] = (j[a] + 0.5 * p.F[a]) / r;
                 for (int k = 0; k < 6; ++k) {
-                    double gabs[Q], phib = 0.0;
+                    double gabs[QMAX], phib = 0.0;
                     for (int i = 0; i < Q; ++i) {
                         gabs[i] = g[k][i][n];
                         phib += gabs[i];
                     }
-                    double known[Q];
+                    double known[QMAX];
                     for (int i = 0; i < Q; ++i) known[i] = gabs[i];
                     for (int i = 0; i < Q; ++i) {
                         if (!unknown[i]) continue;
-                        const int o = OPP[i];
-                        gabs[i] = geq(i, phib, ub);
-                        if (!unknown[o]) gabs[i] += known[o] - geq(o, phib, ub);
+                        const int o = lat.OPP[i];
+                        gabs[i] = geq(lat, i, phib, ub);
+                        if (!unknown[o]) gabs[i] += known[o] - geq(lat, o, phib, ub);
                     }
                     double rest = phib;
                     for (int i = 0; i < Q; ++i)
-                        if (E[i][0] != 0 || E[i][1] != 0 || E[i][2] != 0) rest -= gabs[i];
+                        if (!lat.rest(i)) rest -= gabs[i];
                     for (int i = 0; i < Q; ++i)
-                        if (E[i][0] == 0 && E[i][1] == 0 && E[i][2] == 0) gabs[i] = rest;
+                        if (lat.rest(i)) gabs[i] = rest;
                     for (int i = 0; i < Q; ++i) g[k][i][n] = gabs[i];
                 }
             }
@@ -439,9 +493,10 @@ struct Sim {
 
 extern "C" {
 
-void* o3_create(int nx, int ny, int nz, int ywall) {
-    if (nx < 1 || ny < 1 || nz < 1 || (ywall && ny < 3)) return nullptr;
-    return new Sim(nx, ny, nz, ywall ? 1 : 0);
+// q: 19 (D3Q19) or 27 (D3Q27).
+void* o3_create(int nx, int ny, int nz, int ywall, int q) {
+    if (nx < 1 || ny < 1 || nz < 1 || (ywall && ny < 3) || (q != 19 && q != 27)) return nullptr;
+    return new Sim(q == 27 ? LAT27 : LAT19, nx, ny, nz, ywall ? 1 : 0);
 }
 void o3_destroy(void* h) { delete static_cast<Sim*>(h); }
 
@@ -490,18 +545,20 @@ void o3_read(void* h, double* rho, double* ux, double* uy, double* uz, double* a
     }
 }
 
-// Lattice tables and the third-order combinations h_{c,+}, h_{c,-} at every velocity
-// (19 x 6).
-void o3_lattice(int* e, double* w, int* opp, double* h3) {
-    for (int i = 0; i < Q; ++i) {
-        for (int a = 0; a < 3; ++a) e[3 * i + a] = E[i][a];
-        w[i] = W[i];
-        opp[i] = OPP[i];
-        for (int c = 0; c < 3; ++c) {
-            h3[6 * i + 2 * c] = hc(i, c, +1);
-            h3[6 * i + 2 * c + 1] = hc(i, c, -1);
-        }
+// Lattice tables of D3Q19 or D3Q27 (q) and the third-order basis at every velocity
+// (q x nb3, nb3 returned: 6 on D3Q19 -- h_{c,+}, h_{c,-} for c = 0, 1, 2 --, 7 on D3Q27 --
+// H_xxy, H_xxz, H_yyx, H_yyz, H_zzx, H_zzy, H_xyz).  Arrays sized for 27 velocities and
+// 7 basis functions.  Returns -1 for another q.
+int o3_lattice(int q, int* e, double* w, int* opp, double* h3) {
+    if (q != 19 && q != 27) return -1;
+    const Lattice& L = q == 27 ? LAT27 : LAT19;
+    for (int i = 0; i < L.Q; ++i) {
+        for (int a = 0; a < 3; ++a) e[3 * i + a] = L.E[i][a];
+        w[i] = L.W[i];
+        opp[i] = L.OPP[i];
+        for (int m = 0; m < L.nb3; ++m) h3[L.nb3 * i + m] = L.h3(i, m);
     }
+    return L.nb3;
 }
 
 }  // extern "C"

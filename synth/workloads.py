@@ -378,6 +378,7 @@ class Problem3D:
     steps: int = 0
     precision: str = "fp32"
     meta: dict = field(default_factory=dict)
+    q: int = 19  # lattice: 19 (D3Q19) or 27 (D3Q27)
 
     @property
     def nodes(self) -> int:
@@ -402,7 +403,7 @@ class Problem3D:
 
 def random3d(nx, ny, nz, seed, ymode="periodic", amp_u=0.02, amp_rho=0.01, amp_a=0.2,
              nu_s=0.1, eta_p=0.07, lam=40.0, kappa=0.02, Lambda_s=0.25, Lambda_p=0.05,
-             F=(1e-5, -2e-5, 1.5e-5), precision="fp64") -> Problem3D:
+             F=(1e-5, -2e-5, 1.5e-5), precision="fp64", q=19) -> Problem3D:
     """Seeded random state: density, velocity and a symmetric positive-definite
     conformation (A = R diag(l) R^T with a random rotation R and eigenvalues l drawn near
     1) node by node from default_rng(seed)."""
@@ -417,13 +418,13 @@ def random3d(nx, ny, nz, seed, ymode="periodic", amp_u=0.02, amp_rho=0.01, amp_a
     init = dict(rho=rho, ux=u[0], uy=u[1], uz=u[2], axx=A[..., 0, 0], axy=A[..., 0, 1],
                 axz=A[..., 0, 2], ayy=A[..., 1, 1], ayz=A[..., 1, 2], azz=A[..., 2, 2])
     init = {k: np.ascontiguousarray(v) for k, v in init.items()}
-    return Problem3D(name=f"random3d_{nx}x{ny}x{nz}_s{seed}", nx=nx, ny=ny, nz=nz, ymode=ymode,
+    return Problem3D(name=f"random3d_q{q}_{nx}x{ny}x{nz}_s{seed}", nx=nx, ny=ny, nz=nz, ymode=ymode,
                      nu_s=nu_s, eta_p=eta_p, lam=lam, kappa=kappa, Lambda_s=Lambda_s,
-                     Lambda_p=Lambda_p, F=tuple(F), init=init, precision=precision)
+                     Lambda_p=Lambda_p, F=tuple(F), init=init, precision=precision, q=q)
 
 
 def channel3d(nx=4, ny=32, nz=4, Re=1.0, Wi=1.0, beta=0.5, Ma=0.1, Sc=1e6, Lambda_s=0.25,
-              Lambda_p=1e-6, axis="x", steps=10000, precision="fp64") -> Problem3D:
+              Lambda_p=1e-6, axis="x", steps=10000, precision="fp64", q=19) -> Problem3D:
     """Force-driven plane Poiseuille flow between half-way walls normal to y (the
     channel of Sec. 4.2 with a third, periodic direction), driven along x or z:
     H = L_c = ny, F = 8 (nu_s + nu_p) U_c / L_c^2, start from rest with A = I."""
@@ -431,9 +432,9 @@ def channel3d(nx=4, ny=32, nz=4, Re=1.0, Wi=1.0, beta=0.5, Ma=0.1, Sc=1e6, Lambd
     p = lattice_units(Re, Wi, beta, Sc, Ma, Lc)
     Fm = 8.0 * p["nu0"] * p["Uc"] / (Lc * Lc)
     F = (Fm, 0.0, 0.0) if axis == "x" else (0.0, 0.0, Fm)
-    return Problem3D(name=f"channel3d_{nx}x{ny}x{nz}_{axis}_Wi{Wi:g}", nx=nx, ny=ny, nz=nz,
+    return Problem3D(name=f"channel3d_q{q}_{nx}x{ny}x{nz}_{axis}_Wi{Wi:g}", nx=nx, ny=ny, nz=nz,
                      ymode="wall", nu_s=p["nu_s"], eta_p=p["eta_p"], lam=p["lam"],
                      kappa=p["kappa"], Lambda_s=Lambda_s, Lambda_p=Lambda_p, F=F, steps=steps,
-                     precision=precision,
+                     precision=precision, q=q,
                      meta=dict(Re=Re, Wi=Wi, beta=beta, Sc=Sc, Ma=Ma, Uc=p["Uc"], Lc=Lc, H=Lc,
                                Tc=Lc / p["Uc"]))

@@ -1,4 +1,4 @@
-"""Pins of the three-dimensional (D3Q19) oracle (test infrastructure) against facts that
+"""Pins of the three-dimensional (D3Q19 and D3Q27) oracle (test infrastructure) against facts that
 do not come from the oracle itself: lattice quadrature identities, the moments its
 equilibria must carry, the closed-form steady channel of Sec. 4.2 driven along x and
 along z, the viscous decay of a shear wave along z, exact conservation and the rest
@@ -50,8 +50,42 @@ def test_d3q19_quadrature_and_third_order_basis(o3):
     assert np.abs(np.einsum("i,ip,iq->pq", w, h3, low)).max() < 1e-15
 
 
-def _channel(o3, ny, axis):
-    pr = synth.channel3d(ny=ny, axis=axis, Ma=0.1)
+def test_d3q27_quadrature_and_third_order_basis(o3):
+    """D3Q27 is the tensor product of D1Q3: weights 8/27, 2/27, 1/54, 1/216 (1, 6, 12 and
+    8 velocities), isotropy to fourth order, opposites; H_aaa vanishes at every velocity;
+    the seven third-order polynomials H_aab (a != b) and H_xyz are orthogonal to each
+    other and to orders 0-2 with their continuous norms 2 c_s^6 and c_s^6."""
+    e, w, opp, h3 = o3.lattice3d(27)
+    assert e.shape == (27, 3) and h3.shape == (27, 7)
+    assert abs(w.sum() - 1) < 1e-15
+    assert sorted(np.round(w * 216).astype(int).tolist()) == [1] * 8 + [4] * 12 + [16] * 6 + [64]
+    n2 = (e * e).sum(1)
+    for k, wk in ((0, 8 / 27), (1, 2 / 27), (2, 1 / 54), (3, 1 / 216)):
+        assert np.allclose(w[n2 == k], wk, rtol=0, atol=1e-16)
+    d = np.eye(3)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, e, e), CS2 * d, atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    iso = CS2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                      + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(m4, iso, atol=1e-15)
+    assert np.array_equal(e[opp], -e)
+
+    def H3(a, b, c):
+        return (e[:, a] * e[:, b] * e[:, c]
+                - CS2 * (e[:, a] * d[b, c] + e[:, b] * d[a, c] + e[:, c] * d[a, b]))
+    for a in range(3):
+        assert np.abs(H3(a, a, a)).max() < 1e-15
+    ref = np.stack([H3(0, 0, 1), H3(0, 0, 2), H3(1, 1, 0), H3(1, 1, 2), H3(2, 2, 0),
+                    H3(2, 2, 1), H3(0, 1, 2)], axis=1)
+    assert np.allclose(h3, ref, atol=1e-15)
+    G = np.einsum("i,ip,iq->pq", w, h3, h3)
+    assert np.allclose(G, np.diag([2, 2, 2, 2, 2, 2, 1]) * CS2 ** 3, atol=1e-15)
+    low = np.column_stack([np.ones(27), e, np.einsum("ia,ib->iab", e, e).reshape(27, 9)])
+    assert np.abs(np.einsum("i,ip,iq->pq", w, h3, low)).max() < 1e-15
+
+
+def _channel(o3, ny, axis, q):
+    pr = synth.channel3d(ny=ny, axis=axis, Ma=0.1, q=q)
     o = o3.OracleSim3D(pr)
     o.step(int(round(30 * pr.meta["Tc"])))
     return pr, o.read()
@@ -61,7 +95,8 @@ def _gre(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
 
 
-def test_channel_closed_form_along_x_and_z(o3):
+@pytest.mark.parametrize("q", [19, 27])
+def test_channel_closed_form_along_x_and_z(o3, q):
     """Force-driven Oldroyd-B channel between half-way walls normal to y (Wi = 1,
     beta = 0.5, Sc = 1e6; 30 T_c): the closed form u = 4 U y (H - y) / H^2,
     A_xy = lambda u', A_xx = 1 + 2 (lambda u')^2, every other component at rest, at
@@ -71,7 +106,7 @@ def test_channel_closed_form_along_x_and_z(o3):
     for ny in (16, 32):
         res = {}
         for axis in ("x", "z"):
-            pr, r = _channel(o3, ny, axis)
+            pr, r = _channel(o3, ny, axis, q)
             res[axis] = r
         rx, rz = res["x"], res["z"]
         for a, b in (("ux", "uz"), ("uz", "ux"), ("uy", "uy"), ("axy", "ayz"), ("axx", "azz"),
@@ -93,8 +128,8 @@ def test_channel_closed_form_along_x_and_z(o3):
     assert all(a / b > 2.3 for a, b in zip(err[16], err[32])), err
 
 
-def _wave(o3, eta, N=32, nu=0.05, lam=1.0, U=1e-4, steps=400):
-    pr = synth.Problem3D(name="wave_z", nx=4, ny=4, nz=N, ymode="periodic", nu_s=nu,
+def _wave(o3, eta, q, N=32, nu=0.05, lam=1.0, U=1e-4, steps=400):
+    pr = synth.Problem3D(name="wave_z", nx=4, ny=4, nz=N, ymode="periodic", nu_s=nu, q=q,
                          eta_p=eta, lam=lam, kappa=0.05, Lambda_s=0.25, Lambda_p=0.25)
     z = np.indices((N, 4, 4))[0].astype(float)
     k = 2 * np.pi / N
@@ -108,22 +143,24 @@ def _wave(o3, eta, N=32, nu=0.05, lam=1.0, U=1e-4, steps=400):
     return np.log(amp[0] / amp[1]) / steps / k ** 2
 
 
-def test_shear_wave_along_z_decays_viscously(o3):
+@pytest.mark.parametrize("q", [19, 27])
+def test_shear_wave_along_z_decays_viscously(o3, q):
     """u_x = U sin(k z) decays at nu k^2: with the solvent alone nu = nu_s (0.3 % at
     N = 32), and with a polymer that relaxes fast against the decay (lambda = 1 step,
     decay time 260 steps) at nu_s + eta_p (0.7 %): the z components of the velocity
     gradient, the source and the polymer stress all take part."""
-    nu0 = _wave(o3, 0.0)
+    nu0 = _wave(o3, 0.0, q)
     assert abs(nu0 / 0.05 - 1) < 5e-3, nu0
-    nu1 = _wave(o3, 0.05)
+    nu1 = _wave(o3, 0.05, q)
     assert abs(nu1 / 0.10 - 1) < 1.5e-2, nu1
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("ymode", ["periodic", "wall"])
-def test_mass_and_conformation_budget_exact(o3, ymode):
+def test_mass_and_conformation_budget_exact(o3, ymode, q):
     """Total mass exact (periodic streaming, half-way walls); with the constitutive source
     off every conformation component's total is exact too (CNEBB at the walls, Sec. 3.3)."""
-    pr = synth.random3d(10, 8, 6, seed=4, ymode=ymode)
+    pr = synth.random3d(10, 8, 6, seed=4, ymode=ymode, q=q)
     o = o3.OracleSim3D(pr, no_source=True)
     r0 = o.read()
     o.step(30)
@@ -133,9 +170,10 @@ def test_mass_and_conformation_budget_exact(o3, ymode):
         assert abs(r1[c].sum() - r0[c].sum()) < 1e-12 * np.abs(r0[c]).sum(), c
 
 
-def test_rest_state_is_exact(o3):
+@pytest.mark.parametrize("q", [19, 27])
+def test_rest_state_is_exact(o3, q):
     """rho = 1, u = 0, A = I, no force: every step leaves it unchanged (walls included)."""
-    pr = synth.Problem3D(name="rest", nx=6, ny=7, nz=5, ymode="wall", nu_s=0.1, eta_p=0.1,
+    pr = synth.Problem3D(name="rest", nx=6, ny=7, nz=5, ymode="wall", nu_s=0.1, eta_p=0.1, q=q,
                          lam=50.0, kappa=1e-3)
     o = o3.OracleSim3D(pr)
     o.step(40)
