@@ -383,19 +383,19 @@ def cpu_baseline(pr, seconds):
             "value_1_core": v1}
 
 
-def d3_leg(steps, warmup, cpu_steps=0):
-    """Three-dimensional (D3Q19) form: force-driven Oldroyd-B channel 256 x 64 x 256
-    (4.2 M nodes, half-way walls normal to y), FP32 storage.  Algorithmic bytes per node
-    and step: 133 populations read and written (7 lattices x 19 directions) and the
-    history of S (6) and u (3) read and written: 2 x 142 x 4 = 1,136 B; the rho/u planes
-    of the neighbour differences (16 B written, 16 B read) and the 76 B of hydrodynamic
-    pulls of the rho/u launch are reported beside it.  HIP events on the simulation's
-    stream bracket both launches of every step."""
+def d3_leg(steps, warmup, cpu_steps=0, q=19):
+    """Three-dimensional form on D3Q19 (q = 19) or D3Q27 (q = 27): force-driven Oldroyd-B
+    channel 256 x 64 x 256 (4.2 M nodes, half-way walls normal to y), FP32 storage.
+    Algorithmic bytes per node and step: 7 q populations read and written (7 lattices)
+    and the history of S (6) and u (3) read and written: 2 x (7 q + 9) x 4 = 1,136 B on
+    D3Q19, 1,584 B on D3Q27; the rho/u planes of the neighbour differences (16 B written,
+    16 B read) and the 4 q B of hydrodynamic pulls of the rho/u launch are reported beside
+    it.  HIP events on the simulation's stream bracket both launches of every step."""
     import torch
     import synth
     from paper_2508_16997_amd.sim3d import Simulation3D
 
-    pr = synth.channel3d(nx=256, ny=64, nz=256, Ma=0.1, precision="fp32")
+    pr = synth.channel3d(nx=256, ny=64, nz=256, Ma=0.1, precision="fp32", q=q)
     stream = torch.cuda.Stream()
     sim = Simulation3D.from_problem(pr, stream=stream)
     sim.step(warmup)
@@ -414,13 +414,13 @@ def d3_leg(steps, warmup, cpu_steps=0):
     finite = bool(torch.isfinite(r["ux"]).all())
     sim.close()
     nodes = pr.nx * pr.ny * pr.nz
-    bpn = 2 * (7 * 19 + 9) * 4
+    bpn = 2 * (7 * q + 9) * 4
     achieved = bpn * nodes / step_s / 1e9
-    out = {"workload": "D3Q19 Oldroyd-B channel 256x64x256, half-way walls in y, FP32 storage, "
+    out = {"workload": f"D3Q{q} Oldroyd-B channel 256x64x256, half-way walls in y, FP32 storage, "
                        "Wi=1, beta=0.5",
            "nodes": nodes, "steps": steps, "MLUPS": round(nodes * steps / wall / 1e6, 2),
            "us_per_step": round(step_s * 1e6, 3), "bytes_per_node": bpn,
-           "extra_bytes_per_node": {"rho_u_planes": 32, "rho_u_launch_pulls": 76},
+           "extra_bytes_per_node": {"rho_u_planes": 32, "rho_u_launch_pulls": 4 * q},
            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
            "kernels": "k3_macro + k3_step", "finite": finite}
     if cpu_steps:
@@ -435,7 +435,7 @@ def d3_leg(steps, warmup, cpu_steps=0):
         out["cpu_baseline"] = {"value": round(nodes * cpu_steps / dt / 1e6, 3), "unit": "MLUPS",
                                "cores": os.cpu_count() or 1, "kind": "oracle",
                                "sample": f"{cpu_steps} coupled FP64 steps of the same "
-                                         f"256x64x256 channel, {dt:.1f} s"}
+                                         f"256x64x256 D3Q{q} channel, {dt:.1f} s"}
     return out
 
 
@@ -588,6 +588,7 @@ def main():
                                      args.graph_chunk)
     if not args.no_3d:
         out["d3q19"] = d3_leg(args.d3_steps, 20, 0 if args.no_cpu_baseline else args.cpu_3d_steps)
+        out["d3q27"] = d3_leg(args.d3_steps, 20, 0, q=27)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

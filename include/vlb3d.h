@@ -1,16 +1,17 @@
-/* vlb3d.h -- C ABI of the three-dimensional (D3Q19) form of the coupled viscoelastic
- * lattice Boltzmann step (arXiv:2508.16997 extended to three dimensions, which the paper
- * calls straightforward in Sec. 3.1).
+/* vlb3d.h -- C ABI of the three-dimensional (D3Q19 or D3Q27) form of the coupled
+ * viscoelastic lattice Boltzmann step (arXiv:2508.16997 extended to three dimensions,
+ * which the paper calls straightforward in Sec. 3.1).
  *
  * One step is the two-dimensional method of Sec. 3.1-3.3 with every tensor index over
- * x, y, z: a hydrodynamic D3Q19 TRT regularized collision with the Galilean correction
- * G_i for the three diagonal cubic defects d_a(rho u_a^3), the body force F_i and the
- * polymer stress T_i; six convection-diffusion D3Q19 lattices (A_xx, A_xy, A_xz, A_yy,
- * A_yz, A_zz) with the auxiliary term, the constitutive source Phi = -(A - I)/lambda +
- * A L + (A L)^T + A tr L (Oldroyd-B, L = grad u by central differences) and half its time
+ * x, y, z: a hydrodynamic TRT regularized collision with the Galilean correction G_i
+ * for the three diagonal cubic defects d_a(rho u_a^3), the body force F_i and the
+ * polymer stress T_i; six convection-diffusion lattices (A_xx, A_xy, A_xz, A_yy, A_yz,
+ * A_zz) with the auxiliary term, the constitutive source Phi = -(A - I)/lambda + A L +
+ * (A L)^T + A tr L (Oldroyd-B, L = grad u by central differences) and half its time
  * difference; half-way bounce-back of f and CNEBB of the conformation lattices at flat
- * walls.  The third order of the hydrodynamic lattice is expanded and projected in the
- * six D3Q19-orthogonal combinations H_aab -+ H_bcc with their lattice norms.
+ * walls.  The third order of the hydrodynamic lattice is expanded and projected in an
+ * orthogonal basis with its lattice norms: on D3Q19 the six combinations H_aab -+ H_bcc,
+ * on D3Q27 the six H_aab and H_xyz.
  *
  * Geometry: x and z periodic; y periodic (VLB_PERIODIC) or bounded by half-way walls
  * half a spacing outside rows 0 and ny - 1 (VLB_WALL).  Uniform body force.  Fields are
@@ -35,12 +36,12 @@ extern "C" {
 
 typedef struct vlb3_sim vlb3_sim;
 
-/* Host object for an nx x ny x nz grid (each >= 1; ny >= 3 with VLB_WALL; nz <= 65535,
- * ny <= 262140; 133 (nx * ny * nz + 4224) below 2^31).  prec: VLB_FP32 or VLB_FP64;
- * ymode: VLB_PERIODIC or VLB_WALL.
+/* Host object for an nx x ny x nz grid on the lattice q (19: D3Q19, 27: D3Q27); each
+ * size >= 1, ny >= 3 with VLB_WALL, nz <= 65535, ny <= 262140, 7 q (nx * ny * nz + 4224)
+ * below 2^31.  prec: VLB_FP32 or VLB_FP64; ymode: VLB_PERIODIC or VLB_WALL.
  * Errors: VLB_E_INVALID_ARG. */
-int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out);
-/* Device workspace the simulation needs: two buffers of 133 population planes, 9
+int vlb3_create(int nx, int ny, int nz, int q, int prec, int ymode, vlb3_sim** out);
+/* Device workspace the simulation needs: two buffers of 7 q population planes, 9
  * history planes (S of the six components and u), 4 planes of rho and u (256-byte
  * aligned sections; each plane nx * ny * nz rounded up to 64 elements plus 4160 of
  * padding). */

@@ -140,7 +140,7 @@ def load():
             getattr(lib, name).restype = I
     D = C.c_double
     PA = C.POINTER(C.c_void_p)
-    lib.vlb3_create.argtypes = [I, I, I, I, I, C.POINTER(P)]
+    lib.vlb3_create.argtypes = [I, I, I, I, I, I, C.POINTER(P)]
     lib.vlb3_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.vlb3_bind.argtypes = [P, P, C.c_size_t, P]
     lib.vlb3_set_params.argtypes = [P, D, D, D, D, D, D, D, D, D, I]

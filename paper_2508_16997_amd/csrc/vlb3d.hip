@@ -1,14 +1,15 @@
-// vlb3d.hip -- the coupled step in three dimensions (D3Q19) for gfx950, and its C ABI
-// (include/vlb3d.h).
+// vlb3d.hip -- the coupled step in three dimensions (D3Q19 or D3Q27) for gfx950, and its
+// C ABI (include/vlb3d.h).
 //
-// State: two population buffers of 133 planes (7 lattices x 19 directions; plane
-// (L * 19 + i), node (z * ny + y) * nx + x), storing deviations from the rest state
+// State: two population buffers of 7 q planes (7 lattices x q directions; plane
+// (L * q + i), node (z * ny + y) * nx + x), storing deviations from the rest state
 // (f_i - w_i, g_i - w_i phi0 with phi0 = 1 for A_xx, A_yy, A_zz and 0 otherwise); history
 // of S (6 planes) and u (3 planes); rho and u at time n (4 planes) for the neighbours'
 // differences.  Per step two launches:
 //   k3_macro  rho and u of every node from its pulled populations (mac planes)
 //   k3_step   per node: pulls of all seven lattices (the conformation populations held in
-//             registers in FP32 storage, pulled again for the collision in FP64), the
+//             registers in FP32 storage -- four of the six lattices on D3Q27 -- and
+//             pulled again for the collision otherwise), the
 //             conformation's zeroth moments, the velocity gradient from the mac planes of
 //             the six axis neighbours, the constitutive source, the hydrodynamic collision
 //             (stored at once), then lattice by lattice CNEBB at wall-adjacent nodes and
@@ -32,19 +33,27 @@ namespace vlb3 {
 namespace {
 
 using T = double;
-constexpr int Q = 19;
 constexpr int NLAT = 7;  // hydrodynamic + six conformation lattices
 constexpr int TX = 64, TY = 4;
 // Conformation lattices whose pulled populations k3_step holds in registers from the
-// zeroth-moment pass to the collision (the others are pulled twice): all six in FP32
-// storage (two waves per SIMD, no second read), none in FP64, where holding them would
-// leave one wave per SIMD.
-template <class S>
-constexpr int kHold = sizeof(S) == 4 ? 6 : 0;
+// zeroth-moment pass to the collision (the others are pulled twice).  FP32 storage: all
+// six on D3Q19 (two waves per SIMD, no second read), four of six on D3Q27 (the most
+// that keeps two waves; measured 1723, 1643, 1607 and 1566 us per step on the 2^22-node
+// channel for none, two, three and four).  FP64: none, where holding them would leave
+// one wave per SIMD.
+template <class S, class Lat>
+constexpr int kHold = sizeof(S) == 4 ? (Lat::Q == 19 ? 6 : 4) : 0;
 constexpr T CS2 = 1.0 / 3.0;
 
-// D3Q19 velocities: rest; +-x, +-y, +-z; the twelve face diagonals in opposite pairs.
-__host__ __device__ constexpr int ec(int i, int a) {
+// conformation components: (a, b) of component k, rest value phi0
+__host__ __device__ constexpr int ka(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
+__host__ __device__ constexpr int kb(int k) { return k == 0 ? 0 : (k == 1 || k == 3) ? 1 : 2; }
+__host__ __device__ constexpr T phi0(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
+// Velocities come in opposite pairs (2j - 1, 2j) after the rest velocity 0.
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// D3Q19 velocities: rest; +-x, +-y, +-z; the twelve face diagonals.
+__host__ __device__ constexpr int e19(int i, int a) {
     return a == 0 ? ((i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
                      : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0)
          : a == 1 ? ((i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
@@ -52,27 +61,60 @@ __host__ __device__ constexpr int ec(int i, int a) {
                   : ((i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
                      : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0);
 }
-__host__ __device__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr T w3(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
-// conformation components: (a, b) of component k, rest value phi0
-__host__ __device__ constexpr int ka(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
-__host__ __device__ constexpr int kb(int k) { return k == 0 ? 0 : (k == 1 || k == 3) ? 1 : 2; }
-__host__ __device__ constexpr T phi0(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
+// H_aab with a != b: e_a^2 e_b - c_s^2 e_b (H_abc = e_a e_b e_c - c_s^2 (e_a d_bc + e_b d_ac
+// + e_c d_ab)).
+__host__ __device__ constexpr T h3aab(int ea, int eb) { return (T)(ea * ea * eb) - CS2 * (T)eb; }
 
-// Third-order Hermite combinations on D3Q19: h_{c,s} = H_aab + s H_bcc for
-// (a, b, c) = (x, y, z), (z, x, y), (y, z, x), with H_abc = e_a e_b e_c - c_s^2 (e_a d_bc +
-// e_b d_ac + e_c d_ab); lattice norms 2 c_s^6 (s = +1) and 6 c_s^6 (s = -1).
-__host__ __device__ constexpr int hca(int c) { return c == 0 ? 0 : (c == 1 ? 2 : 1); }
-__host__ __device__ constexpr int hcb(int c) { return c == 0 ? 1 : (c == 1 ? 0 : 2); }
-__host__ __device__ constexpr int hcc(int c) { return c == 0 ? 2 : (c == 1 ? 1 : 0); }
-__host__ __device__ constexpr T h3aab(int i, int a, int b) {
-    // H_aab with a != b: e_a^2 e_b - c_s^2 e_b
-    return (T)(ec(i, a) * ec(i, a) * ec(i, b)) - CS2 * (T)ec(i, b);
-}
-__host__ __device__ constexpr T hcomb(int i, int c, int s) {
-    return h3aab(i, hca(c), hcb(c)) + (T)s * h3aab(i, hcc(c), hcb(c));
-}
-__host__ __device__ constexpr T hinvnorm(int s) { return s > 0 ? 13.5 : 4.5; }  // 1/(2 cs^6), 1/(6 cs^6)
+// D3Q19.  Third order (no H_aaa, no H_xyz on this lattice): the six combinations
+// h_{c,s} = H_aab + s H_bcc for (a, b, c) = (x, y, z), (z, x, y), (y, z, x), basis index
+// m = 2c (s = +1) and 2c + 1 (s = -1), orthogonal with lattice norms 2 c_s^6 and 6 c_s^6;
+// the equilibrium's coefficient of h_{c,s} per unit density is u_a^2 u_b + s u_b u_c^2.
+struct D3Q19 {
+    static constexpr int Q = 19, NB3 = 6;
+    __host__ __device__ static constexpr int e(int i, int a) { return e19(i, a); }
+    __host__ __device__ static constexpr T w(int i) {
+        return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+    __host__ __device__ static constexpr int ca(int c) { return c == 0 ? 0 : (c == 1 ? 2 : 1); }
+    __host__ __device__ static constexpr int cb(int c) { return c == 0 ? 1 : (c == 1 ? 0 : 2); }
+    __host__ __device__ static constexpr int cc(int c) { return c == 0 ? 2 : (c == 1 ? 1 : 0); }
+    __host__ __device__ static constexpr T h3(int i, int m) {
+        return h3aab(e(i, ca(m >> 1)), e(i, cb(m >> 1))) +
+               ((m & 1) ? -1.0 : 1.0) * h3aab(e(i, cc(m >> 1)), e(i, cb(m >> 1)));
+    }
+    __host__ __device__ static constexpr T h3inv(int m) { return (m & 1) ? 4.5 : 13.5; }
+    __host__ __device__ static T u3(int m, const T u[3]) {
+        const int a = ca(m >> 1), b = cb(m >> 1), c = cc(m >> 1);
+        const T t1 = u[a] * u[a] * u[b], t2 = u[b] * u[c] * u[c];
+        return (m & 1) ? t1 - t2 : t1 + t2;
+    }
+};
+
+// D3Q27: the D3Q19 velocities, then the eight corners in opposite pairs -- (+,+,+),
+// (+,+,-), (+,-,+), (-,+,+) at odd indices 19-25, their negatives after them.  Weights are
+// products of the D1Q3 weights 2/3 and 1/6.  Third order: the six H_aab (a != b; basis
+// index m for (a, b) = (x, y), (x, z), (y, x), (y, z), (z, x), (z, y)) and H_xyz (m = 6),
+// orthogonal with their continuous norms 2 c_s^6 and c_s^6; equilibrium coefficients
+// per unit density u_a^2 u_b and u_x u_y u_z.
+struct D3Q27 {
+    static constexpr int Q = 27, NB3 = 7;
+    __host__ __device__ static constexpr int e(int i, int a) {
+        return i < 19 ? e19(i, a)
+                      : ((i & 1) ? 1 : -1) * ((((i - 19) >> 1) != 0 && a == 3 - ((i - 19) >> 1)) ? -1 : 1);
+    }
+    __host__ __device__ static constexpr T w(int i) {
+        return i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+    __host__ __device__ static constexpr int ma(int m) { return m >> 1; }
+    __host__ __device__ static constexpr int mb(int m) { return (m >> 1) == 0 ? 1 + (m & 1) : ((m >> 1) == 1 ? 2 * (m & 1) : (m & 1)); }
+    __host__ __device__ static constexpr T h3(int i, int m) {
+        return m == 6 ? (T)(e(i, 0) * e(i, 1) * e(i, 2)) : h3aab(e(i, ma(m)), e(i, mb(m)));
+    }
+    __host__ __device__ static constexpr T h3inv(int m) { return m == 6 ? 27.0 : 13.5; }
+    __host__ __device__ static T u3(int m, const T u[3]) {
+        return m == 6 ? u[0] * u[1] * u[2] : u[ma(m)] * u[ma(m)] * u[mb(m)];
+    }
+};
 
 template <class S>
 struct Run3 {
@@ -90,9 +132,10 @@ struct Run3 {
 
 // c0 + e_i.c + e_i.M.e_i for the symmetric M stored as (xx, xy, xz, yy, yz, zz): with
 // components of e_i in {-1, 0, 1} this is a handful of additions per direction.
+template <class Lat>
 __device__ __forceinline__ T quad_at(int i, T c0, const T c[3], const T M[6]) {
     T v = c0;
-    const int e0 = ec(i, 0), e1 = ec(i, 1), e2 = ec(i, 2);
+    const int e0 = Lat::e(i, 0), e1 = Lat::e(i, 1), e2 = Lat::e(i, 2);
     if (e0) v += e0 > 0 ? c[0] : -c[0];
     if (e1) v += e1 > 0 ? c[1] : -c[1];
     if (e2) v += e2 > 0 ? c[2] : -c[2];
@@ -169,20 +212,20 @@ __device__ __forceinline__ void put(const Planes<S>& P, int plane, int slot, T v
     bstore((S)v, P.r, (unsigned)slot * (unsigned)sizeof(S), (unsigned)plane * P.stride);
 }
 // The 19 planes of lattice L of the source or destination buffer.
-template <class S>
+template <class Lat, class S>
 __device__ __forceinline__ Planes<S> src_lattice(const Run3<S>& R, int L) {
-    return planes(R.src + (size_t)L * Q * (size_t)R.N, R.N);
+    return planes(R.src + (size_t)L * Lat::Q * (size_t)R.N, R.N);
 }
-template <class S>
+template <class Lat, class S>
 __device__ __forceinline__ Planes<S> dst_lattice(const Run3<S>& R, int L) {
-    return planes((const S*)R.dst + (size_t)L * Q * (size_t)R.N, R.N);
+    return planes((const S*)R.dst + (size_t)L * Lat::Q * (size_t)R.N, R.N);
 }
 // Population i of a lattice arriving at the node from x - e_i with the periodic wrap in
 // all three axes (the wall fix-up below replaces the pulls from beyond a y wall).
-template <class S>
+template <class Lat, class S>
 __device__ __forceinline__ S pullb(const Planes<S>& P, const Nbr& b, int i) {
     if (b.first) return at(P, i, b.n);
-    const int ex = ec(i, 0), ey = ec(i, 1), ez = ec(i, 2);
+    const int ex = Lat::e(i, 0), ey = Lat::e(i, 1), ez = Lat::e(i, 2);
     const int s = b.n + (ex > 0 ? b.dx[0] : (ex < 0 ? b.dx[1] : 0)) +
                   (ey > 0 ? b.dy[0] : (ey < 0 ? b.dy[1] : 0)) +
                   (ez > 0 ? b.dz[0] : (ez < 0 ? b.dz[1] : 0));
@@ -200,50 +243,50 @@ __device__ __forceinline__ Nbr fresh(const Nbr& b) {
 // Pulls of lattice L with the directions arriving from beyond a y wall taken as the node's
 // own post-collision value of the opposite direction.  (A wave holds one row, so the wall
 // branches are uniform.)
-template <class S>
-__device__ __forceinline__ void pull_all(const Run3<S>& R, const Nbr& b, int L, S g[Q]) {
-    const Planes<S> P = src_lattice(R, L);
+template <class Lat, class S>
+__device__ __forceinline__ void pull_all(const Run3<S>& R, const Nbr& b, int L, S g[Lat::Q]) {
+    const Planes<S> P = src_lattice<Lat>(R, L);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = pullb(P, b, i);
+    for (int i = 0; i < Lat::Q; ++i) g[i] = pullb<Lat>(P, b, i);
     if (b.first) return;
     if (b.ylo_wall) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (ec(i, 1) > 0) g[i] = at(P, opp3(i), b.n);
+        for (int i = 0; i < Lat::Q; ++i)
+            if (Lat::e(i, 1) > 0) g[i] = at(P, opp(i), b.n);
     }
     if (b.yhi_wall) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (ec(i, 1) < 0) g[i] = at(P, opp3(i), b.n);
+        for (int i = 0; i < Lat::Q; ++i)
+            if (Lat::e(i, 1) < 0) g[i] = at(P, opp(i), b.n);
     }
 }
 
-template <class S>
-__device__ __forceinline__ void hydro_pull(const Run3<S>& R, const Nbr& b, S f[Q], T& rho, T u[3]) {
-    pull_all(R, b, 0, f);
+template <class Lat, class S>
+__device__ __forceinline__ void hydro_pull(const Run3<S>& R, const Nbr& b, S f[Lat::Q], T& rho, T u[3]) {
+    pull_all<Lat>(R, b, 0, f);
     T dr = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < Lat::Q; ++i) {
         const T v = (T)f[i];
         dr += v;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            if (ec(i, a) != 0) j[a] += ec(i, a) > 0 ? v : -v;
+            if (Lat::e(i, a) != 0) j[a] += Lat::e(i, a) > 0 ? v : -v;
     }
     rho = 1.0 + dr;
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * R.F[a]) / rho;
 }
 
-template <class S>
+template <class S, class Lat>
 __global__ __launch_bounds__(TX * TY) void k3_macro(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
     const Nbr b = make_nbr(R, x, y, z);
     const int n = b.n;
-    S f[Q];
+    S f[Lat::Q];
     T rho, u[3];
-    hydro_pull(R, b, f, rho, u);
+    hydro_pull<Lat>(R, b, f, rho, u);
     const Planes<S> M = planes((const S*)R.mac, R.N);
     put(M, 0, n, rho);
 #pragma unroll
@@ -263,22 +306,22 @@ __device__ __forceinline__ T fd(bool lo_wall, T vlo, T v0, bool hi_wall, T vhi) 
 // one copy of the code and its registers) from its pulled populations: CNEBB at a
 // wall-adjacent node, moments, collision, store.
 __device__ __forceinline__ T phi0_rt(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
-template <class S>
-__device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, const S gs[Q], const T u[3],
+template <class Lat, class S>
+__device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, const S gs[Lat::Q], const T u[3],
                                              const T up[3], T rho, T uu, T dp, T Sk, T Spk,
                                              bool wall_lo, bool wall_hi) {
     const T phi = phi0_rt(k) + dp;
     // first and second moments of the pulled deviations
     T J[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < Lat::Q; ++i) {
         const T v = (T)gs[i];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            if (ec(i, a) != 0) J[a] += ec(i, a) > 0 ? v : -v;
+            if (Lat::e(i, a) != 0) J[a] += Lat::e(i, a) > 0 ? v : -v;
 #pragma unroll
         for (int m = 0; m < 6; ++m)
-            if (ec(i, ka(m)) * ec(i, kb(m)) != 0) P[m] += (ec(i, ka(m)) * ec(i, kb(m)) > 0) ? v : -v;
+            if (Lat::e(i, ka(m)) * Lat::e(i, kb(m)) != 0) P[m] += (Lat::e(i, ka(m)) * Lat::e(i, kb(m)) > 0) ? v : -v;
     }
     if (wall_lo || wall_hi) {
         // CNEBB: each unknown (a direction arriving from beyond the wall) becomes the
@@ -286,21 +329,21 @@ __device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, con
         // opposite; g_0 takes the remainder of phi_b, so the zeroth moment is unchanged
         // and the first and second moments change by the unknowns' corrections only.
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const bool unk = wall_lo ? ec(i, 1) > 0 : ec(i, 1) < 0;
+        for (int i = 1; i < Lat::Q; ++i) {
+            const bool unk = wall_lo ? Lat::e(i, 1) > 0 : Lat::e(i, 1) < 0;
             if (unk) {
-                const int o = opp3(i);
-                const T eui = ec(i, 0) * u[0] + ec(i, 1) * u[1] + ec(i, 2) * u[2];
-                const T eqi = w3(i) * (dp + phi * (3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
-                const T eqo = w3(o) * (dp + phi * (-3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
+                const int o = opp(i);
+                const T eui = Lat::e(i, 0) * u[0] + Lat::e(i, 1) * u[1] + Lat::e(i, 2) * u[2];
+                const T eqi = Lat::w(i) * (dp + phi * (3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
+                const T eqo = Lat::w(o) * (dp + phi * (-3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
                 const T delta = eqi + (T)gs[o] - eqo - (T)gs[i];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    if (ec(i, a) != 0) J[a] += ec(i, a) > 0 ? delta : -delta;
+                    if (Lat::e(i, a) != 0) J[a] += Lat::e(i, a) > 0 ? delta : -delta;
 #pragma unroll
                 for (int m = 0; m < 6; ++m)
-                    if (ec(i, ka(m)) * ec(i, kb(m)) != 0)
-                        P[m] += (ec(i, ka(m)) * ec(i, kb(m)) > 0) ? delta : -delta;
+                    if (Lat::e(i, ka(m)) * Lat::e(i, kb(m)) != 0)
+                        P[m] += (Lat::e(i, ka(m)) * Lat::e(i, kb(m)) > 0) ? delta : -delta;
             }
         }
     }
@@ -327,25 +370,25 @@ __device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, con
                3.0 * R.h2 * (1.5 * Sk * u[a] - 0.5 * Spk * up[a]);
 #pragma unroll
     for (int m = 0; m < 6; ++m) M[m] = 4.5 * (phi * u[ka(m)] * u[kb(m)] + R.p2 * B2[m]);
-    const Planes<S> out = dst_lattice(R, 1 + k);
+    const Planes<S> out = dst_lattice<Lat>(R, 1 + k);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) put(out, i, n, w3(i) * quad_at(i, c0, c, M));
+    for (int i = 0; i < Lat::Q; ++i) put(out, i, n, Lat::w(i) * quad_at<Lat>(i, c0, c, M));
 }
 
 // Pulls and collision of conformation lattice k.
-template <class S>
+template <class Lat, class S>
 __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, int k, const T u[3],
                                              const T up[3], T rho, T uu, T dp, T Sk, T Spk,
                                              bool wall_lo, bool wall_hi) {
     const Nbr b = fresh(nb);
-    S gs[Q];
-    pull_all(R, b, 1 + k, gs);
-    conf_collide(R, b.n, k, gs, u, up, rho, uu, dp, Sk, Spk, wall_lo, wall_hi);
+    S gs[Lat::Q];
+    pull_all<Lat>(R, b, 1 + k, gs);
+    conf_collide<Lat>(R, b.n, k, gs, u, up, rho, uu, dp, Sk, Spk, wall_lo, wall_hi);
 }
 
 // WALLS: the y walls' fix-ups, one-sided differences and CNEBB compiled in (a wave holds
 // one row, so they are uniform branches); without walls they are compiled out.
-template <class S, bool WALLS, int HOLD>
+template <class S, class Lat, bool WALLS, int HOLD>
 __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
@@ -355,9 +398,9 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     const int n = nbr.n;
 
     // ---- hydrodynamic pulls, rho, u ----
-    S f[Q];
+    S f[Lat::Q];
     T rho, u[3];
-    hydro_pull(R, nbr, f, rho, u);
+    hydro_pull<Lat>(R, nbr, f, rho, u);
 
     // ---- conformation (zeroth moments of the pulled populations; CNEBB keeps them) ----
     // Per-lattice values wait in LDS, one column per lane, so that the lattice loops run
@@ -365,23 +408,23 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     __shared__ T s_dphi[6][TX * TY], s_Sc[6][TX * TY], s_Sp[6][TX * TY];
     const int tid = threadIdx.y * TX + threadIdx.x;
     T dphi[6];
-    S G[HOLD > 0 ? HOLD : 1][Q];  // the held lattices 6 - HOLD .. 5
+    S G[HOLD > 0 ? HOLD : 1][Lat::Q];  // the held lattices 6 - HOLD .. 5
 #pragma unroll 1
     for (int k = 0; k < 6 - HOLD; ++k) {
-        S g[Q];
-        pull_all(R, fresh(nbr), 1 + k, g);
+        S g[Lat::Q];
+        pull_all<Lat>(R, fresh(nbr), 1 + k, g);
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)g[i];
+        for (int i = 0; i < Lat::Q; ++i) s += (T)g[i];
         s_dphi[k][tid] = s;
     }
 #pragma unroll
     for (int j = 0; j < HOLD; ++j) {
         const int k = 6 - HOLD + j;
-        pull_all(R, nbr, 1 + k, G[j]);
+        pull_all<Lat>(R, nbr, 1 + k, G[j]);
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)G[j][i];
+        for (int i = 0; i < Lat::Q; ++i) s += (T)G[j][i];
         s_dphi[k][tid] = s;
     }
 #pragma unroll
@@ -450,47 +493,43 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
 
     // ---- hydrodynamic collision (moment form) ----
     {
-        const Planes<S> out = dst_lattice(R, 0);
-        // second moments and third-order combinations of the pulled deviations
-        T P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Qm[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        const Planes<S> out = dst_lattice<Lat>(R, 0);
+        // second moments and third-order basis moments of the pulled deviations
+        T P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Qm[Lat::NB3];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
+        for (int m = 0; m < Lat::NB3; ++m) Qm[m] = 0.0;
+#pragma unroll
+        for (int i = 0; i < Lat::Q; ++i) {
             const T v = (T)f[i];
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                if (ec(i, ka(k)) * ec(i, kb(k)) != 0) P[k] += (ec(i, ka(k)) * ec(i, kb(k)) > 0) ? v : -v;
+                if (Lat::e(i, ka(k)) * Lat::e(i, kb(k)) != 0) P[k] += (Lat::e(i, ka(k)) * Lat::e(i, kb(k)) > 0) ? v : -v;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Qm[c][0] += hcomb(i, c, -1) * v;
-                Qm[c][1] += hcomb(i, c, +1) * v;
-            }
+            for (int m = 0; m < Lat::NB3; ++m)
+                if (Lat::h3(i, m) != 0.0) Qm[m] += Lat::h3(i, m) * v;
         }
         // off-equilibrium moments: A1 = -F/2 (literal), A2 = Pi - c_s^2 d (rho - 1) - rho u u
-        // (deviations carry the rest part), A3 along h_{c,s}: moment - rho (u_a^2 u_b +- u_b u_c^2)
+        // (deviations carry the rest part), A3 along each basis function: moment - rho u3
         const T dr = rho - 1.0;
-        T A2[6], A3[3][2], uc[3][2];
+        T A2[6], A3[Lat::NB3], uc[Lat::NB3];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const int a = ka(k), b = kb(k);
             A2[k] = P[k] - (a == b ? CS2 * dr : 0.0) - rho * u[a] * u[b];
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int a = hca(c), b = hcb(c), d = hcc(c);
-            const T t1 = u[a] * u[a] * u[b], t2 = u[b] * u[d] * u[d];
-            uc[c][0] = t1 - t2;
-            uc[c][1] = t1 + t2;
-            A3[c][0] = Qm[c][0] - rho * uc[c][0];
-            A3[c][1] = Qm[c][1] - rho * uc[c][1];
+        for (int m = 0; m < Lat::NB3; ++m) {
+            uc[m] = Lat::u3(m, u);
+            A3[m] = Qm[m] - rho * uc[m];
         }
         const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const T trA2 = A2[0] + A2[3] + A2[5], trt = tau[0] + tau[3] + tau[5];
-        // Post-collision deviation f_i - w_i = w_i (c0 + e_i.c + e_i.M.e_i + sum h_{c,s}(e_i)
-        // d_{c,s}), collecting the equilibrium, c1 times the regularized orders 1-2 (A1 =
+        // Post-collision deviation f_i - w_i = w_i (c0 + e_i.c + e_i.M.e_i + sum_m h_m(e_i)
+        // d_m), collecting the equilibrium, c1 times the regularized orders 1-2 (A1 =
         // -F/2), c2 times the projected third order, G_i, T_i and F_i:
         const T c0 = dr - 1.5 * rho * uu - 1.5 * R.c1 * trA2 +
                      1.5 * R.h1 * (D[0] + D[1] + D[2]) + 1.5 * R.inv_ts1 * trt;
-        T c[3], M[6], d[3][2];
+        T c[3], M[6], d[Lat::NB3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) c[a] = 3.0 * rho * u[a] - 1.5 * R.c1 * R.F[a] + 3.0 * R.h1 * R.F[a];
 #pragma unroll
@@ -500,19 +539,14 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         M[3] -= 4.5 * R.h1 * D[1];
         M[5] -= 4.5 * R.h1 * D[2];
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            d[cc][0] = hinvnorm(-1) * (rho * uc[cc][0] + R.c2 * A3[cc][0]);
-            d[cc][1] = hinvnorm(1) * (rho * uc[cc][1] + R.c2 * A3[cc][1]);
-        }
+        for (int m = 0; m < Lat::NB3; ++m) d[m] = Lat::h3inv(m) * (rho * uc[m] + R.c2 * A3[m]);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T v = quad_at(i, c0, c, M);
+        for (int i = 0; i < Lat::Q; ++i) {
+            T v = quad_at<Lat>(i, c0, c, M);
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-                if (hcomb(i, cc, -1) != 0.0) v += hcomb(i, cc, -1) * d[cc][0];
-                if (hcomb(i, cc, 1) != 0.0) v += hcomb(i, cc, 1) * d[cc][1];
-            }
-            put(out, i, n, w3(i) * v);
+            for (int m = 0; m < Lat::NB3; ++m)
+                if (Lat::h3(i, m) != 0.0) v += Lat::h3(i, m) * d[m];
+            put(out, i, n, Lat::w(i) * v);
         }
     }
 
@@ -527,13 +561,13 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         // (held in storage precision: the empty asm keeps the widened copies of the
         // zeroth-moment sum from being kept instead)
 #pragma unroll
-        for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(G[j][i]));
-        conf_collide(R, n, k, G[j], u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid],
+        for (int i = 0; i < Lat::Q; ++i) asm volatile("" : "+v"(G[j][i]));
+        conf_collide<Lat>(R, n, k, G[j], u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid],
                      wall_lo, wall_hi);
     }
 #pragma unroll 1
     for (int k = 5 - HOLD; k >= 0; --k)
-        conf_lattice(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], wall_lo,
+        conf_lattice<Lat>(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], wall_lo,
                      wall_hi);
 #pragma unroll
     for (int k = 0; k < 6; ++k) put(hist, k, n, s_Sc[k][tid]);
@@ -543,7 +577,7 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
 
 // Equilibrium state of the given fields at every node's own slot (read without a pull
 // by the first step); history cleared.
-template <class S>
+template <class S, class Lat>
 __global__ __launch_bounds__(TX * TY) void k3_init(Run3<S> R, S* pop, const S* const* fields) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
@@ -555,26 +589,21 @@ __global__ __launch_bounds__(TX * TY) void k3_init(Run3<S> R, S* pop, const S* c
     for (int c = 0; c < 10; ++c) v[c] = fields[c] ? (T)fields[c][n] : dflt[c];
     const T rho = v[0], u[3] = {v[1], v[2], v[3]};
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    T uc[3][2];
+    T uc[Lat::NB3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int a = hca(c), b = hcb(c), d = hcc(c);
-        uc[c][0] = u[a] * u[a] * u[b] - u[b] * u[d] * u[d];
-        uc[c][1] = u[a] * u[a] * u[b] + u[b] * u[d] * u[d];
-    }
+    for (int m = 0; m < Lat::NB3; ++m) uc[m] = Lat::u3(m, u);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T eu = ec(i, 0) * u[0] + ec(i, 1) * u[1] + ec(i, 2) * u[2];
+    for (int i = 0; i < Lat::Q; ++i) {
+        const T eu = Lat::e(i, 0) * u[0] + Lat::e(i, 1) * u[1] + Lat::e(i, 2) * u[2];
         T third = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            third += hinvnorm(-1) * hcomb(i, c, -1) * uc[c][0] + hinvnorm(1) * hcomb(i, c, 1) * uc[c][1];
-        pop[(long long)i * N + n] = (S)(w3(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu) + third)));
+        for (int m = 0; m < Lat::NB3; ++m) third += Lat::h3inv(m) * Lat::h3(i, m) * uc[m];
+        pop[(long long)i * N + n] = (S)(Lat::w(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu) + third)));
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const T phi = v[4 + k];
-            pop[((long long)(1 + k) * Q + i) * N + n] =
-                (S)(w3(i) * ((phi - phi0(k)) + phi * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu))));
+            pop[((long long)(1 + k) * Lat::Q + i) * N + n] =
+                (S)(Lat::w(i) * ((phi - phi0(k)) + phi * (3.0 * eu + 4.5 * (eu * eu - CS2 * uu))));
         }
     }
 #pragma unroll
@@ -582,23 +611,23 @@ __global__ __launch_bounds__(TX * TY) void k3_init(Run3<S> R, S* pop, const S* c
 }
 
 // rho, u (half-force shift) and A of the current state.
-template <class S>
+template <class S, class Lat>
 __global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
     const Nbr nbr = make_nbr(R, x, y, z);
     const int n = nbr.n;
-    S f[Q];
+    S f[Lat::Q];
     T rho, u[3];
-    hydro_pull(R, nbr, f, rho, u);
+    hydro_pull<Lat>(R, nbr, f, rho, u);
     T v[10] = {rho, u[0], u[1], u[2]};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        S g[Q];
-        pull_all(R, nbr, 1 + k, g);
+        S g[Lat::Q];
+        pull_all<Lat>(R, nbr, 1 + k, g);
         T s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (T)g[i];
+        for (int i = 0; i < Lat::Q; ++i) s += (T)g[i];
         v[4 + k] = phi0(k) + s;
     }
 #pragma unroll
@@ -613,7 +642,7 @@ __global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
 // Host side
 // ---------------------------------------------------------------------------------------
 struct vlb3_sim {
-    int nx, ny, nz, prec, ywall;
+    int nx, ny, nz, q, prec, ywall;
     size_t esz;
     long long N, P;  // nodes; plane stride in elements
     bool bound = false, params_set = false, inited = false;
@@ -631,16 +660,16 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Plane stride: the node count rounded up to 64 elements plus 4160 (4096 + 64), so that
-// the 133 planes a node touches do not all start at the same offset modulo a large power
-// of two (worth about 4% on a 2^22-node grid).
+// the 133 (189) planes a node touches do not all start at the same offset modulo a large
+// power of two (worth about 4% on a 2^22-node grid).
 long long plane_stride(long long N) { return ((N + 63) & ~63LL) + 4160; }
 
 void layout(vlb3_sim* s) {
     size_t o = 0;
     auto take = [&](size_t b) { const size_t r = o; o = align256(o + b); return r; };
     const size_t plane = (size_t)s->P * s->esz;
-    s->off_pop[0] = take(vlb3::NLAT * vlb3::Q * plane);
-    s->off_pop[1] = take(vlb3::NLAT * vlb3::Q * plane);
+    s->off_pop[0] = take((size_t)vlb3::NLAT * s->q * plane);
+    s->off_pop[1] = take((size_t)vlb3::NLAT * s->q * plane);
     s->off_hist = take(9 * plane);
     s->off_mac = take(4 * plane);
     s->off_ptrs = take(10 * sizeof(void*));
@@ -696,16 +725,17 @@ int check_ready(const vlb3_sim* s) {
             return vlb::report_error(VLB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-template <class S>
+template <class S, class Lat>
 int do_steps(vlb3_sim* s, int64_t n) {
     const dim3 blk(vlb3::TX, vlb3::TY), grd = grid_of(s);
+    constexpr int hold = vlb3::kHold<S, Lat>;
     for (int64_t k = 0; k < n; ++k) {
         const vlb3::Run3<S> r = make_run<S>(s);
-        hipLaunchKernelGGL((vlb3::k3_macro<S>), grd, blk, 0, s->stream, r);
+        hipLaunchKernelGGL((vlb3::k3_macro<S, Lat>), grd, blk, 0, s->stream, r);
         if (s->ywall)
-            hipLaunchKernelGGL((vlb3::k3_step<S, true, vlb3::kHold<S>>), grd, blk, 0, s->stream, r);
+            hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, hold>), grd, blk, 0, s->stream, r);
         else
-            hipLaunchKernelGGL((vlb3::k3_step<S, false, vlb3::kHold<S>>), grd, blk, 0, s->stream, r);
+            hipLaunchKernelGGL((vlb3::k3_step<S, Lat, false, hold>), grd, blk, 0, s->stream, r);
         VLB3_HIP(hipGetLastError());
         s->parity ^= 1;
         s->first = 0;
@@ -714,7 +744,7 @@ int do_steps(vlb3_sim* s, int64_t n) {
     return VLB_OK;
 }
 
-template <class S>
+template <class S, class Lat>
 int do_init(vlb3_sim* s, const void* const fields[10]) {
     void* host_ptrs[10];
     for (int c = 0; c < 10; ++c) host_ptrs[c] = const_cast<void*>(fields ? fields[c] : nullptr);
@@ -724,7 +754,7 @@ int do_init(vlb3_sim* s, const void* const fields[10]) {
     s->first = 1;
     s->step = 0;
     const vlb3::Run3<S> r = make_run<S>(s);
-    hipLaunchKernelGGL((vlb3::k3_init<S>), grid_of(s), dim3(vlb3::TX, vlb3::TY), 0, s->stream, r,
+    hipLaunchKernelGGL((vlb3::k3_init<S, Lat>), grid_of(s), dim3(vlb3::TX, vlb3::TY), 0, s->stream, r,
                        reinterpret_cast<S*>(s->ws + s->off_pop[0]),
                        reinterpret_cast<const S* const*>(dev_ptrs));
     VLB3_HIP(hipGetLastError());
@@ -734,28 +764,49 @@ int do_init(vlb3_sim* s, const void* const fields[10]) {
     return VLB_OK;
 }
 
-template <class S>
+template <class S, class Lat>
 int do_read(vlb3_sim* s, void* const out[10]) {
     void* host_ptrs[10];
     for (int c = 0; c < 10; ++c) host_ptrs[c] = out ? out[c] : nullptr;
     void** dev_ptrs = reinterpret_cast<void**>(s->ws + s->off_ptrs);
     VLB3_HIP(hipMemcpyAsync(dev_ptrs, host_ptrs, sizeof(host_ptrs), hipMemcpyHostToDevice, s->stream));
     const vlb3::Run3<S> r = make_run<S>(s);
-    hipLaunchKernelGGL((vlb3::k3_read<S>), grid_of(s), dim3(vlb3::TX, vlb3::TY), 0, s->stream, r,
+    hipLaunchKernelGGL((vlb3::k3_read<S, Lat>), grid_of(s), dim3(vlb3::TX, vlb3::TY), 0, s->stream, r,
                        reinterpret_cast<S* const*>(dev_ptrs));
     VLB3_HIP(hipGetLastError());
     VLB3_HIP(hipStreamSynchronize(s->stream));
     return VLB_OK;
 }
 
+// Entry points by storage type and lattice.
+template <class S, class Lat>
+struct StepOp {
+    static int run(vlb3_sim* s, int64_t n) { return do_steps<S, Lat>(s, n); }
+};
+template <class S, class Lat>
+struct InitOp {
+    static int run(vlb3_sim* s, const void* const* f) { return do_init<S, Lat>(s, f); }
+};
+template <class S, class Lat>
+struct ReadOp {
+    static int run(vlb3_sim* s, void* const* o) { return do_read<S, Lat>(s, o); }
+};
+template <template <class, class> class Op, class Arg>
+int by_kind(vlb3_sim* s, Arg a) {
+    if (s->prec == VLB_FP32)
+        return s->q == 27 ? Op<float, vlb3::D3Q27>::run(s, a) : Op<float, vlb3::D3Q19>::run(s, a);
+    return s->q == 27 ? Op<double, vlb3::D3Q27>::run(s, a) : Op<double, vlb3::D3Q19>::run(s, a);
+}
+
 }  // namespace
 
 extern "C" {
 
-int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out) {
+int vlb3_create(int nx, int ny, int nz, int q, int prec, int ymode, vlb3_sim** out) {
     if (!out) return vlb::report_error(VLB_E_INVALID_ARG, "null output");
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return vlb::report_error(VLB_E_INVALID_ARG, "grid sizes must be >= 1");
+    if (q != 19 && q != 27) return vlb::report_error(VLB_E_INVALID_ARG, "lattice must be 19 (D3Q19) or 27 (D3Q27)");
     if (prec != VLB_FP32 && prec != VLB_FP64) return vlb::report_error(VLB_E_INVALID_ARG, "unknown precision");
     if (ymode != VLB_PERIODIC && ymode != VLB_WALL)
         return vlb::report_error(VLB_E_INVALID_ARG, "ymode must be VLB_PERIODIC or VLB_WALL");
@@ -763,13 +814,14 @@ int vlb3_create(int nx, int ny, int nz, int prec, int ymode, vlb3_sim** out) {
     if (nz > 65535 || (ny + vlb3::TY - 1) / vlb3::TY > 65535)
         return vlb::report_error(VLB_E_INVALID_ARG, "nz and ny / 4 must stay within the launch grid (65535)");
     const long long N = (long long)nx * ny * nz;
-    if (plane_stride(N) >= (1LL << 31) / (vlb3::NLAT * vlb3::Q))
+    if (plane_stride(N) >= (1LL << 31) / (vlb3::NLAT * q))
         return vlb::report_error(VLB_E_INVALID_ARG, "grid too large for 32-bit plane offsets");
     vlb3_sim* s = new (std::nothrow) vlb3_sim();
     if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "out of host memory");
     s->nx = nx;
     s->ny = ny;
     s->nz = nz;
+    s->q = q;
     s->prec = prec;
     s->ywall = ymode == VLB_WALL ? 1 : 0;
     s->esz = prec == VLB_FP32 ? 4 : 8;
@@ -827,7 +879,7 @@ int vlb3_set_params(vlb3_sim* s, double nu_s, double eta_p, double lambda, doubl
 int vlb3_init_equilibrium(vlb3_sim* s, const void* const fields[10]) {
     int rc = check_ready(s);
     if (rc) return rc;
-    return s->prec == VLB_FP32 ? do_init<float>(s, fields) : do_init<double>(s, fields);
+    return by_kind<InitOp>(s, fields);
 }
 
 int vlb3_step(vlb3_sim* s, int64_t n) {
@@ -835,14 +887,14 @@ int vlb3_step(vlb3_sim* s, int64_t n) {
     if (rc) return rc;
     if (!s->inited) return vlb::report_error(VLB_E_STATE, "state not initialised (vlb3_init_equilibrium)");
     if (n < 0) return vlb::report_error(VLB_E_INVALID_ARG, "nsteps must be >= 0");
-    return s->prec == VLB_FP32 ? do_steps<float>(s, n) : do_steps<double>(s, n);
+    return by_kind<StepOp>(s, n);
 }
 
 int vlb3_read_fields(vlb3_sim* s, void* const out[10]) {
     int rc = check_ready(s);
     if (rc) return rc;
     if (!s->inited) return vlb::report_error(VLB_E_STATE, "state not initialised (vlb3_init_equilibrium)");
-    return s->prec == VLB_FP32 ? do_read<float>(s, out) : do_read<double>(s, out);
+    return by_kind<ReadOp>(s, out);
 }
 
 int vlb3_get_step(const vlb3_sim* s, int64_t* step) {

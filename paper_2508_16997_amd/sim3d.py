@@ -1,4 +1,4 @@
-"""Three-dimensional (D3Q19) simulation object over libvlb.so (include/vlb3d.h).
+"""Three-dimensional (D3Q19 / D3Q27) simulation object over libvlb.so (include/vlb3d.h).
 
 Argument marshalling only: every step runs in the library's HIP kernels; PyTorch
 provides the device workspace, the stream and the field tensors.
@@ -18,19 +18,21 @@ FIELDS3 = ("rho", "ux", "uy", "uz", "axx", "axy", "axz", "ayy", "ayz", "azz")
 
 
 class Simulation3D:
-    """One D3Q19 simulation: x and z periodic, y periodic or half-way walls."""
+    """One D3Q19 (q = 19) or D3Q27 (q = 27) simulation: x and z periodic, y periodic or
+    half-way walls."""
 
     def __init__(self, nx: int, ny: int, nz: int, ymode: str = "periodic",
                  precision: str = "fp32", device: Optional[torch.device] = None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, q: int = 19):
         self.lib = L.load()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.precision = precision
         self.dtype = torch.float32 if precision == "fp32" else torch.float64
         prec = L.VLB_FP32 if precision == "fp32" else L.VLB_FP64
         h = C.c_void_p()
-        L.check(self.lib.vlb3_create(self.nx, self.ny, self.nz, prec, L.MODES[ymode], C.byref(h)),
-                "vlb3_create")
+        self.q = int(q)
+        L.check(self.lib.vlb3_create(self.nx, self.ny, self.nz, self.q, prec, L.MODES[ymode],
+                                     C.byref(h)), "vlb3_create")
         self._h = h
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         v = C.c_size_t()
@@ -45,6 +47,7 @@ class Simulation3D:
     @classmethod
     def from_problem(cls, prob, precision: Optional[str] = None, **kw) -> "Simulation3D":
         """Build, parameterise and initialise from a synth.Problem3D."""
+        kw.setdefault("q", prob.q)
         sim = cls(prob.nx, prob.ny, prob.nz, prob.ymode, precision or prob.precision, **kw)
         sim.set_params(prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s,
                        prob.Lambda_p, *prob.F)

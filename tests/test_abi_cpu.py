@@ -60,13 +60,25 @@ def test_3d_create_validates_without_a_gpu(vlb):
 
     lib = vlb.load()
     h = C.c_void_p()
-    assert lib.vlb3_create(0, 4, 4, _lib.VLB_FP32, _lib.VLB_PERIODIC, C.byref(h)) == _lib.VLB_E_INVALID_ARG
-    assert lib.vlb3_create(4, 2, 4, _lib.VLB_FP32, _lib.VLB_WALL, C.byref(h)) == _lib.VLB_E_INVALID_ARG
-    assert lib.vlb3_create(4, 4, 4, _lib.VLB_FP32, _lib.VLB_OPEN, C.byref(h)) == _lib.VLB_E_INVALID_ARG
-    assert lib.vlb3_create(8, 6, 5, _lib.VLB_FP64, _lib.VLB_WALL, C.byref(h)) == _lib.VLB_OK
-    v = C.c_size_t()
-    assert lib.vlb3_workspace_bytes(h, C.byref(v)) == _lib.VLB_OK
-    assert v.value >= (2 * 133 + 13) * 240 * 8
+    F32, F64, PER, WALL = _lib.VLB_FP32, _lib.VLB_FP64, _lib.VLB_PERIODIC, _lib.VLB_WALL
+    assert lib.vlb3_create(0, 4, 4, 19, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(4, 2, 4, 19, F32, WALL, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(4, 4, 4, 19, F32, _lib.VLB_OPEN, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(4, 4, 4, 15, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    # 7 q planes of (nodes rounded up to 64) + 4160 elements must stay below 2^31
+    assert lib.vlb3_create(1024, 1024, 15, 27, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(1024, 1024, 15, 19, F32, PER, C.byref(h)) == _lib.VLB_OK
+    lib.vlb3_destroy(h)
+    sizes = {}
+    for q in (19, 27):
+        assert lib.vlb3_create(8, 6, 5, q, F64, WALL, C.byref(h)) == _lib.VLB_OK
+        v = C.c_size_t()
+        assert lib.vlb3_workspace_bytes(h, C.byref(v)) == _lib.VLB_OK
+        sizes[q] = v.value
+        assert v.value >= (2 * 7 * q + 13) * (256 + 4160) * 8
+        lib.vlb3_destroy(h)
+    assert sizes[27] > sizes[19]
+    assert lib.vlb3_create(8, 6, 5, 27, F64, WALL, C.byref(h)) == _lib.VLB_OK
     assert lib.vlb3_set_params(h, 0.1, 0.1, 10.0, 0.01, 0.25, 0.25, 0.0, 0.0, 0.0, 0) == _lib.VLB_OK
     assert lib.vlb3_set_params(h, -0.1, 0.1, 10.0, 0.01, 0.25, 0.25, 0.0, 0.0, 0.0, 0) == _lib.VLB_E_INVALID_ARG
     assert lib.vlb3_step(h, 1) == _lib.VLB_E_STATE  # not bound

@@ -1,6 +1,6 @@
-"""Three-dimensional (D3Q19) form on the GPU against the 3-D oracle: seeded random states
-on ragged grids (periodic and walled, FP64 and FP32), the channel closed form, and at a
-larger size the exchange symmetry of x and z and exact mass."""
+"""Three-dimensional form (D3Q19 and D3Q27) on the GPU against the 3-D oracle: seeded
+random states on ragged grids (periodic and walled, FP64 and FP32), the channel closed
+form, and at a larger size the exchange symmetry of x and z and exact mass."""
 import numpy as np
 import pytest
 
@@ -66,12 +66,13 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
 @pytest.mark.parametrize("name", list(CASES))
-def test_random_state_3d(name, precision, tol):
+def test_random_state_3d(name, precision, tol, q):
     kw = dict(CASES[name])
-    pr = synth.random3d(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), seed=31, **kw)
-    say("3d", name, precision)
+    pr = synth.random3d(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), seed=31, q=q, **kw)
+    say("3d", name, precision, "q", q)
     g, o = _run_pair(pr, 30, precision)
     err = _parity(g, o)
     # rho is read out in the storage precision: in FP32 rho - 1 ~ 1e-2 keeps 1e-5 of it
@@ -79,13 +80,14 @@ def test_random_state_3d(name, precision, tol):
     assert max(err[k] for k in keys) < tol, err
 
 
-def test_first_readout_is_the_initial_state():
+@pytest.mark.parametrize("q", [19, 27])
+def test_first_readout_is_the_initial_state(q):
     """At step 0 the read-out is the initial state (u with the half-force shift, reading
     A17, as the oracle reports it)."""
     import oracle
     from paper_2508_16997_amd.sim3d import Simulation3D
 
-    pr = synth.random3d(20, 6, 3, seed=5, ymode="wall")
+    pr = synth.random3d(20, 6, 3, seed=5, ymode="wall", q=q)
     sim = Simulation3D.from_problem(pr, precision="fp64")
     g = _gpu_fields(sim)
     sim.close()
@@ -98,12 +100,13 @@ def test_first_readout_is_the_initial_state():
     assert np.abs(g["ux"] - init["ux"] - 0.5 * pr.F[0] / init["rho"]).max() < 1e-14
 
 
-def test_channel_3d_fp64_matches_oracle_and_closed_form():
+@pytest.mark.parametrize("q", [19, 27])
+def test_channel_3d_fp64_matches_oracle_and_closed_form(q):
     """The force-driven Oldroyd-B channel (ny = 16, Wi = 1, 8 T_c) equals the oracle to
     1e-10 and, run on to 30 T_c, the closed form as closely as the oracle does."""
     from paper_2508_16997_amd.sim3d import Simulation3D
 
-    pr = synth.channel3d(nx=8, ny=16, nz=8, Ma=0.1)
+    pr = synth.channel3d(nx=8, ny=16, nz=8, Ma=0.1, q=q)
     steps = int(round(8 * pr.meta["Tc"]))
     say("3d channel", steps)
     g, o = _run_pair(pr, steps, "fp64")
@@ -125,7 +128,8 @@ def test_channel_3d_fp64_matches_oracle_and_closed_form():
     assert gre(r["axx"][0, :, 0] - 1, 2 * (lam * du) ** 2) < 3e-2
 
 
-def test_3d_exchange_symmetry_and_mass_at_size():
+@pytest.mark.parametrize("q", [19, 27])
+def test_3d_exchange_symmetry_and_mass_at_size(q):
     """128 x 32 x 128 FP32 channel driven along x and along z for 300 steps: the two runs
     are the same flow with x and z exchanged (to FP32 rounding: the velocity sums run over
     the directions in a fixed order, which the exchange permutes), and the total mass is
@@ -135,8 +139,8 @@ def test_3d_exchange_symmetry_and_mass_at_size():
 
     res = {}
     for axis in ("x", "z"):
-        pr = synth.channel3d(nx=128, ny=32, nz=128, axis=axis, Ma=0.1, precision="fp32")
-        say("3d symmetry", axis)
+        pr = synth.channel3d(nx=128, ny=32, nz=128, axis=axis, Ma=0.1, precision="fp32", q=q)
+        say("3d symmetry", axis, "q", q)
         sim = Simulation3D.from_problem(pr)
         m0 = float(sim.read()["rho"].double().sum())
         sim.step(300)
