@@ -34,16 +34,16 @@ ORDER_NAMES = {0: "automatic", 1: "xcd bands", 2: "row-major", 3: "column strips
 # times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
     "four_roll_512": [
-        {"sources": "a883368e44549859", "tile": 8, "store_mode": "streaming",
-         "tile_order": "xcd bands", "fetch_KiB": 25471.3, "write_KiB": 42147.1,
+        {"sources": "313ff680cd08a8f6", "tile": 8, "store_mode": "streaming",
+         "tile_order": "xcd bands", "fetch_KiB": 25661.1, "write_KiB": 42155.7,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
-        {"sources": "a883368e44549859", "tile": 8, "store_mode": "cached",
-         "tile_order": "xcd bands", "fetch_KiB": 25936.0, "write_KiB": 42128.0,
+        {"sources": "313ff680cd08a8f6", "tile": 8, "store_mode": "cached",
+         "tile_order": "xcd bands", "fetch_KiB": 25819.8, "write_KiB": 42128.0,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
     ],
     "cylinder_4096x1024": [
-        {"sources": "a883368e44549859", "tile": 4, "store_mode": "streaming",
-         "tile_order": "row-major", "fetch_KiB": 442043.1, "write_KiB": 663800.8,
+        {"sources": "313ff680cd08a8f6", "tile": 4, "store_mode": "streaming",
+         "tile_order": "row-major", "fetch_KiB": 442513.1, "write_KiB": 663802.7,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
     ],
 }
