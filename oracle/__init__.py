@@ -313,6 +313,8 @@ def _load3():
     lib.o3_init.argtypes = [P] + [DP] * 10
     lib.o3_step.argtypes = [P, C.c_longlong]
     lib.o3_read.argtypes = [P] + [DP] * 10
+    lib.o3_collide_hydro.restype = C.c_int
+    lib.o3_collide_hydro.argtypes = [C.c_int, DP, D, DP, DP, DP, DP, D, D, DP]
     lib.o3_lattice.restype = C.c_int
     lib.o3_lattice.argtypes = [C.c_int, C.c_void_p, DP, C.c_void_p, DP]
     _lib3 = lib
@@ -350,6 +352,20 @@ class OracleSim3D:
         out = {k: np.zeros(self.shape) for k in FIELDS3}
         _load3().o3_read(self.h, *[_dp(out[k]) for k in FIELDS3])
         return out
+
+
+def collide_hydro3d(q, f, rho, u, F=(0.0, 0.0, 0.0), tau=None, D=(0.0, 0.0, 0.0), tau_s1=1.0,
+                    tau_s2=1.0):
+    """One hydrodynamic collision of the three-dimensional step at a single node (q
+    populations in, q out); tau is the 3 x 3 polymer stress, D the diagonal defects."""
+    f = _c64(np.asarray(f, float))
+    out = np.zeros(int(q))
+    t = _c64(np.zeros((3, 3)) if tau is None else np.asarray(tau, float))
+    a = [_c64(np.asarray(v, float)) for v in (u, F, D)]
+    if _load3().o3_collide_hydro(int(q), _dp(f), float(rho), _dp(a[0]), _dp(a[1]), _dp(t),
+                                 _dp(a[2]), float(tau_s1), float(tau_s2), _dp(out)) != 0:
+        raise ValueError("oracle3d: q must be 19 or 27")
+    return out
 
 
 def lattice3d(q: int = 19):

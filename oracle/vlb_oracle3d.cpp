@@ -561,4 +561,22 @@ int o3_lattice(int q, int* e, double* w, int* opp, double* h3) {
     return L.nb3;
 }
 
+// One hydrodynamic collision at a single node (the collision of the step, exposed for
+// the per-node pins): populations f (q values), rho, u, force F, polymer stress tau
+// (row-major 3 x 3), the diagonal defects D, relaxation times tau_s1, tau_s2; out gets
+// the q post-collision populations.  Returns -1 for another q.
+int o3_collide_hydro(int q, const double* f, double rho, const double* u, const double* F,
+                     const double* tau, const double* D, double tau_s1, double tau_s2,
+                     double* out) {
+    if (q != 19 && q != 27) return -1;
+    Params p;
+    p.tau_s1 = tau_s1;
+    p.tau_s2 = tau_s2;
+    double t[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) t[a][b] = tau[3 * a + b];
+    collide_hydro(q == 27 ? LAT27 : LAT19, f, rho, u, F, t, D, p, out);
+    return 0;
+}
+
 }  // extern "C"

@@ -183,3 +183,44 @@ def test_rest_state_is_exact(o3, q):
         assert np.abs(r[c]).max() < 1e-14, c
     for c in ("axx", "ayy", "azz"):
         assert np.abs(r[c] - 1).max() < 1e-14, c
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_collision_relaxes_each_hermite_order_and_drops_the_rest(o3, q):
+    """Per-node check of the hydrodynamic TRT regularized collision (Sec. 3.1) at fixed
+    rho and u: a non-equilibrium perturbation along a second-order Hermite direction comes
+    out scaled by 1 - 1/tau_s1, one along each third-order basis function of the lattice
+    by 1 - 1/tau_s2, and one orthogonal (in the lattice's weighted inner product) to every
+    Hermite polynomial up to third order is removed.  Catches a basis function left out
+    of the third-order projection (H_xyz on D3Q27, say), a wrong norm, the two relaxation
+    times exchanged, and an unregularized collision."""
+    e, w, opp, h3 = o3.lattice3d(q)
+    ef = e.astype(float)
+    rho, u = 1.02, np.array([0.03, -0.02, 0.015])
+    f0 = w * (1.0 + 0.05 * ef[:, 0] - 0.02 * ef[:, 2])  # any state: rho, u are inputs
+    ts1, ts2 = 0.7, 0.8
+    c1, c2 = 1 - 1 / ts1, 1 - 1 / ts2
+    base = o3.collide_hydro3d(q, f0, rho, u, tau_s1=ts1, tau_s2=ts2)
+
+    def resp(d):
+        return o3.collide_hydro3d(q, f0 + d, rho, u, tau_s1=ts1, tau_s2=ts2) - base
+
+    def H2(a, b):
+        return ef[:, a] * ef[:, b] - CS2 * (a == b)
+
+    eps = 1e-3
+    tol = 1e-12 * eps
+    for d in (w * H2(0, 1), w * H2(1, 2), w * (H2(0, 0) - H2(1, 1)), w * (H2(0, 0) + H2(1, 1) + H2(2, 2))):
+        assert np.abs(resp(eps * d) - c1 * eps * d).max() < tol
+    for m in range(h3.shape[1]):
+        d = eps * w * h3[:, m]
+        assert np.abs(d).max() > 1e-6
+        assert np.abs(resp(d) - c2 * d).max() < tol, m
+    # the content beyond third order: a random vector made orthogonal to 1, e, H2, h3
+    B = np.column_stack([np.ones(q), ef] + [H2(a, b) for a in range(3) for b in range(a, 3)]
+                        + [h3])
+    v = np.random.default_rng(3).normal(size=q)
+    coef = np.linalg.solve(B.T @ (w[:, None] * B), B.T @ (w * v))
+    g = eps * w * (v - B @ coef)
+    assert np.abs(g).max() > 1e-6
+    assert np.abs(resp(g)).max() < tol
