@@ -315,6 +315,8 @@ def _load3():
     lib.o3_read.argtypes = [P] + [DP] * 10
     lib.o3_collide_hydro.restype = C.c_int
     lib.o3_collide_hydro.argtypes = [C.c_int, DP, D, DP, DP, DP, DP, D, D, DP]
+    lib.o3_collide_cde.restype = C.c_int
+    lib.o3_collide_cde.argtypes = [C.c_int, DP, D, D, DP, DP, D, D, DP, D, D, DP]
     lib.o3_lattice.restype = C.c_int
     lib.o3_lattice.argtypes = [C.c_int, C.c_void_p, DP, C.c_void_p, DP]
     _lib3 = lib
@@ -364,6 +366,19 @@ def collide_hydro3d(q, f, rho, u, F=(0.0, 0.0, 0.0), tau=None, D=(0.0, 0.0, 0.0)
     a = [_c64(np.asarray(v, float)) for v in (u, F, D)]
     if _load3().o3_collide_hydro(int(q), _dp(f), float(rho), _dp(a[0]), _dp(a[1]), _dp(t),
                                  _dp(a[2]), float(tau_s1), float(tau_s2), _dp(out)) != 0:
+        raise ValueError("oracle3d: q must be 19 or 27")
+    return out
+
+
+def collide_cde3d(q, g, phi, rho, u, F=(0.0, 0.0, 0.0), S=0.0, Sp=0.0, up=None, tau_p1=1.0,
+                  tau_p2=1.0):
+    """One convection-diffusion collision of the three-dimensional step at a single node."""
+    g = _c64(np.asarray(g, float))
+    out = np.zeros(int(q))
+    a = [_c64(np.asarray(v, float)) for v in (u, F, u if up is None else up)]
+    if _load3().o3_collide_cde(int(q), _dp(g), float(phi), float(rho), _dp(a[0]), _dp(a[1]),
+                               float(S), float(Sp), _dp(a[2]), float(tau_p1), float(tau_p2),
+                               _dp(out)) != 0:
         raise ValueError("oracle3d: q must be 19 or 27")
     return out
 

@@ -579,4 +579,19 @@ int o3_collide_hydro(int q, const double* f, double rho, const double* u, const 
     return 0;
 }
 
+// One convection-diffusion collision at a single node: populations g (q values), phi,
+// rho, u, force F, source S and its previous value Sp, previous velocity up, relaxation
+// times tau_p1, tau_p2; out gets the q post-collision populations.  Returns -1 for
+// another q.
+int o3_collide_cde(int q, const double* g, double phi, double rho, const double* u,
+                   const double* F, double S, double Sp, const double* up, double tau_p1,
+                   double tau_p2, double* out) {
+    if (q != 19 && q != 27) return -1;
+    Params p;
+    p.tau_p1 = tau_p1;
+    p.tau_p2 = tau_p2;
+    collide_cde(q == 27 ? LAT27 : LAT19, g, phi, rho, u, F, S, Sp, up, p, out);
+    return 0;
+}
+
 }  // extern "C"

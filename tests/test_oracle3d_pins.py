@@ -224,3 +224,44 @@ def test_collision_relaxes_each_hermite_order_and_drops_the_rest(o3, q):
     g = eps * w * (v - B @ coef)
     assert np.abs(g).max() > 1e-6
     assert np.abs(resp(g)).max() < tol
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_conformation_collision_relaxes_orders_one_and_two(o3, q):
+    """Per-node check of the convection-diffusion TRT regularized collision (Sec. 3.2) at
+    fixed phi, rho and u without source: a non-equilibrium perturbation along e_a comes out
+    scaled by 1 - 1/tau_p1, one along a second-order Hermite direction by 1 - 1/tau_p2,
+    and anything orthogonal to orders 0-2 is removed; the source enters the zeroth moment
+    as 1.5 S - 0.5 S_prev.  Catches the two relaxation times exchanged, an unregularized
+    collision and a wrong source time difference."""
+    e, w, opp, h3 = o3.lattice3d(q)
+    ef = e.astype(float)
+    phi, rho, u = 1.3, 1.01, np.array([0.02, 0.01, -0.03])
+    g0 = w * (1.2 + 0.04 * ef[:, 1])
+    tp1, tp2 = 0.75, 0.6
+    c1, c2 = 1 - 1 / tp1, 1 - 1 / tp2
+    base = o3.collide_cde3d(q, g0, phi, rho, u, tau_p1=tp1, tau_p2=tp2)
+
+    def resp(d):
+        return o3.collide_cde3d(q, g0 + d, phi, rho, u, tau_p1=tp1, tau_p2=tp2) - base
+
+    def H2(a, b):
+        return ef[:, a] * ef[:, b] - CS2 * (a == b)
+
+    eps = 1e-3
+    tol = 1e-12 * eps
+    for a in range(3):
+        d = eps * w * ef[:, a]
+        assert np.abs(resp(d) - c1 * d).max() < tol, a
+    for d in (w * H2(0, 2), w * (H2(1, 1) - H2(2, 2)), w * (H2(0, 0) + H2(1, 1) + H2(2, 2))):
+        assert np.abs(resp(eps * d) - c2 * eps * d).max() < tol
+    B = np.column_stack([np.ones(q), ef] + [H2(a, b) for a in range(3) for b in range(a, 3)])
+    v = np.random.default_rng(5).normal(size=q)
+    coef = np.linalg.solve(B.T @ (w[:, None] * B), B.T @ (w * v))
+    g = eps * w * (v - B @ coef)
+    assert np.abs(g).max() > 1e-6
+    assert np.abs(resp(g)).max() < tol
+    # source: the zeroth moment of the output grows by 1.5 S - 0.5 S_prev
+    S, Sp = 2e-3, 5e-4
+    out = o3.collide_cde3d(q, g0, phi, rho, u, S=S, Sp=Sp, tau_p1=tp1, tau_p2=tp2)
+    assert abs((out - base).sum() - (1.5 * S - 0.5 * Sp)) < 1e-15
