@@ -317,6 +317,7 @@ def _load3():
     lib.o3_collide_hydro.argtypes = [C.c_int, DP, D, DP, DP, DP, DP, D, D, DP]
     lib.o3_collide_cde.restype = C.c_int
     lib.o3_collide_cde.argtypes = [C.c_int, DP, D, D, DP, DP, D, D, DP, D, D, DP]
+    lib.o3_source.argtypes = [DP, DP, D, DP]
     lib.o3_lattice.restype = C.c_int
     lib.o3_lattice.argtypes = [C.c_int, C.c_void_p, DP, C.c_void_p, DP]
     _lib3 = lib
@@ -380,6 +381,15 @@ def collide_cde3d(q, g, phi, rho, u, F=(0.0, 0.0, 0.0), S=0.0, Sp=0.0, up=None, 
                                float(S), float(Sp), _dp(a[2]), float(tau_p1), float(tau_p2),
                                _dp(out)) != 0:
         raise ValueError("oracle3d: q must be 19 or 27")
+    return out
+
+
+def source3d(A, L, lam):
+    """The three-dimensional constitutive source for the conformation A and the velocity
+    gradient L[g][b] = d_g u_b (3 x 3 each), relaxation time lam."""
+    a, l = _c64(np.asarray(A, float)), _c64(np.asarray(L, float))
+    out = np.zeros((3, 3))
+    _load3().o3_source(_dp(a), _dp(l), float(lam), _dp(out))
     return out
 
 

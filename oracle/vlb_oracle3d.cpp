@@ -284,6 +284,19 @@ double fd(bool lo_wall, double vlo, double v0, bool hi_wall, double vhi) {
     return 0.0;
 }
 
+// Constitutive source of the conformation equation (Sec. 3.2, Oldroyd-B, every index over
+// x, y, z): Phi_ab = -(A_ab - d_ab)/lambda + sum_g (A_ag L_gb + A_gb L_ga) + A_ab tr L with
+// L_gb = d_g u_b.
+void source3(const double Am[3][3], const double L[3][3], double lam, double S[3][3]) {
+    const double trL = L[0][0] + L[1][1] + L[2][2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = -(Am[a][b] - kd(a, b)) / lam;
+            for (int gm = 0; gm < 3; ++gm) s += Am[a][gm] * L[gm][b] + Am[gm][b] * L[gm][a];
+            S[a][b] = s + Am[a][b] * trL;
+        }
+}
+
 struct Sim {
     const Lattice& lat;
     int Q;
@@ -390,14 +403,10 @@ struct Sim {
                 for (int b = 0; b < 3; ++b) Am[a][b] = A[comp(a, b)][n];
             // constitutive source (Oldroyd-B)
             double S[3][3];
-            const double trL = L[0][0] + L[1][1] + L[2][2];
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    double s = -(Am[a][b] - kd(a, b)) / p.lam;
-                    for (int gm = 0; gm < 3; ++gm) s += Am[a][gm] * L[gm][b] + Am[gm][b] * L[gm][a];
-                    s += Am[a][b] * trL;
-                    S[a][b] = p.no_source ? 0.0 : s;
-                }
+            source3(Am, L, p.lam, S);
+            if (p.no_source)
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) S[a][b] = 0.0;
             double tau[3][3];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) tau[a][b] = p.eta_p / p.lam * (Am[a][b] - kd(a, b));
@@ -592,6 +601,20 @@ int o3_collide_cde(int q, const double* g, double phi, double rho, const double*
     p.tau_p2 = tau_p2;
     collide_cde(q == 27 ? LAT27 : LAT19, g, phi, rho, u, F, S, Sp, up, p, out);
     return 0;
+}
+
+// The constitutive source for a conformation A and velocity gradient L_gb = d_g u_b
+// (both row-major 3 x 3), relaxation time lam, into S (row-major 3 x 3).
+void o3_source(const double* A, const double* L, double lam, double* S) {
+    double a[3][3], l[3][3], s[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            a[i][j] = A[3 * i + j];
+            l[i][j] = L[3 * i + j];
+        }
+    source3(a, l, lam, s);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S[3 * i + j] = s[i][j];
 }
 
 }  // extern "C"

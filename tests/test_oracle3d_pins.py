@@ -265,3 +265,32 @@ def test_conformation_collision_relaxes_orders_one_and_two(o3, q):
     S, Sp = 2e-3, 5e-4
     out = o3.collide_cde3d(q, g0, phi, rho, u, S=S, Sp=Sp, tau_p1=tp1, tau_p2=tp2)
     assert abs((out - base).sum() - (1.5 * S - 0.5 * Sp)) < 1e-15
+
+
+def test_source_vanishes_on_the_steady_states_of_three_dimensional_flows(o3):
+    """The constitutive source (Sec. 3.2, Oldroyd-B with every index over x, y, z) is zero
+    on the closed-form steady conformations: uniaxial extension u = e (x, -y/2, -z/2),
+    A = diag(1/(1 - 2 Wi), 1/(1 + Wi), 1/(1 + Wi)) with Wi = lambda e; simple shear
+    u_x = g z in the x-z plane, A_xz = lambda g, A_xx = 1 + 2 (lambda g)^2; and A = I
+    under a rigid rotation.  A uniform dilation L = d I at A = I gives (2 + 3) d I (the
+    upper-convected terms and A tr L).  Catches a transposed gradient, a dropped or
+    doubled upper-convected term, a wrong z index and the A tr L term left out."""
+    lam = 3.0
+    for e in (0.02, -0.05, 0.1):
+        L = np.diag([e, -e / 2, -e / 2])
+        Wi = lam * e
+        A = np.diag([1 / (1 - 2 * Wi), 1 / (1 + Wi), 1 / (1 + Wi)])
+        assert np.abs(o3.source3d(A, L, lam)).max() < 1e-15, e
+    for g in (0.01, 0.2):
+        L = np.zeros((3, 3))
+        L[2, 0] = g  # d_z u_x
+        A = np.eye(3)
+        A[0, 2] = A[2, 0] = lam * g
+        A[0, 0] = 1 + 2 * (lam * g) ** 2
+        assert np.abs(o3.source3d(A, L, lam)).max() < 1e-15, g
+        # the transposed arrangement (u_z = g x) is a different flow: not steady here
+        assert np.abs(o3.source3d(A, L.T, lam)).max() > 1e-3 * g
+    W = np.array([[0.0, 0.03, -0.02], [-0.03, 0.0, 0.05], [0.02, -0.05, 0.0]])
+    assert np.abs(o3.source3d(np.eye(3), W, lam)).max() < 1e-16
+    d = 0.01
+    assert np.abs(o3.source3d(np.eye(3), d * np.eye(3), lam) - 5 * d * np.eye(3)).max() < 1e-16
