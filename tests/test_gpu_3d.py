@@ -63,6 +63,9 @@ CASES = {
     "periodic_ragged": dict(nx=70, ny=9, nz=5, ymode="periodic"),
     "walls_ragged": dict(nx=67, ny=10, nz=4, ymode="wall"),
     "walls_small": dict(nx=5, ny=6, nz=7, ymode="wall"),
+    # one-node periodic axes: every pull along x and z wraps onto the node itself
+    "degenerate_axes": dict(nx=1, ny=7, nz=1, ymode="wall"),
+    "one_row_periodic": dict(nx=3, ny=1, nz=2, ymode="periodic"),
 }
 
 
