@@ -157,3 +157,39 @@ def test_3d_exchange_symmetry_and_mass_at_size(q):
     for axis in ("x", "z"):
         r, m0 = res[axis]
         assert abs(r["rho"].sum() / m0 - 1) < 1e-6
+
+
+@pytest.mark.parametrize("q,nz", [(19, 985), (27, 693)])
+def test_largest_grid_matches_its_one_column_problem(q, nz):
+    """The largest grid vlb3_create accepts on each lattice (256 x 64 x nz, 7 q planes of
+    just under 2^31 / (7 q) elements: 16.1 M nodes on D3Q19, 11.4 M on D3Q27), FP64, where
+    the byte offsets of the upper planes within a lattice pass 2^31: an x- and
+    z-invariant channel state stays bit-identical, column by column, to the same state on
+    a 1 x 64 x 1 grid after 20 steps."""
+    import torch
+    from paper_2508_16997_amd.sim3d import Simulation3D
+
+    ny = 64
+    pr = synth.channel3d(nx=1, ny=ny, nz=1, Ma=0.1, q=q)
+    y = np.arange(ny) + 0.5
+    Uc, lam = pr.meta["Uc"], pr.lam
+    ux = 4 * Uc * y * (ny - y) / ny ** 2
+    du = 4 * Uc * (ny - 2 * y) / ny ** 2
+    prof = dict(ux=ux, axy=0.5 * lam * du, axx=1 + (lam * du) ** 2)
+    res = {}
+    for nx_, nz_ in ((1, 1), (256, nz)):
+        say("3d largest", q, nx_, ny, nz_)
+        sim = Simulation3D(nx_, ny, nz_, "wall", "fp64", q=q)
+        sim.set_params(pr.nu_s, pr.eta_p, pr.lam, pr.kappa, pr.Lambda_s, pr.Lambda_p, *pr.F)
+        sim.init(**{k: v.reshape(1, ny, 1) for k, v in prof.items()})
+        sim.step(20)
+        res[nx_] = sim.read()
+        torch.cuda.synchronize()
+        sim.close()
+        del sim
+    small, big = res[1], res[256]
+    for k in small:
+        assert torch.equal(big[k], small[k].expand_as(big[k])), k
+    assert float(small["ux"].abs().max()) > 0.5 * Uc
+    del res, small, big
+    torch.cuda.empty_cache()
