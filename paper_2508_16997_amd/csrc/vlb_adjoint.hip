@@ -266,18 +266,88 @@ __device__ __forceinline__ void block_sum(T v, T* s_red, double* slot, bool add)
     __syncthreads();
 }
 
+// Transpose of the finite differences and of the macroscopic moments at fluid node
+// (x, y) (slot p, geometry bits b) from the per-node intermediates sc of the local pass:
+// the final hydrodynamic adjoint populations v and this node's contributions to dL/dF.
+template <class S, bool WALLS>
+__device__ __forceinline__ void gather_at(const RunDev<S>& R, long long plane, const S* sc, int x,
+                                          int y, unsigned p, unsigned b, T v[9], T& gFx, T& gFy) {
+    auto rd = [&](int c, unsigned q) -> T { return ldu(sc + c * plane, q); };
+    // The derivative along an axis at node n is c0(n) psi(n - e) + c1(n) psi(n) +
+    // c2(n) psi(n + e) with coefficients set by n's own walls.  Node x enters its own
+    // derivatives with c1(x), those of its fluid low neighbour with c2(low) and those of
+    // its fluid high neighbour with c0(high).
+    T cx[3], cy[3];
+    node_fd_coefs(R, (int)p, b, cx, cy);
+    T wLx[3] = {0.0, 0.0, 0.0}, wLy[3] = {0.0, 0.0, 0.0};  // a_Lxx/a_Lxy/a_Dx, a_Lyx/a_Lyy/a_Dy
+    const int cxs[3] = {SC_LXX, SC_LXY, SC_DX}, cys[3] = {SC_LYX, SC_LYY, SC_DY};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        wLx[c] = cx[1] * rd(cxs[c], p);
+        wLy[c] = cy[1] * rd(cys[c], p);
+    }
+    auto neighbour = [&](int bitdir, int dx, int dy, int slot_c, T* w, const int* chans) {
+        if ((b >> bitdir) & 1u) return;  // not a fluid node
+        const unsigned q = (unsigned)nb_slot(R, x, y, dx, dy);
+        T c[3], cdum[3];
+        const unsigned bn = WALLS ? node_bits(R, (int)q) : 0u;
+        if (dx != 0) node_fd_coefs(R, (int)q, bn, c, cdum);
+        else node_fd_coefs(R, (int)q, bn, cdum, c);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] += c[slot_c] * rd(chans[k], q);
+    };
+    neighbour(1, -1, 0, 2, wLx, cxs);  // low x neighbour: x is its high neighbour
+    neighbour(3, 1, 0, 0, wLx, cxs);
+    neighbour(2, 0, -1, 2, wLy, cys);
+    neighbour(4, 0, 1, 0, wLy, cys);
+
+    const T rho = rd(SC_R, p), ux = rd(SC_VX, p), uy = rd(SC_VY, p);
+    T a_rho = rd(SC_RHO, p), a_ux = rd(SC_UX, p), a_uy = rd(SC_UY, p);
+    a_ux += wLx[0] + wLy[0];
+    a_uy += wLx[1] + wLy[1];
+    const T a_px = wLx[2], a_py = wLy[2];  // adjoints of rho ux^3, rho uy^3
+    a_rho += a_px * ux * ux * ux + a_py * uy * uy * uy;
+    a_ux += 3.0 * a_px * rho * ux * ux;
+    a_uy += 3.0 * a_py * rho * uy * uy;
+    // rho = 1 + sum f, u = (j + F/2) / rho
+    const T inv = 1.0 / rho;
+    Mom m;
+    m.m0 = rd(SC_MF + 0, p) + a_rho - (ux * a_ux + uy * a_uy) * inv;
+    m.mx = rd(SC_MF + 1, p) + a_ux * inv;
+    m.my = rd(SC_MF + 2, p) + a_uy * inv;
+    m.pxx = rd(SC_MF + 3, p);
+    m.pyy = rd(SC_MF + 4, p);
+    m.pxy = rd(SC_MF + 5, p);
+    m.qxxy = rd(SC_MF + 6, p);
+    m.qxyy = rd(SC_MF + 7, p);
+    expand(m, v);
+    gFx = rd(SC_FX, p) + 0.5 * a_ux * inv;
+    gFy = rd(SC_FY, p) + 0.5 * a_uy * inv;
+}
+
 // WALLS = false compiles the periodic form (no geometry bits: every wall branch folds
 // away and the kernel keeps the register budget of three waves per SIMD).
-template <class S, int TY, bool WALLS>
+// FUSED: the hydrodynamic adjoints of the state after this step -- the gather of the
+// later step, from its intermediates scr_in -- are formed here for the tile and its
+// one-node ring into LDS (rounded to the storage type, as the separate gather stores
+// them) instead of being read from ain, and this tile's dL/dF contributions of that
+// gather are added; ain then supplies the conformation and history adjoints only.
+// Not FUSED (the first reverse step): all of them come from ain.  Intermediates of this
+// step go to scr_out (a different buffer: other tiles' rings still read scr_in).
+template <class S, int TY, bool WALLS, bool FUSED>
 __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __restrict__ run,
                                                        const AdjDev<S>* __restrict__ adj,
                                                        const Item* __restrict__ items, int first,
                                                        const S* __restrict__ ain,
-                                                       S* __restrict__ aout) {
+                                                       S* __restrict__ aout,
+                                                       const S* __restrict__ scr_in,
+                                                       S* __restrict__ scr_out) {
     __shared__ T s_rho[TY + 2][66];
     __shared__ T s_ux[TY + 2][66];
     __shared__ T s_uy[TY + 2][66];
     __shared__ T s_red[TY];
+    constexpr int AF = FUSED ? 9 : 1, AFY = FUSED ? TY + 2 : 1, AFX = FUSED ? 66 : 1;
+    __shared__ S s_af[AF][AFY][AFX];
     const Item it = items[blockIdx.x];
     const RunDev<S>& R = *run;
     const AdjDev<S>& A = *adj;
@@ -296,6 +366,28 @@ __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __res
     // ---- forward front end of step n (as in the step kernel) ----
     S f[9], g[3][9];
     T Fx = 0.0, Fy = 0.0, hS[3] = {0.0, 0.0, 0.0}, hux = 0.0, huy = 0.0;
+    if (FUSED) {
+        // gather of the later step over the tile and its ring (wrapped on every axis, as
+        // the pulls' neighbours are; cells no fluid node of the tile reads are harmless
+        // extra work); the tile's own nodes add that gather's dL/dF, each node once over
+        // the grid, in the order of the reverse steps as the separate gather did
+        for (int r = tid; r < (TY + 2) * 66; r += 64 * TY) {
+            const int lcy = r / 66, lcx = r - lcy * 66;
+            const int cx = x0 - 1 + lcx, cy = y0 - 1 + lcy;
+            const int wx = ((cx % R.nx) + R.nx) % R.nx, wy = ((cy % R.ny) + R.ny) % R.ny;
+            const unsigned q = (unsigned)node_index(R, wx, wy);
+            const unsigned bq = WALLS ? node_bits(R, (int)q) : 0u;
+            if (bq & BIT_SELF_SOLID) continue;
+            T v[9], fx, fy;
+            gather_at<S, WALLS>(R, plane, scr_in, wx, wy, q, bq, v, fx, fy);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) s_af[i][lcy][lcx] = (S)v[i];
+            if (lcx >= 1 && lcx <= 64 && lcy >= 1 && lcy <= TY && cx < R.nx && cy < R.ny) {
+                A.gF[q] += fx;
+                A.gF[plane + q] += fy;
+            }
+        }
+    }
     if (active) {
         pull36(R, src, p, pull, f, g);
         node_force(R, p, Fx, Fy);
@@ -334,7 +426,7 @@ __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __res
     if (in_dom && !active) {
         // solid node: nothing flows through it
         for (int c = 0; c < 41; ++c) stu(aout + c * plane, (unsigned)p, 0.0);
-        for (int c = 0; c < SC_NPLANES; ++c) stu(A.scr + c * plane, (unsigned)p, 0.0);
+        for (int c = 0; c < SC_NPLANES; ++c) stu(scr_out + c * plane, (unsigned)p, 0.0);
     }
     if (active) {
         // velocity gradient by the step kernel's differences (wall-aware at fraction q)
@@ -395,21 +487,26 @@ __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __res
         };
         auto solid_nb = [&](int i) -> bool { return (b >> opp(i)) & 1u; };
 
+        // hydrodynamic adjoint of direction c at the node (dx, dy) from this one (slot)
+        auto afh = [&](int c, int dx, int dy, unsigned slot) -> T {
+            if constexpr (FUSED) return (T)s_af[c][ly + 1 + dy][lx + 1 + dx];
+            else return ldu(ain + c * plane, slot);
+        };
         T o[9];
-        o[0] = ldu(ain, (unsigned)p);
+        o[0] = afh(0, 0, 0, (unsigned)p);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int d = opp(i);
             T v;
             if (!solid_nb(i)) {
                 const unsigned q_ = nb(i);
-                v = ldu(ain + i * plane, q_);
+                v = afh(i, ex(i), ey(i), q_);
                 if (WALLS && R.has_curved) {
                     // (first branch at the neighbour) x + e_i pulls d from x + 2 e_i
                     const unsigned bn = node_bits(R, (int)q_);
                     if ((bn >> d) & 1u) {
                         const T qn = lq(bn, (int)q_, d);
-                        if (qn < 0.5) v += (1.0 - 2.0 * qn) * ldu(ain + d * plane, q_);
+                        if (qn < 0.5) v += (1.0 - 2.0 * qn) * afh(d, ex(i), ey(i), q_);
                     }
                 }
             } else {
@@ -417,12 +514,12 @@ __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __res
                 T alpha;
                 if (q < 0.5) alpha = ((b >> i) & 1u) ? 1.0 : 2.0 * q;  // far = x - e_i
                 else alpha = 1.0 / (2.0 * q);
-                v = alpha * ldu(ain + d * plane, (unsigned)p);
+                v = alpha * afh(d, 0, 0, (unsigned)p);
             }
             if ((b >> i) & 1u) {
                 // (second branch) this node pulls i from x - e_i solid with q > 1/2
                 const T q = lq(b, p, i);
-                if (q > 0.5) v += (2.0 * q - 1.0) / (2.0 * q) * ldu(ain + i * plane, (unsigned)p);
+                if (q > 0.5) v += (2.0 * q - 1.0) / (2.0 * q) * afh(i, 0, 0, (unsigned)p);
             }
             o[i] = v;
         }
@@ -525,7 +622,7 @@ __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __res
         stu(aout + (ADJ_HIST + 3) * plane, (unsigned)p, a_uxp);
         stu(aout + (ADJ_HIST + 4) * plane, (unsigned)p, a_uyp);
 
-        S* sc = A.scr;
+        S* sc = scr_out;
         const T mfv[8] = {ha.mf.m0, ha.mf.mx, ha.mf.my, ha.mf.pxx, ha.mf.pyy, ha.mf.pxy,
                           ha.mf.qxxy, ha.mf.qxyy};
 #pragma unroll
@@ -549,10 +646,13 @@ __global__ __launch_bounds__(64 * TY, 2) void k_adj_local(const RunDev<S>* __res
     block_sum<TY>(geta, s_red, A.part + 2 * blockIdx.x + 1, true);
 }
 
+// The gather as a launch of its own: after the last reverse step (step 0), whose
+// hydrodynamic adjoints no later step takes into its own launch.
 template <class S, int TY, bool WALLS>
 __global__ __launch_bounds__(64 * TY) void k_adj_gather(const RunDev<S>* __restrict__ run,
                                                         const AdjDev<S>* __restrict__ adj,
                                                         const Item* __restrict__ items,
+                                                        const S* __restrict__ scr,
                                                         S* __restrict__ aout) {
     const Item it = items[blockIdx.x];
     const RunDev<S>& R = *run;
@@ -563,62 +663,13 @@ __global__ __launch_bounds__(64 * TY) void k_adj_gather(const RunDev<S>* __restr
     const unsigned p = (unsigned)node_index(R, x, y);
     const unsigned b = WALLS ? node_bits(R, (int)p) : 0u;
     if (b & BIT_SELF_SOLID) return;
-    const S* sc = A.scr;
-    auto rd = [&](int c, unsigned q) -> T { return ldu(sc + c * plane, q); };
-    // The derivative along an axis at node n is c0(n) psi(n - e) + c1(n) psi(n) +
-    // c2(n) psi(n + e) with coefficients set by n's own walls.  Node x enters its own
-    // derivatives with c1(x), those of its fluid low neighbour with c2(low) and those of
-    // its fluid high neighbour with c0(high).
-    T cx[3], cy[3];
-    node_fd_coefs(R, (int)p, b, cx, cy);
-    T wLx[3] = {0.0, 0.0, 0.0}, wLy[3] = {0.0, 0.0, 0.0};  // a_Lxx/a_Lxy/a_Dx, a_Lyx/a_Lyy/a_Dy
-    const int cxs[3] = {SC_LXX, SC_LXY, SC_DX}, cys[3] = {SC_LYX, SC_LYY, SC_DY};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        wLx[c] = cx[1] * rd(cxs[c], p);
-        wLy[c] = cy[1] * rd(cys[c], p);
-    }
-    auto neighbour = [&](int bitdir, int dx, int dy, int slot_c, T* w, const int* chans) {
-        if ((b >> bitdir) & 1u) return;  // not a fluid node
-        const unsigned q = (unsigned)nb_slot(R, x, y, dx, dy);
-        T c[3], cdum[3];
-        const unsigned bn = WALLS ? node_bits(R, (int)q) : 0u;
-        if (dx != 0) node_fd_coefs(R, (int)q, bn, c, cdum);
-        else node_fd_coefs(R, (int)q, bn, cdum, c);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) w[k] += c[slot_c] * rd(chans[k], q);
-    };
-    neighbour(1, -1, 0, 2, wLx, cxs);  // low x neighbour: x is its high neighbour
-    neighbour(3, 1, 0, 0, wLx, cxs);
-    neighbour(2, 0, -1, 2, wLy, cys);
-    neighbour(4, 0, 1, 0, wLy, cys);
-
-    const T rho = rd(SC_R, p), ux = rd(SC_VX, p), uy = rd(SC_VY, p);
-    T a_rho = rd(SC_RHO, p), a_ux = rd(SC_UX, p), a_uy = rd(SC_UY, p);
-    a_ux += wLx[0] + wLy[0];
-    a_uy += wLx[1] + wLy[1];
-    const T a_px = wLx[2], a_py = wLy[2];  // adjoints of rho ux^3, rho uy^3
-    a_rho += a_px * ux * ux * ux + a_py * uy * uy * uy;
-    a_ux += 3.0 * a_px * rho * ux * ux;
-    a_uy += 3.0 * a_py * rho * uy * uy;
-    // rho = 1 + sum f, u = (j + F/2) / rho
-    const T inv = 1.0 / rho;
-    Mom m;
-    m.m0 = rd(SC_MF + 0, p) + a_rho - (ux * a_ux + uy * a_uy) * inv;
-    m.mx = rd(SC_MF + 1, p) + a_ux * inv;
-    m.my = rd(SC_MF + 2, p) + a_uy * inv;
-    m.pxx = rd(SC_MF + 3, p);
-    m.pyy = rd(SC_MF + 4, p);
-    m.pxy = rd(SC_MF + 5, p);
-    m.qxxy = rd(SC_MF + 6, p);
-    m.qxyy = rd(SC_MF + 7, p);
-    T v[9];
-    expand(m, v);
+    T v[9], gFx, gFy;
+    gather_at<S, WALLS>(R, plane, scr, x, y, p, b, v, gFx, gFy);
 #pragma unroll
     for (int i = 0; i < 9; ++i) stu(aout + i * plane, p, v[i]);
     double* gF = A.gF;
-    gF[p] += rd(SC_FX, p) + 0.5 * a_ux * inv;
-    gF[plane + p] += rd(SC_FY, p) + 0.5 * a_uy * inv;
+    gF[p] += gFx;
+    gF[plane + p] += gFy;
 }
 
 // Adjoint of the state after the last step from dL/du there (u read out with the
@@ -692,26 +743,28 @@ hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, c
     return hipGetLastError();
 }
 
-template <class S, bool WALLS>
-hipError_t launch_adj_step_w(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
-                             int nitems, int ty, int first, const S* ain, S* aout, hipStream_t s) {
+template <class S, bool WALLS, bool FUSED>
+hipError_t launch_adj_local_w(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                              int nitems, int ty, int first, const S* ain, S* aout,
+                              const S* scr_in, S* scr_out, hipStream_t s) {
     switch (ty) {
-        case 1:
-            hipLaunchKernelGGL((k_adj_local<S, 1, WALLS>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 1, WALLS>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, aout);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_adj_local<S, 2, WALLS>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 2, WALLS>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, aout);
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_adj_local<S, 4, WALLS>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 4, WALLS>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, aout);
-            break;
-        case 8:
-            hipLaunchKernelGGL((k_adj_local<S, 8, WALLS>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, first, ain, aout);
-            hipLaunchKernelGGL((k_adj_gather<S, 8, WALLS>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, aout);
-            break;
+        case 1: hipLaunchKernelGGL((k_adj_local<S, 1, WALLS, FUSED>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, first, ain, aout, scr_in, scr_out); break;
+        case 2: hipLaunchKernelGGL((k_adj_local<S, 2, WALLS, FUSED>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, first, ain, aout, scr_in, scr_out); break;
+        case 4: hipLaunchKernelGGL((k_adj_local<S, 4, WALLS, FUSED>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, first, ain, aout, scr_in, scr_out); break;
+        case 8: hipLaunchKernelGGL((k_adj_local<S, 8, WALLS, FUSED>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, first, ain, aout, scr_in, scr_out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class S, bool WALLS>
+hipError_t launch_adj_gather_w(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                               int nitems, int ty, const S* scr, S* aout, hipStream_t s) {
+    switch (ty) {
+        case 1: hipLaunchKernelGGL((k_adj_gather<S, 1, WALLS>), dim3(nitems), dim3(64, 1), 0, s, run_dev, adj_dev, items, scr, aout); break;
+        case 2: hipLaunchKernelGGL((k_adj_gather<S, 2, WALLS>), dim3(nitems), dim3(64, 2), 0, s, run_dev, adj_dev, items, scr, aout); break;
+        case 4: hipLaunchKernelGGL((k_adj_gather<S, 4, WALLS>), dim3(nitems), dim3(64, 4), 0, s, run_dev, adj_dev, items, scr, aout); break;
+        case 8: hipLaunchKernelGGL((k_adj_gather<S, 8, WALLS>), dim3(nitems), dim3(64, 8), 0, s, run_dev, adj_dev, items, scr, aout); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -719,16 +772,29 @@ hipError_t launch_adj_step_w(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev,
 
 template <class S>
 hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
-                           int nitems, int ty, int first, int walls, const S* ain, S* aout,
-                           hipStream_t s) {
+                           int nitems, int ty, int first, int walls, int fused, const S* ain,
+                           S* aout, const S* scr_in, S* scr_out, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    return walls ? launch_adj_step_w<S, true>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, s)
-                 : launch_adj_step_w<S, false>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, s);
+    if (walls)
+        return fused ? launch_adj_local_w<S, true, true>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, scr_in, scr_out, s)
+                     : launch_adj_local_w<S, true, false>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, scr_in, scr_out, s);
+    return fused ? launch_adj_local_w<S, false, true>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, scr_in, scr_out, s)
+                 : launch_adj_local_w<S, false, false>(run_dev, adj_dev, items, nitems, ty, first, ain, aout, scr_in, scr_out, s);
+}
+
+template <class S>
+hipError_t launch_adj_gather(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                             int nitems, int ty, int walls, const S* scr, S* aout, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    return walls ? launch_adj_gather_w<S, true>(run_dev, adj_dev, items, nitems, ty, scr, aout, s)
+                 : launch_adj_gather_w<S, false>(run_dev, adj_dev, items, nitems, ty, scr, aout, s);
 }
 
 template hipError_t launch_adj_seed<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, const float*, int, float*, hipStream_t);
 template hipError_t launch_adj_seed<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, const double*, int, double*, hipStream_t);
-template hipError_t launch_adj_step<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, int, int, const float*, float*, hipStream_t);
-template hipError_t launch_adj_step<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_adj_step<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, int, int, int, const float*, float*, const float*, float*, hipStream_t);
+template hipError_t launch_adj_step<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, int, int, int, const double*, double*, const double*, double*, hipStream_t);
+template hipError_t launch_adj_gather<float>(const RunDev<float>*, const AdjDev<float>*, const Item*, int, int, int, const float*, float*, hipStream_t);
+template hipError_t launch_adj_gather<double>(const RunDev<double>*, const AdjDev<double>*, const Item*, int, int, int, const double*, double*, hipStream_t);
 
 }  // namespace vlb

@@ -1049,7 +1049,7 @@ struct AdjLayout {
     size_t state = 0;  // bytes of one saved state (vlb_save_state layout), 256-aligned
     int K = 1, nseg = 0;
     size_t off_desc = 0, off_adjdev = 0, off_ckpt = 0, off_slot = 0, off_a[2] = {0, 0},
-           off_scr = 0, off_gF = 0, off_part = 0, off_loss = 0, total = 0;
+           off_scr[2] = {0, 0}, off_gF = 0, off_part = 0, off_loss = 0, total = 0;
 };
 
 AdjLayout adj_layout(const vlb_sim* s, int64_t nsteps, int stride) {
@@ -1068,7 +1068,9 @@ AdjLayout adj_layout(const vlb_sim* s, int64_t nsteps, int stride) {
     L.off_slot = take((size_t)L.K * L.state);
     L.off_a[0] = take(41 * pb);
     L.off_a[1] = take(41 * pb);
-    L.off_scr = take(22 * pb);
+    // intermediates of consecutive reverse steps alternate between two buffers
+    L.off_scr[0] = take(22 * pb);
+    L.off_scr[1] = take(22 * pb);
     L.off_gF = take(2 * (size_t)s->plane * sizeof(double));
     L.off_part = take(2 * (size_t)std::max(1, s->nitems) * sizeof(double));
     L.off_loss = take((size_t)std::max(1, s->nitems) * sizeof(double));
@@ -1144,7 +1146,8 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
     if (rc) return rc;
     vlb::AdjDev<T> a{};
     a.nx = s->nx; a.ny = s->ny; a.pitch = s->pitch; a.off0 = s->off0; a.plane = s->plane;
-    a.scr = reinterpret_cast<T*>(ws + L.off_scr);
+    a.scr = nullptr;
+    T* scr[2] = {reinterpret_cast<T*>(ws + L.off_scr[0]), reinterpret_cast<T*>(ws + L.off_scr[1])};
     a.gF = reinterpret_cast<double*>(ws + L.off_gF);
     a.part = reinterpret_cast<double*>(ws + L.off_part);
     a.lossp = reinterpret_cast<double*>(ws + L.off_loss);
@@ -1163,7 +1166,7 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
     const Run<T>* rs = s->dptr<Run<T>>(s->off_run);
     VLB_HIP(vlb::launch_adj_seed<T>(rs, ad, items, s->nitems, s->ty, s->dptr<T>(s->off_pop[s->parity]),
                                     s->first ? 0 : 1, abuf[0], s->stream));
-    int cur = 0;
+    int cur = 0, sc = 0, fused = 0;
     const Run<T>* desc = reinterpret_cast<const Run<T>*>(ws + L.off_desc);
     for (int g = L.nseg - 1; g >= 0; --g) {
         const int64_t len = std::min<int64_t>(stride, nsteps - (int64_t)g * stride);
@@ -1177,12 +1180,18 @@ int adj_backward(vlb_sim* s, const void* gx, const void* gy, int is_target, doub
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const int first = (g == 0 && k == 0 && s->adj.first0) ? 1 : 0;
+            // the later step's gather runs inside this launch (all but the first)
             VLB_HIP(vlb::launch_adj_step<T>(desc + k, ad, items, s->nitems, s->ty, first,
-                                            s->has_bits ? 1 : 0, abuf[cur],
-                                            abuf[cur ^ 1], s->stream));
+                                            s->has_bits ? 1 : 0, fused, abuf[cur],
+                                            abuf[cur ^ 1], scr[sc], scr[sc ^ 1], s->stream));
             cur ^= 1;
+            sc ^= 1;
+            fused = 1;
         }
     }
+    if (fused)
+        VLB_HIP(vlb::launch_adj_gather<T>(rs, ad, items, s->nitems, s->ty, s->has_bits ? 1 : 0,
+                                          scr[sc], abuf[cur], s->stream));
     const size_t row = (size_t)s->nx * sizeof(double);
     const size_t pitchb = (size_t)s->pitch * sizeof(double);
     const double* gF = reinterpret_cast<const double*>(ws + L.off_gF) + s->off0;

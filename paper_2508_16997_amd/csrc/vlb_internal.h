@@ -101,7 +101,7 @@ template <class S>
 struct AdjDev {
     int nx, ny, pitch, off0;
     long long plane;
-    S* scr;          // 22 planes of per-node intermediates written by the local pass
+    S* scr;          // unused (the intermediates' two buffers are launch arguments)
     double* gF;      // 2 planes: accumulated dL/dF_x, dL/dF_y
     double* part;    // 2 per work item: accumulated dL/dlambda, dL/deta_p partials
     double* lossp;   // 1 per work item: loss partials of the seed
@@ -154,11 +154,19 @@ hipError_t launch_monitor(const RunDev<S>& run_host, const RunDev<S>* run_dev, i
 template <class S>
 hipError_t launch_adj_seed(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
                            int nitems, int ty, const S* src, int pull, S* aout, hipStream_t s);
-// walls: the run has geometry bits (walls, solids); 0 selects the periodic kernels.
+// One reverse step: walls: the run has geometry bits (walls, solids), 0 selects the
+// periodic kernels; fused: the hydrodynamic adjoints of ain are formed in the launch from
+// the later step's intermediates scr_in (every reverse step but the first); the step's
+// own intermediates go to scr_out.
 template <class S>
 hipError_t launch_adj_step(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
-                           int nitems, int ty, int first, int walls, const S* ain, S* aout,
-                           hipStream_t s);
+                           int nitems, int ty, int first, int walls, int fused, const S* ain,
+                           S* aout, const S* scr_in, S* scr_out, hipStream_t s);
+// The gather of the last reverse step (step 0): its hydrodynamic adjoints into aout and
+// its dL/dF, from its intermediates scr.
+template <class S>
+hipError_t launch_adj_gather(const RunDev<S>* run_dev, const AdjDev<S>* adj_dev, const Item* items,
+                             int nitems, int ty, int walls, const S* scr, S* aout, hipStream_t s);
 // Momentum-exchange force: per block of 256 boundary links, 2 partial sums (F_x, F_y).
 template <class S>
 hipError_t launch_drag(const RunDev<S>* run_dev, const int* links, int nlinks, int circle,
