@@ -34,16 +34,16 @@ ORDER_NAMES = {0: "automatic", 1: "xcd bands", 2: "row-major", 3: "column strips
 # times; otherwise the bench reports null.
 MEASURED_TRAFFIC = {
     "four_roll_512": [
-        {"sources": "313ff680cd08a8f6", "tile": 8, "store_mode": "streaming",
-         "tile_order": "xcd bands", "fetch_KiB": 25661.1, "write_KiB": 42155.7,
+        {"sources": "fe274e1098cea5b8", "tile": 8, "store_mode": "streaming",
+         "tile_order": "xcd bands", "fetch_KiB": 25532.4, "write_KiB": 42147.2,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
-        {"sources": "313ff680cd08a8f6", "tile": 8, "store_mode": "cached",
-         "tile_order": "xcd bands", "fetch_KiB": 25819.8, "write_KiB": 42128.0,
+        {"sources": "fe274e1098cea5b8", "tile": 8, "store_mode": "cached",
+         "tile_order": "xcd bands", "fetch_KiB": 25923.2, "write_KiB": 42128.0,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
     ],
     "cylinder_4096x1024": [
-        {"sources": "313ff680cd08a8f6", "tile": 4, "store_mode": "streaming",
-         "tile_order": "row-major", "fetch_KiB": 442513.1, "write_KiB": 663802.7,
+        {"sources": "fe274e1098cea5b8", "tile": 4, "store_mode": "streaming",
+         "tile_order": "row-major", "fetch_KiB": 440269.9, "write_KiB": 663801.3,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
     ],
 }
