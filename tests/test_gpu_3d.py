@@ -193,3 +193,21 @@ def test_largest_grid_matches_its_one_column_problem(q, nz):
     assert float(small["ux"].abs().max()) > 0.5 * Uc
     del res, small, big
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_random_state_at_the_benchmark_size(q):
+    """The benchmark grid (256 x 64 x 256, half-way walls in y, FP32 storage, the launch
+    configuration the bench leg times) from a seeded random state: every field after 3
+    steps against the oracle, element by element (FP32 storage bar)."""
+    import oracle
+
+    pr = synth.random3d(256, 64, 256, seed=8, ymode="wall", q=q, precision="fp32")
+    say("3d bench size", q)
+    g, o = _run_pair(pr, 3, "fp32")
+    err = _parity(g, o)
+    keys = [k for k in err if k != "rho"]
+    assert max(err[k] for k in keys) < 1e-5, err
+    for k in ("ux", "uy", "uz", "axx", "axy", "azz"):
+        scale = np.abs(o[k]).max()
+        assert np.abs(g[k] - o[k]).max() < 1e-5 * scale + 1e-9, k
