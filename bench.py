@@ -485,9 +485,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); the "
-              "coupled step is a single-GPU kernel and multi-GPU runs are not part of this "
-              "build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): the "
+              "coupled step runs on a single GPU; a slab decomposition across GPUs is not "
+              "implemented", file=sys.stderr)
         return 2
 
     import torch
