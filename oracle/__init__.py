@@ -309,6 +309,7 @@ def _load3():
     lib.o3_create.restype = P
     lib.o3_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.o3_destroy.argtypes = [P]
+    lib.o3_set_solid.argtypes = [P, C.c_void_p]
     lib.o3_set_params.argtypes = [P, D, D, D, D, D, D, D, D, D, C.c_int]
     lib.o3_init.argtypes = [P] + [DP] * 10
     lib.o3_step.argtypes = [P, C.c_longlong]
@@ -335,6 +336,9 @@ class OracleSim3D:
                                int(prob.q))
         if not self.h:
             raise ValueError("oracle3d: invalid grid")
+        if getattr(prob, "solid", None) is not None:
+            self._mask = np.ascontiguousarray(prob.solid, dtype=np.uint8).reshape(self.shape)
+            lib.o3_set_solid(self.h, self._mask.ctypes.data)
         Fx, Fy, Fz = (float(v) for v in prob.F)
         if lib.o3_set_params(self.h, prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s,
                              prob.Lambda_p, Fx, Fy, Fz, 1 if no_source else 0) != 0:

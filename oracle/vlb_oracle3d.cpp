@@ -23,13 +23,15 @@
  *                                                                         (Sec. 3.1)
  *   6. six convection-diffusion TRT regularized collisions with the auxiliary term
  *      G~_i, the source term F~_i and half its backward time difference   (Sec. 3.2)
- *   7. streaming (pull) with half-way bounce-back of f at flat walls normal to y; the
+ *   7. streaming (pull) with half-way bounce-back of f at flat walls normal to y and at
+ *      the faces of solid nodes; the
  *      conformation populations that left toward the wall are the CNEBB input
  *   8. conservative non-equilibrium bounce-back for every conformation lattice at
  *      wall-adjacent nodes                                                (Sec. 3.3)
  *   9. history of S and u for the time difference
  *
- * Axes x and z are periodic; y is periodic or bounded by half-way walls.  Uniform body
+ * Axes x and z are periodic; y is periodic or bounded by half-way walls; any node may be
+ * solid (a staircase obstacle, read out at rest).  Uniform body
  * force.  Index convention of fields: [z][y][x], x fastest.
  *
  * Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
@@ -305,6 +307,7 @@ struct Sim {
     Params p;
     std::vector<double> f[QMAX], fp[QMAX], g[6][QMAX], gp[6][QMAX];
     std::vector<double> rho, u[3], A[6], Sprev[6], uprev[3];
+    std::vector<uint8_t> solid;  // 1 = solid node (half-way bounce-back / CNEBB at its links)
     bool first = true;
     long long step = 0;
 
@@ -328,10 +331,12 @@ struct Sim {
             A[k].assign(N, 0.0);
             Sprev[k].assign(N, 0.0);
         }
+        solid.assign(N, 0);
     }
     size_t idx(int x, int y, int z) const { return ((size_t)z * ny + y) * nx + x; }
     static int wrap(int v, int n) { return ((v % n) + n) % n; }
-    // Source node of the pull x - e_i: false when it lies beyond a wall.
+    // Source node of the pull x - e_i: false when it lies beyond a wall or is solid (the
+    // link then ends half way, at the wall or the solid node's face).
     bool source(int x, int y, int z, int i, size_t* s) const {
         int xs = wrap(x - lat.E[i][0], nx), ys = y - lat.E[i][1], zs = wrap(z - lat.E[i][2], nz);
         if (ys < 0 || ys >= ny) {
@@ -339,11 +344,17 @@ struct Sim {
             ys = wrap(ys, ny);
         }
         *s = idx(xs, ys, zs);
-        return true;
+        return solid[*s] == 0;
     }
 
     void macros() {
         for (size_t n = 0; n < N; ++n) {
+            if (solid[n]) {  // read out at rest
+                rho[n] = 1.0;
+                for (int a = 0; a < 3; ++a) u[a][n] = 0.0;
+                for (int k = 0; k < 6; ++k) A[k][n] = KA[k] == KB[k] ? 1.0 : 0.0;
+                continue;
+            }
             double r = 0.0, j[3] = {0.0, 0.0, 0.0};
             for (int i = 0; i < Q; ++i) {
                 r += f[i][n];
@@ -381,17 +392,21 @@ struct Sim {
 #pragma omp parallel for schedule(static)
         for (long long nn = 0; nn < (long long)N; ++nn) {
             const size_t n = (size_t)nn;
+            if (solid[n]) continue;
             const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
-            // neighbours along the axes
-            const size_t nxl = idx(wrap(x - 1, nx), y, z), nxh = idx(wrap(x + 1, nx), y, z);
-            const size_t nzl = idx(x, y, wrap(z - 1, nz)), nzh = idx(x, y, wrap(z + 1, nz));
-            const bool ylo_wall = ywall && y == 0, yhi_wall = ywall && y == ny - 1;
-            const size_t nyl = idx(x, wrap(y - 1, ny), z), nyh = idx(x, wrap(y + 1, ny), z);
+            // neighbours along the axes; a wall or a solid neighbour puts the no-slip value
+            // half a spacing away (reading A6 with q = 1/2)
+            const size_t nb[3][2] = {{idx(wrap(x - 1, nx), y, z), idx(wrap(x + 1, nx), y, z)},
+                                     {idx(x, wrap(y - 1, ny), z), idx(x, wrap(y + 1, ny), z)},
+                                     {idx(x, y, wrap(z - 1, nz)), idx(x, y, wrap(z + 1, nz))}};
+            bool wl[3], wh[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                wl[ax] = (ax == 1 && ywall && y == 0) || solid[nb[ax][0]];
+                wh[ax] = (ax == 1 && ywall && y == ny - 1) || solid[nb[ax][1]];
+            }
             auto dax = [&](int ax, auto val) {
-                if (ax == 0) return fd(false, val(nxl), val(n), false, val(nxh));
-                if (ax == 2) return fd(false, val(nzl), val(n), false, val(nzh));
-                return fd(ylo_wall, ylo_wall ? 0.0 : val(nyl), val(n), yhi_wall,
-                          yhi_wall ? 0.0 : val(nyh));
+                return fd(wl[ax], wl[ax] ? 0.0 : val(nb[ax][0]), val(n), wh[ax],
+                          wh[ax] ? 0.0 : val(nb[ax][1]));
             };
             double L[3][3], D[3];
             for (int gm = 0; gm < 3; ++gm)
@@ -431,6 +446,7 @@ struct Sim {
 #pragma omp parallel for schedule(static)
         for (long long nn = 0; nn < (long long)N; ++nn) {
             const size_t n = (size_t)nn;
+            if (solid[n]) continue;
             const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
             for (int i = 0; i < Q; ++i) {
                 size_t s;
@@ -448,17 +464,19 @@ struct Sim {
         // equilibrium at (phi_b, u_b) plus the non-equilibrium part of the known
         // opposite, g_0 restores phi_b; u_b from the filled f with the half-force shift
         // (reading A11).
-        if (ywall) {
+        {
 #pragma omp parallel for schedule(static)
             for (long long nn = 0; nn < (long long)N; ++nn) {
                 const size_t n = (size_t)nn;
+                if (solid[n]) continue;
                 const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((size_t)nx * ny));
-                if (y != 0 && y != ny - 1) continue;
-                bool unknown[QMAX];
+                bool unknown[QMAX], any = false;
                 for (int i = 0; i < Q; ++i) {
                     size_t s;
                     unknown[i] = !source(x, y, z, i, &s);
+                    any = any || unknown[i];
                 }
+                if (!any) continue;
                 double r = 0.0, j[3] = {0.0, 0.0, 0.0};
                 for (int i = 0; i < Q; ++i) {
                     r += f[i][n];
@@ -508,6 +526,12 @@ void* o3_create(int nx, int ny, int nz, int ywall, int q) {
     return new Sim(q == 27 ? LAT27 : LAT19, nx, ny, nz, ywall ? 1 : 0);
 }
 void o3_destroy(void* h) { delete static_cast<Sim*>(h); }
+
+// Solid nodes: mask [nz][ny][nx], nonzero = solid (before o3_init).
+void o3_set_solid(void* h, const uint8_t* mask) {
+    Sim* s = static_cast<Sim*>(h);
+    for (size_t n = 0; n < s->N; ++n) s->solid[n] = mask[n] ? 1 : 0;
+}
 
 // Relaxation times from the transport coefficients (Sec. 3.1-3.2), rho0 = 1.
 int o3_set_params(void* h, double nu_s, double eta_p, double lam, double kappa, double Lambda_s,

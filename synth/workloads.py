@@ -379,6 +379,7 @@ class Problem3D:
     precision: str = "fp32"
     meta: dict = field(default_factory=dict)
     q: int = 19  # lattice: 19 (D3Q19) or 27 (D3Q27)
+    solid: Optional[np.ndarray] = None  # [nz][ny][nx] uint8, 1 = solid node
 
     @property
     def nodes(self) -> int:
