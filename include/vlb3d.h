@@ -14,7 +14,8 @@
  * on D3Q27 the six H_aab and H_xyz.
  *
  * Geometry: x and z periodic; y periodic (VLB_PERIODIC) or bounded by half-way walls
- * half a spacing outside rows 0 and ny - 1 (VLB_WALL).  Uniform body force.  Fields are
+ * half a spacing outside rows 0 and ny - 1 (VLB_WALL); optionally solid nodes from a mask,
+ * whose faces are half-way walls too (vlb3_set_solid).  Uniform body force.  Fields are
  * [nz][ny][nx] arrays, x fastest, in the simulation's precision (float for VLB_FP32,
  * double for VLB_FP64).  Arithmetic is double in both.
  *
@@ -42,14 +43,21 @@ typedef struct vlb3_sim vlb3_sim;
  * Errors: VLB_E_INVALID_ARG. */
 int vlb3_create(int nx, int ny, int nz, int q, int prec, int ymode, vlb3_sim** out);
 /* Device workspace the simulation needs: two buffers of 7 q population planes, 9
- * history planes (S of the six components and u), 4 planes of rho and u (256-byte
- * aligned sections; each plane nx * ny * nz rounded up to 64 elements plus 4160 of
- * padding). */
+ * history planes (S of the six components and u), 4 planes of rho and u, one 32-bit
+ * plane of solid-link bits (256-byte aligned sections; each plane nx * ny * nz rounded up
+ * to 64 elements plus 4160 of padding). */
 int vlb3_workspace_bytes(const vlb3_sim* sim, size_t* bytes);
 /* Attach the caller's 256-byte aligned device workspace of at least
  * vlb3_workspace_bytes and the HIP stream (NULL: the null stream) all work goes to.
  * Errors: VLB_E_WORKSPACE. */
 int vlb3_bind(vlb3_sim* sim, void* workspace_dev, size_t bytes, void* hip_stream);
+/* Solid nodes (host mask [nz][ny][nx], nonzero = solid; NULL removes them).  A fluid
+ * node's pull from a solid node is the half-way bounce-back of f and the CNEBB input of
+ * the conformation lattices (Sec. 3.3), a difference toward a solid neighbour takes the
+ * no-slip value half a spacing away; solid nodes are read out at rest (rho = 1, u = 0,
+ * A = I).  Call after vlb3_bind and before vlb3_init_equilibrium (it clears the state).
+ * Synchronizes the stream.  Errors: VLB_E_STATE (not bound), VLB_E_HIP. */
+int vlb3_set_solid(vlb3_sim* sim, const unsigned char* mask);
 /* Lattice-unit parameters (Sec. 2.4, 3.1-3.2): solvent viscosity nu_s, polymer
  * viscosity eta_p, relaxation time lambda, conformation diffusivity kappa, the two magic
  * parameters, the uniform body force.  flags: VLB_FLAG_NO_SOURCE or 0.

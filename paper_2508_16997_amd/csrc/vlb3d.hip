@@ -25,6 +25,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "vlb3d.h"
 #include "vlb_internal.h"
@@ -41,8 +42,10 @@ constexpr int TX = 64, TY = 4;
 // that keeps two waves; measured 1723, 1643, 1607 and 1566 us per step on the 2^22-node
 // channel for none, two, three and four).  FP64: none, where holding them would leave
 // one wave per SIMD.
-template <class S, class Lat>
-constexpr int kHold = sizeof(S) == 4 ? (Lat::Q == 19 ? 6 : 4) : 0;
+// With solid nodes (general unknown sets in CNEBB) one lattice fewer on D3Q19 and two
+// fewer on D3Q27 keep two waves.
+template <class S, class Lat, bool SOLIDS = false>
+constexpr int kHold = sizeof(S) == 4 ? (SOLIDS ? (Lat::Q == 19 ? 5 : 2) : (Lat::Q == 19 ? 6 : 4)) : 0;
 constexpr T CS2 = 1.0 / 3.0;
 
 // conformation components: (a, b) of component k, rest value phi0
@@ -124,6 +127,8 @@ struct Run3 {
     S* dst;
     S* hist;  // 9 planes: S_xx, S_xy, S_xz, S_yy, S_yz, S_zz, u_x, u_y, u_z (previous step)
     S* mac;   // 4 planes: rho, u_x, u_y, u_z at time n
+    const unsigned* bits;  // per node (solid nodes present): bit i = the pull of direction i
+                           // comes from a solid node, bit 31 = the node is solid
     T c1, c2, h1, inv_ts1;  // hydrodynamic: 1 - 1/tau_s1, 1 - 1/tau_s2, 1 - 1/(2 tau_s1), 1/tau_s1
     T p1, p2, h2;           // conformation: 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)
     T inv_lam, eta_over_lam, F[3];
@@ -156,7 +161,9 @@ struct Nbr {
     int n;
     int dx[2], dy[2], dz[2];
     bool ylo_wall, yhi_wall, first;
+    unsigned sol;  // directions whose pull comes from a solid node (0 without solids)
 };
+constexpr unsigned SELF_SOLID = 1u << 31;
 template <class S>
 __device__ __forceinline__ Nbr make_nbr(const Run3<S>& R, int x, int y, int z) {
     Nbr b;
@@ -171,7 +178,17 @@ __device__ __forceinline__ Nbr make_nbr(const Run3<S>& R, int x, int y, int z) {
     b.ylo_wall = R.ywall && y == 0;
     b.yhi_wall = R.ywall && y == R.ny - 1;
     b.first = R.first != 0;
+    b.sol = 0u;
     return b;
+}
+// Directions arriving from beyond a y wall: e_y > 0 at the low wall (sgn > 0), e_y < 0 at
+// the high wall.
+template <class Lat>
+__host__ __device__ constexpr unsigned ymask(int sgn) {
+    unsigned m = 0u;
+    for (int i = 1; i < Lat::Q; ++i)
+        if (sgn > 0 ? Lat::e(i, 1) > 0 : Lat::e(i, 1) < 0) m |= 1u << i;
+    return m;
 }
 // Memory access by plane and slot through raw buffer instructions: a uniform resource
 // for a group of planes (scalar registers), the plane's byte offset as the scalar offset
@@ -240,9 +257,9 @@ __device__ __forceinline__ Nbr fresh(const Nbr& b) {
                  "+v"(c.dz[0]), "+v"(c.dz[1]));
     return c;
 }
-// Pulls of lattice L with the directions arriving from beyond a y wall taken as the node's
-// own post-collision value of the opposite direction.  (A wave holds one row, so the wall
-// branches are uniform.)
+// Pulls of lattice L with the directions arriving from beyond a y wall or from a solid
+// node taken as the node's own post-collision value of the opposite direction.  (A wave
+// holds one row, so the wall branches are uniform.)
 template <class Lat, class S>
 __device__ __forceinline__ void pull_all(const Run3<S>& R, const Nbr& b, int L, S g[Lat::Q]) {
     const Planes<S> P = src_lattice<Lat>(R, L);
@@ -258,6 +275,11 @@ __device__ __forceinline__ void pull_all(const Run3<S>& R, const Nbr& b, int L, 
 #pragma unroll
         for (int i = 0; i < Lat::Q; ++i)
             if (Lat::e(i, 1) < 0) g[i] = at(P, opp(i), b.n);
+    }
+    if (b.sol) {
+#pragma unroll
+        for (int i = 1; i < Lat::Q; ++i)
+            if ((b.sol >> i) & 1u) g[i] = at(P, opp(i), b.n);
     }
 }
 
@@ -278,12 +300,17 @@ __device__ __forceinline__ void hydro_pull(const Run3<S>& R, const Nbr& b, S f[L
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * R.F[a]) / rho;
 }
 
-template <class S, class Lat>
+template <class S, class Lat, bool SOLIDS>
 __global__ __launch_bounds__(TX * TY) void k3_macro(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
-    const Nbr b = make_nbr(R, x, y, z);
+    Nbr b = make_nbr(R, x, y, z);
     const int n = b.n;
+    if (SOLIDS) {
+        const unsigned bits = R.bits[n];
+        if (bits & SELF_SOLID) return;
+        b.sol = bits & ~SELF_SOLID;
+    }
     S f[Lat::Q];
     T rho, u[3];
     hydro_pull<Lat>(R, b, f, rho, u);
@@ -306,10 +333,12 @@ __device__ __forceinline__ T fd(bool lo_wall, T vlo, T v0, bool hi_wall, T vhi) 
 // one copy of the code and its registers) from its pulled populations: CNEBB at a
 // wall-adjacent node, moments, collision, store.
 __device__ __forceinline__ T phi0_rt(int k) { return (k == 0 || k == 3 || k == 5) ? 1.0 : 0.0; }
-template <class Lat, class S>
+// BOTH: an unknown's opposite may be unknown too (solid nodes on both sides of a lattice
+// line); never next to the flat y walls alone.
+template <class Lat, bool BOTH, class S>
 __device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, const S gs[Lat::Q], const T u[3],
                                              const T up[3], T rho, T uu, T dp, T Sk, T Spk,
-                                             bool wall_lo, bool wall_hi) {
+                                             unsigned unk) {
     const T phi = phi0_rt(k) + dp;
     // first and second moments of the pulled deviations
     T J[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -323,20 +352,22 @@ __device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, con
         for (int m = 0; m < 6; ++m)
             if (Lat::e(i, ka(m)) * Lat::e(i, kb(m)) != 0) P[m] += (Lat::e(i, ka(m)) * Lat::e(i, kb(m)) > 0) ? v : -v;
     }
-    if (wall_lo || wall_hi) {
-        // CNEBB: each unknown (a direction arriving from beyond the wall) becomes the
+    if (unk) {
+        // CNEBB: each unknown (a direction arriving from beyond a wall or from a solid
+        // node) becomes the
         // equilibrium deviation at (phi_b, u_b) plus the non-equilibrium part of its known
         // opposite; g_0 takes the remainder of phi_b, so the zeroth moment is unchanged
         // and the first and second moments change by the unknowns' corrections only.
 #pragma unroll
         for (int i = 1; i < Lat::Q; ++i) {
-            const bool unk = wall_lo ? Lat::e(i, 1) > 0 : Lat::e(i, 1) < 0;
-            if (unk) {
+            if ((unk >> i) & 1u) {
                 const int o = opp(i);
                 const T eui = Lat::e(i, 0) * u[0] + Lat::e(i, 1) * u[1] + Lat::e(i, 2) * u[2];
                 const T eqi = Lat::w(i) * (dp + phi * (3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
                 const T eqo = Lat::w(o) * (dp + phi * (-3.0 * eui + 4.5 * (eui * eui - CS2 * uu)));
-                const T delta = eqi + (T)gs[o] - eqo - (T)gs[i];
+                // (an unknown whose opposite is unknown too: the equilibrium alone)
+                const T delta = (BOTH && ((unk >> o) & 1u)) ? eqi - (T)gs[i]
+                                                            : eqi + (T)gs[o] - eqo - (T)gs[i];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     if (Lat::e(i, a) != 0) J[a] += Lat::e(i, a) > 0 ? delta : -delta;
@@ -376,19 +407,20 @@ __device__ __forceinline__ void conf_collide(const Run3<S>& R, int n, int k, con
 }
 
 // Pulls and collision of conformation lattice k.
-template <class Lat, class S>
+template <class Lat, bool BOTH, class S>
 __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, int k, const T u[3],
                                              const T up[3], T rho, T uu, T dp, T Sk, T Spk,
-                                             bool wall_lo, bool wall_hi) {
+                                             unsigned unk) {
     const Nbr b = fresh(nb);
     S gs[Lat::Q];
     pull_all<Lat>(R, b, 1 + k, gs);
-    conf_collide<Lat>(R, b.n, k, gs, u, up, rho, uu, dp, Sk, Spk, wall_lo, wall_hi);
+    conf_collide<Lat, BOTH>(R, b.n, k, gs, u, up, rho, uu, dp, Sk, Spk, unk);
 }
 
 // WALLS: the y walls' fix-ups, one-sided differences and CNEBB compiled in (a wave holds
 // one row, so they are uniform branches); without walls they are compiled out.
-template <class S, class Lat, bool WALLS, int HOLD>
+// SOLIDS: solid nodes present (their own lanes idle; their faces act as half-way walls).
+template <class S, class Lat, bool WALLS, bool SOLIDS, int HOLD>
 __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
@@ -396,6 +428,11 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     Nbr nbr = make_nbr(R, x, y, z);
     if (!WALLS) nbr.ylo_wall = nbr.yhi_wall = false;
     const int n = nbr.n;
+    if (SOLIDS) {
+        const unsigned bits = R.bits[n];
+        if (bits & SELF_SOLID) return;
+        nbr.sol = bits & ~SELF_SOLID;
+    }
 
     // ---- hydrodynamic pulls, rho, u ----
     S f[Lat::Q];
@@ -440,7 +477,10 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
                               {n + nbr.dz[0], n + nbr.dz[1]}};
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            const bool lw = g == 1 && wl, hw = g == 1 && wh;
+            // a wall or a solid neighbour along the axis (directions 1 + 2g and 2 + 2g
+            // pull from the low and the high neighbour)
+            const bool lw = (g == 1 && wl) || ((nbr.sol >> (1 + 2 * g)) & 1u);
+            const bool hw = (g == 1 && wh) || ((nbr.sol >> (2 + 2 * g)) & 1u);
             T rl = 0.0, rh = 0.0, vl[3] = {0.0, 0.0, 0.0}, vh[3] = {0.0, 0.0, 0.0};
             if (!lw) {
                 rl = at(mac, 0, nb[g][0]);
@@ -551,7 +591,10 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     }
 
     // ---- conformation lattices: pulls, CNEBB at wall-adjacent nodes, collision ----
-    const bool wall_lo = WALLS && nbr.ylo_wall && !R.first, wall_hi = WALLS && nbr.yhi_wall && !R.first;
+    // directions CNEBB rebuilds (none on the first step: its pulls are the node's own slots)
+    const unsigned unk = R.first ? 0u
+                                 : ((WALLS && nbr.ylo_wall) ? ymask<Lat>(1) : 0u) |
+                                       ((WALLS && nbr.yhi_wall) ? ymask<Lat>(-1) : 0u) | nbr.sol;
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     // The held lattices (the last HOLD of the zeroth-moment pass) from their registers,
     // then the others pulled again, most recently read first.
@@ -562,13 +605,12 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         // zeroth-moment sum from being kept instead)
 #pragma unroll
         for (int i = 0; i < Lat::Q; ++i) asm volatile("" : "+v"(G[j][i]));
-        conf_collide<Lat>(R, n, k, G[j], u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid],
-                     wall_lo, wall_hi);
+        conf_collide<Lat, SOLIDS>(R, n, k, G[j], u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid],
+                     unk);
     }
 #pragma unroll 1
     for (int k = 5 - HOLD; k >= 0; --k)
-        conf_lattice<Lat>(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], wall_lo,
-                     wall_hi);
+        conf_lattice<Lat, SOLIDS>(R, nbr, k, u, up, rho, uu, s_dphi[k][tid], s_Sc[k][tid], s_Sp[k][tid], unk);
 #pragma unroll
     for (int k = 0; k < 6; ++k) put(hist, k, n, s_Sc[k][tid]);
 #pragma unroll
@@ -615,8 +657,19 @@ template <class S, class Lat>
 __global__ __launch_bounds__(TX * TY) void k3_read(Run3<S> R, S* const* out) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
-    const Nbr nbr = make_nbr(R, x, y, z);
+    Nbr nbr = make_nbr(R, x, y, z);
     const int n = nbr.n;
+    if (R.bits) {
+        const unsigned bits = R.bits[n];
+        if (bits & SELF_SOLID) {  // solid node: read out at rest
+            const T rest[10] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 1.0};
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                if (out[c]) out[c][n] = (S)rest[c];
+            return;
+        }
+        nbr.sol = bits & ~SELF_SOLID;
+    }
     S f[Lat::Q];
     T rho, u[3];
     hydro_pull<Lat>(R, nbr, f, rho, u);
@@ -649,7 +702,8 @@ struct vlb3_sim {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
-    size_t off_pop[2] = {0, 0}, off_hist = 0, off_mac = 0, off_ptrs = 0, total = 0;
+    size_t off_pop[2] = {0, 0}, off_hist = 0, off_mac = 0, off_bits = 0, off_ptrs = 0, total = 0;
+    bool has_solid = false;  // a solid mask is set (the bits plane in the workspace)
     int parity = 0, first = 1;
     int64_t step = 0;
     double nu_s = 0, eta_p = 0, lam = 1, kappa = 0, Ls = 0.25, Lp = 1e-6, F[3] = {0, 0, 0};
@@ -672,6 +726,7 @@ void layout(vlb3_sim* s) {
     s->off_pop[1] = take((size_t)vlb3::NLAT * s->q * plane);
     s->off_hist = take(9 * plane);
     s->off_mac = take(4 * plane);
+    s->off_bits = take((size_t)s->P * sizeof(unsigned));
     s->off_ptrs = take(10 * sizeof(void*));
     s->total = o;
 }
@@ -689,6 +744,7 @@ vlb3::Run3<S> make_run(const vlb3_sim* s) {
     r.dst = reinterpret_cast<S*>(s->ws + s->off_pop[s->parity ^ 1]);
     r.hist = reinterpret_cast<S*>(s->ws + s->off_hist);
     r.mac = reinterpret_cast<S*>(s->ws + s->off_mac);
+    r.bits = s->has_solid ? reinterpret_cast<const unsigned*>(s->ws + s->off_bits) : nullptr;
     // relaxation times from the transport coefficients (Sec. 3.1-3.2), c_s^2 = 1/3
     const double ts1 = 3.0 * s->nu_s + 0.5, ts2 = s->Ls / (3.0 * s->nu_s) + 0.5;
     const double tp1 = 3.0 * s->kappa + 0.5, tp2 = s->Lp / (3.0 * s->kappa) + 0.5;
@@ -731,11 +787,16 @@ int do_steps(vlb3_sim* s, int64_t n) {
     constexpr int hold = vlb3::kHold<S, Lat>;
     for (int64_t k = 0; k < n; ++k) {
         const vlb3::Run3<S> r = make_run<S>(s);
-        hipLaunchKernelGGL((vlb3::k3_macro<S, Lat>), grd, blk, 0, s->stream, r);
-        if (s->ywall)
-            hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, hold>), grd, blk, 0, s->stream, r);
-        else
-            hipLaunchKernelGGL((vlb3::k3_step<S, Lat, false, hold>), grd, blk, 0, s->stream, r);
+        if (s->has_solid) {  // (the wall code is compiled in; it checks the y walls itself)
+            hipLaunchKernelGGL((vlb3::k3_macro<S, Lat, true>), grd, blk, 0, s->stream, r);
+            hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, true, vlb3::kHold<S, Lat, true>>), grd, blk, 0, s->stream, r);
+        } else {
+            hipLaunchKernelGGL((vlb3::k3_macro<S, Lat, false>), grd, blk, 0, s->stream, r);
+            if (s->ywall)
+                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, false, hold>), grd, blk, 0, s->stream, r);
+            else
+                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, false, false, hold>), grd, blk, 0, s->stream, r);
+        }
         VLB3_HIP(hipGetLastError());
         s->parity ^= 1;
         s->first = 0;
@@ -829,6 +890,43 @@ int vlb3_create(int nx, int ny, int nz, int q, int prec, int ymode, vlb3_sim** o
     s->P = plane_stride(N);
     layout(s);
     *out = s;
+    return VLB_OK;
+}
+
+int vlb3_set_solid(vlb3_sim* s, const unsigned char* mask) {
+    if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "null simulation");
+    if (!s->bound) return vlb::report_error(VLB_E_STATE, "workspace not bound (vlb3_bind)");
+    if (!mask) {
+        s->has_solid = false;
+        s->inited = false;
+        return VLB_OK;
+    }
+    // bit i of a node: its pull in direction i comes from a solid node (x - e_i, periodic
+    // in x and z, in y unless beyond a wall, which the wall rule covers); bit 31: solid
+    std::vector<unsigned> bits((size_t)s->N, 0u);
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    auto ex = [&](int i, int a) { return s->q == 27 ? vlb3::D3Q27::e(i, a) : vlb3::D3Q19::e(i, a); };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = ((size_t)z * ny + y) * nx + x;
+                unsigned b = mask[n] ? vlb3::SELF_SOLID : 0u;
+                for (int i = 1; i < s->q; ++i) {
+                    int ys = y - ex(i, 1);
+                    if (ys < 0 || ys >= ny) {
+                        if (s->ywall) continue;
+                        ys = (ys + ny) % ny;
+                    }
+                    const int xs = ((x - ex(i, 0)) % nx + nx) % nx, zs = ((z - ex(i, 2)) % nz + nz) % nz;
+                    if (mask[((size_t)zs * ny + ys) * nx + xs]) b |= 1u << i;
+                }
+                bits[n] = b;
+            }
+    VLB3_HIP(hipMemcpyAsync(s->ws + s->off_bits, bits.data(), bits.size() * sizeof(unsigned),
+                            hipMemcpyHostToDevice, s->stream));
+    VLB3_HIP(hipStreamSynchronize(s->stream));
+    s->has_solid = true;
+    s->inited = false;
     return VLB_OK;
 }
 

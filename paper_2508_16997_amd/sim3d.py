@@ -49,6 +49,8 @@ class Simulation3D:
         """Build, parameterise and initialise from a synth.Problem3D."""
         kw.setdefault("q", prob.q)
         sim = cls(prob.nx, prob.ny, prob.nz, prob.ymode, precision or prob.precision, **kw)
+        if getattr(prob, "solid", None) is not None:
+            sim.set_solid(prob.solid)
         sim.set_params(prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s,
                        prob.Lambda_p, *prob.F)
         sim.init(**prob.init_arrays())
@@ -63,6 +65,16 @@ class Simulation3D:
         cur = torch.cuda.current_stream(self.device)
         if cur.cuda_stream != self.stream.cuda_stream:
             cur.wait_stream(self.stream)
+
+    def set_solid(self, mask):
+        """Solid nodes from a [nz][ny][nx] mask (nonzero = solid), or None for none; call
+        before init()."""
+        if mask is None:
+            L.check(self.lib.vlb3_set_solid(self._h, None), "vlb3_set_solid")
+            return
+        m = np.ascontiguousarray(np.asarray(mask).reshape(self.nz, self.ny, self.nx) != 0,
+                                 dtype=np.uint8)
+        L.check(self.lib.vlb3_set_solid(self._h, m.ctypes.data), "vlb3_set_solid")
 
     def set_params(self, nu_s, eta_p, lam, kappa, Lambda_s=0.25, Lambda_p=1e-6, Fx=0.0, Fy=0.0,
                    Fz=0.0, flags=0):

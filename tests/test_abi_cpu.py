@@ -82,6 +82,8 @@ def test_3d_create_validates_without_a_gpu(vlb):
     assert lib.vlb3_set_params(h, 0.1, 0.1, 10.0, 0.01, 0.25, 0.25, 0.0, 0.0, 0.0, 0) == _lib.VLB_OK
     assert lib.vlb3_set_params(h, -0.1, 0.1, 10.0, 0.01, 0.25, 0.25, 0.0, 0.0, 0.0, 0) == _lib.VLB_E_INVALID_ARG
     assert lib.vlb3_step(h, 1) == _lib.VLB_E_STATE  # not bound
+    mask = np.zeros(8 * 6 * 5, np.uint8)
+    assert lib.vlb3_set_solid(h, mask.ctypes.data) == _lib.VLB_E_STATE  # not bound
     lib.vlb3_destroy(h)
 
 

@@ -211,3 +211,47 @@ def test_random_state_at_the_benchmark_size(q):
     for k in ("ux", "uy", "uz", "axx", "axy", "azz"):
         scale = np.abs(o[k]).max()
         assert np.abs(g[k] - o[k]).max() < 1e-5 * scale + 1e-9, k
+
+
+def _random_solid(shape, seed, frac=0.15):
+    m = (np.random.default_rng(seed).random(shape) < frac).astype(np.uint8)
+    return m
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+@pytest.mark.parametrize("ymode", ["periodic", "wall"])
+def test_random_solids_3d(ymode, precision, tol, q):
+    """Solid nodes (15 % of a ragged grid, seeded, including lines of two or more and
+    nodes between two solids along a lattice line): GPU against the oracle after 30
+    steps, fluid nodes element by element; solid nodes read out at rest."""
+    nx, ny, nz = 67, 9, 6
+    pr = synth.random3d(nx, ny, nz, seed=17, ymode=ymode, q=q)
+    pr.solid = _random_solid((nz, ny, nx), 23)
+    say("3d solids", ymode, precision, q)
+    g, o = _run_pair(pr, 30, precision)
+    fl = pr.solid == 0
+    du = np.sqrt(sum(((g[k] - o[k])[fl] ** 2).sum() for k in ("ux", "uy", "uz")))
+    nu = np.sqrt(sum((o[k][fl] ** 2).sum() for k in ("ux", "uy", "uz")))
+    assert du / nu < tol, du / nu
+    for k in ("axx", "axy", "axz", "ayy", "ayz", "azz"):
+        assert _rel(g[k][fl], o[k][fl]) < tol, (k, _rel(g[k][fl], o[k][fl]))
+    so = ~fl
+    assert np.all(g["rho"][so] == 1.0) and np.all(g["ux"][so] == 0.0) and np.all(g["axx"][so] == 1.0)
+
+
+def test_square_duct_3d_matches_oracle():
+    """The Oldroyd-B square duct (y walls, z solid planes, H = 12): GPU equals the oracle to
+    1e-10 in FP64 after 2 T_c."""
+    H = 12
+    base = synth.channel3d(nx=2, ny=H, nz=2, Ma=0.1)
+    solid = np.zeros((H + 2, H, 2), np.uint8)
+    solid[0] = solid[-1] = 1
+    pr = base.with_(nz=H + 2, solid=solid)
+    steps = int(round(2 * pr.meta["Tc"]))
+    say("3d duct", steps)
+    g, o = _run_pair(pr, steps, "fp64")
+    fl = solid == 0
+    for k in ("ux", "axx", "axy", "axz"):
+        d = np.abs(g[k] - o[k])[fl].max()
+        assert d < 1e-10 * max(1.0, np.abs(o[k]).max()), (k, d)
