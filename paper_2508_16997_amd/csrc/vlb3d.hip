@@ -5,7 +5,7 @@
 // (L * q + i), node (z * ny + y) * nx + x), storing deviations from the rest state
 // (f_i - w_i, g_i - w_i phi0 with phi0 = 1 for A_xx, A_yy, A_zz and 0 otherwise); history
 // of S (6 planes) and u (3 planes); rho and u at time n (4 planes) for the neighbours'
-// differences.  Per step two launches:
+// differences; with solid nodes a plane of per-node link bits.  Per step two launches:
 //   k3_macro  rho and u of every node from its pulled populations (mac planes)
 //   k3_step   per node: pulls of all seven lattices (the conformation populations held in
 //             registers in FP32 storage -- four of the six lattices on D3Q27 -- and
@@ -15,8 +15,9 @@
 //             (stored at once), then lattice by lattice CNEBB at wall-adjacent nodes and
 //             the conformation collision (stored at once); history in place.
 // Pull streaming: node x takes direction i from x - e_i (periodic wrap in x and z, and in
-// y unless walls); a source beyond a wall gives the node's own post-collision value of
-// the opposite direction (half-way bounce-back for f, the CNEBB input for g).
+// y unless walls); a source beyond a wall or a solid source gives the node's own
+// post-collision value of the opposite direction (half-way bounce-back for f, the CNEBB
+// input for g).
 // One node per lane, 64 x 4 lanes per block in x and y, one z slice per block row.
 // All arithmetic in double.
 #include <hip/hip_runtime.h>
