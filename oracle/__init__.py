@@ -319,6 +319,9 @@ def _load3():
     lib.o3_collide_cde.restype = C.c_int
     lib.o3_collide_cde.argtypes = [C.c_int, DP, D, D, DP, DP, D, D, DP, D, D, DP]
     lib.o3_source.argtypes = [DP, DP, D, DP]
+    lib.o3_source_model.argtypes = [DP, DP, D, C.c_int, D, DP]
+    lib.o3_set_model.restype = C.c_int
+    lib.o3_set_model.argtypes = [P, C.c_int, D]
     lib.o3_lattice.restype = C.c_int
     lib.o3_lattice.argtypes = [C.c_int, C.c_void_p, DP, C.c_void_p, DP]
     _lib3 = lib
@@ -343,6 +346,9 @@ class OracleSim3D:
         if lib.o3_set_params(self.h, prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s,
                              prob.Lambda_p, Fx, Fy, Fz, 1 if no_source else 0) != 0:
             raise ValueError("oracle3d: invalid parameters")
+        model = getattr(prob, "model", "oldroyd_b")
+        if lib.o3_set_model(self.h, MODELS[model], float(getattr(prob, "model_param", 0.0))) != 0:
+            raise ValueError(f"oracle3d: invalid model parameter for {model}")
         f = prob.init_arrays()
         arrs = [_c64(f[k]) for k in FIELDS3]
         lib.o3_init(self.h, *[_dp(a) for a in arrs])
@@ -388,12 +394,16 @@ def collide_cde3d(q, g, phi, rho, u, F=(0.0, 0.0, 0.0), S=0.0, Sp=0.0, up=None, 
     return out
 
 
-def source3d(A, L, lam):
+def source3d(A, L, lam, model=None, mpar=0.0):
     """The three-dimensional constitutive source for the conformation A and the velocity
-    gradient L[g][b] = d_g u_b (3 x 3 each), relaxation time lam."""
+    gradient L[g][b] = d_g u_b (3 x 3 each), relaxation time lam; model names a closure
+    as in synth.Problem (None: the Oldroyd-B entry point)."""
     a, l = _c64(np.asarray(A, float)), _c64(np.asarray(L, float))
     out = np.zeros((3, 3))
-    _load3().o3_source(_dp(a), _dp(l), float(lam), _dp(out))
+    if model is None:
+        _load3().o3_source(_dp(a), _dp(l), float(lam), _dp(out))
+    else:
+        _load3().o3_source_model(_dp(a), _dp(l), float(lam), MODELS[model], float(mpar), _dp(out))
     return out
 
 

@@ -12,11 +12,11 @@
  * index running over x, y, z:
  *   1. rho and u with the half-force shift                               (Sec. 3.1)
  *   2. conformation A (six components, one convection-diffusion lattice each) and the
- *      polymer stress (eta_p / lambda)(A - I) (Oldroyd-B)                  (Sec. 2.2-2.3)
+ *      polymer stress (eta_p / lambda) F_s(A) of the closure (Oldroyd-B: A - I) (Sec. 2.2-2.3)
  *   3. velocity gradient L[g][b] = d_g u_b and D_a = d_a(rho u_a^3) by central
  *      differences; next to a flat half-way wall the quadratic through the no-slip wall
  *      value half a spacing away                                         (readings A6/A7)
- *   4. constitutive source Phi = -(A - I)/lambda + A L + (A L)^T + A tr L  (Sec. 3.2)
+ *   4. constitutive source Phi = -F_r(A)/lambda + A L + (A L)^T + A tr L  (Sec. 3.2)
  *   5. hydrodynamic TRT regularized collision: Hermite moments of orders 0..3 of f - f^eq
  *      (third order on the lattice's own orthogonal basis and norms), tau_s1 on orders 0..2,
  *      tau_s2 on order 3, plus G_i (diagonal third-order defects D_a), F_i and T_i
@@ -184,7 +184,51 @@ struct Params {
     double tau_s1 = 1.0, tau_s2 = 1.0, tau_p1 = 1.0, tau_p2 = 1.0, lam = 1.0, eta_p = 0.0;
     double F[3] = {0.0, 0.0, 0.0};
     int no_source = 0;
+    int model = 0;      // constitutive closure (MODEL_*) and its parameter
+    double mpar = 0.0;
 };
+
+// Constitutive closures (Sec. 2.2, the model function F(A)) in conformation form with the
+// three-dimensional trace (tr A = 3 at rest), B = A - I: relaxation function F_r in the
+// conformation equation, stress function F_s in the Kramers relation (reading A28 with
+// every index over x, y, z):
+//   Oldroyd-B  F_r = F_s = B
+//   Giesekus   F_r = B + alpha B B, F_s = B                 (mpar = alpha)
+//   PTT        F_r = Y B, Y = 1 + eps (tr A - 3) (linear) or exp(eps (tr A - 3)), F_s = B
+//   FENE-P     F_r = F_s = f A - I, f = (L^2 - 3) / (L^2 - tr A)   (mpar = L^2)
+enum { MODEL_OLDROYD_B = 0, MODEL_GIESEKUS = 1, MODEL_LPTT = 2, MODEL_EPTT = 3, MODEL_FENE_P = 4 };
+void model_functions3(const double A[3][3], int model, double mp, double Fr[3][3],
+                      double Fs[3][3]) {
+    double B[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) B[a][b] = A[a][b] - kd(a, b);
+    const double tr = A[0][0] + A[1][1] + A[2][2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            Fr[a][b] = B[a][b];
+            Fs[a][b] = B[a][b];
+        }
+    if (model == MODEL_GIESEKUS) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double bb = 0.0;
+                for (int c = 0; c < 3; ++c) bb += B[a][c] * B[c][b];
+                Fr[a][b] += mp * bb;
+            }
+    } else if (model == MODEL_LPTT || model == MODEL_EPTT) {
+        const double x = mp * (tr - 3.0);
+        const double Y = model == MODEL_LPTT ? 1.0 + x : std::exp(x);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Fr[a][b] = Y * B[a][b];
+    } else if (model == MODEL_FENE_P) {
+        const double f = (mp - 3.0) / (mp - tr);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                Fr[a][b] = f * A[a][b] - kd(a, b);
+                Fs[a][b] = Fr[a][b];
+            }
+    }
+}
 
 // Hydrodynamic TRT regularized collision (Sec. 3.1, three-dimensional indices).
 void collide_hydro(const Lattice& L, const double* f, double rho, const double u[3],
@@ -286,14 +330,17 @@ double fd(bool lo_wall, double vlo, double v0, bool hi_wall, double vhi) {
     return 0.0;
 }
 
-// Constitutive source of the conformation equation (Sec. 3.2, Oldroyd-B, every index over
-// x, y, z): Phi_ab = -(A_ab - d_ab)/lambda + sum_g (A_ag L_gb + A_gb L_ga) + A_ab tr L with
-// L_gb = d_g u_b.
-void source3(const double Am[3][3], const double L[3][3], double lam, double S[3][3]) {
+// Constitutive source of the conformation equation (Sec. 3.2, every index over x, y, z):
+// Phi_ab = -F_r(A)_ab / lambda + sum_g (A_ag L_gb + A_gb L_ga) + A_ab tr L with
+// L_gb = d_g u_b (F_r = A - I for Oldroyd-B).
+void source3(const double Am[3][3], const double L[3][3], double lam, double S[3][3],
+             int model = MODEL_OLDROYD_B, double mp = 0.0) {
     const double trL = L[0][0] + L[1][1] + L[2][2];
+    double Fr[3][3], Fs[3][3];
+    model_functions3(Am, model, mp, Fr, Fs);
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
-            double s = -(Am[a][b] - kd(a, b)) / lam;
+            double s = -Fr[a][b] / lam;
             for (int gm = 0; gm < 3; ++gm) s += Am[a][gm] * L[gm][b] + Am[gm][b] * L[gm][a];
             S[a][b] = s + Am[a][b] * trL;
         }
@@ -418,13 +465,14 @@ struct Sim {
                 for (int b = 0; b < 3; ++b) Am[a][b] = A[comp(a, b)][n];
             // constitutive source (Oldroyd-B)
             double S[3][3];
-            source3(Am, L, p.lam, S);
+            source3(Am, L, p.lam, S, p.model, p.mpar);
             if (p.no_source)
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) S[a][b] = 0.0;
-            double tau[3][3];
+            double tau[3][3], Fr[3][3], Fs[3][3];
+            model_functions3(Am, p.model, p.mpar, Fr, Fs);
             for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) tau[a][b] = p.eta_p / p.lam * (Am[a][b] - kd(a, b));
+                for (int b = 0; b < 3; ++b) tau[a][b] = p.eta_p / p.lam * Fs[a][b];
             double fl[QMAX], out[QMAX];
             for (int i = 0; i < Q; ++i) fl[i] = f[i][n];
             const double uu[3] = {u[0][n], u[1][n], u[2][n]};
@@ -625,6 +673,34 @@ int o3_collide_cde(int q, const double* g, double phi, double rho, const double*
     p.tau_p2 = tau_p2;
     collide_cde(q == 27 ? LAT27 : LAT19, g, phi, rho, u, F, S, Sp, up, p, out);
     return 0;
+}
+
+// Constitutive closure (MODEL_*) and its parameter: Giesekus alpha in [0, 1], PTT eps >= 0,
+// FENE-P L^2 > 3.  Returns -1 for an invalid pair.
+int o3_set_model(void* h, int model, double mpar) {
+    if (model < MODEL_OLDROYD_B || model > MODEL_FENE_P) return -1;
+    if (model == MODEL_GIESEKUS && !(mpar >= 0.0 && mpar <= 1.0)) return -1;
+    if ((model == MODEL_LPTT || model == MODEL_EPTT) && !(mpar >= 0.0)) return -1;
+    if (model == MODEL_FENE_P && !(mpar > 3.0)) return -1;
+    Sim* s = static_cast<Sim*>(h);
+    s->p.model = model;
+    s->p.mpar = model == MODEL_OLDROYD_B ? 0.0 : mpar;
+    return 0;
+}
+
+// The constitutive source of a closure for a conformation A and velocity gradient
+// L_gb = d_g u_b (both row-major 3 x 3), relaxation time lam, into S (row-major 3 x 3).
+void o3_source_model(const double* A, const double* L, double lam, int model, double mpar,
+                     double* S) {
+    double a[3][3], l[3][3], s[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            a[i][j] = A[3 * i + j];
+            l[i][j] = L[3 * i + j];
+        }
+    source3(a, l, lam, s, model, mpar);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S[3 * i + j] = s[i][j];
 }
 
 // The constitutive source for a conformation A and velocity gradient L_gb = d_g u_b

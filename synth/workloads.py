@@ -380,6 +380,8 @@ class Problem3D:
     meta: dict = field(default_factory=dict)
     q: int = 19  # lattice: 19 (D3Q19) or 27 (D3Q27)
     solid: Optional[np.ndarray] = None  # [nz][ny][nx] uint8, 1 = solid node
+    model: str = "oldroyd_b"  # constitutive closure, as for Problem (FENE-P: L^2 > 3)
+    model_param: float = 0.0
 
     @property
     def nodes(self) -> int:

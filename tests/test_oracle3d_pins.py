@@ -424,3 +424,45 @@ def test_square_duct_oldroyd_b_closed_form(o3, q):
         assert max(sec.values()) < 1e-10, sec
     else:
         assert sec[24] < 2e-3 and sec[24] < 0.7 * sec[12], sec
+
+
+CLOSURES = [("giesekus", 0.3), ("lptt", 0.25), ("eptt", 0.25), ("fene_p", 30.0)]
+
+
+@pytest.mark.parametrize("model,mp", CLOSURES)
+def test_closures_reduce_to_the_planar_ones(o3, model, mp):
+    """Reading A28 in three dimensions: on a planar state (A_zz = 1, A_xz = A_yz = 0, an
+    in-plane velocity gradient) each closure's 3-D source equals the 2-D oracle's source
+    of the same closure (tr A - 3 in 3-D is tr A - 2 in the plane; FENE-P with L^2 - 1 in
+    the plane), whose closures the two-dimensional pins tie to Giesekus' steady shear
+    solution and the scalar equations of PTT and FENE-P; S_xz, S_yz vanish and (but for
+    FENE-P) S_zz is the divergence term tr L.  Also
+    the 3-D closures are isotropic: S(R A R^T, R L R^T) = R S(A, L) R^T for a rotation R.
+    Catches a wrong trace offset, a transposed or mis-indexed B B and a closure applied
+    to the wrong components."""
+    rng = np.random.default_rng(11)
+    lam = 7.0
+    for _ in range(5):
+        a = np.array([[1.4, 0.3], [0.3, 0.8]]) + 0.1 * rng.normal(size=(2, 2))
+        a = 0.5 * (a + a.T)
+        Lp = 0.05 * rng.normal(size=(2, 2))
+        A = np.eye(3)
+        A[:2, :2] = a
+        L = np.zeros((3, 3))
+        L[:2, :2] = Lp
+        S3 = o3.source3d(A, L, lam, model, mp)
+        mp2 = mp - 1.0 if model == "fene_p" else mp
+        S2 = o3.node_source(np.array([a[0, 0], a[0, 1], a[1, 1]]),
+                            np.array([Lp[0, 0], Lp[0, 1], Lp[1, 0], Lp[1, 1]]), lam, model, mp2)
+        assert np.allclose([S3[0, 0], S3[0, 1], S3[1, 1]], S2, rtol=1e-12, atol=1e-15), (S3, S2)
+        assert abs(S3[0, 2]) < 1e-15 and abs(S3[1, 2]) < 1e-15
+        if model != "fene_p":  # B_zz = 0 leaves only the divergence term A_zz tr L
+            assert abs(S3[2, 2] - np.trace(L)) < 1e-15
+    # isotropy
+    M = rng.normal(size=(3, 3))
+    A = np.eye(3) + 0.2 * (M @ M.T) / 3
+    L = 0.04 * rng.normal(size=(3, 3))
+    Qr, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    S = o3.source3d(A, L, lam, model, mp)
+    Sr = o3.source3d(Qr @ A @ Qr.T, Qr @ L @ Qr.T, lam, model, mp)
+    assert np.allclose(Sr, Qr @ S @ Qr.T, rtol=1e-11, atol=1e-14)
