@@ -66,6 +66,13 @@ int vlb3_set_solid(vlb3_sim* sim, const unsigned char* mask);
 int vlb3_set_params(vlb3_sim* sim, double nu_s, double eta_p, double lambda, double kappa,
                     double Lambda_s, double Lambda_p, double Fx, double Fy, double Fz,
                     int flags);
+/* Constitutive closure (Sec. 2.2; the enum and functions of vlb.h with every tensor
+ * index over x, y, z and the 3-D trace, tr A = 3 at rest: Giesekus alpha (A - I)^2,
+ * PTT factor of eps (tr A - 3), FENE-P f = (L^2 - 3) / (L^2 - tr A)).  The default
+ * is VLB_OLDROYD_B; model_param is ignored for it.  Host call, takes effect at the next
+ * vlb3_step.  Errors: VLB_E_INVALID_ARG (null sim, unknown model, non-finite parameter,
+ * Giesekus alpha outside [0, 1], PTT eps < 0, FENE-P L^2 <= 3). */
+int vlb3_set_closure(vlb3_sim* sim, int model, double model_param);
 /* State at equilibrium of the given fields (device pointers in the simulation's
  * precision, [nz][ny][nx]; any may be NULL for its rest value rho = 1, u = 0, A = I), in
  * the order rho, u_x, u_y, u_z, A_xx, A_xy, A_xz, A_yy, A_yz, A_zz.  Resets the step

@@ -44,7 +44,7 @@ EXPORTS = [
 EXPORTS3 = [
     "vlb3_create", "vlb3_workspace_bytes", "vlb3_bind", "vlb3_set_params",
     "vlb3_init_equilibrium", "vlb3_step", "vlb3_read_fields", "vlb3_get_step", "vlb3_destroy",
-    "vlb3_set_solid",
+    "vlb3_set_solid", "vlb3_set_closure",
 ]
 
 
@@ -143,6 +143,7 @@ def load():
     PA = C.POINTER(C.c_void_p)
     lib.vlb3_create.argtypes = [I, I, I, I, I, I, C.POINTER(P)]
     lib.vlb3_set_solid.argtypes = [P, C.c_void_p]
+    lib.vlb3_set_closure.argtypes = [P, I, D]
     lib.vlb3_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.vlb3_bind.argtypes = [P, P, C.c_size_t, P]
     lib.vlb3_set_params.argtypes = [P, D, D, D, D, D, D, D, D, D, I]

@@ -45,8 +45,10 @@ constexpr int TX = 64, TY = 4;
 // one wave per SIMD.
 // With solid nodes (general unknown sets in CNEBB) one lattice fewer on D3Q19 and two
 // fewer on D3Q27 keep two waves.
-template <class S, class Lat, bool SOLIDS = false>
-constexpr int kHold = sizeof(S) == 4 ? (SOLIDS ? (Lat::Q == 19 ? 5 : 2) : (Lat::Q == 19 ? 6 : 4)) : 0;
+template <class S, class Lat, bool SOLIDS = false, bool CLOSURE = false>
+constexpr int kHold = sizeof(S) == 4 ? (SOLIDS ? (Lat::Q == 19 ? 5 - CLOSURE : 2 - CLOSURE)
+                                               : (Lat::Q == 19 ? 6 - CLOSURE : 4 - CLOSURE))
+                                     : 0;
 constexpr T CS2 = 1.0 / 3.0;
 
 // conformation components: (a, b) of component k, rest value phi0
@@ -134,6 +136,8 @@ struct Run3 {
     T p1, p2, h2;           // conformation: 1 - 1/tau_p1, 1 - 1/tau_p2, 1 - 1/(2 tau_p1)
     T inv_lam, eta_over_lam, F[3];
     int no_source;
+    int model;  // constitutive closure (VLB_OLDROYD_B ... VLB_FENE_P) and its parameter
+    T mpar;
 };
 
 // c0 + e_i.c + e_i.M.e_i for the symmetric M stored as (xx, xy, xz, yy, yz, zz): with
@@ -421,7 +425,9 @@ __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, in
 // WALLS: the y walls' fix-ups, one-sided differences and CNEBB compiled in (a wave holds
 // one row, so they are uniform branches); without walls they are compiled out.
 // SOLIDS: solid nodes present (their own lanes idle; their faces act as half-way walls).
-template <class S, class Lat, bool WALLS, bool SOLIDS, int HOLD>
+// CLOSURE: a constitutive closure other than Oldroyd-B (compiled apart, so that the
+// Oldroyd-B kernels keep their registers).
+template <class S, class Lat, bool WALLS, bool SOLIDS, int HOLD, bool CLOSURE>
 __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
     const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
     if (x >= R.nx || y >= R.ny) return;
@@ -500,7 +506,7 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
         }
     }
 
-    // ---- constitutive source (Oldroyd-B) and polymer stress ----
+    // ---- constitutive source and polymer stress of the closure (B = A - I = dphi) ----
     T Sc[6], tau[6];
     {
         T A[3][3];
@@ -509,16 +515,40 @@ __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
             A[ka(k)][kb(k)] = phi0(k) + dphi[k];
             A[kb(k)][ka(k)] = phi0(k) + dphi[k];
         }
+        // relaxation function F_r and stress function F_s (Oldroyd-B: both B)
+        T Fr[6], Fs[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Fr[k] = Fs[k] = dphi[k];
+        const T trB = dphi[0] + dphi[3] + dphi[5];
+        if (!CLOSURE) {
+        } else if (R.model == VLB_GIESEKUS) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int a = ka(k), b = kb(k);
+                T bb = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bb += (A[a][c] - (a == c ? 1.0 : 0.0)) * (A[c][b] - (c == b ? 1.0 : 0.0));
+                Fr[k] += R.mpar * bb;
+            }
+        } else if (R.model == VLB_LPTT || R.model == VLB_EPTT) {
+            const T Y = R.model == VLB_LPTT ? 1.0 + R.mpar * trB : exp(R.mpar * trB);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Fr[k] = Y * dphi[k];
+        } else if (R.model == VLB_FENE_P) {
+            const T f = (R.mpar - 3.0) / (R.mpar - 3.0 - trB);  // (L^2 - 3) / (L^2 - tr A)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Fr[k] = Fs[k] = f * (phi0(k) + dphi[k]) - phi0(k);
+        }
         const T trL = L[0][0] + L[1][1] + L[2][2];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const int a = ka(k), b = kb(k);
-            T s = -R.inv_lam * (A[a][b] - (a == b ? 1.0 : 0.0));
+            T s = -R.inv_lam * Fr[k];
 #pragma unroll
             for (int g = 0; g < 3; ++g) s += A[a][g] * L[g][b] + A[g][b] * L[g][a];
             s += A[a][b] * trL;
             Sc[k] = R.no_source ? 0.0 : s;
-            tau[k] = R.eta_over_lam * dphi[k];
+            tau[k] = R.eta_over_lam * Fs[k];
         }
     }
     // history: S and u of the previous step (the first step takes this step's)
@@ -709,6 +739,8 @@ struct vlb3_sim {
     int64_t step = 0;
     double nu_s = 0, eta_p = 0, lam = 1, kappa = 0, Ls = 0.25, Lp = 1e-6, F[3] = {0, 0, 0};
     int flags = 0;
+    int model = VLB_OLDROYD_B;
+    double mpar = 0.0;
 };
 
 namespace {
@@ -760,6 +792,8 @@ vlb3::Run3<S> make_run(const vlb3_sim* s) {
     r.eta_over_lam = s->eta_p / s->lam;
     for (int a = 0; a < 3; ++a) r.F[a] = s->F[a];
     r.no_source = (s->flags & VLB_FLAG_NO_SOURCE) ? 1 : 0;
+    r.model = s->model;
+    r.mpar = s->mpar;
     return r;
 }
 
@@ -790,13 +824,23 @@ int do_steps(vlb3_sim* s, int64_t n) {
         const vlb3::Run3<S> r = make_run<S>(s);
         if (s->has_solid) {  // (the wall code is compiled in; it checks the y walls itself)
             hipLaunchKernelGGL((vlb3::k3_macro<S, Lat, true>), grd, blk, 0, s->stream, r);
-            hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, true, vlb3::kHold<S, Lat, true>>), grd, blk, 0, s->stream, r);
+            if (s->model != VLB_OLDROYD_B)
+                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, true, vlb3::kHold<S, Lat, true, true>, true>), grd, blk, 0, s->stream, r);
+            else
+                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, true, vlb3::kHold<S, Lat, true>, false>), grd, blk, 0, s->stream, r);
         } else {
             hipLaunchKernelGGL((vlb3::k3_macro<S, Lat, false>), grd, blk, 0, s->stream, r);
-            if (s->ywall)
-                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, false, hold>), grd, blk, 0, s->stream, r);
-            else
-                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, false, false, hold>), grd, blk, 0, s->stream, r);
+            if (s->model != VLB_OLDROYD_B) {
+                constexpr int hc = vlb3::kHold<S, Lat, false, true>;
+                if (s->ywall)
+                    hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, false, hc, true>), grd, blk, 0, s->stream, r);
+                else
+                    hipLaunchKernelGGL((vlb3::k3_step<S, Lat, false, false, hc, true>), grd, blk, 0, s->stream, r);
+            } else if (s->ywall) {
+                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, true, false, hold, false>), grd, blk, 0, s->stream, r);
+            } else {
+                hipLaunchKernelGGL((vlb3::k3_step<S, Lat, false, false, hold, false>), grd, blk, 0, s->stream, r);
+            }
         }
         VLB3_HIP(hipGetLastError());
         s->parity ^= 1;
@@ -928,6 +972,21 @@ int vlb3_set_solid(vlb3_sim* s, const unsigned char* mask) {
     VLB3_HIP(hipStreamSynchronize(s->stream));
     s->has_solid = true;
     s->inited = false;
+    return VLB_OK;
+}
+
+int vlb3_set_closure(vlb3_sim* s, int model, double model_param) {
+    if (!s) return vlb::report_error(VLB_E_INVALID_ARG, "null simulation");
+    if (model < VLB_OLDROYD_B || model > VLB_FENE_P || !std::isfinite(model_param))
+        return vlb::report_error(VLB_E_INVALID_ARG, "unknown closure or non-finite parameter");
+    if (model == VLB_GIESEKUS && !(model_param >= 0.0 && model_param <= 1.0))
+        return vlb::report_error(VLB_E_INVALID_ARG, "Giesekus alpha must lie in [0, 1]");
+    if ((model == VLB_LPTT || model == VLB_EPTT) && !(model_param >= 0.0))
+        return vlb::report_error(VLB_E_INVALID_ARG, "PTT epsilon must be >= 0");
+    if (model == VLB_FENE_P && !(model_param > 3.0))
+        return vlb::report_error(VLB_E_INVALID_ARG, "FENE-P needs L^2 > 3 in three dimensions");
+    s->model = model;
+    s->mpar = model == VLB_OLDROYD_B ? 0.0 : model_param;
     return VLB_OK;
 }
 

@@ -52,7 +52,8 @@ class Simulation3D:
         if getattr(prob, "solid", None) is not None:
             sim.set_solid(prob.solid)
         sim.set_params(prob.nu_s, prob.eta_p, prob.lam, prob.kappa, prob.Lambda_s,
-                       prob.Lambda_p, *prob.F)
+                       prob.Lambda_p, *prob.F, model=getattr(prob, "model", "oldroyd_b"),
+                       model_param=getattr(prob, "model_param", 0.0))
         sim.init(**prob.init_arrays())
         return sim
 
@@ -77,11 +78,17 @@ class Simulation3D:
         L.check(self.lib.vlb3_set_solid(self._h, m.ctypes.data), "vlb3_set_solid")
 
     def set_params(self, nu_s, eta_p, lam, kappa, Lambda_s=0.25, Lambda_p=1e-6, Fx=0.0, Fy=0.0,
-                   Fz=0.0, flags=0):
+                   Fz=0.0, flags=0, model="oldroyd_b", model_param=0.0):
+        """Lattice-unit parameters and the constitutive closure ('oldroyd_b', 'giesekus'
+        with model_param = alpha, 'lptt' / 'eptt' with epsilon, 'fene_p' with L^2 > 3)."""
+        if model not in L.MODELS:
+            raise ValueError(f"unknown constitutive model {model!r}")
         L.check(self.lib.vlb3_set_params(self._h, float(nu_s), float(eta_p), float(lam),
                                          float(kappa), float(Lambda_s), float(Lambda_p),
                                          float(Fx), float(Fy), float(Fz), int(flags)),
                 "vlb3_set_params")
+        L.check(self.lib.vlb3_set_closure(self._h, L.MODELS[model], float(model_param)),
+                "vlb3_set_closure")
 
     def init(self, **fields):
         shape = (self.nz, self.ny, self.nx)

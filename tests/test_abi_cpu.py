@@ -84,6 +84,15 @@ def test_3d_create_validates_without_a_gpu(vlb):
     assert lib.vlb3_step(h, 1) == _lib.VLB_E_STATE  # not bound
     mask = np.zeros(8 * 6 * 5, np.uint8)
     assert lib.vlb3_set_solid(h, mask.ctypes.data) == _lib.VLB_E_STATE  # not bound
+    M = _lib.MODELS
+    for model, param, ok in [("oldroyd_b", 0.0, True), ("giesekus", 0.5, True),
+                             ("giesekus", 1.5, False), ("lptt", 0.0, True), ("eptt", -0.1, False),
+                             ("fene_p", 3.0, False), ("fene_p", 3.5, True),
+                             ("giesekus", float("nan"), False)]:
+        want = _lib.VLB_OK if ok else _lib.VLB_E_INVALID_ARG
+        assert lib.vlb3_set_closure(h, M[model], param) == want, (model, param)
+    assert lib.vlb3_set_closure(h, 5, 0.0) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_set_closure(None, 0, 0.0) == _lib.VLB_E_INVALID_ARG
     lib.vlb3_destroy(h)
 
 

@@ -255,3 +255,57 @@ def test_square_duct_3d_matches_oracle():
     for k in ("ux", "axx", "axy", "axz"):
         d = np.abs(g[k] - o[k])[fl].max()
         assert d < 1e-10 * max(1.0, np.abs(o[k]).max()), (k, d)
+
+
+CLOSURES = [("giesekus", 0.3), ("lptt", 0.2), ("eptt", 0.2), ("fene_p", 50.0)]
+
+
+def _stretched(pr):
+    """The random state plus a uniform stretch along x (A_xx + 1 everywhere, still
+    positive definite), which the diffusion of the node-scale noise leaves in place, so
+    that the closures' extra terms stay large (A - I of order one)."""
+    init = dict(pr.init)
+    init["axx"] = init["axx"] + 1.0
+    return pr.with_(init=init)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+@pytest.mark.parametrize("name", ["periodic_ragged", "walls_ragged"])
+@pytest.mark.parametrize("model,param", CLOSURES)
+def test_closures_3d(model, param, name, precision, tol, q):
+    """Giesekus, linear and exponential PTT and FENE-P (3-D trace) on seeded random
+    states: GPU against the oracle after 30 steps, element by element; the closure moves
+    the state away from the Oldroyd-B one by far more than the tolerance."""
+    import oracle
+
+    kw = dict(CASES[name])
+    base = _stretched(synth.random3d(kw.pop("nx"), kw.pop("ny"), kw.pop("nz"), seed=43, q=q, **kw))
+    pr = base.with_(model=model, model_param=param)
+    say("3d closure", model, name, precision, "q", q)
+    g, o = _run_pair(pr, 30, precision)
+    err = _parity(g, o)
+    keys = [k for k in err if precision == "fp64" or k != "rho"]
+    assert max(err[k] for k in keys) < tol, err
+    ob = oracle.OracleSim3D(base)
+    ob.step(30)
+    assert _rel(ob.read()["axx"], o["axx"]) > 100 * tol
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+@pytest.mark.parametrize("model,param", CLOSURES)
+def test_closures_with_solids_3d(model, param, precision, tol, q):
+    """Closures with solid nodes (the kernel that carries both): fluid nodes against the
+    oracle after 30 steps."""
+    nx, ny, nz = 67, 9, 6
+    pr = _stretched(synth.random3d(nx, ny, nz, seed=19, ymode="wall", q=q)).with_(
+        model=model, model_param=param, solid=_random_solid((nz, ny, nx), 29))
+    say("3d closure solids", model, precision, q)
+    g, o = _run_pair(pr, 30, precision)
+    fl = pr.solid == 0
+    du = np.sqrt(sum(((g[k] - o[k])[fl] ** 2).sum() for k in ("ux", "uy", "uz")))
+    nu = np.sqrt(sum((o[k][fl] ** 2).sum() for k in ("ux", "uy", "uz")))
+    assert du / nu < tol, du / nu
+    for k in ("axx", "axy", "axz", "ayy", "ayz", "azz"):
+        assert _rel(g[k][fl], o[k][fl]) < tol, (k, _rel(g[k][fl], o[k][fl]))
