@@ -9,13 +9,14 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvlb.so")
 SOURCES = ["vlb_kernels.hip", "vlb_batch.hip", "vlb_fill.hip", "vlb_aux.hip", "vlb_adjoint.hip",
-           "vlb3d.hip", "vlb_api.cpp"]
+           "vlb3d.hip", "vlb3d_f64.hip", "vlb_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VLB_OFFLOAD_ARCH", "gfx950")
@@ -39,8 +40,22 @@ PER_FILE = {
     "vlb_fill.hip": ["-ffp-contract=on"],
     "vlb_adjoint.hip": ["-ffp-contract=on"],
     "vlb3d.hip": ["-ffp-contract=on", "-mllvm", "-pragma-unroll-threshold=1000000"],
+    "vlb3d_f64.hip": ["-ffp-contract=on", "-mllvm", "-pragma-unroll-threshold=1000000"],
     "vlb_aux.hip": ["-ffp-contract=on"],
 }
+
+
+def compile_all(cmds, verbose: bool = False) -> None:
+    """Run the per-source compiler commands side by side (each is its own process)."""
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        futs = []
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            futs.append(pool.submit(subprocess.run, cmd, check=True))
+        for f in futs:
+            f.result()
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
@@ -53,15 +68,13 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     hipcc = HIPCC if os.path.exists(HIPCC) else shutil.which("hipcc")
     objdir = os.path.join(PKG, "_build", os.path.basename(out).replace(".so", ""))
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
-        cmd = [hipcc, *COMMON, *[f"-D{d}" for d in defines], *PER_FILE.get(src, []), "-c",
-               os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc, *COMMON, *[f"-D{d}" for d in defines], *PER_FILE.get(src, []), "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    compile_all(cmds, verbose)
     tmp = out + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
            # roctx ranges around the entry points that enqueue device work

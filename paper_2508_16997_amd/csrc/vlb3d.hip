@@ -20,6 +20,13 @@
 // input for g).
 // One node per lane, 64 x 4 lanes per block in x and y, one z slice per block row.
 // All arithmetic in double.
+//
+// The file is compiled twice: as itself (VLB3_PART 1: the FP32 kernels and the C ABI)
+// and through vlb3d_f64.hip (VLB3_PART 2: the FP64 kernels behind three functions of
+// namespace vlb3_f64), so that the two halves of the kernel set build side by side.
+#ifndef VLB3_PART
+#define VLB3_PART 1
+#endif
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -884,24 +891,50 @@ int do_read(vlb3_sim* s, void* const out[10]) {
     return VLB_OK;
 }
 
+}  // namespace
+
+// FP64 entry points (defined in the VLB3_PART 2 translation unit).
+namespace vlb3_f64 {
+int steps(vlb3_sim* s, int64_t n);
+int init(vlb3_sim* s, const void* const* fields);
+int read(vlb3_sim* s, void* const* out);
+}  // namespace vlb3_f64
+
+#if VLB3_PART == 2
+namespace vlb3_f64 {
+int steps(vlb3_sim* s, int64_t n) {
+    return s->q == 27 ? do_steps<double, vlb3::D3Q27>(s, n) : do_steps<double, vlb3::D3Q19>(s, n);
+}
+int init(vlb3_sim* s, const void* const* f) {
+    return s->q == 27 ? do_init<double, vlb3::D3Q27>(s, f) : do_init<double, vlb3::D3Q19>(s, f);
+}
+int read(vlb3_sim* s, void* const* o) {
+    return s->q == 27 ? do_read<double, vlb3::D3Q27>(s, o) : do_read<double, vlb3::D3Q19>(s, o);
+}
+}  // namespace vlb3_f64
+#else
+namespace {
+
 // Entry points by storage type and lattice.
-template <class S, class Lat>
+template <class Lat>
 struct StepOp {
-    static int run(vlb3_sim* s, int64_t n) { return do_steps<S, Lat>(s, n); }
+    static int run(vlb3_sim* s, int64_t n) { return do_steps<float, Lat>(s, n); }
+    static int f64(vlb3_sim* s, int64_t n) { return vlb3_f64::steps(s, n); }
 };
-template <class S, class Lat>
+template <class Lat>
 struct InitOp {
-    static int run(vlb3_sim* s, const void* const* f) { return do_init<S, Lat>(s, f); }
+    static int run(vlb3_sim* s, const void* const* f) { return do_init<float, Lat>(s, f); }
+    static int f64(vlb3_sim* s, const void* const* f) { return vlb3_f64::init(s, f); }
 };
-template <class S, class Lat>
+template <class Lat>
 struct ReadOp {
-    static int run(vlb3_sim* s, void* const* o) { return do_read<S, Lat>(s, o); }
+    static int run(vlb3_sim* s, void* const* o) { return do_read<float, Lat>(s, o); }
+    static int f64(vlb3_sim* s, void* const* o) { return vlb3_f64::read(s, o); }
 };
-template <template <class, class> class Op, class Arg>
+template <template <class> class Op, class Arg>
 int by_kind(vlb3_sim* s, Arg a) {
-    if (s->prec == VLB_FP32)
-        return s->q == 27 ? Op<float, vlb3::D3Q27>::run(s, a) : Op<float, vlb3::D3Q19>::run(s, a);
-    return s->q == 27 ? Op<double, vlb3::D3Q27>::run(s, a) : Op<double, vlb3::D3Q19>::run(s, a);
+    if (s->prec == VLB_FP32) return s->q == 27 ? Op<vlb3::D3Q27>::run(s, a) : Op<vlb3::D3Q19>::run(s, a);
+    return Op<vlb3::D3Q19>::f64(s, a);
 }
 
 }  // namespace
@@ -1064,3 +1097,4 @@ int vlb3_get_step(const vlb3_sim* s, int64_t* step) {
 void vlb3_destroy(vlb3_sim* s) { delete s; }
 
 }  // extern "C"
+#endif  // VLB3_PART

@@ -142,7 +142,7 @@ def test_library_host_code_under_asan_ubsan(tmpdir_mod):
     asan = _runtime([clang_dir, "-print-file-name=libclang_rt.asan-x86_64.so"])
     if not asan:
         pytest.skip("clang ASan runtime not installed")
-    objs = []
+    objs, cmds = [], []
     for src in B.SOURCES:
         obj = os.path.join(tmpdir_mod, src.replace(".", "_") + ".o")
         extra = []
@@ -150,10 +150,10 @@ def test_library_host_code_under_asan_ubsan(tmpdir_mod):
             extra = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                      "-Xarch_host", "-fno-sanitize-recover=undefined",
                      "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
-        subprocess.run([B.HIPCC, *B.COMMON, *B.PER_FILE.get(src, []), *extra, "-c",
-                        os.path.join(B.CSRC, src), "-o", obj], check=True,
-                       stderr=subprocess.DEVNULL)
+        cmds.append([B.HIPCC, *B.COMMON, *B.PER_FILE.get(src, []), *extra, "-c",
+                     os.path.join(B.CSRC, src), "-o", obj, "-w"])
         objs.append(obj)
+    B.compile_all(cmds)
     so = os.path.join(tmpdir_mod, "libvlb_san.so")
     subprocess.run([B.HIPCC, f"--offload-arch={B.ARCH}", "-shared", "-fPIC", "-o", so, *objs,
                     f"-L{B.ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{B.ROCM_LIB}"],
