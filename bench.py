@@ -40,6 +40,12 @@ MEASURED_TRAFFIC = {
         {"sources": "fe274e1098cea5b8", "tile": 8, "store_mode": "cached",
          "tile_order": "xcd bands", "fetch_KiB": 25923.2, "write_KiB": 42128.0,
          "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
+        {"sources": "fe274e1098cea5b8", "tile": 8, "store_mode": "streaming",
+         "tile_order": "row-major", "fetch_KiB": 30198.8, "write_KiB": 42150.6,
+         "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
+        {"sources": "fe274e1098cea5b8", "tile": 8, "store_mode": "streaming",
+         "tile_order": "column strips", "fetch_KiB": 30186.9, "write_KiB": 42150.6,
+         "profile": "profiles/k_step_four_roll_512_cylinder_4096x1024_fp32_fetch_write.md"},
     ],
     "cylinder_4096x1024": [
         {"sources": "fe274e1098cea5b8", "tile": 4, "store_mode": "streaming",

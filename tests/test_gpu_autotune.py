@@ -29,7 +29,7 @@ def _exact(sim):
 
 def test_autotune_sweeps_restores_and_caches(tmp_path):
     from paper_2508_16997_amd import Simulation
-    from paper_2508_16997_amd.autotune import size_class, tune
+    from paper_2508_16997_amd.autotune import ORDERS, STORE_MODES, size_class, tune
 
     pr = synth.random_periodic(150, 70, seed=9, ymode="wall", precision="fp32")
     say("autotune", pr.nx, pr.ny)
@@ -42,7 +42,13 @@ def test_autotune_sweeps_restores_and_caches(tmp_path):
     rec = tune(sim, steps=20, warmup=3, cache=cache)
     assert rec["tile"] in (1, 2, 4, 8) and rec["store_mode"] in (1, 2)
     assert rec["tile_order"] in (1, 2, 3) and rec["waves"] in (3, 4)
-    assert len(rec["sweep_us"]) == 48 and min(rec["sweep_us"].values()) == rec["us_per_step"]
+    assert len(rec["sweep_us"]) == 48 and len(rec["refine_us"]) == 4
+    # the refined candidates are the sweep's four fastest; the lowest median wins
+    fastest = sorted(rec["sweep_us"], key=rec["sweep_us"].get)[:4]
+    assert set(rec["refine_us"]) == set(fastest)
+    assert min(rec["refine_us"].values()) == rec["us_per_step"]
+    key = f"{rec['tile']}/{STORE_MODES[rec['store_mode']]}/{ORDERS[rec['tile_order']]}/w{rec['waves']}"
+    assert rec["refine_us"][key] == rec["us_per_step"]
     after = _exact(sim)
     for k in FIELDS:
         assert np.array_equal(before[k], after[k]), k
