@@ -7,8 +7,8 @@
  * for the three diagonal cubic defects d_a(rho u_a^3), the body force F_i and the
  * polymer stress T_i; six convection-diffusion lattices (A_xx, A_xy, A_xz, A_yy, A_yz,
  * A_zz) with the auxiliary term, the constitutive source Phi = -(A - I)/lambda + A L +
- * (A L)^T + A tr L (Oldroyd-B, L = grad u by central differences) and half its time
- * difference; half-way bounce-back of f and CNEBB of the conformation lattices at flat
+ * (A L)^T + A tr L (Oldroyd-B, L = grad u by central differences; the other closures
+ * of vlb.h through vlb3_set_closure) and half its time difference; half-way bounce-back of f and CNEBB of the conformation lattices at flat
  * walls.  The third order of the hydrodynamic lattice is expanded and projected in an
  * orthogonal basis with its lattice norms: on D3Q19 the six combinations H_aab -+ H_bcc,
  * on D3Q27 the six H_aab and H_xyz.

@@ -51,7 +51,8 @@ constexpr int TX = 64, TY = 4;
 // channel for none, two, three and four).  FP64: none, where holding them would leave
 // one wave per SIMD.
 // With solid nodes (general unknown sets in CNEBB) one lattice fewer on D3Q19 and two
-// fewer on D3Q27 keep two waves.
+// fewer on D3Q27 keep two waves; a closure other than Oldroyd-B (its extra arithmetic)
+// holds one lattice fewer again.
 template <class S, class Lat, bool SOLIDS = false, bool CLOSURE = false>
 constexpr int kHold = sizeof(S) == 4 ? (SOLIDS ? (Lat::Q == 19 ? 5 - CLOSURE : 2 - CLOSURE)
                                                : (Lat::Q == 19 ? 6 - CLOSURE : 4 - CLOSURE))
