@@ -38,7 +38,7 @@ extern "C" {
 typedef struct vlb3_sim vlb3_sim;
 
 /* Host object for an nx x ny x nz grid on the lattice q (19: D3Q19, 27: D3Q27); each
- * size >= 1, ny >= 3 with VLB_WALL, nz <= 65535, ny <= 262140, 7 q (nx * ny * nz + 4224)
+ * size >= 1, ny >= 3 with VLB_WALL, nz <= 65535, ny <= 65535, 7 q (nx * ny * nz + 4224)
  * below 2^31.  prec: VLB_FP32 or VLB_FP64; ymode: VLB_PERIODIC or VLB_WALL.
  * Errors: VLB_E_INVALID_ARG. */
 int vlb3_create(int nx, int ny, int nz, int q, int prec, int ymode, vlb3_sim** out);

@@ -18,7 +18,7 @@
 // y unless walls); a source beyond a wall or a solid source gives the node's own
 // post-collision value of the opposite direction (half-way bounce-back for f, the CNEBB
 // input for g).
-// One node per lane, 64 x 4 lanes per block in x and y, one z slice per block row.
+// One node per lane, one 64-lane row (one wave) per block, one z slice per block row.
 // All arithmetic in double.
 //
 // The file is compiled twice: as itself (VLB3_PART 1: the FP32 kernels and the C ABI)
@@ -43,7 +43,13 @@ namespace {
 
 using T = double;
 constexpr int NLAT = 7;  // hydrodynamic + six conformation lattices
-constexpr int TX = 64, TY = 4;
+// Block: TX x TY lanes, one wave per row.  One row per block measured fastest on the
+// 2^22-node channel (D3Q19 1049, 1065, 1068 and 1164 us per step for TY = 1, 2, 4, 8;
+// D3Q27 1517, 1539, 1558, 1705 us).
+#ifndef VLB3_TY
+#define VLB3_TY 1
+#endif
+constexpr int TX = 64, TY = VLB3_TY;
 // Conformation lattices whose pulled populations k3_step holds in registers from the
 // zeroth-moment pass to the collision (the others are pulled twice).  FP32 storage: all
 // six on D3Q19 (two waves per SIMD, no second read), four of six on D3Q27 (the most
@@ -988,7 +994,7 @@ int vlb3_create(int nx, int ny, int nz, int q, int prec, int ymode, vlb3_sim** o
         return vlb::report_error(VLB_E_INVALID_ARG, "ymode must be VLB_PERIODIC or VLB_WALL");
     if (ymode == VLB_WALL && ny < 3) return vlb::report_error(VLB_E_INVALID_ARG, "walls need ny >= 3");
     if (nz > 65535 || (ny + vlb3::TY - 1) / vlb3::TY > 65535)
-        return vlb::report_error(VLB_E_INVALID_ARG, "nz and ny / 4 must stay within the launch grid (65535)");
+        return vlb::report_error(VLB_E_INVALID_ARG, "nz and the rows of blocks in y must stay within the launch grid (65535)");
     const long long N = (long long)nx * ny * nz;
     if (plane_stride(N) >= (1LL << 31) / (vlb3::NLAT * q))
         return vlb::report_error(VLB_E_INVALID_ARG, "grid too large for 32-bit plane offsets");

@@ -65,6 +65,11 @@ def test_3d_create_validates_without_a_gpu(vlb):
     assert lib.vlb3_create(4, 2, 4, 19, F32, WALL, C.byref(h)) == _lib.VLB_E_INVALID_ARG
     assert lib.vlb3_create(4, 4, 4, 19, F32, _lib.VLB_OPEN, C.byref(h)) == _lib.VLB_E_INVALID_ARG
     assert lib.vlb3_create(4, 4, 4, 15, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    # one block row per grid row in y: at most 65535 rows (and slices in z)
+    assert lib.vlb3_create(1, 65536, 1, 19, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(1, 1, 65536, 19, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
+    assert lib.vlb3_create(1, 65535, 1, 19, F32, PER, C.byref(h)) == _lib.VLB_OK
+    lib.vlb3_destroy(h)
     # 7 q planes of (nodes rounded up to 64) + 4160 elements must stay below 2^31
     assert lib.vlb3_create(1024, 1024, 15, 27, F32, PER, C.byref(h)) == _lib.VLB_E_INVALID_ARG
     assert lib.vlb3_create(1024, 1024, 15, 19, F32, PER, C.byref(h)) == _lib.VLB_OK
