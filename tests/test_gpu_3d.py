@@ -159,13 +159,14 @@ def test_3d_exchange_symmetry_and_mass_at_size(q):
         assert abs(r["rho"].sum() / m0 - 1) < 1e-6
 
 
+@pytest.mark.parametrize("model,param", [("oldroyd_b", 0.0), ("giesekus", 0.3)])
 @pytest.mark.parametrize("q,nz", [(19, 985), (27, 693)])
-def test_largest_grid_matches_its_one_column_problem(q, nz):
+def test_largest_grid_matches_its_one_column_problem(q, nz, model, param):
     """The largest grid vlb3_create accepts on each lattice (256 x 64 x nz, 7 q planes of
     just under 2^31 / (7 q) elements: 16.1 M nodes on D3Q19, 11.4 M on D3Q27), FP64, where
     the byte offsets of the upper planes within a lattice pass 2^31: an x- and
     z-invariant channel state stays bit-identical, column by column, to the same state on
-    a 1 x 64 x 1 grid after 20 steps."""
+    a 1 x 64 x 1 grid after 20 steps (Oldroyd-B, and the Giesekus closure kernel)."""
     import torch
     from paper_2508_16997_amd.sim3d import Simulation3D
 
@@ -178,9 +179,10 @@ def test_largest_grid_matches_its_one_column_problem(q, nz):
     prof = dict(ux=ux, axy=0.5 * lam * du, axx=1 + (lam * du) ** 2)
     res = {}
     for nx_, nz_ in ((1, 1), (256, nz)):
-        say("3d largest", q, nx_, ny, nz_)
+        say("3d largest", q, nx_, ny, nz_, model)
         sim = Simulation3D(nx_, ny, nz_, "wall", "fp64", q=q)
-        sim.set_params(pr.nu_s, pr.eta_p, pr.lam, pr.kappa, pr.Lambda_s, pr.Lambda_p, *pr.F)
+        sim.set_params(pr.nu_s, pr.eta_p, pr.lam, pr.kappa, pr.Lambda_s, pr.Lambda_p, *pr.F,
+                       model=model, model_param=param)
         sim.init(**{k: v.reshape(1, ny, 1) for k, v in prof.items()})
         sim.step(20)
         res[nx_] = sim.read()
