@@ -197,15 +197,19 @@ def test_largest_grid_matches_its_one_column_problem(q, nz, model, param):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("model,param", [("oldroyd_b", 0.0), ("fene_p", 50.0)])
 @pytest.mark.parametrize("q", [19, 27])
-def test_random_state_at_the_benchmark_size(q):
+def test_random_state_at_the_benchmark_size(q, model, param):
     """The benchmark grid (256 x 64 x 256, half-way walls in y, FP32 storage, the launch
     configuration the bench leg times) from a seeded random state: every field after 3
-    steps against the oracle, element by element (FP32 storage bar)."""
+    steps against the oracle, element by element (FP32 storage bar); also the FENE-P
+    closure kernel on the stretched state."""
     import oracle
 
     pr = synth.random3d(256, 64, 256, seed=8, ymode="wall", q=q, precision="fp32")
-    say("3d bench size", q)
+    if model != "oldroyd_b":
+        pr = _stretched(pr).with_(model=model, model_param=param)
+    say("3d bench size", q, model)
     g, o = _run_pair(pr, 3, "fp32")
     err = _parity(g, o)
     keys = [k for k in err if k != "rho"]
